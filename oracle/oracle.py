@@ -1,0 +1,218 @@
+"""Python access to the FP64 CPU oracle (``am_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+CPU-baseline leg of the benchmark.  The product library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborc.so")
+SRC = os.path.join(HERE, "am_oracle.c")
+
+
+def build(force: bool = True, out: str = LIB_PATH, mutate: int = 0) -> str:
+    """Compile the oracle with gcc (generic x86-64, -O2, no GPU code).
+
+    ``mutate`` > 0 builds a deliberately broken variant (see ORC_MUTATE in the
+    C source); only the mutation test asks for one, into a temporary path.
+    """
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wno-unused-function"]
+        if mutate:
+            cmd.append(f"-DORC_MUTATE={int(mutate)}")
+        subprocess.check_call(cmd + [SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+class _Net(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("width", C.POINTER(C.c_int32)),
+                ("n_blocks", C.c_int32), ("blk_dst", C.POINTER(C.c_int32)),
+                ("blk_src", C.POINTER(C.c_int32)), ("blk_off", C.POINTER(C.c_int64)),
+                ("weights", C.POINTER(C.c_double)), ("bias_off", C.POINTER(C.c_int64)),
+                ("biases", C.POINTER(C.c_double))]
+
+
+_libs = {}
+
+
+def lib(path: str = LIB_PATH):
+    L = _libs.get(path)
+    if L is None:
+        if not os.path.exists(path):
+            if path != LIB_PATH:
+                raise FileNotFoundError(path)
+            build()
+        L = C.CDLL(path)
+        P = C.POINTER
+        L.orc_code_words.argtypes = [P(_Net)]
+        L.orc_code_words.restype = C.c_int
+        L.orc_forward.argtypes = [P(_Net), P(C.c_double), P(C.c_double), P(C.c_int32)]
+        L.orc_forward.restype = C.c_double
+        L.orc_code.argtypes = [P(_Net), P(C.c_double), P(C.c_uint64), P(C.c_int32)]
+        L.orc_code.restype = C.c_double
+        L.orc_chain.argtypes = [P(_Net), P(C.c_uint64), P(C.c_double)]
+        L.orc_chain.restype = None
+        L.orc_face.argtypes = [P(_Net), P(C.c_uint64), C.c_int32, C.c_int, P(C.c_int32),
+                               P(C.c_double), P(C.c_double), P(C.c_int32)]
+        L.orc_face.restype = C.c_int
+        L.orc_seed_ray.argtypes = [P(_Net), P(C.c_double), P(C.c_double), C.c_int,
+                                   P(C.c_double), P(C.c_uint64), P(C.c_int32)]
+        L.orc_seed_ray.restype = C.c_int
+        L.orc_march.argtypes = [P(_Net), P(C.c_uint64), P(C.c_int32), C.c_int64, C.c_int64]
+        L.orc_march.restype = C.c_void_p
+        L.orc_result_free.argtypes = [C.c_void_p]
+        L.orc_result_counts.argtypes = [C.c_void_p, P(C.c_int64)]
+        L.orc_result_fetch.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double),
+                                       P(C.c_int64), P(C.c_uint64), P(C.c_int32)]
+        _libs[path] = L
+    return L
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class OracleNet:
+    """A :class:`am_workloads.nets.Net` marshalled for the C oracle."""
+
+    def __init__(self, net, lib_path: str = LIB_PATH):
+        self.net = net
+        self._L = lib(lib_path)
+        self.width = np.asarray(net.widths, np.int32)
+        self.dst = np.asarray([d for d, _, _ in net.blocks], np.int32)
+        self.src = np.asarray([s for _, s, _ in net.blocks], np.int32)
+        offs, o = [], 0
+        for _, _, W in net.blocks:
+            offs.append(o)
+            o += W.size
+        self.blk_off = np.asarray(offs, np.int64)
+        self.weights = np.concatenate([W.ravel() for _, _, W in net.blocks]).astype(np.float64)
+        boffs, o = [0], 0
+        for b in net.bias:
+            boffs.append(o)
+            o += b.size
+        self.bias_off = np.asarray(boffs, np.int64)
+        self.biases = np.concatenate(net.bias).astype(np.float64)
+        self.s = _Net(len(self.width), _ptr(self.width, C.c_int32), len(self.dst),
+                      _ptr(self.dst, C.c_int32), _ptr(self.src, C.c_int32),
+                      _ptr(self.blk_off, C.c_int64), _ptr(self.weights, C.c_double),
+                      _ptr(self.bias_off, C.c_int64), _ptr(self.biases, C.c_double))
+        self.N = net.n_hidden
+        self.M = net.n_heads
+        self.W = self._L.orc_code_words(C.byref(self.s))
+
+    # -- per-point / per-cell primitives ----------------------------------
+    def forward(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        pre = np.zeros(self.N + self.M)
+        am = C.c_int32()
+        F = self._L.orc_forward(C.byref(self.s), _ptr(x, C.c_double), _ptr(pre, C.c_double), C.byref(am))
+        return F, pre, am.value
+
+    def code(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        code = np.zeros(self.W, np.uint64)
+        am = C.c_int32()
+        F = self._L.orc_code(C.byref(self.s), _ptr(x, C.c_double), _ptr(code, C.c_uint64), C.byref(am))
+        return code, am.value, F
+
+    def chain(self, code):
+        code = np.ascontiguousarray(code, np.uint64)
+        rows = np.zeros((self.N + self.M, 4))
+        self._L.orc_chain(C.byref(self.s), _ptr(code, C.c_uint64), _ptr(rows, C.c_double))
+        return rows
+
+    def face(self, code, argmax=0, max_m=128):
+        code = np.ascontiguousarray(code, np.uint64)
+        ids = np.zeros(max_m, np.int32)
+        verts = np.zeros((max_m, 3))
+        area = C.c_double()
+        flags = C.c_int32()
+        m = self._L.orc_face(C.byref(self.s), _ptr(code, C.c_uint64), int(argmax), max_m,
+                           _ptr(ids, C.c_int32), _ptr(verts, C.c_double), C.byref(area),
+                           C.byref(flags))
+        return ids[:m].copy(), verts[:m].copy(), area.value, flags.value
+
+    def seed_ray(self, o, d, max_iter=200):
+        o = np.ascontiguousarray(o, np.float64)
+        d = np.ascontiguousarray(d, np.float64)
+        x = np.zeros(3)
+        code = np.zeros(self.W, np.uint64)
+        am = C.c_int32()
+        st = self._L.orc_seed_ray(C.byref(self.s), _ptr(o, C.c_double), _ptr(d, C.c_double),
+                                int(max_iter), _ptr(x, C.c_double), _ptr(code, C.c_uint64),
+                                C.byref(am))
+        return st, x, code, am.value
+
+    def seed_rays(self, origins, dirs, max_iter=200):
+        """Seeds for a batch of rays; returns (codes[S,W], argmax[S], points[S,3], status[R])."""
+        codes, ams, pts, sts = [], [], [], []
+        for o, d in zip(origins, dirs):
+            st, x, code, am = self.seed_ray(o, d, max_iter)
+            sts.append(st)
+            if st == 0:
+                codes.append(code)
+                ams.append(am)
+                pts.append(x)
+        W = self.W
+        return (np.asarray(codes, np.uint64).reshape(-1, W), np.asarray(ams, np.int32),
+                np.asarray(pts, np.float64).reshape(-1, 3), np.asarray(sts, np.int32))
+
+    def march(self, seed_codes, seed_argmax=None, max_cells=0):
+        seed_codes = np.ascontiguousarray(np.asarray(seed_codes, np.uint64).reshape(-1, self.W))
+        S = seed_codes.shape[0]
+        if seed_argmax is None:
+            seed_argmax = np.zeros(S, np.int32)
+        seed_argmax = np.ascontiguousarray(seed_argmax, np.int32)
+        L = self._L
+        R = L.orc_march(C.byref(self.s), _ptr(seed_codes, C.c_uint64), _ptr(seed_argmax, C.c_int32),
+                        S, int(max_cells))
+        if not R:
+            raise MemoryError("oracle march failed")
+        try:
+            cnt = np.zeros(7, np.int64)
+            L.orc_result_counts(R, _ptr(cnt, C.c_int64))
+            F, nv = int(cnt[0]), int(cnt[1])
+            offsets = np.zeros(F + 1, np.int64)
+            ids = np.zeros(nv, np.int32)
+            verts = np.zeros((nv, 3))
+            nbr = np.zeros(nv, np.int64)
+            codes = np.zeros((F, self.W), np.uint64)
+            am = np.zeros(F, np.int32)
+            L.orc_result_fetch(R, _ptr(offsets, C.c_int64), _ptr(ids, C.c_int32),
+                               _ptr(verts, C.c_double), _ptr(nbr, C.c_int64),
+                               _ptr(codes, C.c_uint64), _ptr(am, C.c_int32))
+        finally:
+            L.orc_result_free(R)
+        stats = dict(faces=F, face_verts=nv, cells=int(cnt[2]), seeds_in=int(cnt[3]),
+                     seed_dup=int(cnt[4]), seed_empty=int(cnt[5]), degenerate=int(cnt[6]))
+        return Mesh(codes, am, offsets, ids, verts, nbr, stats)
+
+
+@dataclasses.dataclass
+class Mesh:
+    """Polygon mesh in canonical face order (faces sorted by code, then argmax)."""
+    codes: np.ndarray     # [F, W] uint64
+    argmax: np.ndarray    # [F] int32
+    offsets: np.ndarray   # [F+1] int64
+    ids: np.ndarray       # [V] int32 edge (constraint) id of edge i of each face
+    verts: np.ndarray     # [V, 3] float64, vertex i starts edge i
+    nbr: np.ndarray       # [V] int64 face across edge i (-1 domain, -2 missing)
+    stats: dict
+
+    @property
+    def n_faces(self):
+        return len(self.offsets) - 1
+
+    def face(self, f):
+        a, b = self.offsets[f], self.offsets[f + 1]
+        return self.ids[a:b], self.verts[a:b], self.nbr[a:b]
