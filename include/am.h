@@ -1,0 +1,178 @@
+/*
+ * am.h -- C ABI of the analytic-marching library for AMD MI355X (gfx950).
+ *
+ * The library meshes the exact zero-level set of a ReLU network F (Sec. 2.2
+ * of Lei, Jia, Ma: "Learning and Meshing from Deep Implicit Surface Networks
+ * Using an Efficient Implementation of Analytic Marching") as a polygon mesh
+ * Z = {V, {P}}: one convex polygon (the analytic face, Eqn (AnalyticFace)) per
+ * analytic cell, each with its vertices (Eqn (VertexEquationSystem)) and the
+ * face across each of its edges.  Cells are visited by analytic marching
+ * (Algorithm 1, parallel marching of Sec. 4.2.2): all cells of the active set
+ * are solved at once on the GPU and their neighbours, found by flipping one
+ * unit's state (Sec. 3.1), are deduplicated in a device hash set.
+ *
+ * Network model (Sec. 2.2, Sec. 5.1 shortcuts, Sec. 5.2 max pooling): layer 0
+ * is the input x in R^3, layers 1..L are ReLU layers, layer L+1 holds M >= 1
+ * heads and F(x) = max_i head_i(x).  A block (dst, src, W) adds W act[src] to
+ * the pre-activation of layer dst for any src < dst (identity or linear
+ * shortcuts are ordinary blocks); act[0] = x, act[l] = relu(pre[l]).
+ *
+ * Conventions (fixed; the CPU reference follows the same ones):
+ *   - activation code: N = n_1 + ... + n_L bits, layer-major; bit g lives in
+ *     bit (g % 64) of 64-bit word g / 64; a unit is on iff its
+ *     pre-activation is > 0 (Eqn (NeuronState)).  W = max(1, ceil(N/64))
+ *     words per code.  The argmax head j (lowest index on ties) is part of
+ *     the cell's identity (Eqn (StateFuntionalMaxPoolingOperation)).
+ *   - domain: the box [-1,1]^3.  Edge (constraint) ids: 0..N-1 hidden units,
+ *     N+i the max-pool comparison with head i, -1..-6 the box planes
+ *     x<=1, x>=-1, y<=1, y>=-1, z<=1, z>=-1 (no neighbour).
+ *   - polygons run counter-clockwise seen from +grad F and start at the
+ *     edge with the smallest id; vertex i starts edge i.
+ *   - a vertex lies ON a constraint line when |c.[v;1]| <= 2^-40 *
+ *     (|c_uv| (1 + |v_uv|) + |c_w|) in the plane frame; only constraints
+ *     carrying an edge of positive length spawn neighbours.
+ *
+ * Memory: every pointer argument is either a host pointer or a device pointer
+ * as stated per call.  The context owns its device scratch (allocated on
+ * am_load_net / am_march and freed by am_destroy) and enqueues all work on
+ * the HIP stream given to am_create.  No call throws or aborts across the
+ * ABI; failures return a status and am_last_error() describes them.  A
+ * context must not be used from two threads at once.
+ */
+#ifndef AM_H
+#define AM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AM_OK = 0,
+    AM_E_INVALID = 1,    /* bad argument, bad network, NaN/Inf weights */
+    AM_E_OOM = 2,        /* device allocation failed */
+    AM_E_CAPACITY = 3,   /* a capacity in am_march_opts was too small; see stats */
+    AM_E_SEED = 4,       /* no seed produced a non-empty face */
+    AM_E_DEGENERATE = 5, /* strict mode: a degenerate face was met */
+    AM_E_HIP = 6,        /* a HIP runtime call failed */
+    AM_E_STATE = 7       /* call out of order (e.g. march before load) */
+} am_status;
+
+typedef struct am_ctx am_ctx;
+
+/* Network description.  All pointers are HOST pointers, borrowed for the
+ * call only (the weights are copied to the device, widened to FP64). */
+typedef struct {
+    int32_t n_layers;             /* L + 2 (input, hidden layers, head layer) */
+    const int32_t *width;         /* [n_layers]; width[0] must be 3 */
+    int32_t n_blocks;
+    const int32_t *blk_dst;       /* [n_blocks], 1 <= dst < n_layers */
+    const int32_t *blk_src;       /* [n_blocks], 0 <= src < dst */
+    const double *const *blk_w;   /* [n_blocks] row-major width[dst] x width[src] */
+    const double *const *bias;    /* [n_layers]; bias[l] has width[l] entries, bias[0] unused */
+} am_net_desc;
+
+typedef struct {
+    int64_t max_cells;    /* capacity of discovered cells (0: 1<<20) */
+    int32_t max_steps;    /* bound on marching steps (0: unbounded) */
+    int32_t strict;       /* 1: return AM_E_DEGENERATE on a degenerate face */
+    int32_t reserved[8];
+} am_march_opts;
+
+typedef struct {
+    int64_t faces;            /* cells with a non-empty face */
+    int64_t face_verts;       /* sum of polygon sizes */
+    int64_t triangles;        /* sum of (m - 2): fan triangulation count */
+    int64_t cells;            /* distinct cells discovered (incl. empty) */
+    int64_t steps;            /* marching steps (frontier generations) */
+    int64_t max_frontier;     /* largest frontier */
+    int64_t seeds_in;         /* seed cells before deduplication */
+    int64_t seed_cells;       /* distinct seed cells */
+    int64_t seed_empty;       /* seed cells whose face is empty */
+    int64_t degenerate;       /* non-seed cells with an empty or degenerate face */
+    int64_t domain_edges;     /* edges on the box */
+    int64_t required_cells;   /* on AM_E_CAPACITY: the cell capacity needed so far */
+    double march_ms;          /* device time of the march (HIP events) */
+    double reserved[7];
+} am_march_stats;
+
+/* Creates a context on `device` that enqueues its work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+am_status am_create(am_ctx **out, int device, void *hip_stream);
+
+/* Frees the context and every device buffer it owns.  NULL is a no-op. */
+void am_destroy(am_ctx *ctx);
+
+/* Text of the last failure on this context (owned by ctx; valid until the
+ * next call on it). */
+const char *am_last_error(const am_ctx *ctx);
+
+/* Loads a network (Sec. 2.2, 5.1, 5.2); see am_net_desc.  Rejects widths
+ * < 1, width[0] != 3, non-feed-forward or duplicate blocks, layers with no
+ * input block, N > 4096 and NaN/Inf parameters with AM_E_INVALID.  Resets
+ * any seeds and results. */
+am_status am_load_net(am_ctx *ctx, const am_net_desc *net);
+
+/* Dimensions of the loaded network: N hidden units, M heads, W code words. */
+am_status am_net_dims(const am_ctx *ctx, int32_t *n_hidden, int32_t *n_heads, int32_t *code_words);
+
+/* Forward pass: code and F at n points (Eqns (NeuronState)-(MLPState)).
+ * DEVICE pointers: pts [n][3] f64 in; codes [n][W] u64, argmax [n] i32,
+ * F [n] f64 out (any output may be NULL).  Enqueued; returns before the
+ * results are ready (synchronise the stream). */
+am_status am_codes(am_ctx *ctx, const double *pts, int64_t n, uint64_t *codes, int32_t *argmax,
+                   double *F);
+
+/* Affine chain (Lemma 1, Corollary 1): for each of n cells given by its
+ * code, the rows Z[g] = (a, b, c, d) with pre_g(x) = a x + b y + c z + d
+ * inside the cell, g = 0..N-1 hidden units then N..N+M-1 heads.  DEVICE
+ * pointers: codes [n][W] u64 in; rows [n][N+M][4] f64 out.  Enqueued. */
+am_status am_chain(am_ctx *ctx, const uint64_t *codes, int64_t n, double *rows);
+
+/* Analytic faces of n given cells (Eqn (AnalyticFace) clipped to the box,
+ * vertices by Eqn (VertexEquationSystem)), without marching.  DEVICE
+ * pointers: codes [n][W], argmax [n] in; m [n] i32 (0 = empty face),
+ * ids [n][max_m] i32, verts [n][max_m][3] f64, flags [n] i32 out.
+ * max_m must be in 3..64.  Enqueued. */
+am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n,
+                   int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags);
+
+/* Seeds by dichotomy along rays o + t d, t in [0,1] (Sec. 4.3.2): bisect
+ * until both bracket ends share one code (at most max_iter halvings, <= 0
+ * means 200), then take the linear root inside that cell; the seed cell is
+ * the code and argmax at the root.  DEVICE pointers: orig [R][3], dir [R][3]
+ * f64.  Rays without a sign change are skipped (counted in status_out, a
+ * DEVICE [R] i32 array that may be NULL: 0 ok, 1 no sign change, 2 no
+ * convergence).  Replaces any previous seeds; the seed cells are kept in
+ * the context for am_march.  Enqueued. */
+am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, int64_t n_rays,
+                       int32_t max_iter, int32_t *status_out);
+
+/* Seeds given directly as cells.  DEVICE pointers: codes [S][W] u64,
+ * argmax [S] i32 (NULL = all 0).  Replaces any previous seeds.  Enqueued. */
+am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n);
+
+/* Marches from the current seeds (Algorithm 1, all active cells at once)
+ * until the active set is empty.  Blocks until done.  opts may be NULL.
+ * Returns AM_E_CAPACITY (stats->required_cells set) when max_cells is too
+ * small; AM_E_SEED when every seed face is empty. */
+am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats);
+
+/* Sizes of the last march's result. */
+am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, int64_t *cells);
+
+/* Copies the last march's mesh into caller-owned DEVICE buffers, faces in
+ * discovery order:  offsets [F+1] i64 (CSR into the per-edge arrays),
+ * ids [V] i32 edge constraint ids, verts [V][3] f64 (vertex i starts edge i),
+ * nbr [V] i64 face index across edge i (-1 box edge, -2 neighbour cell has
+ * no face), codes [F][W] u64, argmax [F] i32.  Any pointer may be NULL to
+ * skip that output.  Enqueued. */
+am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
+                   uint64_t *codes, int32_t *argmax);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AM_H */

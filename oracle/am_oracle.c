@@ -357,7 +357,10 @@ int orc_face_from_rows(const orc_net *net, const uint64_t *code, int32_t argmax,
     }
     if (m < 3) { *flags = ORC_FACE_EMPTY; return 0; }
     for (int i = 0; i < m; i++) {
-        if (P[i].e <= -7) *flags |= ORC_FACE_DEGEN;
+        if (P[i].e <= -7) { /* a frame edge survived the box planes: unusable face */
+            *flags |= ORC_FACE_DEGEN | ORC_FACE_EMPTY;
+            return 0;
+        }
         for (int j = i + 1; j < m; j++)
             if (P[i].e == P[j].e) *flags |= ORC_FACE_DEGEN;
     }

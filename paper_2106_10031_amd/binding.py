@@ -1,0 +1,233 @@
+"""Thin Python binding of the C ABI in include/am.h (argument marshalling only).
+
+Every step of analytic marching runs in the HIP kernels of libam.so; this
+module only passes pointers.  PyTorch supplies device memory and the stream.
+The library must have been built (``paper_2106_10031_amd/build.py``); there is
+no fallback: if it is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libam.so")
+
+AM_OK, AM_E_INVALID, AM_E_OOM, AM_E_CAPACITY, AM_E_SEED, AM_E_DEGENERATE, AM_E_HIP, AM_E_STATE = range(8)
+STATUS_NAMES = {0: "AM_OK", 1: "AM_E_INVALID", 2: "AM_E_OOM", 3: "AM_E_CAPACITY", 4: "AM_E_SEED",
+                5: "AM_E_DEGENERATE", 6: "AM_E_HIP", 7: "AM_E_STATE"}
+
+# every symbol include/am.h declares
+EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_net_dims", "am_codes", "am_chain",
+           "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch"]
+
+
+class AmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("width", C.POINTER(C.c_int32)), ("n_blocks", C.c_int32),
+                ("blk_dst", C.POINTER(C.c_int32)), ("blk_src", C.POINTER(C.c_int32)),
+                ("blk_w", C.POINTER(C.POINTER(C.c_double))), ("bias", C.POINTER(C.POINTER(C.c_double)))]
+
+
+class MarchOpts(C.Structure):
+    _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
+                ("reserved", C.c_int32 * 8)]
+
+
+class MarchStats(C.Structure):
+    _fields_ = [("faces", C.c_int64), ("face_verts", C.c_int64), ("triangles", C.c_int64),
+                ("cells", C.c_int64), ("steps", C.c_int64), ("max_frontier", C.c_int64),
+                ("seeds_in", C.c_int64), ("seed_cells", C.c_int64), ("seed_empty", C.c_int64),
+                ("degenerate", C.c_int64), ("domain_edges", C.c_int64), ("required_cells", C.c_int64),
+                ("march_ms", C.c_double), ("reserved", C.c_double * 7)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib(path: str = LIB_PATH):
+    """Loads libam.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python paper_2106_10031_amd/build.py")
+    L = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.am_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.am_destroy.argtypes = [vp]
+    L.am_destroy.restype = None
+    L.am_last_error.argtypes = [vp]
+    L.am_last_error.restype = C.c_char_p
+    L.am_load_net.argtypes = [vp, C.POINTER(NetDesc)]
+    L.am_net_dims.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.am_codes.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.am_chain.argtypes = [vp, vp, i64, vp]
+    L.am_faces.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, vp]
+    L.am_seed_rays.argtypes = [vp, vp, vp, i64, i32, vp]
+    L.am_seed_cells.argtypes = [vp, vp, vp, i64]
+    L.am_march.argtypes = [vp, C.POINTER(MarchOpts), C.POINTER(MarchStats)]
+    L.am_get_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("am_destroy", "am_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _p(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One am_ctx bound to a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.L = lib()
+        h = C.c_void_p()
+        st = self.L.am_create(C.byref(h), int(device), C.c_void_p(stream.cuda_stream))
+        if st != AM_OK:
+            raise AmError(st, "am_create failed")
+        self.h = h
+        self.N = self.M = self.W = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.am_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != AM_OK:
+            raise AmError(st, self.L.am_last_error(self.h).decode())
+
+    # ------------------------------------------------------------------ net
+    def load_net(self, net):
+        """Loads a network given as (widths, blocks [(dst, src, W)], bias [per layer >= 1])."""
+        widths = np.asarray(net.widths, np.int32)
+        dst = np.asarray([d for d, _, _ in net.blocks], np.int32)
+        src = np.asarray([s for _, s, _ in net.blocks], np.int32)
+        ws = [np.ascontiguousarray(W, np.float64) for _, _, W in net.blocks]
+        bs = [np.zeros(3)] + [np.ascontiguousarray(b, np.float64) for b in net.bias]
+        DP = C.POINTER(C.c_double)
+        wp = (DP * len(ws))(*[w.ctypes.data_as(DP) for w in ws])
+        bp = (DP * len(bs))(*[b.ctypes.data_as(DP) for b in bs])
+        desc = NetDesc(len(widths), widths.ctypes.data_as(C.POINTER(C.c_int32)), len(ws),
+                       dst.ctypes.data_as(C.POINTER(C.c_int32)), src.ctypes.data_as(C.POINTER(C.c_int32)),
+                       wp, bp)
+        self._check(self.L.am_load_net(self.h, C.byref(desc)))
+        n, m, w = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.L.am_net_dims(self.h, C.byref(n), C.byref(m), C.byref(w)))
+        self.N, self.M, self.W = n.value, m.value, w.value
+        return self
+
+    # ------------------------------------------------------------ per point
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return t.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=self.device)
+
+    def codes(self, pts):
+        t = self.torch
+        pts = self._dev(pts, t.float64).reshape(-1, 3)
+        n = pts.shape[0]
+        codes = t.empty((n, self.W), dtype=t.int64, device=self.device)
+        am = t.empty(n, dtype=t.int32, device=self.device)
+        F = t.empty(n, dtype=t.float64, device=self.device)
+        self._check(self.L.am_codes(self.h, _p(pts), n, _p(codes), _p(am), _p(F)))
+        return codes, am, F
+
+    def chain(self, codes):
+        t = self.torch
+        codes = self._dev(codes, t.int64).reshape(-1, self.W)
+        n = codes.shape[0]
+        rows = t.empty((n, self.N + self.M, 4), dtype=t.float64, device=self.device)
+        self._check(self.L.am_chain(self.h, _p(codes), n, _p(rows)))
+        return rows
+
+    def faces(self, codes, argmax=None, max_m=32):
+        t = self.torch
+        codes = self._dev(codes, t.int64).reshape(-1, self.W)
+        n = codes.shape[0]
+        am = None if argmax is None else self._dev(argmax, t.int32)
+        m = t.empty(n, dtype=t.int32, device=self.device)
+        ids = t.empty((n, max_m), dtype=t.int32, device=self.device)
+        verts = t.empty((n, max_m, 3), dtype=t.float64, device=self.device)
+        flags = t.empty(n, dtype=t.int32, device=self.device)
+        self._check(self.L.am_faces(self.h, _p(codes), _p(am), n, int(max_m), _p(m), _p(ids), _p(verts),
+                                    _p(flags)))
+        return m, ids, verts, flags
+
+    # --------------------------------------------------------------- march
+    def seed_rays(self, orig, dirs, max_iter=200):
+        t = self.torch
+        o = self._dev(orig, t.float64).reshape(-1, 3)
+        d = self._dev(dirs, t.float64).reshape(-1, 3)
+        status = t.empty(o.shape[0], dtype=t.int32, device=self.device)
+        self._check(self.L.am_seed_rays(self.h, _p(o), _p(d), o.shape[0], int(max_iter), _p(status)))
+        return status
+
+    def seed_cells(self, codes, argmax=None):
+        t = self.torch
+        codes = self._dev(codes, t.int64).reshape(-1, self.W)
+        am = None if argmax is None else self._dev(argmax, t.int32)
+        self._seed_keep = (codes, am)       # the copy is enqueued on the stream
+        self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), codes.shape[0]))
+
+    def march(self, max_cells=0, max_steps=0, strict=False):
+        opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)))
+        stats = MarchStats()
+        st = self.L.am_march(self.h, C.byref(opts), C.byref(stats))
+        if st != AM_OK:
+            err = AmError(st, self.L.am_last_error(self.h).decode())
+            err.stats = stats.as_dict()
+            raise err
+        return stats.as_dict()
+
+    def counts(self):
+        f, v, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.L.am_get_counts(self.h, C.byref(f), C.byref(v), C.byref(c)))
+        return f.value, v.value, c.value
+
+    def fetch(self):
+        """The mesh as device tensors (faces in discovery order)."""
+        t = self.torch
+        F, V, _ = self.counts()
+        dev = self.device
+        out = dict(offsets=t.empty(F + 1, dtype=t.int64, device=dev), ids=t.empty(V, dtype=t.int32, device=dev),
+                   verts=t.empty((V, 3), dtype=t.float64, device=dev), nbr=t.empty(V, dtype=t.int64, device=dev),
+                   codes=t.empty((F, self.W), dtype=t.int64, device=dev), argmax=t.empty(F, dtype=t.int32, device=dev))
+        self._check(self.L.am_fetch(self.h, _p(out["offsets"]), _p(out["ids"]), _p(out["verts"]), _p(out["nbr"]),
+                                    _p(out["codes"]), _p(out["argmax"])))
+        return out
+
+
+def mesh_to_host(out):
+    """Device mesh dict -> numpy arrays (codes as uint64)."""
+    h = {k: v.cpu().numpy() for k, v in out.items()}
+    h["codes"] = h["codes"].view(np.uint64)
+    return h

@@ -1,0 +1,647 @@
+// am_api.hip -- host side of the C ABI declared in include/am.h.
+//
+// Owns the device copy of the network, the seed buffers and the marching
+// state, and drives the step loop of parallel marching (Algorithm 1 with all
+// active cells solved at once): chain -> clip -> insert -> commit -> resolve
+// per batch of active cells, one small device-to-host read of the counters
+// per step to learn the next active range.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/am.h"
+#include "am_internal.h"
+
+namespace am {
+void launch_clip(const DevNet &, const uint64_t *, const int *, const uint64_t *, long long, long long, long long,
+                 const double *, const ClipOut &, const Candidates &, unsigned long long, Counters *, hipStream_t);
+void launch_chain(const DevNet &, const uint64_t *, long long, long long, double *, hipStream_t);
+void launch_rows_unpad(const DevNet &, long long, const double *, double *, hipStream_t);
+void launch_insert(const DevNet &, const Candidates &, const uint64_t *, const int *, const uint64_t *,
+                   const int *, unsigned long long *, unsigned long long, Counters *, unsigned long long,
+                   long long, hipStream_t);
+void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, uint64_t *, int *, int *,
+                   const uint64_t *, const int *, unsigned long long *, Counters *, unsigned long long,
+                   unsigned long long, long long, hipStream_t);
+void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t);
+void launch_codes(const DevNet &, const double *, long long, uint64_t *, int *, double *, hipStream_t);
+void launch_seed_rays(const DevNet &, const double *, const double *, long long, int, uint64_t *, int *, int *,
+                      hipStream_t);
+void launch_seed_cands(const DevNet &, const uint64_t *, const int *, const int *, long long,
+                       const Candidates &, Counters *, unsigned long long, hipStream_t);
+hipError_t scan_tmp_bytes(long long, size_t *);
+hipError_t launch_fetch(const DevNet &, long long, const int *, const int *, const double *, const int *,
+                        const uint64_t *, const int *, int, int *, int *, long long *, long long *, void *,
+                        size_t, long long, long long *, int *, double *, long long *, uint64_t *, int *,
+                        hipStream_t);
+}  // namespace am
+
+using namespace am;
+
+struct am_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // network
+    bool loaded = false;
+    DevNet dn{};
+    double *d_weights = nullptr;
+    double *d_bias = nullptr;
+    int *d_row_of_unit = nullptr;
+    uint64_t *d_zobrist = nullptr;
+
+    // seeds
+    uint64_t *d_seed_codes = nullptr;
+    int *d_seed_am = nullptr;
+    int *d_seed_status = nullptr;
+    long long n_seeds = 0;
+    long long seed_cap = 0;
+    bool seeds_have_status = false;
+
+    // marching state
+    long long cap_cells = 0;
+    uint64_t *d_codes = nullptr;
+    int *d_am = nullptr;
+    uint64_t *d_hash = nullptr;
+    int *d_entry = nullptr;
+    int *d_fm = nullptr;
+    int *d_fids = nullptr;
+    double *d_fverts = nullptr;
+    int *d_fnbr = nullptr;
+    int *d_fflags = nullptr;
+    unsigned long long hcap = 0;
+    unsigned long long *d_slots = nullptr;
+    unsigned long long cand_cap = 0;
+    Candidates cand{};
+    long long chunk_cells = 0;
+    double *d_rows = nullptr;
+    size_t rows_bytes = 0;
+    Counters *d_ctr = nullptr;
+    Counters *h_ctr = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // fetch scratch
+    int *d_has = nullptr;
+    int *d_fidx = nullptr;
+    long long *d_mcount = nullptr;
+    long long *d_voff = nullptr;
+    char *d_scan = nullptr;
+    size_t scan_bytes = 0;
+    long long scan_n = 0;
+
+    // last result
+    bool have_result = false;
+    long long res_cells = 0, res_faces = 0, res_fverts = 0;
+};
+
+namespace {
+
+am_status fail(am_ctx *c, am_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, AM_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+template <class T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+template <class T>
+am_status dalloc(am_ctx *ctx, T *&p, size_t count) {
+    dfree(p);
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)&p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, AM_E_OOM, "hipMalloc of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
+    }
+    return AM_OK;
+}
+
+#define TRY(expr)                    \
+    do {                             \
+        am_status s_ = (expr);       \
+        if (s_ != AM_OK) return s_;  \
+    } while (0)
+
+uint64_t splitmix64(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+void free_march(am_ctx *c) {
+    dfree(c->d_codes);
+    dfree(c->d_am);
+    dfree(c->d_hash);
+    dfree(c->d_entry);
+    dfree(c->d_fm);
+    dfree(c->d_fids);
+    dfree(c->d_fverts);
+    dfree(c->d_fnbr);
+    dfree(c->d_fflags);
+    dfree(c->d_slots);
+    dfree(c->cand.parent);
+    dfree(c->cand.slot);
+    dfree(c->cand.unit);
+    dfree(c->cand.hash);
+    dfree(c->cand.kind);
+    dfree(c->cand.ref);
+    dfree(c->cand.cell);
+    dfree(c->d_rows);
+    dfree(c->d_has);
+    dfree(c->d_fidx);
+    dfree(c->d_mcount);
+    dfree(c->d_voff);
+    dfree(c->d_scan);
+    c->cap_cells = 0;
+    c->hcap = 0;
+    c->cand_cap = 0;
+    c->rows_bytes = 0;
+    c->scan_n = 0;
+    c->have_result = false;
+}
+
+void free_net(am_ctx *c) {
+    dfree(c->d_weights);
+    dfree(c->d_bias);
+    dfree(c->d_row_of_unit);
+    dfree(c->d_zobrist);
+    dfree(c->d_seed_codes);
+    dfree(c->d_seed_am);
+    dfree(c->d_seed_status);
+    c->n_seeds = c->seed_cap = 0;
+    c->loaded = false;
+}
+
+am_status set_device(am_ctx *ctx) {
+    HIPCHK(hipSetDevice(ctx->device));
+    return AM_OK;
+}
+
+// Sizes every marching buffer for `cells` cells.
+am_status ensure_march(am_ctx *ctx, long long cells) {
+    if (cells <= ctx->cap_cells && ctx->d_codes) return AM_OK;
+    free_march(ctx);
+    const DevNet &n = ctx->dn;
+    TRY(dalloc(ctx, ctx->d_codes, (size_t)cells * n.W));
+    TRY(dalloc(ctx, ctx->d_am, cells));
+    TRY(dalloc(ctx, ctx->d_hash, cells));
+    TRY(dalloc(ctx, ctx->d_entry, cells));
+    TRY(dalloc(ctx, ctx->d_fm, cells));
+    TRY(dalloc(ctx, ctx->d_fids, (size_t)cells * kFaceSlots));
+    TRY(dalloc(ctx, ctx->d_fverts, (size_t)cells * kFaceSlots * 3));
+    TRY(dalloc(ctx, ctx->d_fnbr, (size_t)cells * kFaceSlots));
+    TRY(dalloc(ctx, ctx->d_fflags, cells));
+    unsigned long long h = 1;
+    while (h < 2ull * (unsigned long long)cells) h <<= 1;
+    ctx->hcap = h;
+    TRY(dalloc(ctx, ctx->d_slots, h));
+    // rows for one batch of active cells: at most ~1 GiB, at least 4096 cells
+    const size_t per_cell = sizeof(double) * 4 * (size_t)n.R;
+    long long chunk = (long long)((1ull << 30) / per_cell);
+    chunk = std::max<long long>(4096, std::min<long long>(chunk, 1 << 18));
+    chunk = (chunk + 3) & ~3LL;
+    ctx->chunk_cells = chunk;
+    TRY(dalloc(ctx, ctx->d_rows, (size_t)chunk * 4 * n.R));
+    ctx->rows_bytes = per_cell * chunk;
+    // candidates: the seeds, or up to 16 edges per active cell on average
+    ctx->cand_cap = (unsigned long long)std::max<long long>(16 * chunk, ctx->seed_cap + 64);
+    TRY(dalloc(ctx, ctx->cand.parent, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.slot, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.unit, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.hash, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.kind, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.ref, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.cell, ctx->cand_cap));
+    ctx->cap_cells = cells;
+    return AM_OK;
+}
+
+am_status ensure_scan(am_ctx *ctx, long long n) {
+    if (n <= ctx->scan_n && ctx->d_scan) return AM_OK;
+    TRY(dalloc(ctx, ctx->d_has, n));
+    TRY(dalloc(ctx, ctx->d_fidx, n));
+    TRY(dalloc(ctx, ctx->d_mcount, n));
+    TRY(dalloc(ctx, ctx->d_voff, n));
+    size_t b = 0;
+    HIPCHK(scan_tmp_bytes(n, &b));
+    TRY(dalloc(ctx, ctx->d_scan, b));
+    ctx->scan_bytes = b;
+    ctx->scan_n = n;
+    return AM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+am_status am_create(am_ctx **out, int device, void *hip_stream) {
+    if (!out) return AM_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return AM_E_HIP;
+    if (device < 0 || device >= count) return AM_E_INVALID;
+    am_ctx *ctx = new am_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void **)&ctx->h_ctr, sizeof(Counters)) != hipSuccess ||
+        hipMalloc((void **)&ctx->d_ctr, sizeof(Counters)) != hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        delete ctx;
+        return AM_E_HIP;
+    }
+    *out = ctx;
+    return AM_OK;
+}
+
+void am_destroy(am_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    free_march(ctx);
+    free_net(ctx);
+    dfree(ctx->d_ctr);
+    if (ctx->h_ctr) (void)hipHostFree(ctx->h_ctr);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+const char *am_last_error(const am_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
+    if (!ctx) return AM_E_INVALID;
+    if (!nd || !nd->width || nd->n_layers < 2 || nd->n_layers > kMaxLayers || nd->n_blocks < 1 ||
+        nd->n_blocks > kMaxBlocks || !nd->blk_dst || !nd->blk_src || !nd->blk_w || !nd->bias)
+        return fail(ctx, AM_E_INVALID, "bad network descriptor (layers 2..%d, blocks 1..%d)", kMaxLayers,
+                    kMaxBlocks);
+    TRY(set_device(ctx));
+    const int L2 = nd->n_layers;
+    if (nd->width[0] != 3) return fail(ctx, AM_E_INVALID, "width[0] must be 3");
+    for (int l = 1; l < L2; ++l)
+        if (nd->width[l] < 1) return fail(ctx, AM_E_INVALID, "width[%d] < 1", l);
+    long long N = 0;
+    for (int l = 1; l < L2 - 1; ++l) N += nd->width[l];
+    const int M = nd->width[L2 - 1];
+    if (N > kMaxHidden) return fail(ctx, AM_E_INVALID, "N = %lld hidden units exceeds %d", N, kMaxHidden);
+    if (M > kMaxHeads) return fail(ctx, AM_E_INVALID, "M = %d heads exceeds %d", M, kMaxHeads);
+    std::vector<int> has_input(L2, 0);
+    for (int b = 0; b < nd->n_blocks; ++b) {
+        const int d = nd->blk_dst[b], s = nd->blk_src[b];
+        if (!(0 <= s && s < d && d < L2)) return fail(ctx, AM_E_INVALID, "block %d: %d <- %d not feed-forward", b, d, s);
+        if (!nd->blk_w[b]) return fail(ctx, AM_E_INVALID, "block %d has no weights", b);
+        for (int b2 = 0; b2 < b; ++b2)
+            if (nd->blk_dst[b2] == d && nd->blk_src[b2] == s)
+                return fail(ctx, AM_E_INVALID, "duplicate block %d <- %d", d, s);
+        has_input[d] = 1;
+    }
+    for (int l = 1; l < L2; ++l) {
+        if (!has_input[l]) return fail(ctx, AM_E_INVALID, "layer %d has no input block", l);
+        if (!nd->bias[l]) return fail(ctx, AM_E_INVALID, "layer %d has no bias", l);
+    }
+
+    free_march(ctx);
+    free_net(ctx);
+    DevNet dn{};
+    dn.n_layers = L2;
+    dn.N = (int)N;
+    dn.M = M;
+    dn.W = std::max(1, (int)((N + 63) / 64));
+    int row = 0, unit = 0, boff = 0;
+    for (int l = 0; l < L2; ++l) {
+        dn.width[l] = nd->width[l];
+        if (l == 0) continue;
+        dn.row_off[l] = row;
+        dn.unit_off[l] = unit;
+        dn.bias_off[l] = boff;
+        row += (nd->width[l] + 3) & ~3;
+        unit += nd->width[l];
+        boff += nd->width[l];
+    }
+    dn.R = row;
+    // weights: each block padded to 16-row multiples and ld = 4-column multiples
+    std::vector<double> hw;
+    dn.n_blocks = nd->n_blocks;
+    for (int b = 0; b < nd->n_blocks; ++b) {
+        const int d = nd->blk_dst[b], s = nd->blk_src[b];
+        const int nd_ = nd->width[d], ns = nd->width[s];
+        const int ld = (ns + 3) & ~3, rows = (nd_ + 15) & ~15;
+        dn.blk_dst[b] = d;
+        dn.blk_src[b] = s;
+        dn.blk_ld[b] = ld;
+        dn.blk_off[b] = (long long)hw.size();
+        hw.resize(hw.size() + (size_t)rows * ld, 0.0);
+        double *dst = hw.data() + dn.blk_off[b];
+        const double *src = nd->blk_w[b];
+        for (int i = 0; i < nd_; ++i)
+            for (int k = 0; k < ns; ++k) {
+                const double w = src[(size_t)i * ns + k];
+                if (!std::isfinite(w)) return fail(ctx, AM_E_INVALID, "block %d has a non-finite weight", b);
+                dst[(size_t)i * ld + k] = w;
+            }
+    }
+    std::vector<double> hb(boff);
+    for (int l = 1; l < L2; ++l)
+        for (int k = 0; k < nd->width[l]; ++k) {
+            const double v = nd->bias[l][k];
+            if (!std::isfinite(v)) return fail(ctx, AM_E_INVALID, "bias of layer %d is not finite", l);
+            hb[dn.bias_off[l] + k] = v;
+        }
+    std::vector<int> rou(N + M);
+    for (int l = 1; l < L2; ++l)
+        for (int k = 0; k < nd->width[l]; ++k) rou[dn.unit_off[l] + k] = dn.row_off[l] + k;
+    std::vector<uint64_t> zob(N + M);
+    uint64_t sm = 0x5eed0fa11c0de5ull;
+    for (auto &z : zob) z = splitmix64(sm);
+
+    TRY(dalloc(ctx, ctx->d_weights, hw.size()));
+    TRY(dalloc(ctx, ctx->d_bias, hb.size()));
+    TRY(dalloc(ctx, ctx->d_row_of_unit, rou.size()));
+    TRY(dalloc(ctx, ctx->d_zobrist, zob.size()));
+    HIPCHK(hipMemcpy(ctx->d_weights, hw.data(), sizeof(double) * hw.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_bias, hb.data(), sizeof(double) * hb.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_row_of_unit, rou.data(), sizeof(int) * rou.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_zobrist, zob.data(), sizeof(uint64_t) * zob.size(), hipMemcpyHostToDevice));
+    dn.weights = ctx->d_weights;
+    dn.bias = ctx->d_bias;
+    dn.row_of_unit = ctx->d_row_of_unit;
+    dn.zobrist = ctx->d_zobrist;
+    ctx->dn = dn;
+    ctx->loaded = true;
+    return AM_OK;
+}
+
+am_status am_net_dims(const am_ctx *ctx, int32_t *n_hidden, int32_t *n_heads, int32_t *code_words) {
+    if (!ctx || !ctx->loaded) return AM_E_STATE;
+    if (n_hidden) *n_hidden = ctx->dn.N;
+    if (n_heads) *n_heads = ctx->dn.M;
+    if (code_words) *code_words = ctx->dn.W;
+    return AM_OK;
+}
+
+am_status am_codes(am_ctx *ctx, const double *pts, int64_t n, uint64_t *codes, int32_t *argmax, double *F) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n < 0 || (n > 0 && !pts)) return fail(ctx, AM_E_INVALID, "bad points");
+    TRY(set_device(ctx));
+    launch_codes(ctx->dn, pts, n, codes, argmax, F, ctx->stream);
+    HIPCHK(hipGetLastError());
+    return AM_OK;
+}
+
+am_status am_chain(am_ctx *ctx, const uint64_t *codes, int64_t n, double *rows) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n < 0 || (n > 0 && (!codes || !rows))) return fail(ctx, AM_E_INVALID, "bad arguments");
+    TRY(set_device(ctx));
+    TRY(ensure_march(ctx, std::max<long long>(ctx->cap_cells, 1024)));
+    for (long long lo = 0; lo < n; lo += ctx->chunk_cells) {
+        const long long hi = std::min<long long>(n, lo + ctx->chunk_cells);
+        launch_chain(ctx->dn, codes, lo, hi, ctx->d_rows, ctx->stream);
+        launch_rows_unpad(ctx->dn, hi - lo, ctx->d_rows, rows + lo * 4 * (ctx->dn.N + ctx->dn.M), ctx->stream);
+    }
+    HIPCHK(hipGetLastError());
+    return AM_OK;
+}
+
+am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n, int32_t max_m,
+                   int32_t *m, int32_t *ids, double *verts, int32_t *flags) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n < 0 || max_m < 3 || max_m > kMaxPoly || (n > 0 && (!codes || !m || !ids || !verts)))
+        return fail(ctx, AM_E_INVALID, "bad arguments (max_m must be 3..%d)", kMaxPoly);
+    TRY(set_device(ctx));
+    TRY(ensure_march(ctx, std::max<long long>(ctx->cap_cells, 1024)));
+    for (long long lo = 0; lo < n; lo += ctx->chunk_cells) {
+        const long long hi = std::min<long long>(n, lo + ctx->chunk_cells);
+        launch_chain(ctx->dn, codes, lo, hi, ctx->d_rows, ctx->stream);
+        ClipOut out{};
+        out.m = m;
+        out.ids = ids;
+        out.verts = verts;
+        out.nbr = nullptr;
+        out.flags = flags;
+        out.stride = max_m;
+        out.out_base = 0;
+        Candidates none{};
+        launch_clip(ctx->dn, codes, argmax, nullptr, lo, hi, 0, ctx->d_rows, out, none, 0, nullptr, ctx->stream);
+    }
+    HIPCHK(hipGetLastError());
+    return AM_OK;
+}
+
+static am_status ensure_seed_cap(am_ctx *ctx, long long n) {
+    if (n <= ctx->seed_cap && ctx->d_seed_codes) return AM_OK;
+    TRY(dalloc(ctx, ctx->d_seed_codes, (size_t)n * ctx->dn.W));
+    TRY(dalloc(ctx, ctx->d_seed_am, n));
+    TRY(dalloc(ctx, ctx->d_seed_status, n));
+    ctx->seed_cap = n;
+    return AM_OK;
+}
+
+am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, int64_t n_rays, int32_t max_iter,
+                       int32_t *status_out) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n_rays <= 0 || !orig || !dir) return fail(ctx, AM_E_INVALID, "need at least one ray");
+    TRY(set_device(ctx));
+    TRY(ensure_seed_cap(ctx, n_rays));
+    launch_seed_rays(ctx->dn, orig, dir, n_rays, max_iter > 0 ? max_iter : 200, ctx->d_seed_codes,
+                     ctx->d_seed_am, ctx->d_seed_status, ctx->stream);
+    if (status_out)
+        HIPCHK(hipMemcpyAsync(status_out, ctx->d_seed_status, sizeof(int) * n_rays, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+    HIPCHK(hipGetLastError());
+    ctx->n_seeds = n_rays;
+    ctx->seeds_have_status = true;
+    ctx->have_result = false;
+    return AM_OK;
+}
+
+am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n <= 0 || !codes) return fail(ctx, AM_E_INVALID, "need at least one seed cell");
+    TRY(set_device(ctx));
+    TRY(ensure_seed_cap(ctx, n));
+    HIPCHK(hipMemcpyAsync(ctx->d_seed_codes, codes, sizeof(uint64_t) * n * ctx->dn.W, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    if (argmax)
+        HIPCHK(hipMemcpyAsync(ctx->d_seed_am, argmax, sizeof(int) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    else
+        HIPCHK(hipMemsetAsync(ctx->d_seed_am, 0, sizeof(int) * n, ctx->stream));
+    ctx->n_seeds = n;
+    ctx->seeds_have_status = false;
+    ctx->have_result = false;
+    return AM_OK;
+}
+
+am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (ctx->n_seeds <= 0) return fail(ctx, AM_E_STATE, "no seeds");
+    TRY(set_device(ctx));
+    am_march_opts o{};
+    if (opts) o = *opts;
+    const long long cap = o.max_cells > 0 ? o.max_cells : (1LL << 20);
+    if (cap >= (1LL << 31)) return fail(ctx, AM_E_INVALID, "max_cells must be < 2^31");
+    if (cap < ctx->n_seeds) return fail(ctx, AM_E_INVALID, "max_cells smaller than the seed count");
+    TRY(ensure_march(ctx, cap));
+    if (ctx->cand_cap < (unsigned long long)ctx->n_seeds) {
+        ctx->cap_cells = 0;   // force a re-size with room for the seeds
+        TRY(ensure_march(ctx, cap));
+    }
+    am_march_stats st{};
+    hipStream_t s = ctx->stream;
+    const DevNet &net = ctx->dn;
+    ctx->have_result = false;
+
+    HIPCHK(hipEventRecord(ctx->ev0, s));
+    HIPCHK(hipMemsetAsync(ctx->d_ctr, 0, sizeof(Counters), s));
+    HIPCHK(hipMemsetAsync(ctx->d_slots, 0, sizeof(unsigned long long) * ctx->hcap, s));
+    const unsigned long long hmask = ctx->hcap - 1;
+
+    // seeds -> cells 0..S-1 (deduplicated)
+    launch_seed_cands(net, ctx->d_seed_codes, ctx->d_seed_am, ctx->seeds_have_status ? ctx->d_seed_status : nullptr,
+                      ctx->n_seeds, ctx->cand, ctx->d_ctr, ctx->cand_cap, s);
+    launch_insert(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots, hmask,
+                  ctx->d_ctr, ctx->cand_cap, ctx->n_seeds, s);
+    launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_entry, ctx->d_fm, ctx->d_seed_codes,
+                  ctx->d_seed_am, ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, ctx->n_seeds, s);
+    HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    st.seeds_in = (long long)ctx->h_ctr->n_cand;
+    long long lo = 0, hi = (long long)ctx->h_ctr->n_cells;
+    st.seed_cells = hi;
+    if (ctx->h_ctr->overflow_cells || ctx->h_ctr->overflow_cand || ctx->h_ctr->overflow_hash) {
+        st.required_cells = hi;
+        if (stats) *stats = st;
+        return fail(ctx, AM_E_CAPACITY, "seed insertion overflowed the capacities");
+    }
+    if (hi == 0) {
+        if (stats) *stats = st;
+        return fail(ctx, AM_E_SEED, "no ray produced a seed");
+    }
+
+    ClipOut out{};
+    out.m = ctx->d_fm;
+    out.ids = ctx->d_fids;
+    out.verts = ctx->d_fverts;
+    out.nbr = ctx->d_fnbr;
+    out.flags = ctx->d_fflags;
+    out.stride = kFaceSlots;
+    out.out_base = 0;
+    const long long seed_cells = hi;
+    while (lo < hi) {
+        if (o.max_steps > 0 && st.steps >= o.max_steps) break;
+        const long long n = std::min<long long>(hi - lo, ctx->chunk_cells);
+        st.max_frontier = std::max<long long>(st.max_frontier, hi - lo);
+        HIPCHK(hipMemsetAsync(&ctx->d_ctr->n_cand, 0, sizeof(unsigned long long), s));
+        launch_chain(net, ctx->d_codes, lo, lo + n, ctx->d_rows, s);
+        launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, lo, lo + n, seed_cells, ctx->d_rows, out, ctx->cand,
+                    ctx->cand_cap, ctx->d_ctr, s);
+        const long long nh = n * 6;
+        launch_insert(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots,
+                      hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
+        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_entry, ctx->d_fm,
+                      ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
+                      (unsigned long long)cap, nh, s);
+        launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
+        HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipGetLastError());
+        st.steps++;
+        const Counters &c = *ctx->h_ctr;
+        if (c.overflow_cells || c.overflow_cand || c.overflow_hash) {
+            st.required_cells = (long long)c.n_cells;
+            st.cells = std::min<long long>((long long)c.n_cells, cap);
+            if (stats) *stats = st;
+            return fail(ctx, AM_E_CAPACITY,
+                        "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu)",
+                        c.n_cells, cap, c.overflow_cand, c.overflow_hash);
+        }
+        lo += n;
+        hi = (long long)c.n_cells;
+    }
+    HIPCHK(hipEventRecord(ctx->ev1, s));
+    HIPCHK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    const Counters &c = *ctx->h_ctr;
+    st.cells = (long long)c.n_cells;
+    st.face_verts = (long long)c.face_verts;
+    st.domain_edges = (long long)c.domain_edges;
+    st.degenerate = (long long)c.degenerate;
+    st.march_ms = ms;
+
+    // faces and empty seeds: count through the fetch scan
+    TRY(ensure_scan(ctx, std::max<long long>(st.cells, 1)));
+    HIPCHK(launch_fetch(net, st.cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
+                        ctx->d_am, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff, ctx->d_scan,
+                        ctx->scan_bytes, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+    int last_idx = 0, last_has = 0;
+    HIPCHK(hipMemcpyAsync(&last_idx, ctx->d_fidx + st.cells - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&last_has, ctx->d_has + st.cells - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<int> seed_m(seed_cells);
+    HIPCHK(hipMemcpyAsync(seed_m.data(), ctx->d_fm, sizeof(int) * seed_cells, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    st.faces = (long long)last_idx + last_has;
+    st.triangles = st.face_verts - 2 * st.faces;
+    for (int v : seed_m) st.seed_empty += v == 0;
+    ctx->res_cells = st.cells;
+    ctx->res_faces = st.faces;
+    ctx->res_fverts = st.face_verts;
+    ctx->have_result = true;
+    if (stats) *stats = st;
+    if (st.seed_empty == seed_cells && st.faces == 0) return fail(ctx, AM_E_SEED, "every seed face is empty");
+    if (o.strict && st.degenerate > 0) return fail(ctx, AM_E_DEGENERATE, "%lld degenerate faces", st.degenerate);
+    return AM_OK;
+}
+
+am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, int64_t *cells) {
+    if (!ctx || !ctx->have_result) return AM_E_STATE;
+    if (faces) *faces = ctx->res_faces;
+    if (face_verts) *face_verts = ctx->res_fverts;
+    if (cells) *cells = ctx->res_cells;
+    return AM_OK;
+}
+
+am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr, uint64_t *codes,
+                   int32_t *argmax) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->have_result) return fail(ctx, AM_E_STATE, "no march result");
+    TRY(set_device(ctx));
+    TRY(ensure_scan(ctx, std::max<long long>(ctx->res_cells, 1)));
+    HIPCHK(launch_fetch(ctx->dn, ctx->res_cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
+                        ctx->d_am, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff, ctx->d_scan,
+                        ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts, (long long *)nbr, codes,
+                        argmax, ctx->stream));
+    return AM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,490 @@
+// am_frontier.hip -- seeding, the device hash set of discovered cells, and the
+// result compaction (gfx950).
+//
+// Marching (Algorithm 1 of the paper, parallel form of Sec. 4.2.2) keeps an
+// active set and checks every newly inferred state against the states seen so
+// far.  Here the active set is a contiguous range of cell ids, and a
+// lock-free open-addressing hash set over 64-bit slots deduplicates the
+// neighbour candidates of a whole step at once:
+//   insert : each candidate probes from its fingerprint; an empty slot is
+//            claimed with CAS as PENDING|tag|candidate; a slot with the same
+//            tag is compared on the full code (committed cell or pending
+//            candidate) and, if equal, the candidate is a duplicate;
+//   commit : every claiming candidate gets the next cell id, writes its code
+//            and turns its slot into tag|cell;
+//   resolve: every candidate writes the neighbour cell id into its parent's
+//            face.
+// Fingerprints are Zobrist hashes (XOR of one random key per set bit and one
+// per argmax head), so a flip updates them in O(1).
+#include <hipcub/hipcub.hpp>
+
+#include "am_internal.h"
+
+namespace am {
+
+constexpr uint64_t kPending = 1ull << 63;
+
+__device__ __forceinline__ uint32_t slot_tag(uint64_t h) {
+    return (uint32_t)((h >> 32) & 0x7fffffffu) | 0x40000000u;   // never zero
+}
+
+// Where the code of candidate t comes from: a parent cell with one flip, or
+// a seed code.
+struct CodeRef {
+    const uint64_t *base;
+    int flip;     // unit to flip, -1 = none
+    int am;
+};
+
+__device__ __forceinline__ CodeRef cand_code(const DevNet &net, const Candidates &cand, long long t,
+                                             const uint64_t *codes, const int *argmax,
+                                             const uint64_t *seed_codes, const int *seed_am) {
+    CodeRef r;
+    const int p = cand.parent[t];
+    if (p >= 0) {
+        const int u = cand.unit[t];
+        r.base = codes + (long long)p * net.W;
+        if (u < net.N) {
+            r.flip = u;
+            r.am = argmax[p];
+        } else {
+            r.flip = -1;
+            r.am = u - net.N;
+        }
+    } else {
+        const long long s = -1LL - p;
+        r.base = seed_codes + s * net.W;
+        r.flip = -1;
+        r.am = seed_am[s];
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint64_t code_word(const CodeRef &r, int w) {
+    uint64_t x = r.base[w];
+    if (r.flip >= 0 && (r.flip >> 6) == w) x ^= 1ull << (r.flip & 63);
+    return x;
+}
+
+__device__ __forceinline__ bool code_eq(int W, const CodeRef &a, const CodeRef &b) {
+    if (a.am != b.am) return false;
+    for (int w = 0; w < W; ++w)
+        if (code_word(a, w) != code_word(b, w)) return false;
+    return true;
+}
+
+// ------------------------------------------------------------------ insert
+
+__global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, const uint64_t *codes,
+                                                const int *argmax, const uint64_t *seed_codes,
+                                                const int *seed_am, unsigned long long *slots,
+                                                unsigned long long hmask, Counters *ctr,
+                                                unsigned long long cand_cap) {
+    const unsigned long long n = min(ctr->n_cand, cand_cap);
+    for (unsigned long long t = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; t < n;
+         t += (unsigned long long)gridDim.x * blockDim.x) {
+        const uint64_t h = cand.hash[t];
+        const unsigned long long tag = slot_tag(h);
+        const CodeRef me = cand_code(net, cand, (long long)t, codes, argmax, seed_codes, seed_am);
+        unsigned long long pos = h & hmask;
+        int kind = kLost;
+        long long ref = -1;
+        for (unsigned long long probe = 0; probe <= hmask; ++probe) {
+            unsigned long long s = __hip_atomic_load(&slots[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (s == 0) {
+                const unsigned long long mine = kPending | (tag << 32) | (unsigned long long)t;
+                s = atomicCAS(&slots[pos], 0ull, mine);
+                if (s == 0) {
+                    kind = kOwner;
+                    ref = (long long)pos;
+                    break;
+                }
+            }
+            if (((s >> 32) & 0x7fffffffull) == tag) {
+                const long long other = (long long)(s & 0xffffffffull);
+                CodeRef o;
+                if (s & kPending) {
+                    o = cand_code(net, cand, other, codes, argmax, seed_codes, seed_am);
+                } else {
+                    o.base = codes + other * net.W;
+                    o.flip = -1;
+                    o.am = argmax[other];
+                }
+                if (code_eq(net.W, me, o)) {
+                    kind = (s & kPending) ? kDup : kFound;
+                    ref = other;
+                    break;
+                }
+            }
+            pos = (pos + 1) & hmask;
+        }
+        if (kind == kLost) atomicAdd(&ctr->overflow_hash, 1ull);
+        cand.kind[t] = kind;
+        cand.ref[t] = ref;
+    }
+}
+
+// ------------------------------------------------------------------ commit
+
+__global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uint64_t *codes, int *argmax,
+                                                uint64_t *cell_hash, int *entry_unit, int *face_m,
+                                                const uint64_t *seed_codes, const int *seed_am,
+                                                unsigned long long *slots, Counters *ctr,
+                                                unsigned long long cand_cap, unsigned long long cap_cells) {
+    const unsigned long long n = min(ctr->n_cand, cand_cap);
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    // every lane of the wave runs the same number of iterations (wave_reserve)
+    const unsigned long long n_round = (n + 63) & ~63ull;
+    for (unsigned long long t = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; t < n_round;
+         t += stride) {
+        const bool own = t < n && cand.kind[t] == kOwner;
+        unsigned long long base;
+        const unsigned long long id = wave_reserve(&ctr->n_cells, own, &base);
+        if (!own) continue;
+        if (id >= cap_cells) {
+            atomicAdd(&ctr->overflow_cells, 1ull);
+            cand.cell[t] = -1;
+            continue;
+        }
+        const CodeRef me = cand_code(net, cand, (long long)t, codes, argmax, seed_codes, seed_am);
+        uint64_t *dst = codes + (long long)id * net.W;
+        for (int w = 0; w < net.W; ++w) dst[w] = code_word(me, w);
+        argmax[id] = me.am;
+        const uint64_t h = cand.hash[t];
+        cell_hash[id] = h;
+        const int p = cand.parent[t];
+        int entry = -1;
+        if (p >= 0) {
+            const int u = cand.unit[t];
+            entry = u < net.N ? u : net.N + argmax[p];
+        }
+        entry_unit[id] = entry;
+        face_m[id] = 0;
+        slots[cand.ref[t]] = ((unsigned long long)slot_tag(h) << 32) | id;
+        cand.cell[t] = (int)id;
+    }
+}
+
+// ----------------------------------------------------------------- resolve
+
+__global__ __launch_bounds__(256) void k_resolve(Candidates cand, int *face_nbr, int stride, Counters *ctr,
+                                                 unsigned long long cand_cap) {
+    const unsigned long long n = min(ctr->n_cand, cand_cap);
+    for (unsigned long long t = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; t < n;
+         t += (unsigned long long)gridDim.x * blockDim.x) {
+        const int p = cand.parent[t];
+        if (p < 0) continue;
+        const int kind = cand.kind[t];
+        int c = -1;
+        if (kind == kOwner) c = cand.cell[t];
+        else if (kind == kFound) c = (int)cand.ref[t];
+        else if (kind == kDup) c = cand.cell[cand.ref[t]];
+        face_nbr[(long long)p * stride + cand.slot[t]] = c;
+    }
+}
+
+// ------------------------------------------------------------------- seeds
+
+// Forward pass of one point by a workgroup (Sec. 2.2).  act: LDS of
+// 3 + N + M doubles; code: LDS of W words.  Returns F = max over heads and
+// the argmax (lowest index on ties) to every thread.
+__device__ double wg_forward(const DevNet &net, const double x[3], double *act, uint64_t *code, int *am_out) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid < 3) act[tid] = x[tid];
+    for (int w = tid; w < net.W; w += nt) code[w] = 0;
+    __syncthreads();
+    const int L2 = net.n_layers;
+    for (int l = 1; l < L2; ++l) {
+        const int nl = net.width[l];
+        const int aoff = 3 + net.unit_off[l];
+        for (int k = tid; k < nl; k += nt) {
+            double acc = net.bias[net.bias_off[l] + k];
+            for (int b = 0; b < net.n_blocks; ++b) {
+                if (net.blk_dst[b] != l) continue;
+                const int j = net.blk_src[b];
+                const double *Wr = net.weights + net.blk_off[b] + (long long)k * net.blk_ld[b];
+                const double *aj = act + (j == 0 ? 0 : 3 + net.unit_off[j]);
+                const int nj = net.width[j];
+                for (int q = 0; q < nj; ++q) acc += Wr[q] * aj[q];
+            }
+            if (l < L2 - 1) {
+                act[aoff + k] = acc > 0.0 ? acc : 0.0;
+                if (acc > 0.0) {
+                    const int g = net.unit_off[l] + k;
+                    atomicOr((unsigned long long *)&code[g >> 6], 1ull << (g & 63));
+                }
+            } else {
+                act[aoff + k] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    const double *heads = act + 3 + net.N;
+    int best = 0;
+    for (int i = 1; i < net.M; ++i)
+        if (heads[i] > heads[best]) best = i;
+    const double F = heads[best];
+    *am_out = best;
+    __syncthreads();
+    return F;
+}
+
+__global__ __launch_bounds__(256) void k_codes(DevNet net, const double *pts, long long n, uint64_t *codes,
+                                               int *argmax, double *Fout) {
+    extern __shared__ double lds[];
+    double *act = lds;
+    uint64_t *code = (uint64_t *)(lds + 3 + net.N + net.M);
+    for (long long p = blockIdx.x; p < n; p += gridDim.x) {
+        double x[3] = {pts[p * 3], pts[p * 3 + 1], pts[p * 3 + 2]};
+        int am;
+        const double F = wg_forward(net, x, act, code, &am);
+        if (codes)
+            for (int w = threadIdx.x; w < net.W; w += blockDim.x) codes[p * net.W + w] = code[w];
+        if (threadIdx.x == 0) {
+            if (argmax) argmax[p] = am;
+            if (Fout) Fout[p] = F;
+        }
+        __syncthreads();
+    }
+}
+
+// Dichotomy along o + t d, t in [0, 1]: keep a bracket with a sign change,
+// halve it until both ends share one code, then take the linear root.
+__global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *orig, const double *dir,
+                                                   long long n_rays, int max_iter, uint64_t *seed_codes,
+                                                   int *seed_am, int *status) {
+    extern __shared__ double lds[];
+    double *act = lds;
+    uint64_t *c_lo = (uint64_t *)(lds + 3 + net.N + net.M);
+    uint64_t *c_hi = c_lo + net.W;
+    uint64_t *c_m = c_hi + net.W;
+    __shared__ int s_eq;
+    for (long long r = blockIdx.x; r < n_rays; r += gridDim.x) {
+        const double o[3] = {orig[r * 3], orig[r * 3 + 1], orig[r * 3 + 2]};
+        const double d[3] = {dir[r * 3], dir[r * 3 + 1], dir[r * 3 + 2]};
+        int a_lo, a_hi, a_m;
+        double x[3];
+        double f_lo = wg_forward(net, o, act, c_m, &a_lo);
+        for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_lo[w] = c_m[w];
+        for (int i = 0; i < 3; ++i) x[i] = o[i] + d[i];
+        double f_hi = wg_forward(net, x, act, c_m, &a_hi);
+        for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_hi[w] = c_m[w];
+        __syncthreads();
+        int st = 0;
+        double t_lo = 0.0, t_hi = 1.0;
+        if ((f_lo > 0.0) == (f_hi > 0.0)) {
+            st = 1;
+        } else {
+            for (int it = 0;; ++it) {
+                if (threadIdx.x == 0) s_eq = (a_lo == a_hi);
+                __syncthreads();
+                for (int w = threadIdx.x; w < net.W; w += blockDim.x)
+                    if (c_lo[w] != c_hi[w]) s_eq = 0;
+                __syncthreads();
+                const int eq = s_eq;
+                __syncthreads();
+                if (eq) break;
+                if (it >= max_iter) {
+                    st = 2;
+                    break;
+                }
+                const double tm = 0.5 * (t_lo + t_hi);
+                for (int i = 0; i < 3; ++i) x[i] = o[i] + tm * d[i];
+                const double fm = wg_forward(net, x, act, c_m, &a_m);
+                if ((fm > 0.0) == (f_lo > 0.0)) {
+                    t_lo = tm;
+                    f_lo = fm;
+                    a_lo = a_m;
+                    for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_lo[w] = c_m[w];
+                } else {
+                    t_hi = tm;
+                    f_hi = fm;
+                    a_hi = a_m;
+                    for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_hi[w] = c_m[w];
+                }
+                __syncthreads();
+            }
+        }
+        if (st == 0) {
+            const double ts = t_lo - f_lo * (t_hi - t_lo) / (f_hi - f_lo);
+            for (int i = 0; i < 3; ++i) x[i] = o[i] + ts * d[i];
+            wg_forward(net, x, act, c_m, &a_m);
+            for (int w = threadIdx.x; w < net.W; w += blockDim.x) seed_codes[r * net.W + w] = c_m[w];
+            if (threadIdx.x == 0) seed_am[r] = a_m;
+        } else {
+            for (int w = threadIdx.x; w < net.W; w += blockDim.x) seed_codes[r * net.W + w] = 0;
+            if (threadIdx.x == 0) seed_am[r] = 0;
+        }
+        if (threadIdx.x == 0 && status) status[r] = st;
+        __syncthreads();
+    }
+}
+
+// Seeds with status 0 become candidates (parent = -(1 + seed index)).
+__global__ __launch_bounds__(256) void k_seed_cands(DevNet net, const uint64_t *seed_codes, const int *seed_am,
+                                                    const int *seed_ok, long long n, Candidates cand,
+                                                    Counters *ctr, unsigned long long cand_cap) {
+    const long long n_round = (n + 63) & ~63LL;
+    for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < n_round;
+         s += (long long)gridDim.x * blockDim.x) {
+        const bool ok = s < n && (!seed_ok || seed_ok[s] == 0) && seed_am[s] >= 0 && seed_am[s] < net.M;
+        unsigned long long base;
+        const unsigned long long idx = wave_reserve(&ctr->n_cand, ok, &base);
+        if (!ok) continue;
+        if (idx >= cand_cap) {
+            atomicAdd(&ctr->overflow_cand, 1ull);
+            continue;
+        }
+        uint64_t h = net.zobrist[net.N + seed_am[s]];
+        for (int w = 0; w < net.W; ++w) {
+            uint64_t x = seed_codes[s * net.W + w];
+            while (x) {
+                const int b = __builtin_ctzll(x);
+                x &= x - 1;
+                const int g = w * 64 + b;
+                if (g < net.N) h ^= net.zobrist[g];
+            }
+        }
+        cand.parent[idx] = (int)(-1 - s);
+        cand.slot[idx] = -1;
+        cand.unit[idx] = -1;
+        cand.hash[idx] = h;
+    }
+}
+
+// ------------------------------------------------------------------- fetch
+
+__global__ void k_face_flags(const int *face_m, long long n, int *has, long long *mcount) {
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int m = face_m[c];
+        has[c] = m > 0 ? 1 : 0;
+        mcount[c] = m;
+    }
+}
+
+__global__ void k_fetch(const DevNet net, long long n, const int *face_m, const int *fidx, const long long *voff,
+                        const int *ids, const double *verts, const int *nbr, const uint64_t *codes,
+                        const int *argmax, int stride, long long *o_off, int *o_ids, double *o_verts,
+                        long long *o_nbr, uint64_t *o_codes, int *o_am) {
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int m = face_m[c];
+        if (m <= 0) continue;
+        const long long f = fidx[c];
+        const long long o = voff[c];
+        if (o_off) o_off[f] = o;
+        if (o_codes)
+            for (int w = 0; w < net.W; ++w) o_codes[f * net.W + w] = codes[c * net.W + w];
+        if (o_am) o_am[f] = argmax[c];
+        for (int i = 0; i < m; ++i) {
+            const long long s = c * stride + i;
+            if (o_ids) o_ids[o + i] = ids[s];
+            if (o_verts) {
+                o_verts[(o + i) * 3 + 0] = verts[s * 3 + 0];
+                o_verts[(o + i) * 3 + 1] = verts[s * 3 + 1];
+                o_verts[(o + i) * 3 + 2] = verts[s * 3 + 2];
+            }
+            if (o_nbr) {
+                const int g = nbr[s];
+                o_nbr[o + i] = g < 0 ? -1 : (face_m[g] > 0 ? (long long)fidx[g] : -2);
+            }
+        }
+    }
+}
+
+__global__ void k_fetch_tail(long long *o_off, long long F, const long long *voff, const int *face_m,
+                             long long n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && o_off) o_off[F] = n > 0 ? voff[n - 1] + face_m[n - 1] : 0;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static unsigned grid_for(long long n, int block = 256, long long cap = 2048) {
+    long long b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+void launch_insert(const DevNet &net, const Candidates &cand, const uint64_t *codes, const int *argmax,
+                   const uint64_t *seed_codes, const int *seed_am, unsigned long long *slots,
+                   unsigned long long hmask, Counters *ctr, unsigned long long cand_cap, long long n_hint,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_insert, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, codes, argmax,
+                       seed_codes, seed_am, slots, hmask, ctr, cand_cap);
+}
+
+void launch_commit(const DevNet &net, const Candidates &cand, uint64_t *codes, int *argmax, uint64_t *cell_hash,
+                   int *entry_unit, int *face_m, const uint64_t *seed_codes, const int *seed_am,
+                   unsigned long long *slots, Counters *ctr, unsigned long long cand_cap,
+                   unsigned long long cap_cells, long long n_hint, hipStream_t st) {
+    hipLaunchKernelGGL(k_commit, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, codes, argmax, cell_hash,
+                       entry_unit, face_m, seed_codes, seed_am, slots, ctr, cand_cap, cap_cells);
+}
+
+void launch_resolve(const Candidates &cand, int *face_nbr, int stride, Counters *ctr, unsigned long long cand_cap,
+                    long long n_hint, hipStream_t st) {
+    hipLaunchKernelGGL(k_resolve, dim3(grid_for(n_hint)), dim3(256), 0, st, cand, face_nbr, stride, ctr,
+                       cand_cap);
+}
+
+size_t forward_lds_bytes(const DevNet &net, int code_bufs) {
+    return sizeof(double) * (3 + net.N + net.M) + sizeof(uint64_t) * net.W * code_bufs;
+}
+
+void launch_codes(const DevNet &net, const double *pts, long long n, uint64_t *codes, int *argmax, double *F,
+                  hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_codes, dim3(grid_for(n, 1, 8192)), dim3(256), forward_lds_bytes(net, 1), st, net, pts,
+                       n, codes, argmax, F);
+}
+
+void launch_seed_rays(const DevNet &net, const double *orig, const double *dir, long long n, int max_iter,
+                      uint64_t *seed_codes, int *seed_am, int *status, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_seed_rays, dim3(grid_for(n, 1, 8192)), dim3(256), forward_lds_bytes(net, 3), st, net,
+                       orig, dir, n, max_iter, seed_codes, seed_am, status);
+}
+
+void launch_seed_cands(const DevNet &net, const uint64_t *seed_codes, const int *seed_am, const int *seed_ok,
+                       long long n, const Candidates &cand, Counters *ctr, unsigned long long cand_cap,
+                       hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_seed_cands, dim3(grid_for(n)), dim3(256), 0, st, net, seed_codes, seed_am, seed_ok, n,
+                       cand, ctr, cand_cap);
+}
+
+// Compacts faces of cells 0..n-1 into CSR form.  tmp must hold scan_tmp_bytes(n).
+hipError_t scan_tmp_bytes(long long n, size_t *bytes) {
+    size_t a = 0, b = 0;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, a, (int *)nullptr, (int *)nullptr, (int)n);
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (long long *)nullptr, (long long *)nullptr, (int)n);
+    *bytes = a > b ? a : b;
+    return e;
+}
+
+hipError_t launch_fetch(const DevNet &net, long long n, const int *face_m, const int *ids, const double *verts,
+                        const int *nbr, const uint64_t *codes, const int *argmax, int stride, int *has, int *fidx,
+                        long long *mcount, long long *voff, void *tmp, size_t tmp_bytes, long long F,
+                        long long *o_off, int *o_ids, double *o_verts, long long *o_nbr, uint64_t *o_codes,
+                        int *o_am, hipStream_t st) {
+    if (n <= 0) {
+        if (o_off) return hipMemsetAsync(o_off, 0, sizeof(long long), st);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_face_flags, dim3(grid_for(n)), dim3(256), 0, st, face_m, n, has, mcount);
+    size_t tb = tmp_bytes;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, has, fidx, (int)n, st);
+    if (e != hipSuccess) return e;
+    tb = tmp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, mcount, voff, (int)n, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fetch, dim3(grid_for(n)), dim3(256), 0, st, net, n, face_m, fidx, voff, ids, verts, nbr,
+                       codes, argmax, stride, o_off, o_ids, o_verts, o_nbr, o_codes, o_am);
+    hipLaunchKernelGGL(k_fetch_tail, dim3(1), dim3(64), 0, st, o_off, F, voff, face_m, n);
+    return hipGetLastError();
+}
+
+}  // namespace am

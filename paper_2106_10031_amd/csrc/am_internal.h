@@ -1,0 +1,143 @@
+// am_internal.h -- device data layout and wave-level helpers shared by the
+// analytic-marching kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace am {
+
+constexpr int kMaxLayers = 40;
+constexpr int kMaxBlocks = 64;
+constexpr int kMaxHidden = 4096;
+constexpr int kMaxHeads = 64;
+constexpr int kWave = 64;
+constexpr int kMaxPoly = 64;      // polygon vertices held by one wave (one per lane)
+constexpr int kFaceSlots = 64;    // stored vertices per cell in the face buffers
+
+// On-line tolerance of the halfplane clip: 2^-40 relative (see am.h).
+constexpr double kTau = 9.094947017729282379150390625e-13;
+// Half-size of the starting square in the plane frame: the box section lies
+// within distance sqrt(3) of the plane's foot point.
+constexpr double kSquareHalf = 2.0;
+
+// Network as laid out in device memory.  Rows of the affine chain are kept
+// per cell in a padded layout: layer l (1..L+1) occupies rows
+// row_off[l] .. row_off[l] + width[l] - 1, with row_off a multiple of 4 so
+// that no 128-byte line straddles two layers.
+struct DevNet {
+    int n_layers;              // L + 2
+    int N, M, W;               // hidden units, heads, code words
+    int R;                     // padded rows per cell
+    int width[kMaxLayers];
+    int row_off[kMaxLayers];   // padded row offset (layers >= 1)
+    int unit_off[kMaxLayers];  // global unit offset (layer l >= 1; heads at N)
+    int bias_off[kMaxLayers];  // offset of layer l's bias in `bias`
+    int n_blocks;
+    int blk_dst[kMaxBlocks], blk_src[kMaxBlocks];
+    int blk_ld[kMaxBlocks];    // leading dimension (= src width rounded up to 4)
+    long long blk_off[kMaxBlocks];   // offset of the block in `weights` (rows padded to 16)
+    const double *weights;     // blocks, row-major, zero padded to (16*ceil(n_dst/16)) x ld
+    const double *bias;
+    const int *row_of_unit;    // [N + M] padded row of global unit g
+    const uint64_t *zobrist;   // [N + M] keys of the cell fingerprint
+};
+
+// Candidate neighbour cells produced by one marching step.
+struct Candidates {
+    int *parent;       // cell the candidate was found from; < 0: seed -(1+index)
+    int *slot;         // edge index in the parent's face
+    int *unit;         // constraint id crossed (hidden unit or N + head)
+    uint64_t *hash;    // fingerprint of the candidate's cell
+    int *kind;         // insert outcome
+    long long *ref;    // slot position (owner), cell id (found) or candidate (dup)
+    int *cell;         // resolved cell id
+};
+
+enum : int { kOwner = 0, kFound = 1, kDup = 2, kLost = 3 };
+
+// Where the clip kernel writes faces.
+struct ClipOut {
+    int *m;               // [cells] vertex count, 0 = empty face
+    int *ids;             // [cells][stride]
+    double *verts;        // [cells][stride][3]
+    int *nbr;             // [cells][stride] neighbour cell (-1 box edge) or NULL
+    int *flags;           // [cells] or NULL
+    int stride;           // vertices stored per cell (<= kMaxPoly)
+    long long out_base;   // output index = cell - out_base
+};
+
+// Device-side counters of a march (one struct in device memory).
+struct Counters {
+    unsigned long long n_cells;
+    unsigned long long n_cand;
+    unsigned long long overflow_cells;
+    unsigned long long overflow_cand;
+    unsigned long long overflow_hash;
+    unsigned long long degenerate;
+    unsigned long long domain_edges;
+    unsigned long long face_verts;
+    unsigned long long too_big;
+    unsigned long long pad[7];
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Broadcast a value from lane `src` (uniform) to the whole wave.
+__device__ __forceinline__ double bcast(double x, int src) {
+    const uint64_t u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, src);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+    return __longlong_as_double(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int bcast(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
+
+// Value of `x` in lane `src` (per-lane source).
+__device__ __forceinline__ double shfl(double x, int src) { return __shfl(x, src, kWave); }
+__device__ __forceinline__ int shfl(int x, int src) { return __shfl(x, src, kWave); }
+
+__device__ __forceinline__ double wave_sum(double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ int wave_min(int x) {
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int code_bit(const uint64_t *code, int g) {
+    return (int)((code[g >> 6] >> (g & 63)) & 1ull);
+}
+
+// Wave-aggregated atomic add: every active lane with `want` gets a slot.
+__device__ __forceinline__ unsigned long long wave_reserve(unsigned long long *ctr, bool want,
+                                                           unsigned long long *base_out) {
+    const uint64_t m = ballot(want);
+    unsigned long long base = 0;
+    const int leader = m ? __builtin_ctzll(m) : 0;
+    if (m && lane_id() == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
+    base = (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader) |
+           ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader)
+            << 32);
+    *base_out = base;
+    return base + (unsigned long long)__popcll(m & lanemask_lt());
+}
+
+}  // namespace am
