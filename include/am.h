@@ -77,7 +77,8 @@ typedef struct {
     int64_t max_cells;    /* capacity of discovered cells (0: 1<<20) */
     int32_t max_steps;    /* bound on marching steps (0: unbounded) */
     int32_t strict;       /* 1: return AM_E_DEGENERATE on a degenerate face */
-    int32_t reserved[8];
+    int32_t time_kernels; /* 1: time each kernel class with HIP events on the stream */
+    int32_t reserved[7];
 } am_march_opts;
 
 typedef struct {
@@ -94,7 +95,14 @@ typedef struct {
     int64_t domain_edges;     /* edges on the box */
     int64_t required_cells;   /* on AM_E_CAPACITY: the cell capacity needed so far */
     double march_ms;          /* device time of the march (HIP events) */
-    double reserved[7];
+    /* with opts.time_kernels: summed HIP-event durations and launch counts */
+    double chain_ms;          /* affine chain (FP64 MFMA) */
+    double clip_ms;           /* halfplane clip + vertex solve + candidates */
+    double hash_ms;           /* insert + commit + resolve */
+    int64_t chain_launches;
+    int64_t clip_launches;
+    int64_t hash_launches;
+    double reserved[2];
 } am_march_stats;
 
 /* Creates a context on `device` that enqueues its work on `hip_stream`

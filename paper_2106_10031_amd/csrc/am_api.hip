@@ -86,6 +86,7 @@ struct am_ctx {
     Counters *d_ctr = nullptr;
     Counters *h_ctr = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evk[4] = {nullptr, nullptr, nullptr, nullptr};   // per-step kernel timing
 
     // fetch scratch
     int *d_has = nullptr;
@@ -269,7 +270,9 @@ am_status am_create(am_ctx **out, int device, void *hip_stream) {
     ctx->stream = (hipStream_t)hip_stream;
     if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void **)&ctx->h_ctr, sizeof(Counters)) != hipSuccess ||
         hipMalloc((void **)&ctx->d_ctr, sizeof(Counters)) != hipSuccess ||
-        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        hipEventCreate(&ctx->evk[0]) != hipSuccess || hipEventCreate(&ctx->evk[1]) != hipSuccess ||
+        hipEventCreate(&ctx->evk[2]) != hipSuccess || hipEventCreate(&ctx->evk[3]) != hipSuccess) {
         delete ctx;
         return AM_E_HIP;
     }
@@ -288,6 +291,8 @@ void am_destroy(am_ctx *ctx) {
     if (ctx->h_ctr) (void)hipHostFree(ctx->h_ctr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (auto &e : ctx->evk)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -562,9 +567,13 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         const long long n = std::min<long long>(hi - lo, ctx->chunk_cells);
         st.max_frontier = std::max<long long>(st.max_frontier, hi - lo);
         HIPCHK(hipMemsetAsync(&ctx->d_ctr->n_cand, 0, sizeof(unsigned long long), s));
+        const bool tk = o.time_kernels != 0;
+        if (tk) HIPCHK(hipEventRecord(ctx->evk[0], s));
         launch_chain(net, ctx->d_codes, lo, lo + n, ctx->d_rows, s);
+        if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
         launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, lo, lo + n, seed_cells, ctx->d_rows, out, ctx->cand,
                     ctx->cand_cap, ctx->d_ctr, s);
+        if (tk) HIPCHK(hipEventRecord(ctx->evk[2], s));
         const long long nh = n * 6;
         launch_insert(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots,
                       hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
@@ -572,9 +581,22 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
                       ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
                       (unsigned long long)cap, nh, s);
         launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
+        if (tk) HIPCHK(hipEventRecord(ctx->evk[3], s));
         HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         HIPCHK(hipGetLastError());
+        if (tk) {
+            float a = 0.f, b = 0.f, c3 = 0.f;
+            HIPCHK(hipEventElapsedTime(&a, ctx->evk[0], ctx->evk[1]));
+            HIPCHK(hipEventElapsedTime(&b, ctx->evk[1], ctx->evk[2]));
+            HIPCHK(hipEventElapsedTime(&c3, ctx->evk[2], ctx->evk[3]));
+            st.chain_ms += a;
+            st.clip_ms += b;
+            st.hash_ms += c3;
+            st.chain_launches++;
+            st.clip_launches++;
+            st.hash_launches += 3;
+        }
         st.steps++;
         const Counters &c = *ctx->h_ctr;
         if (c.overflow_cells || c.overflow_cand || c.overflow_hash) {

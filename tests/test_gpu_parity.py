@@ -216,3 +216,53 @@ def test_empty_seed_cell_is_reported(binding):
     ctx.seed_cells(codes, torch.tensor([0], dtype=torch.int32).cuda())
     st = ctx.march()
     assert st["faces"] == 32
+
+
+# ------------------------------------------- full-size workload (bench's)
+
+@pytest.fixture(scope="module")
+def c2_case():
+    from am_workloads import nets as N
+    net = N.load_fitted("c2")
+    prim = np.load(__import__("os").path.join(N.DATA_DIR, "c2_primitives.npz"))
+    o, d = seeds.centre_rays(prim["p0"], 128)
+    return net, o, d
+
+
+def test_c2_full_march_sampled_faces_and_closedness(binding, c2_case):
+    """The bench workload at full size: sampled faces one by one + invariants."""
+    net, o, d = c2_case
+    say("c2 full march (sampled)")
+    ctx = _ctx(binding, net)
+    ctx.seed_rays(o, d)
+    st = ctx.march(max_cells=1 << 21)
+    got = fetch_host(ctx)
+    assert st["faces"] == got.n_faces and st["degenerate"] == 0
+    on = O.OracleNet(net)
+    rng = np.random.default_rng(7)
+    for f in rng.choice(got.n_faces, 2000, replace=False):
+        ids, vs, nb = got.face(f)
+        rid, rv, _, fl = on.face(got.codes[f], got.argmax[f])
+        assert fl == 0 and np.array_equal(ids, rid)
+        assert np.max(np.abs(vs - rv)) <= 1e-9 * max(1.0, np.abs(rv).max())
+    bad, dom = MC.edge_pairing(got, n_hidden=net.n_hidden)
+    assert bad == 0
+    # every seed the oracle finds is a marched cell
+    codes, ams, _, _ = on.seed_rays(o, d)
+    have = {MC.code_key(got.codes[f], got.argmax[f]) for f in range(got.n_faces)}
+    assert all(MC.code_key(c, a) in have for c, a in zip(codes, ams))
+
+
+def test_c2_full_march_equals_oracle(binding, c2_case):
+    """The whole cell set, cycles and adjacency against the oracle's full march."""
+    net, o, d = c2_case
+    on = O.OracleNet(net)
+    codes, ams, _, _ = on.seed_rays(o, d)
+    ref = on.march(codes, ams)
+    say("c2 full march vs oracle", ref.n_faces)
+    ctx = _ctx(binding, net)
+    ctx.seed_rays(o, d)
+    st = ctx.march(max_cells=1 << 21)
+    got = fetch_host(ctx)
+    assert st["faces"] == ref.n_faces and st["cells"] == ref.stats["cells"]
+    compare_meshes(ref, got)
