@@ -78,7 +78,9 @@ typedef struct {
     int32_t max_steps;    /* bound on marching steps (0: unbounded) */
     int32_t strict;       /* 1: return AM_E_DEGENERATE on a degenerate face */
     int32_t time_kernels; /* 1: time each kernel class with HIP events on the stream */
-    int32_t reserved[7];
+    int32_t kernel_path;  /* 0: the library's choice; 1: split (chain rows through HBM, then
+                             the clip); 2: fused chain+clip in LDS (AM_E_INVALID if too big) */
+    int32_t reserved[6];
 } am_march_opts;
 
 typedef struct {
@@ -96,13 +98,15 @@ typedef struct {
     int64_t required_cells;   /* on AM_E_CAPACITY: the cell capacity needed so far */
     double march_ms;          /* device time of the march (HIP events) */
     /* with opts.time_kernels: summed HIP-event durations and launch counts */
-    double chain_ms;          /* affine chain (FP64 MFMA) */
-    double clip_ms;           /* halfplane clip + vertex solve + candidates */
+    double chain_ms;          /* affine chain (FP64 MFMA); fused path: chain + clip */
+    double clip_ms;           /* halfplane clip + vertex solve + candidates (split path) */
     double hash_ms;           /* insert + commit + resolve */
     int64_t chain_launches;
     int64_t clip_launches;
     int64_t hash_launches;
-    double reserved[2];
+    int32_t fused;            /* 1 if the fused chain+clip kernel ran */
+    int32_t pad;
+    double reserved[1];
 } am_march_stats;
 
 /* Creates a context on `device` that enqueues its work on `hip_stream`

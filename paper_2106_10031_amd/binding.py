@@ -38,7 +38,7 @@ class NetDesc(C.Structure):
 
 class MarchOpts(C.Structure):
     _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
-                ("time_kernels", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class MarchStats(C.Structure):
@@ -48,10 +48,11 @@ class MarchStats(C.Structure):
                 ("degenerate", C.c_int64), ("domain_edges", C.c_int64), ("required_cells", C.c_int64),
                 ("march_ms", C.c_double), ("chain_ms", C.c_double), ("clip_ms", C.c_double),
                 ("hash_ms", C.c_double), ("chain_launches", C.c_int64), ("clip_launches", C.c_int64),
-                ("hash_launches", C.c_int64), ("reserved", C.c_double * 2)]
+                ("hash_launches", C.c_int64), ("fused", C.c_int32), ("pad", C.c_int32),
+                ("reserved", C.c_double * 1)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "pad")}
 
 
 _lib = None
@@ -200,8 +201,9 @@ class Context:
         self._seed_keep = (codes, am)       # the copy is enqueued on the stream
         self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), codes.shape[0]))
 
-    def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False):
-        opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)))
+    def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0):
+        opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
+                         int(kernel_path))
         stats = MarchStats()
         st = self.L.am_march(self.h, C.byref(opts), C.byref(stats))
         if st != AM_OK:

@@ -19,9 +19,14 @@
 #include "am_internal.h"
 
 namespace am {
-void launch_clip(const DevNet &, const uint64_t *, const int *, const uint64_t *, long long, long long, long long,
-                 const double *, const ClipOut &, const Candidates &, unsigned long long, Counters *, hipStream_t);
+void launch_clip(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long, long long,
+                 long long, const double *, const ClipOut &, const Candidates &, unsigned long long, Counters *,
+                 hipStream_t);
 void launch_chain(const DevNet &, const uint64_t *, long long, long long, double *, hipStream_t);
+void launch_fused(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long, long long,
+                  long long, const ClipOut &, const Candidates &, unsigned long long, Counters *, hipStream_t);
+size_t fused_lds_bytes(const DevNet &);
+hipError_t prepare_fused(size_t);
 void launch_rows_unpad(const DevNet &, long long, const double *, double *, hipStream_t);
 void launch_insert(const DevNet &, const Candidates &, const uint64_t *, const int *, const uint64_t *,
                    const int *, unsigned long long *, unsigned long long, Counters *, unsigned long long,
@@ -53,6 +58,10 @@ struct am_ctx {
     bool loaded = false;
     DevNet dn{};
     double *d_weights = nullptr;
+    double *d_wfrag = nullptr;
+    size_t lds_limit = 0;       // dynamic LDS a workgroup may use
+    bool fused_ok = false;      // the fused kernel's rows fit in LDS
+    bool prefer_fused = false;  // kernel_path 0 choice (the split path measured faster at width 90)
     double *d_bias = nullptr;
     int *d_row_of_unit = nullptr;
     uint64_t *d_zobrist = nullptr;
@@ -70,7 +79,7 @@ struct am_ctx {
     uint64_t *d_codes = nullptr;
     int *d_am = nullptr;
     uint64_t *d_hash = nullptr;
-    int *d_entry = nullptr;
+    int *d_hints = nullptr;     // [cap][3] lines to clip first (entry edge and its neighbours)
     int *d_fm = nullptr;
     int *d_fids = nullptr;
     double *d_fverts = nullptr;
@@ -157,7 +166,7 @@ void free_march(am_ctx *c) {
     dfree(c->d_codes);
     dfree(c->d_am);
     dfree(c->d_hash);
-    dfree(c->d_entry);
+    dfree(c->d_hints);
     dfree(c->d_fm);
     dfree(c->d_fids);
     dfree(c->d_fverts);
@@ -171,6 +180,8 @@ void free_march(am_ctx *c) {
     dfree(c->cand.kind);
     dfree(c->cand.ref);
     dfree(c->cand.cell);
+    dfree(c->cand.hint_prev);
+    dfree(c->cand.hint_next);
     dfree(c->d_rows);
     dfree(c->d_has);
     dfree(c->d_fidx);
@@ -187,6 +198,7 @@ void free_march(am_ctx *c) {
 
 void free_net(am_ctx *c) {
     dfree(c->d_weights);
+    dfree(c->d_wfrag);
     dfree(c->d_bias);
     dfree(c->d_row_of_unit);
     dfree(c->d_zobrist);
@@ -210,7 +222,7 @@ am_status ensure_march(am_ctx *ctx, long long cells) {
     TRY(dalloc(ctx, ctx->d_codes, (size_t)cells * n.W));
     TRY(dalloc(ctx, ctx->d_am, cells));
     TRY(dalloc(ctx, ctx->d_hash, cells));
-    TRY(dalloc(ctx, ctx->d_entry, cells));
+    TRY(dalloc(ctx, ctx->d_hints, (size_t)cells * 3));
     TRY(dalloc(ctx, ctx->d_fm, cells));
     TRY(dalloc(ctx, ctx->d_fids, (size_t)cells * kFaceSlots));
     TRY(dalloc(ctx, ctx->d_fverts, (size_t)cells * kFaceSlots * 3));
@@ -237,6 +249,8 @@ am_status ensure_march(am_ctx *ctx, long long cells) {
     TRY(dalloc(ctx, ctx->cand.kind, ctx->cand_cap));
     TRY(dalloc(ctx, ctx->cand.ref, ctx->cand_cap));
     TRY(dalloc(ctx, ctx->cand.cell, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.hint_prev, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.hint_next, ctx->cand_cap));
     ctx->cap_cells = cells;
     return AM_OK;
 }
@@ -276,6 +290,9 @@ am_status am_create(am_ctx **out, int device, void *hip_stream) {
         delete ctx;
         return AM_E_HIP;
     }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
+    ctx->lds_limit = (size_t)lds;
     *out = ctx;
     return AM_OK;
 }
@@ -369,6 +386,16 @@ am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
                 dst[(size_t)i * ld + k] = w;
             }
     }
+    // MFMA A fragments: per block, per 16-row tile, per K-step, 64 doubles in lane order
+    std::vector<double> hf;
+    for (int b = 0; b < nd->n_blocks; ++b) {
+        const int ld = dn.blk_ld[b], rows = (nd->width[dn.blk_dst[b]] + 15) & ~15;
+        const double *Wp = hw.data() + dn.blk_off[b];
+        dn.blk_frag_off[b] = (long long)hf.size();
+        for (int mt = 0; mt < rows / 16; ++mt)
+            for (int ks = 0; ks < ld / 4; ++ks)
+                for (int l = 0; l < 64; ++l) hf.push_back(Wp[(size_t)(mt * 16 + l % 16) * ld + ks * 4 + l / 16]);
+    }
     std::vector<double> hb(boff);
     for (int l = 1; l < L2; ++l)
         for (int k = 0; k < nd->width[l]; ++k) {
@@ -384,6 +411,8 @@ am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
     for (auto &z : zob) z = splitmix64(sm);
 
     TRY(dalloc(ctx, ctx->d_weights, hw.size()));
+    TRY(dalloc(ctx, ctx->d_wfrag, hf.size()));
+    HIPCHK(hipMemcpy(ctx->d_wfrag, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice));
     TRY(dalloc(ctx, ctx->d_bias, hb.size()));
     TRY(dalloc(ctx, ctx->d_row_of_unit, rou.size()));
     TRY(dalloc(ctx, ctx->d_zobrist, zob.size()));
@@ -392,10 +421,15 @@ am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
     HIPCHK(hipMemcpy(ctx->d_row_of_unit, rou.data(), sizeof(int) * rou.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_zobrist, zob.data(), sizeof(uint64_t) * zob.size(), hipMemcpyHostToDevice));
     dn.weights = ctx->d_weights;
+    dn.wfrag = ctx->d_wfrag;
     dn.bias = ctx->d_bias;
     dn.row_of_unit = ctx->d_row_of_unit;
     dn.zobrist = ctx->d_zobrist;
     ctx->dn = dn;
+    // the fused kernel keeps the rows of four cells in LDS next to 4 x 1.75 KiB of clip scratch
+    const size_t fb = fused_lds_bytes(dn);
+    ctx->fused_ok = fb + 8192 <= ctx->lds_limit && prepare_fused(fb) == hipSuccess;
+    (void)hipGetLastError();
     ctx->loaded = true;
     return AM_OK;
 }
@@ -453,7 +487,8 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, in
         out.stride = max_m;
         out.out_base = 0;
         Candidates none{};
-        launch_clip(ctx->dn, codes, argmax, nullptr, lo, hi, 0, ctx->d_rows, out, none, 0, nullptr, ctx->stream);
+        launch_clip(ctx->dn, codes, argmax, nullptr, nullptr, lo, hi, 0, ctx->d_rows, out, none, 0, nullptr,
+                    ctx->stream);
     }
     HIPCHK(hipGetLastError());
     return AM_OK;
@@ -520,7 +555,13 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         ctx->cap_cells = 0;   // force a re-size with room for the seeds
         TRY(ensure_march(ctx, cap));
     }
+    if (o.kernel_path < 0 || o.kernel_path > 2) return fail(ctx, AM_E_INVALID, "kernel_path must be 0, 1 or 2");
+    if (o.kernel_path == 2 && !ctx->fused_ok)
+        return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
+                    fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
+    const bool fused = o.kernel_path == 2 || (o.kernel_path == 0 && ctx->prefer_fused && ctx->fused_ok);
     am_march_stats st{};
+    st.fused = fused ? 1 : 0;
     hipStream_t s = ctx->stream;
     const DevNet &net = ctx->dn;
     ctx->have_result = false;
@@ -535,7 +576,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
                       ctx->n_seeds, ctx->cand, ctx->d_ctr, ctx->cand_cap, s);
     launch_insert(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots, hmask,
                   ctx->d_ctr, ctx->cand_cap, ctx->n_seeds, s);
-    launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_entry, ctx->d_fm, ctx->d_seed_codes,
+    launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_fm, ctx->d_seed_codes,
                   ctx->d_seed_am, ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, ctx->n_seeds, s);
     HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -569,15 +610,21 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         HIPCHK(hipMemsetAsync(&ctx->d_ctr->n_cand, 0, sizeof(unsigned long long), s));
         const bool tk = o.time_kernels != 0;
         if (tk) HIPCHK(hipEventRecord(ctx->evk[0], s));
-        launch_chain(net, ctx->d_codes, lo, lo + n, ctx->d_rows, s);
-        if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
-        launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, lo, lo + n, seed_cells, ctx->d_rows, out, ctx->cand,
-                    ctx->cand_cap, ctx->d_ctr, s);
+        if (fused) {
+            launch_fused(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells, out,
+                         ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
+            if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
+        } else {
+            launch_chain(net, ctx->d_codes, lo, lo + n, ctx->d_rows, s);
+            if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
+            launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells, ctx->d_rows,
+                        out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
+        }
         if (tk) HIPCHK(hipEventRecord(ctx->evk[2], s));
         const long long nh = n * 6;
         launch_insert(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots,
                       hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
-        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_entry, ctx->d_fm,
+        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_fm,
                       ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
                       (unsigned long long)cap, nh, s);
         launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
@@ -594,7 +641,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             st.clip_ms += b;
             st.hash_ms += c3;
             st.chain_launches++;
-            st.clip_launches++;
+            st.clip_launches += fused ? 0 : 1;
             st.hash_launches += 3;
         }
         st.steps++;
@@ -616,7 +663,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     const Counters &c = *ctx->h_ctr;
     st.cells = (long long)c.n_cells;
-    st.face_verts = (long long)c.face_verts;
+
     st.domain_edges = (long long)c.domain_edges;
     st.degenerate = (long long)c.degenerate;
     st.march_ms = ms;
@@ -632,7 +679,11 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     std::vector<int> seed_m(seed_cells);
     HIPCHK(hipMemcpyAsync(seed_m.data(), ctx->d_fm, sizeof(int) * seed_cells, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    long long tail[2] = {0, 0};   // exclusive scan of the vertex counts and the last count
+    HIPCHK(hipMemcpy(&tail[0], ctx->d_voff + st.cells - 1, sizeof(long long), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&tail[1], ctx->d_mcount + st.cells - 1, sizeof(long long), hipMemcpyDeviceToHost));
     st.faces = (long long)last_idx + last_has;
+    st.face_verts = tail[0] + tail[1];
     st.triangles = st.face_verts - 2 * st.faces;
     for (int v : seed_m) st.seed_empty += v == 0;
     ctx->res_cells = st.cells;

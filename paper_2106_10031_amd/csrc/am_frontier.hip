@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, con
 // ------------------------------------------------------------------ commit
 
 __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uint64_t *codes, int *argmax,
-                                                uint64_t *cell_hash, int *entry_unit, int *face_m,
+                                                uint64_t *cell_hash, int *hints, int *face_m,
                                                 const uint64_t *seed_codes, const int *seed_am,
                                                 unsigned long long *slots, Counters *ctr,
                                                 unsigned long long cand_cap, unsigned long long cap_cells) {
@@ -153,12 +153,16 @@ __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uin
         const uint64_t h = cand.hash[t];
         cell_hash[id] = h;
         const int p = cand.parent[t];
-        int entry = -1;
+        int entry = -1, hp = -1, hn = -1;
         if (p >= 0) {
             const int u = cand.unit[t];
-            entry = u < net.N ? u : net.N + argmax[p];
+            entry = u < net.N ? u : net.N + argmax[p];   // the crossed plane, in this cell's ids
+            hp = cand.hint_prev[t];
+            hn = cand.hint_next[t];
         }
-        entry_unit[id] = entry;
+        hints[id * 3 + 0] = entry;
+        hints[id * 3 + 1] = hp;
+        hints[id * 3 + 2] = hn;
         face_m[id] = 0;
         slots[cand.ref[t]] = ((unsigned long long)slot_tag(h) << 32) | id;
         cand.cell[t] = (int)id;
@@ -416,11 +420,11 @@ void launch_insert(const DevNet &net, const Candidates &cand, const uint64_t *co
 }
 
 void launch_commit(const DevNet &net, const Candidates &cand, uint64_t *codes, int *argmax, uint64_t *cell_hash,
-                   int *entry_unit, int *face_m, const uint64_t *seed_codes, const int *seed_am,
+                   int *hints, int *face_m, const uint64_t *seed_codes, const int *seed_am,
                    unsigned long long *slots, Counters *ctr, unsigned long long cand_cap,
                    unsigned long long cap_cells, long long n_hint, hipStream_t st) {
     hipLaunchKernelGGL(k_commit, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, codes, argmax, cell_hash,
-                       entry_unit, face_m, seed_codes, seed_am, slots, ctr, cand_cap, cap_cells);
+                       hints, face_m, seed_codes, seed_am, slots, ctr, cand_cap, cap_cells);
 }
 
 void launch_resolve(const Candidates &cand, int *face_nbr, int stride, Counters *ctr, unsigned long long cand_cap,

@@ -37,7 +37,11 @@ struct DevNet {
     int blk_dst[kMaxBlocks], blk_src[kMaxBlocks];
     int blk_ld[kMaxBlocks];    // leading dimension (= src width rounded up to 4)
     long long blk_off[kMaxBlocks];   // offset of the block in `weights` (rows padded to 16)
+    long long blk_frag_off[kMaxBlocks];   // offset of the block in `wfrag`
     const double *weights;     // blocks, row-major, zero padded to (16*ceil(n_dst/16)) x ld
+    // the same blocks as MFMA A fragments: for 16-row tile mt and K-step ks,
+    // 64 doubles in lane order, lane l = W[16 mt + l % 16][4 ks + l / 16]
+    const double *wfrag;
     const double *bias;
     const int *row_of_unit;    // [N + M] padded row of global unit g
     const uint64_t *zobrist;   // [N + M] keys of the cell fingerprint
@@ -52,6 +56,8 @@ struct Candidates {
     int *kind;         // insert outcome
     long long *ref;    // slot position (owner), cell id (found) or candidate (dup)
     int *cell;         // resolved cell id
+    int *hint_prev;    // the parent's edges next to the crossed one (clip-order hints)
+    int *hint_next;
 };
 
 enum : int { kOwner = 0, kFound = 1, kDup = 2, kLost = 3 };

@@ -1,0 +1,607 @@
+// am_kernels.hip -- per-cell work of analytic marching on gfx950: the affine
+// chain on FP64 matrix cores and the analytic face by halfplane clipping.
+//
+// Affine chain.  For a cell with activation code s, Lemma 1 and Corollary 1 of
+// the paper give every pre-activation as an affine function of x inside the
+// cell.  With the bias carried by the homogeneous coordinate, the rows Z_l
+// (n_l x 4) obey
+//     Z_0 = [I_3 | 0],
+//     Z_l = sum over blocks (l <- j) of W_{l<-j} diag(s_j) Z_j  +  b_l e_4^T,
+// where diag(s_0) = I (the input is never rectified); the shortcut blocks of
+// Sec. 5.1 and the max-pooled heads of Sec. 5.2 are ordinary blocks.  Batched
+// over cells this is a dense GEMM per layer, W (n_l x n_j) times the stacked
+// masked rows [diag(s^(c)) Z_j^(c)]_c (n_j x 4C); a workgroup of four waves
+// owns four cells = 16 columns, the N size of v_mfma_f64_16x16x4f64.  The
+// mask diag(s_j) is applied while loading the B operand.
+//
+// Analytic face.  The face of a cell (Eqn (AnalyticFace)) is the part of the
+// zero plane a_F . [x;1] = 0 where every oriented constraint
+// (1 - 2 s_k) a_k . [x;1] <= 0 holds (Eqn (AnalyticCellSystem)), plus the
+// max-pool sub-cell rows (a_F(i) - a_F(j)) . [x;1] <= 0 of Eqn
+// (AnalyticCellSystemMaxPooling), inside the domain box.  Instead of the
+// paper's pair enumeration (Algorithm 1) or pivoting (Sec. 4.2.1), one wave
+// clips a polygon in a 2-D frame of the plane:
+//   * lane i holds vertex i (frame coordinates, id of the edge it starts);
+//   * constraints are tested 64 at a time, one per lane, against every
+//     vertex (broadcast with readlane); only the lines that cut are applied;
+//   * a cut is one Sutherland-Hodgman pass: each lane emits 0-2 vertices,
+//     positions come from two ballots and a popcount (wave compaction), the
+//     new polygon goes through the wave's LDS scratch.
+// Vertices are then recomputed in FP64 from their two edge ids and the plane
+// (Eqn (VertexEquationSystem)), and each edge on a hidden unit or head
+// comparison becomes a neighbour candidate (state flip, Sec. 3.1).
+#include "am_internal.h"
+
+namespace am {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Affine chain of up to four cells c0..c0+ncell-1 (16 MFMA columns: cell =
+// col / 4, homogeneous component q = col % 4).  Element (row, cell, q) of the
+// rows is zb[row * rs + cell * cs + q].  Every wave of the workgroup takes
+// the 16-row output tiles wave, wave + nwaves, ...  Ends with a barrier.
+#ifndef AM_KCHUNK
+#define AM_KCHUNK 8
+#endif
+constexpr int kKChunk = AM_KCHUNK;     // K-steps whose operands are loaded before their MFMAs issue
+constexpr int kMaxWords = kMaxHidden / 64;
+
+// Affine chain of up to four cells c0..c0+ncell-1 (16 MFMA columns: cell =
+// col / 4, homogeneous component q = col % 4).  Element (row, cell, q) of the
+// rows is zb[row * rs + cell * cs + q].  Each wave takes two 16-row output
+// tiles at a time (mt and mt + nwaves) so that one B value feeds two MFMAs,
+// and loads the operands of kKChunk K-steps before issuing their MFMAs.  The
+// four codes are staged in LDS (code_lds, 4 x W words).  Ends with a barrier.
+__device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes, long long c0, int ncell,
+                           double *zb, long long rs, long long cs, uint64_t *code_lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int col = lane & 15;       // MFMA column (B, D) / row within the tile (A)
+    const int kq = lane >> 4;        // k within the K-step of 4 (A, B) / row offset (D)
+    const int q = col & 3;           // homogeneous component of this column
+    const int cl = col >> 2;         // cell of this column within the tile
+    const bool cell_ok = cl < ncell;
+    for (int t = threadIdx.x; t < 4 * net.W; t += blockDim.x) {
+        const int c = t / net.W;
+        code_lds[t] = c < ncell ? codes[(c0 + c) * net.W + (t - c * net.W)] : 0ull;
+    }
+    __syncthreads();
+    const uint64_t *code = code_lds + cl * net.W;
+    double *zc = zb + cl * cs + q;
+
+    for (int l = 1; l < net.n_layers; ++l) {
+        const int nl = net.width[l];
+        const int mtiles = (nl + 15) >> 4;
+        for (int mt0 = wave; mt0 < mtiles; mt0 += 2 * nwaves) {
+            const int mt1 = mt0 + nwaves;
+            const bool two = mt1 < mtiles;
+            v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < net.n_blocks; ++b) {
+                if (net.blk_dst[b] != l) continue;
+                const int j = net.blk_src[b];
+                const int ks_n = net.blk_ld[b] >> 2;
+                const int nj = net.width[j];
+                // A fragments: 64 doubles per (tile, K-step), already in lane order
+                const double *fr0 = net.wfrag + net.blk_frag_off[b] + (long long)mt0 * ks_n * 64 + lane;
+                const double *fr1 = fr0 + (long long)(mt1 - mt0) * ks_n * 64;
+                if (j == 0) {
+                    // Z_0 = [I | 0]: one K-step; row k of B is e_k for k < 3
+                    const double bv = (kq < 3 && kq == q) ? 1.0 : 0.0;
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fr0[0], bv, acc0, 0, 0, 0);
+                    if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fr1[0], bv, acc1, 0, 0, 0);
+                    continue;
+                }
+                const int uoff = net.unit_off[j];
+                const double *zj = zc + (long long)net.row_off[j] * rs;
+                for (int ks0 = 0; ks0 < ks_n; ks0 += kKChunk) {
+                    double a0[kKChunk], a1[kKChunk], bv[kKChunk];
+#pragma unroll
+                    for (int u = 0; u < kKChunk; ++u) {
+                        const int ks = ks0 + u;
+                        const bool kv = ks < ks_n;
+                        const int k = ks * 4 + kq;
+                        a0[u] = kv ? fr0[ks * 64] : 0.0;
+                        a1[u] = (kv && two) ? fr1[ks * 64] : 0.0;
+                        bv[u] = (kv && k < nj && cell_ok && code_bit(code, uoff + k)) ? zj[k * rs] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kKChunk; ++u) {
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc0, 0, 0, 0);
+                        if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc1, 0, 0, 0);
+                    }
+                }
+            }
+            if (cell_ok) {
+                const double *bias = net.bias + net.bias_off[l];
+                // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r of
+                // lane (kq * 16 + col)
+                double *z0 = zc + (long long)net.row_off[l] * rs;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i0 = mt0 * 16 + kq + 4 * r;
+                    if (i0 < nl) z0[i0 * rs] = acc0[r] + (q == 3 ? bias[i0] : 0.0);
+                    const int i1 = mt1 * 16 + kq + 4 * r;
+                    if (two && i1 < nl) z0[i1 * rs] = acc1[r] + (q == 3 ? bias[i1] : 0.0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+struct PolyScratch {
+    double a[kMaxPoly];
+    double b[kMaxPoly];
+    double r[kMaxPoly];
+    int e[kMaxPoly];
+};
+
+struct Poly {
+    double a, b;   // this lane's vertex in the plane frame
+    double r;      // 1 + |(a, b)|, the vertex scale of the on-line tolerance
+    int e;         // id of the edge starting at this vertex
+    int m;         // vertex count (uniform)
+};
+
+enum : int { kFlagEmpty = 1, kFlagDegen = 2, kFlagSingular = 4, kFlagTooBig = 8 };
+
+// One Sutherland-Hodgman pass with the halfplane cu a + cv b + cw <= 0 (id);
+// nrm = |(cu, cv)| scales the on-line tolerance.
+// Returns false when the polygon has no interior left.
+__device__ bool sh_clip(Poly &P, double cu, double cv, double cw, double nrm, int id, PolyScratch &s,
+                        int &flags) {
+    const int lane = lane_id();
+    const bool act = lane < P.m;
+    const double d = cu * P.a + cv * P.b + cw;
+    const double tol = kTau * (nrm * P.r + fabs(cw));
+    const int cls = !act ? 0 : (d > tol ? 1 : (d < -tol ? -1 : 0));
+    const uint64_t outm = ballot(act && cls == 1);
+    if (!outm) return true;
+    const uint64_t inm = ballot(act && cls == -1);
+    if (!inm) {
+        P.m = 0;
+        return false;
+    }
+    const int j = (lane + 1 >= P.m) ? 0 : lane + 1;
+    const double ja = shfl(P.a, j), jb = shfl(P.b, j), jd = shfl(d, j);
+    const int jc = shfl(cls, j);
+    const bool c1 = act && cls != 1;
+    const bool c2 = act && ((cls == -1 && jc == 1) || (cls == 1 && jc == -1));
+    const uint64_t b1 = ballot(c1), b2 = ballot(c2);
+    const uint64_t lt = lanemask_lt();
+    const int pos = __popcll(b1 & lt) + __popcll(b2 & lt);
+    const int nm = __popcll(b1) + __popcll(b2);
+    if (nm > kMaxPoly) {
+        flags |= kFlagTooBig;
+        P.m = 0;
+        return false;
+    }
+    if (c1) {
+        s.a[pos] = P.a;
+        s.b[pos] = P.b;
+        s.r[pos] = P.r;
+        s.e[pos] = (cls == 0 && jc == 1) ? id : P.e;
+    }
+    if (c2) {
+        const double t = d / (d - jd);
+        const double xa = P.a + t * (ja - P.a);
+        const double xb = P.b + t * (jb - P.b);
+        const int p2 = pos + (c1 ? 1 : 0);
+        s.a[p2] = xa;
+        s.b[p2] = xb;
+        s.r[p2] = 1.0 + sqrt(xa * xa + xb * xb);
+        s.e[p2] = (cls == -1) ? id : P.e;
+    }
+    wave_lds_sync();
+    P.m = nm;
+    if (lane < nm) {
+        P.a = s.a[lane];
+        P.b = s.b[lane];
+        P.r = s.r[lane];
+        P.e = s.e[lane];
+    }
+    wave_lds_sync();
+    return true;
+}
+
+// Oriented constraint row of id (feasible side <= 0).
+__device__ __forceinline__ void constraint_row(const DevNet &net, int id, const uint64_t *code, int am,
+                                               const double *rb, long long rs, double c[4]) {
+    if (id < 0) {
+        const int t = -id - 1;
+        const int ax = t >> 1;
+        c[0] = c[1] = c[2] = 0.0;
+        c[ax] = (t & 1) ? -1.0 : 1.0;
+        c[3] = -1.0;
+    } else if (id < net.N) {
+        const double *z = rb + (long long)net.row_of_unit[id] * rs;
+        const double sg = code_bit(code, id) ? -1.0 : 1.0;
+        c[0] = sg * z[0];
+        c[1] = sg * z[1];
+        c[2] = sg * z[2];
+        c[3] = sg * z[3];
+    } else {
+        const double *zi = rb + (long long)net.row_of_unit[id] * rs;
+        const double *zj = rb + (long long)net.row_of_unit[net.N + am] * rs;
+        c[0] = zi[0] - zj[0];
+        c[1] = zi[1] - zj[1];
+        c[2] = zi[2] - zj[2];
+        c[3] = zi[3] - zj[3];
+    }
+}
+
+// Solves A x = r (3x3) by elimination with row pivoting; false if singular.
+__device__ bool solve3(double A[3][3], double r[3], double x[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int p = c;
+        for (int i = c + 1; i < 3; ++i)
+            if (fabs(A[i][c]) > fabs(A[p][c])) p = i;
+        if (A[p][c] == 0.0) return false;
+        if (p != c) {
+            for (int k = 0; k < 3; ++k) {
+                const double t = A[c][k];
+                A[c][k] = A[p][k];
+                A[p][k] = t;
+            }
+            const double t = r[c];
+            r[c] = r[p];
+            r[p] = t;
+        }
+        const double inv = 1.0 / A[c][c];
+        for (int i = c + 1; i < 3; ++i) {
+            const double f = A[i][c] * inv;
+            for (int k = c; k < 3; ++k) A[i][k] -= f * A[c][k];
+            r[i] -= f * r[c];
+        }
+    }
+    for (int i = 2; i >= 0; --i) {
+        double s = r[i];
+        for (int k = i + 1; k < 3; ++k) s -= A[i][k] * x[k];
+        x[i] = s / A[i][i];
+    }
+    return true;
+}
+
+// Clips the face of one cell (one wave) and writes it; rows of the cell's
+// chain are read as rb[row * rs + q].
+__device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ argmax,
+                          const uint64_t *__restrict__ cell_hash, const int *__restrict__ hints, long long cell,
+                          long long n_seed_cells, const double *rb, long long rs, PolyScratch &S, const ClipOut &out,
+                          const Candidates &cand, unsigned long long cand_cap, Counters *ctr) {
+    const int lane = lane_id();
+    const uint64_t *code = codes + cell * net.W;
+    const int am_in = argmax ? argmax[cell] : 0;
+    const bool am_ok = am_in >= 0 && am_in < net.M;   // a bad argmax gives an empty face
+    const int am = am_ok ? am_in : 0;
+    const long long oi = cell - out.out_base;
+    int flags = 0;
+
+    // ---- plane frame: n = a_F[0:3], foot point p0, orthonormal u, v with u x v = n/|n|
+    const double *aF = rb + (long long)net.row_of_unit[net.N + am] * rs;
+    const double fx = aF[0], fy = aF[1], fz = aF[2], fw = aF[3];
+    const double nn = fx * fx + fy * fy + fz * fz;
+    Poly P;
+    P.m = 0;
+    double p0[3], u[3], v[3];
+    if (nn > 0.0 && am_ok) {
+        p0[0] = -fw * fx / nn;
+        p0[1] = -fw * fy / nn;
+        p0[2] = -fw * fz / nn;
+        const double inl = 1.0 / sqrt(nn);
+        const double n0 = fx * inl, n1 = fy * inl, n2 = fz * inl;
+        int ax = 0;
+        if (fabs(n1) < fabs(n0)) ax = 1;
+        if (fabs(n2) < fabs(ax == 0 ? n0 : n1)) ax = 2;
+        // u = normalize(n x e_ax)
+        double ux = ax == 0 ? 0.0 : (ax == 1 ? -n2 : n1);
+        double uy = ax == 0 ? n2 : (ax == 1 ? 0.0 : -n0);
+        double uz = ax == 0 ? -n1 : (ax == 1 ? n0 : 0.0);
+        const double iu = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+        u[0] = ux * iu;
+        u[1] = uy * iu;
+        u[2] = uz * iu;
+        v[0] = n1 * u[2] - n2 * u[1];
+        v[1] = n2 * u[0] - n0 * u[2];
+        v[2] = n0 * u[1] - n1 * u[0];
+        // starting square, counter-clockwise, edges -7..-10
+        const double sa[4] = {-kSquareHalf, kSquareHalf, kSquareHalf, -kSquareHalf};
+        const double sb[4] = {-kSquareHalf, -kSquareHalf, kSquareHalf, kSquareHalf};
+        const int li = lane < 4 ? lane : 0;
+        P.a = sa[li];
+        P.b = sb[li];
+        P.r = 1.0 + sqrt(P.a * P.a + P.b * P.b);
+        P.e = -7 - li;
+        P.m = 4;
+        // lines the parent's face says bound this one: the entry edge and the
+        // parent's edges on either side of it (the cells around a cell edge
+        // share both planes).  Any order gives the same polygon; these first
+        // leave most later lines with nothing to cut.
+        if (hints) {
+            for (int h = 0; h < 3 && P.m > 0; ++h) {
+                const int id = hints[cell * 3 + h];
+                if (id < 0 || id >= net.N + net.M || id == net.N + am) continue;
+                double c[4];
+                constraint_row(net, id, code, am, rb, rs, c);
+                const double hu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+                const double hv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
+                const double hw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
+                sh_clip(P, hu, hv, hw, sqrt(hu * hu + hv * hv), id, S, flags);
+            }
+        }
+        // hidden units, 64 lines per pass
+        for (int base = 0; base < net.N && P.m > 0; base += kWave) {
+            const int g = base + lane;
+            const bool valid = g < net.N;
+            double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0;
+            bool cuts = false;
+            if (valid) {
+                const double *z = rb + (long long)net.row_of_unit[g] * rs;
+                const double sg = code_bit(code, g) ? -1.0 : 1.0;
+                const double c0 = sg * z[0], c1 = sg * z[1], c2 = sg * z[2], c3 = sg * z[3];
+                cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
+                cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
+                cw = c0 * p0[0] + c1 * p0[1] + c2 * p0[2] + c3;
+                nrm = sqrt(cu * cu + cv * cv);
+            }
+            for (int i = 0; i < P.m; ++i) {
+                const double ai = bcast(P.a, i), bi = bcast(P.b, i), ri = bcast(P.r, i);
+                cuts |= (cu * ai + cv * bi + cw) > kTau * (nrm * ri + fabs(cw));
+            }
+            uint64_t mask = ballot(valid && cuts);
+            while (mask) {
+                const int t = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                if (!sh_clip(P, bcast(cu, t), bcast(cv, t), bcast(cw, t), bcast(nrm, t), base + t, S, flags)) break;
+            }
+        }
+        // max-pool comparisons with every other head
+        if (net.M > 1 && P.m > 0) {
+            const int hd = lane;
+            const bool valid = hd < net.M && hd != am;
+            double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0;
+            if (valid) {
+                const double *zi = rb + (long long)net.row_of_unit[net.N + hd] * rs;
+                const double c0 = zi[0] - fx, c1 = zi[1] - fy, c2 = zi[2] - fz, c3 = zi[3] - fw;
+                cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
+                cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
+                cw = c0 * p0[0] + c1 * p0[1] + c2 * p0[2] + c3;
+                nrm = sqrt(cu * cu + cv * cv);
+            }
+            uint64_t mask = ballot(valid);
+            while (mask && P.m > 0) {
+                const int t = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                if (!sh_clip(P, bcast(cu, t), bcast(cv, t), bcast(cw, t), bcast(nrm, t), net.N + t, S, flags)) break;
+            }
+        }
+
+        // the six box planes, ids -1..-6.  The box section lies strictly inside
+        // the starting square, so the result does not depend on when they are
+        // applied; last, they rarely cut.
+        for (int t = 0; t < 6 && P.m > 0; ++t) {
+            const int axb = t >> 1;
+            const double sg = (t & 1) ? -1.0 : 1.0;
+            sh_clip(P, sg * u[axb], sg * v[axb], sg * p0[axb] - 1.0, sqrt(u[axb] * u[axb] + v[axb] * v[axb]), -1 - t,
+                    S, flags);
+        }
+    }
+
+    // ---- validity: >= 3 vertices, positive area, distinct ids, no frame edge
+    int m = P.m;
+    const bool act = lane < m;
+    if (m >= 3) {
+        const int j = (lane + 1 >= m) ? 0 : lane + 1;
+        const double ja = shfl(P.a, j), jb = shfl(P.b, j);
+        const double area2 = wave_sum(act ? (P.a * jb - ja * P.b) : 0.0);
+        bool dup = false;
+        for (int k = 0; k < m; ++k) {
+            const int ek = bcast(P.e, k);
+            dup |= act && k != lane && ek == P.e;
+        }
+        if (ballot(dup)) flags |= kFlagDegen;
+        // a starting-square edge cannot survive the box planes; if one did, the
+        // face is unusable (and its id names no constraint row)
+        if (ballot(act && P.e <= -7)) {
+            flags |= kFlagDegen;
+            m = 0;
+        }
+        if (!(area2 > 0.0)) m = 0;
+    } else {
+        m = 0;
+    }
+    if (m == 0) flags |= kFlagEmpty;
+
+    if (m > out.stride) {
+        flags |= kFlagTooBig;
+        m = 0;
+    }
+
+    int e_out = 0;
+    if (m > 0) {
+        // rotate so that the smallest edge id comes first
+        const int minid = wave_min(lane < m ? P.e : 0x7fffffff);
+        const int r0 = __builtin_ctzll(ballot(lane < m && P.e == minid));
+        int src = lane + r0;
+        if (src >= m) src -= m;
+        if (lane >= m) src = lane;
+        const int e = shfl(P.e, src);
+        const int eprev = shfl(e, lane == 0 ? m - 1 : lane - 1);
+        e_out = e;
+        if (lane < m) {
+            // vertex i = [c_{e(i-1)}; c_{e(i)}; a_F] x = -[...]
+            double ca[4], cb[4];
+            constraint_row(net, eprev, code, am, rb, rs, ca);
+            constraint_row(net, e, code, am, rb, rs, cb);
+            double A[3][3] = {{ca[0], ca[1], ca[2]}, {cb[0], cb[1], cb[2]}, {fx, fy, fz}};
+            double rr[3] = {-ca[3], -cb[3], -fw};
+            double x[3];
+            if (!solve3(A, rr, x)) {
+                flags |= kFlagSingular;
+                x[0] = x[1] = x[2] = __builtin_nan("");
+            }
+            const long long o = oi * out.stride + lane;
+            out.ids[o] = e;
+            out.verts[o * 3 + 0] = x[0];
+            out.verts[o * 3 + 1] = x[1];
+            out.verts[o * 3 + 2] = x[2];
+            if (out.nbr) out.nbr[o] = -1;
+        }
+        for (int o = 32; o > 0; o >>= 1) flags |= __shfl_xor(flags, o, kWave);
+    }
+    if (lane == 0) {
+        out.m[oi] = m;
+        if (out.flags) out.flags[oi] = flags;
+    }
+
+    if (ctr && lane == 0) {
+        if (m == 0) {
+            if (cell >= n_seed_cells) atomicAdd(&ctr->degenerate, 1ull);
+        } else if (flags & kFlagDegen) {
+            atomicAdd(&ctr->degenerate, 1ull);
+        }
+        if (flags & kFlagTooBig) atomicAdd(&ctr->too_big, 1ull);
+    }
+
+    // ---- neighbour candidates: flip the unit (or the argmax) behind each edge
+    if (cand.parent && m > 0) {
+        const bool want = lane < m && e_out >= 0;
+        const int e_prev = shfl(e_out, lane == 0 ? m - 1 : lane - 1);
+        const int e_next = shfl(e_out, lane + 1 >= m ? 0 : lane + 1);
+        if (ctr) {
+            const uint64_t dm = ballot(lane < m && e_out < 0);
+            if (lane == 0 && dm) atomicAdd(&ctr->domain_edges, (unsigned long long)__popcll(dm));
+        }
+        unsigned long long basev;
+        const unsigned long long idx = wave_reserve(&ctr->n_cand, want, &basev);
+        if (want) {
+            if (idx < cand_cap) {
+                const uint64_t h = cell_hash[cell];
+                uint64_t hn;
+                if (e_out < net.N) hn = h ^ net.zobrist[e_out];
+                else hn = h ^ net.zobrist[net.N + am] ^ net.zobrist[e_out];
+                cand.parent[idx] = (int)cell;
+                cand.slot[idx] = lane;
+                cand.unit[idx] = e_out;
+                cand.hash[idx] = hn;
+                cand.hint_prev[idx] = e_prev;
+                cand.hint_next[idx] = e_next;
+            } else {
+                atomicAdd(&ctr->overflow_cand, 1ull);
+            }
+        }
+    }
+}
+
+
+
+// Unfused chain: rows of cells lo..hi-1 to the global buffer [cell][R][4].
+__global__ __launch_bounds__(256) void k_chain_f64(DevNet net, const uint64_t *__restrict__ codes,
+                                                   long long lo, long long hi, double *__restrict__ rows) {
+    __shared__ uint64_t code_lds[4 * kMaxWords];
+    const long long c0 = lo + 4LL * blockIdx.x;
+    const int ncell = (int)min(4LL, hi - c0);
+    chain_tile(net, codes, c0, ncell, rows + (c0 - lo) * (long long)net.R * 4, 4, (long long)net.R * 4,
+               code_lds);
+}
+
+// Unfused clip: one wave per cell, four cells per workgroup.
+__global__ __launch_bounds__(256) void k_clip_f64(DevNet net, const uint64_t *__restrict__ codes,
+                                                  const int *__restrict__ argmax,
+                                                  const uint64_t *__restrict__ cell_hash,
+                                                  const int *__restrict__ hints, long long lo,
+                                                  long long hi, long long n_seed_cells,
+                                                  const double *__restrict__ rows, ClipOut out,
+                                                  Candidates cand, unsigned long long cand_cap,
+                                                  Counters *ctr) {
+    __shared__ PolyScratch scratch[4];
+    const int wave = threadIdx.x >> 6;
+    const long long cell = lo + 4LL * blockIdx.x + wave;
+    if (cell >= hi) return;
+    clip_cell(net, codes, argmax, cell_hash, hints, cell, n_seed_cells, rows + (cell - lo) * (long long)net.R * 4,
+              4, scratch[wave], out, cand, cand_cap, ctr);
+}
+
+// Fused step: the chain of four cells lands in LDS as [row][cell][4]
+// (16 consecutive doubles per row: conflict-free B loads and D stores), then
+// wave w clips cell w straight from LDS.  No row ever goes to HBM.
+__global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t *__restrict__ codes,
+                                                     const int *__restrict__ argmax,
+                                                     const uint64_t *__restrict__ cell_hash,
+                                                     const int *__restrict__ hints, long long lo,
+                                                     long long hi, long long n_seed_cells, ClipOut out,
+                                                     Candidates cand, unsigned long long cand_cap,
+                                                     Counters *ctr) {
+    extern __shared__ double zl[];
+    __shared__ PolyScratch scratch[4];
+    __shared__ uint64_t code_lds[4 * kMaxWords];
+    const int wave = threadIdx.x >> 6;
+    const long long c0 = lo + 4LL * blockIdx.x;
+    const int ncell = (int)min(4LL, hi - c0);
+    chain_tile(net, codes, c0, ncell, zl, 16, 4, code_lds);
+    if (wave >= ncell) return;
+    clip_cell(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zl + wave * 4, 16, scratch[wave], out,
+              cand, cand_cap, ctr);
+}
+
+// Repacks padded per-cell rows into the dense [n][N+M][4] layout of am_chain.
+__global__ void k_rows_unpad(DevNet net, long long n, const double *__restrict__ rows,
+                             double *__restrict__ out) {
+    const int G = net.N + net.M;
+    const long long total = n * G;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const long long c = t / G;
+        const int g = (int)(t % G);
+        const double *src = rows + (c * net.R + net.row_of_unit[g]) * 4;
+        double *dst = out + t * 4;
+        dst[0] = src[0];
+        dst[1] = src[1];
+        dst[2] = src[2];
+        dst[3] = src[3];
+    }
+}
+
+size_t fused_lds_bytes(const DevNet &net) { return sizeof(double) * 16 * (size_t)net.R; }
+
+hipError_t prepare_fused(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_march_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+void launch_chain(const DevNet &net, const uint64_t *codes, long long lo, long long hi, double *rows,
+                  hipStream_t st) {
+    if (hi <= lo) return;
+    const long long tiles = (hi - lo + 3) / 4;
+    hipLaunchKernelGGL(k_chain_f64, dim3((unsigned)tiles), dim3(256), 0, st, net, codes, lo, hi, rows);
+}
+
+void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
+                 const int *hints, long long lo, long long hi, long long n_seed_cells, const double *rows,
+                 const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, Counters *ctr,
+                 hipStream_t st) {
+    if (hi <= lo) return;
+    const long long blocks = (hi - lo + 3) / 4;
+    hipLaunchKernelGGL(k_clip_f64, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints,
+                       lo, hi, n_seed_cells, rows, out, cand, cand_cap, ctr);
+}
+
+void launch_fused(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
+                  const int *hints, long long lo, long long hi, long long n_seed_cells, const ClipOut &out,
+                  const Candidates &cand, unsigned long long cand_cap, Counters *ctr, hipStream_t st) {
+    if (hi <= lo) return;
+    const long long blocks = (hi - lo + 3) / 4;
+    hipLaunchKernelGGL(k_march_fused, dim3((unsigned)blocks), dim3(256), fused_lds_bytes(net), st, net, codes,
+                       argmax, cell_hash, hints, lo, hi, n_seed_cells, out, cand, cand_cap, ctr);
+}
+
+void launch_rows_unpad(const DevNet &net, long long n, const double *rows, double *out, hipStream_t st) {
+    if (n <= 0) return;
+    const long long total = n * (net.N + net.M);
+    long long blocks = (total + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(k_rows_unpad, dim3((unsigned)blocks), dim3(256), 0, st, net, n, rows, out);
+}
+
+}  // namespace am

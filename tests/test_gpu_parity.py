@@ -123,15 +123,17 @@ def test_seed_rays_match_oracle(binding):
 
 # ------------------------------------------------------------------ march
 
+@pytest.mark.parametrize("path", [1, 2], ids=["split", "fused"])
 @pytest.mark.parametrize("name", list(SMALL_NETS))
-def test_march_matches_oracle(binding, name):
+def test_march_matches_oracle(binding, name, path):
     net = SMALL_NETS[name]()
     o, d = seeds.random_rays(16, seed=4)
     on, ref = _oracle_mesh(net, o, d)
-    say("march", name, ref.n_faces)
+    say("march", name, ref.n_faces, "path", path)
     ctx = _ctx(binding, net)
     ctx.seed_rays(o, d)
-    st = ctx.march()
+    st = ctx.march(kernel_path=path)
+    assert st["fused"] == (path == 2)
     got = fetch_host(ctx)
     assert st["faces"] == ref.n_faces
     assert st["cells"] == ref.stats["cells"]
@@ -253,16 +255,23 @@ def test_c2_full_march_sampled_faces_and_closedness(binding, c2_case):
     assert all(MC.code_key(c, a) in have for c, a in zip(codes, ams))
 
 
-def test_c2_full_march_equals_oracle(binding, c2_case):
-    """The whole cell set, cycles and adjacency against the oracle's full march."""
+@pytest.fixture(scope="module")
+def c2_ref(c2_case):
     net, o, d = c2_case
     on = O.OracleNet(net)
     codes, ams, _, _ = on.seed_rays(o, d)
-    ref = on.march(codes, ams)
-    say("c2 full march vs oracle", ref.n_faces)
+    return on.march(codes, ams)
+
+
+@pytest.mark.parametrize("path", [1, 0], ids=["split", "auto"])
+def test_c2_full_march_equals_oracle(binding, c2_case, c2_ref, path):
+    """The whole cell set, cycles and adjacency against the oracle's full march."""
+    net, o, d = c2_case
+    ref = c2_ref
+    say("c2 full march vs oracle", ref.n_faces, "path", path)
     ctx = _ctx(binding, net)
     ctx.seed_rays(o, d)
-    st = ctx.march(max_cells=1 << 21)
+    st = ctx.march(max_cells=1 << 21, kernel_path=path)
     got = fetch_host(ctx)
     assert st["faces"] == ref.n_faces and st["cells"] == ref.stats["cells"]
     compare_meshes(ref, got)
