@@ -344,3 +344,102 @@ def load_fitted(name: str) -> Net:
     if not os.path.exists(path):
         raise FileNotFoundError(f"fitted fixture {path} missing; run python -m am_workloads.fit {name}")
     return Net.load(path)
+
+
+# ---------------------------------------------------------------------------
+# Shapes sharing one network's weights (latent-conditioned decoders).
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ShapeBatch:
+    """S shapes that share ``net``'s weights; row s of ``shape_bias`` holds the
+    biases of every layer >= 1 (layers in order) for shape s."""
+    net: Net
+    shape_bias: np.ndarray      # [S, sum(widths[1:])]
+
+    @property
+    def n_shapes(self) -> int:
+        return int(self.shape_bias.shape[0])
+
+    def shape_net(self, s: int) -> Net:
+        """The single network that shape s is."""
+        row = self.shape_bias[s]
+        bias, o = [], 0
+        for w in self.net.widths[1:]:
+            bias.append(row[o:o + w].copy())
+            o += w
+        return Net(list(self.net.widths), [(d, k, W.copy()) for d, k, W in self.net.blocks], bias)
+
+
+def latent_sphere_batch(hidden: Sequence[int], reinject: int, latent_dim: int, n_shapes: int, seed: int,
+                        latent_std: float = 0.3, radius=(0.4, 0.8), scale: float = 0.4) -> ShapeBatch:
+    """A latent-conditioned decoder ``scale * MLP([x; z]) + |x|_1 - r_s``.
+
+    The MLP takes [x; z] at layer 1 and again at layer ``reinject`` (a linear
+    shortcut from the input, Sec. 5.1); the latent terms W_z z_s are folded
+    into the biases of those layers.  Shape s has latent z_s ~ N(0, latent_std^2)
+    and radius r_s spread over ``radius`` (so the shapes' sizes, and cell
+    counts, differ).  The L1 norm uses |t| = 2 relu(t) - t (three extra units
+    of layer 1 and an input shortcut to the head).
+    """
+    rng = np.random.default_rng(seed)
+    L = len(hidden)
+    if not (2 <= reinject <= L):
+        raise ValueError("reinject must name a hidden layer after the first")
+    n_in = 3 + latent_dim
+    Wx, Wz, bs = [], [], []
+    for l in range(L):
+        fan = n_in if l == 0 else hidden[l - 1] + (n_in if l + 1 == reinject else 0)
+        W = rng.normal(0.0, np.sqrt(2.0 / fan), (hidden[l], fan))
+        bs.append(rng.normal(0.0, 0.05, hidden[l]))
+        if l == 0:
+            Wx.append(W[:, :3]); Wz.append(W[:, 3:])
+        elif l + 1 == reinject:
+            Wx.append(W); Wz.append(None)
+        else:
+            Wx.append(W); Wz.append(None)
+    Wout = rng.normal(0.0, np.sqrt(2.0 / hidden[-1]), (1, hidden[-1]))
+    bout = rng.normal(0.0, 0.05, 1)
+    Z = rng.normal(0.0, latent_std, (n_shapes, latent_dim))
+    radii = np.linspace(radius[0], radius[1], n_shapes)
+
+    widths = [3, hidden[0] + 3] + list(hidden[1:]) + [1]
+    B10 = np.zeros((hidden[0] + 3, 3)); B10[:hidden[0]] = Wx[0]; B10[hidden[0]:] = np.eye(3)
+    blocks = [(1, 0, B10)]
+    for l in range(1, L):
+        W = Wx[l]
+        if l + 1 == reinject:
+            Wh = W[:, :hidden[l - 1]]                  # from the previous layer
+            Wxr = W[:, hidden[l - 1]:hidden[l - 1] + 3]  # x re-injected
+            Wzr = W[:, hidden[l - 1] + 3:]               # z re-injected (folded into the bias)
+            Wz[l] = Wzr
+            blocks.append((l + 1, 0, Wxr))
+        else:
+            Wh = W
+        Bp = np.zeros((hidden[l], widths[l])); Bp[:, :hidden[l - 1]] = Wh
+        blocks.append((l + 1, l, Bp))
+    Bo = np.zeros((1, widths[L])); Bo[0, :hidden[L - 1]] = scale * Wout[0]
+    if L == 1:
+        Bo[0, hidden[0]:] = 2.0
+        blocks.append((L + 1, L, Bo))
+    else:
+        blocks.append((L + 1, L, Bo))
+        B1h = np.zeros((1, widths[1])); B1h[0, hidden[0]:] = 2.0
+        blocks.append((L + 1, 1, B1h))
+    blocks.append((L + 1, 0, -np.ones((1, 3))))
+
+    rows = []
+    for s in range(n_shapes):
+        bias = []
+        for l in range(L):
+            b = bs[l].copy()
+            if Wz[l] is not None:
+                b = b + Wz[l] @ Z[s]
+            if l == 0:
+                b = np.concatenate([b, np.zeros(3)])
+            bias.append(b)
+        bias.append(np.array([scale * bout[0] - radii[s]]))
+        rows.append(np.concatenate(bias))
+    shape_bias = np.asarray(rows)
+    base = [shape_bias[0][o:o + w] for o, w in zip(np.cumsum([0] + widths[1:-1]), widths[1:])]
+    return ShapeBatch(Net(widths, blocks, base), shape_bias)

@@ -126,44 +126,64 @@ const char *am_last_error(const am_ctx *ctx);
  * any seeds and results. */
 am_status am_load_net(am_ctx *ctx, const am_net_desc *net);
 
-/* Dimensions of the loaded network: N hidden units, M heads, W code words. */
-am_status am_net_dims(const am_ctx *ctx, int32_t *n_hidden, int32_t *n_heads, int32_t *code_words);
+/* Loads S shapes that share one network's weights and differ in their
+ * biases: shape_bias is a HOST array [S][n_1 + ... + n_L + M] (layers in
+ * order), row s replacing the biases of every layer for shape s; the
+ * descriptor's own bias pointers are ignored.  This covers a decoder whose
+ * latent code enters layers linearly (the latent term W_z z_s folds into the
+ * bias of each layer it feeds), e.g. a latent re-injected at an inner layer as
+ * a linear shortcut (Sec. 5.1).  Cells of different shapes are different
+ * cells (the shape id is part of a cell's identity); one march covers all of
+ * them (parallel marching, Sec. 4.2.2).  Same checks as am_load_net. */
+am_status am_load_batch(am_ctx *ctx, const am_net_desc *net, int32_t n_shapes, const double *shape_bias);
+
+/* Dimensions of the loaded network: N hidden units, M heads, W code words,
+ * S shapes (1 after am_load_net).  Any pointer may be NULL. */
+am_status am_net_dims(const am_ctx *ctx, int32_t *n_hidden, int32_t *n_heads, int32_t *code_words,
+                      int32_t *n_shapes);
 
 /* Forward pass: code and F at n points (Eqns (NeuronState)-(MLPState)).
- * DEVICE pointers: pts [n][3] f64 in; codes [n][W] u64, argmax [n] i32,
- * F [n] f64 out (any output may be NULL).  Enqueued; returns before the
- * results are ready (synchronise the stream). */
-am_status am_codes(am_ctx *ctx, const double *pts, int64_t n, uint64_t *codes, int32_t *argmax,
-                   double *F);
+ * DEVICE pointers: pts [n][3] f64 and shape_id [n] i32 (NULL = shape 0) in;
+ * codes [n][W] u64, argmax [n] i32, F [n] f64 out (any output may be NULL;
+ * a shape id out of range gives argmax -1 and F = NaN).  Enqueued; returns
+ * before the results are ready (synchronise the stream). */
+am_status am_codes(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n, uint64_t *codes,
+                   int32_t *argmax, double *F);
 
 /* Affine chain (Lemma 1, Corollary 1): for each of n cells given by its
  * code, the rows Z[g] = (a, b, c, d) with pre_g(x) = a x + b y + c z + d
  * inside the cell, g = 0..N-1 hidden units then N..N+M-1 heads.  DEVICE
- * pointers: codes [n][W] u64 in; rows [n][N+M][4] f64 out.  Enqueued. */
-am_status am_chain(am_ctx *ctx, const uint64_t *codes, int64_t n, double *rows);
+ * pointers: codes [n][W] u64 and shape_id [n] (NULL = shape 0) in;
+ * rows [n][N+M][4] f64 out.  Enqueued. */
+am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, int64_t n, double *rows);
 
 /* Analytic faces of n given cells (Eqn (AnalyticFace) clipped to the box,
  * vertices by Eqn (VertexEquationSystem)), without marching.  DEVICE
- * pointers: codes [n][W], argmax [n] in; m [n] i32 (0 = empty face),
+ * pointers: codes [n][W], argmax [n], shape_id [n] in (argmax and shape_id
+ * may be NULL = 0); m [n] i32 (0 = empty face),
  * ids [n][max_m] i32, verts [n][max_m][3] f64, flags [n] i32 out.
  * max_m must be in 3..64.  Enqueued. */
-am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n,
-                   int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags);
+am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
+                   int64_t n, int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags);
 
 /* Seeds by dichotomy along rays o + t d, t in [0,1] (Sec. 4.3.2): bisect
  * until both bracket ends share one code (at most max_iter halvings, <= 0
  * means 200), then take the linear root inside that cell; the seed cell is
  * the code and argmax at the root.  DEVICE pointers: orig [R][3], dir [R][3]
- * f64.  Rays without a sign change are skipped (counted in status_out, a
- * DEVICE [R] i32 array that may be NULL: 0 ok, 1 no sign change, 2 no
- * convergence).  Replaces any previous seeds; the seed cells are kept in
- * the context for am_march.  Enqueued. */
-am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, int64_t n_rays,
-                       int32_t max_iter, int32_t *status_out);
+ * f64, shape_id [R] i32 (NULL = all shape 0).  Rays without a sign change are
+ * skipped (counted in status_out, a DEVICE [R] i32 array that may be NULL:
+ * 0 ok, 1 no sign change, 2 no convergence, 3 shape id out of range).
+ * Replaces any previous seeds; the seed cells are kept in the context for
+ * am_march.  Enqueued. */
+am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const int32_t *shape_id,
+                       int64_t n_rays, int32_t max_iter, int32_t *status_out);
 
-/* Seeds given directly as cells.  DEVICE pointers: codes [S][W] u64,
- * argmax [S] i32 (NULL = all 0).  Replaces any previous seeds.  Enqueued. */
-am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n);
+/* Seeds given directly as cells.  DEVICE pointers: codes [n][W] u64,
+ * argmax [n] i32 and shape_id [n] i32 (NULL = all 0).  Seeds with an argmax
+ * or shape id out of range are dropped.  Replaces any previous seeds.
+ * Enqueued. */
+am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
+                        int64_t n);
 
 /* Marches from the current seeds (Algorithm 1, all active cells at once)
  * until the active set is empty.  Blocks until done.  opts may be NULL.
@@ -178,10 +198,10 @@ am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, 
  * discovery order:  offsets [F+1] i64 (CSR into the per-edge arrays),
  * ids [V] i32 edge constraint ids, verts [V][3] f64 (vertex i starts edge i),
  * nbr [V] i64 face index across edge i (-1 box edge, -2 neighbour cell has
- * no face), codes [F][W] u64, argmax [F] i32.  Any pointer may be NULL to
- * skip that output.  Enqueued. */
+ * no face), codes [F][W] u64, argmax [F] i32, shape_id [F] i32.  Any pointer
+ * may be NULL to skip that output.  Enqueued. */
 am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
-                   uint64_t *codes, int32_t *argmax);
+                   uint64_t *codes, int32_t *argmax, int32_t *shape_id);
 
 #ifdef __cplusplus
 }

@@ -20,8 +20,8 @@ STATUS_NAMES = {0: "AM_OK", 1: "AM_E_INVALID", 2: "AM_E_OOM", 3: "AM_E_CAPACITY"
                 5: "AM_E_DEGENERATE", 6: "AM_E_HIP", 7: "AM_E_STATE"}
 
 # every symbol include/am.h declares
-EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_net_dims", "am_codes", "am_chain",
-           "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch"]
+EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_batch", "am_net_dims", "am_codes",
+           "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch"]
 
 
 class AmError(RuntimeError):
@@ -73,15 +73,16 @@ def lib(path: str = LIB_PATH):
     L.am_last_error.argtypes = [vp]
     L.am_last_error.restype = C.c_char_p
     L.am_load_net.argtypes = [vp, C.POINTER(NetDesc)]
-    L.am_net_dims.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
-    L.am_codes.argtypes = [vp, vp, i64, vp, vp, vp]
-    L.am_chain.argtypes = [vp, vp, i64, vp]
-    L.am_faces.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, vp]
-    L.am_seed_rays.argtypes = [vp, vp, vp, i64, i32, vp]
-    L.am_seed_cells.argtypes = [vp, vp, vp, i64]
+    L.am_load_batch.argtypes = [vp, C.POINTER(NetDesc), i32, vp]
+    L.am_net_dims.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.am_codes.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.am_chain.argtypes = [vp, vp, vp, i64, vp]
+    L.am_faces.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
+    L.am_seed_rays.argtypes = [vp, vp, vp, vp, i64, i32, vp]
+    L.am_seed_cells.argtypes = [vp, vp, vp, vp, i64]
     L.am_march.argtypes = [vp, C.POINTER(MarchOpts), C.POINTER(MarchStats)]
     L.am_get_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
-    L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("am_destroy", "am_last_error"):
             getattr(L, name).restype = C.c_int
@@ -110,7 +111,7 @@ class Context:
         if st != AM_OK:
             raise AmError(st, "am_create failed")
         self.h = h
-        self.N = self.M = self.W = None
+        self.N = self.M = self.W = self.S = None
 
     def close(self):
         if getattr(self, "h", None):
@@ -128,8 +129,12 @@ class Context:
             raise AmError(st, self.L.am_last_error(self.h).decode())
 
     # ------------------------------------------------------------------ net
-    def load_net(self, net):
-        """Loads a network given as (widths, blocks [(dst, src, W)], bias [per layer >= 1])."""
+    def load_net(self, net, shape_bias=None):
+        """Loads a network given as (widths, blocks [(dst, src, W)], bias [per layer >= 1]).
+
+        With ``shape_bias`` ([S, sum of widths of layers >= 1]), loads S shapes
+        that share the weights and use row s as their biases (am_load_batch).
+        """
         widths = np.asarray(net.widths, np.int32)
         dst = np.asarray([d for d, _, _ in net.blocks], np.int32)
         src = np.asarray([s for _, s, _ in net.blocks], np.int32)
@@ -141,10 +146,14 @@ class Context:
         desc = NetDesc(len(widths), widths.ctypes.data_as(C.POINTER(C.c_int32)), len(ws),
                        dst.ctypes.data_as(C.POINTER(C.c_int32)), src.ctypes.data_as(C.POINTER(C.c_int32)),
                        wp, bp)
-        self._check(self.L.am_load_net(self.h, C.byref(desc)))
-        n, m, w = C.c_int32(), C.c_int32(), C.c_int32()
-        self._check(self.L.am_net_dims(self.h, C.byref(n), C.byref(m), C.byref(w)))
-        self.N, self.M, self.W = n.value, m.value, w.value
+        if shape_bias is None:
+            self._check(self.L.am_load_net(self.h, C.byref(desc)))
+        else:
+            sb = np.ascontiguousarray(shape_bias, np.float64)
+            self._check(self.L.am_load_batch(self.h, C.byref(desc), int(sb.shape[0]), C.c_void_p(sb.ctypes.data)))
+        n, m, w, sh = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.L.am_net_dims(self.h, C.byref(n), C.byref(m), C.byref(w), C.byref(sh)))
+        self.N, self.M, self.W, self.S = n.value, m.value, w.value, sh.value
         return self
 
     # ------------------------------------------------------------ per point
@@ -154,52 +163,61 @@ class Context:
             return a.to(device=self.device, dtype=dtype).contiguous()
         return t.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=self.device)
 
-    def codes(self, pts):
+    def _shape(self, shape_id):
+        return None if shape_id is None else self._dev(shape_id, self.torch.int32)
+
+    def codes(self, pts, shape_id=None):
         t = self.torch
         pts = self._dev(pts, t.float64).reshape(-1, 3)
         n = pts.shape[0]
+        sh = self._shape(shape_id)
         codes = t.empty((n, self.W), dtype=t.int64, device=self.device)
         am = t.empty(n, dtype=t.int32, device=self.device)
         F = t.empty(n, dtype=t.float64, device=self.device)
-        self._check(self.L.am_codes(self.h, _p(pts), n, _p(codes), _p(am), _p(F)))
+        self._check(self.L.am_codes(self.h, _p(pts), _p(sh), n, _p(codes), _p(am), _p(F)))
         return codes, am, F
 
-    def chain(self, codes):
+    def chain(self, codes, shape_id=None):
         t = self.torch
         codes = self._dev(codes, t.int64).reshape(-1, self.W)
         n = codes.shape[0]
+        sh = self._shape(shape_id)
         rows = t.empty((n, self.N + self.M, 4), dtype=t.float64, device=self.device)
-        self._check(self.L.am_chain(self.h, _p(codes), n, _p(rows)))
+        self._check(self.L.am_chain(self.h, _p(codes), _p(sh), n, _p(rows)))
         return rows
 
-    def faces(self, codes, argmax=None, max_m=32):
+    def faces(self, codes, argmax=None, max_m=32, shape_id=None):
         t = self.torch
         codes = self._dev(codes, t.int64).reshape(-1, self.W)
         n = codes.shape[0]
         am = None if argmax is None else self._dev(argmax, t.int32)
+        sh = self._shape(shape_id)
         m = t.empty(n, dtype=t.int32, device=self.device)
         ids = t.empty((n, max_m), dtype=t.int32, device=self.device)
         verts = t.empty((n, max_m, 3), dtype=t.float64, device=self.device)
         flags = t.empty(n, dtype=t.int32, device=self.device)
-        self._check(self.L.am_faces(self.h, _p(codes), _p(am), n, int(max_m), _p(m), _p(ids), _p(verts),
+        self._check(self.L.am_faces(self.h, _p(codes), _p(am), _p(sh), n, int(max_m), _p(m), _p(ids), _p(verts),
                                     _p(flags)))
         return m, ids, verts, flags
 
     # --------------------------------------------------------------- march
-    def seed_rays(self, orig, dirs, max_iter=200):
+    def seed_rays(self, orig, dirs, max_iter=200, shape_id=None):
         t = self.torch
         o = self._dev(orig, t.float64).reshape(-1, 3)
         d = self._dev(dirs, t.float64).reshape(-1, 3)
+        sh = self._shape(shape_id)
         status = t.empty(o.shape[0], dtype=t.int32, device=self.device)
-        self._check(self.L.am_seed_rays(self.h, _p(o), _p(d), o.shape[0], int(max_iter), _p(status)))
+        self._seed_keep = (o, d, sh)        # the kernel reads them on the stream
+        self._check(self.L.am_seed_rays(self.h, _p(o), _p(d), _p(sh), o.shape[0], int(max_iter), _p(status)))
         return status
 
-    def seed_cells(self, codes, argmax=None):
+    def seed_cells(self, codes, argmax=None, shape_id=None):
         t = self.torch
         codes = self._dev(codes, t.int64).reshape(-1, self.W)
         am = None if argmax is None else self._dev(argmax, t.int32)
-        self._seed_keep = (codes, am)       # the copy is enqueued on the stream
-        self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), codes.shape[0]))
+        sh = self._shape(shape_id)
+        self._seed_keep = (codes, am, sh)   # the copy is enqueued on the stream
+        self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), _p(sh), codes.shape[0]))
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0):
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
@@ -224,9 +242,10 @@ class Context:
         dev = self.device
         out = dict(offsets=t.empty(F + 1, dtype=t.int64, device=dev), ids=t.empty(V, dtype=t.int32, device=dev),
                    verts=t.empty((V, 3), dtype=t.float64, device=dev), nbr=t.empty(V, dtype=t.int64, device=dev),
-                   codes=t.empty((F, self.W), dtype=t.int64, device=dev), argmax=t.empty(F, dtype=t.int32, device=dev))
+                   codes=t.empty((F, self.W), dtype=t.int64, device=dev), argmax=t.empty(F, dtype=t.int32, device=dev),
+                   shape=t.empty(F, dtype=t.int32, device=dev))
         self._check(self.L.am_fetch(self.h, _p(out["offsets"]), _p(out["ids"]), _p(out["verts"]), _p(out["nbr"]),
-                                    _p(out["codes"]), _p(out["argmax"])))
+                                    _p(out["codes"]), _p(out["argmax"]), _p(out["shape"])))
         return out
 
 

@@ -22,29 +22,29 @@ namespace am {
 void launch_clip(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long, long long,
                  long long, const double *, const ClipOut &, const Candidates &, unsigned long long, Counters *,
                  hipStream_t);
-void launch_chain(const DevNet &, const uint64_t *, long long, long long, double *, hipStream_t);
-void launch_fused(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long, long long,
-                  long long, const ClipOut &, const Candidates &, unsigned long long, Counters *, hipStream_t);
+void launch_chain(const DevNet &, const uint64_t *, const int *, long long, long long, double *, hipStream_t);
+void launch_fused(const DevNet &, const uint64_t *, const int *, const int *, const uint64_t *, const int *, long long,
+                  long long, long long, const ClipOut &, const Candidates &, unsigned long long, Counters *,
+                  hipStream_t);
 size_t fused_lds_bytes(const DevNet &);
 hipError_t prepare_fused(size_t);
 void launch_rows_unpad(const DevNet &, long long, const double *, double *, hipStream_t);
-void launch_insert(const DevNet &, const Candidates &, const uint64_t *, const int *, const uint64_t *,
-                   const int *, unsigned long long *, unsigned long long, Counters *, unsigned long long,
-                   long long, hipStream_t);
-void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, uint64_t *, int *, int *,
-                   const uint64_t *, const int *, unsigned long long *, Counters *, unsigned long long,
+void launch_insert(const DevNet &, const Candidates &, const CellArrays &, unsigned long long *, unsigned long long,
+                   Counters *, unsigned long long, long long, hipStream_t);
+void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, int *, uint64_t *, int *, int *,
+                   const uint64_t *, const int *, const int *, unsigned long long *, Counters *, unsigned long long,
                    unsigned long long, long long, hipStream_t);
 void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t);
-void launch_codes(const DevNet &, const double *, long long, uint64_t *, int *, double *, hipStream_t);
-void launch_seed_rays(const DevNet &, const double *, const double *, long long, int, uint64_t *, int *, int *,
-                      hipStream_t);
-void launch_seed_cands(const DevNet &, const uint64_t *, const int *, const int *, long long,
+void launch_codes(const DevNet &, const double *, const int *, long long, uint64_t *, int *, double *, hipStream_t);
+void launch_seed_rays(const DevNet &, const double *, const double *, const int *, long long, int, uint64_t *, int *,
+                      int *, int *, hipStream_t);
+void launch_seed_cands(const DevNet &, const uint64_t *, const int *, const int *, const int *, long long,
                        const Candidates &, Counters *, unsigned long long, hipStream_t);
 hipError_t scan_tmp_bytes(long long, size_t *);
 hipError_t launch_fetch(const DevNet &, long long, const int *, const int *, const double *, const int *,
-                        const uint64_t *, const int *, int, int *, int *, long long *, long long *, void *,
-                        size_t, long long, long long *, int *, double *, long long *, uint64_t *, int *,
-                        hipStream_t);
+                        const uint64_t *, const int *, const int *, int, int *, int *, long long *, long long *,
+                        void *, size_t, long long, long long *, int *, double *, long long *, uint64_t *, int *,
+                        int *, hipStream_t);
 }  // namespace am
 
 using namespace am;
@@ -70,6 +70,7 @@ struct am_ctx {
     uint64_t *d_seed_codes = nullptr;
     int *d_seed_am = nullptr;
     int *d_seed_status = nullptr;
+    int *d_seed_shape = nullptr;
     long long n_seeds = 0;
     long long seed_cap = 0;
     bool seeds_have_status = false;
@@ -78,6 +79,7 @@ struct am_ctx {
     long long cap_cells = 0;
     uint64_t *d_codes = nullptr;
     int *d_am = nullptr;
+    int *d_shape = nullptr;
     uint64_t *d_hash = nullptr;
     int *d_hints = nullptr;     // [cap][3] lines to clip first (entry edge and its neighbours)
     int *d_fm = nullptr;
@@ -165,6 +167,7 @@ uint64_t splitmix64(uint64_t &s) {
 void free_march(am_ctx *c) {
     dfree(c->d_codes);
     dfree(c->d_am);
+    dfree(c->d_shape);
     dfree(c->d_hash);
     dfree(c->d_hints);
     dfree(c->d_fm);
@@ -205,6 +208,7 @@ void free_net(am_ctx *c) {
     dfree(c->d_seed_codes);
     dfree(c->d_seed_am);
     dfree(c->d_seed_status);
+    dfree(c->d_seed_shape);
     c->n_seeds = c->seed_cap = 0;
     c->loaded = false;
 }
@@ -221,6 +225,7 @@ am_status ensure_march(am_ctx *ctx, long long cells) {
     const DevNet &n = ctx->dn;
     TRY(dalloc(ctx, ctx->d_codes, (size_t)cells * n.W));
     TRY(dalloc(ctx, ctx->d_am, cells));
+    TRY(dalloc(ctx, ctx->d_shape, cells));
     TRY(dalloc(ctx, ctx->d_hash, cells));
     TRY(dalloc(ctx, ctx->d_hints, (size_t)cells * 3));
     TRY(dalloc(ctx, ctx->d_fm, cells));
@@ -315,7 +320,17 @@ void am_destroy(am_ctx *ctx) {
 
 const char *am_last_error(const am_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
+static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, const double *shape_bias);
+
+am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) { return load_impl(ctx, nd, 1, nullptr); }
+
+am_status am_load_batch(am_ctx *ctx, const am_net_desc *nd, int32_t n_shapes, const double *shape_bias) {
+    if (!ctx) return AM_E_INVALID;
+    if (n_shapes < 1 || !shape_bias) return fail(ctx, AM_E_INVALID, "need n_shapes >= 1 and a bias table");
+    return load_impl(ctx, nd, n_shapes, shape_bias);
+}
+
+static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, const double *shape_bias) {
     if (!ctx) return AM_E_INVALID;
     if (!nd || !nd->width || nd->n_layers < 2 || nd->n_layers > kMaxLayers || nd->n_blocks < 1 ||
         nd->n_blocks > kMaxBlocks || !nd->blk_dst || !nd->blk_src || !nd->blk_w || !nd->bias)
@@ -343,7 +358,7 @@ am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
     }
     for (int l = 1; l < L2; ++l) {
         if (!has_input[l]) return fail(ctx, AM_E_INVALID, "layer %d has no input block", l);
-        if (!nd->bias[l]) return fail(ctx, AM_E_INVALID, "layer %d has no bias", l);
+        if (!shape_bias && !nd->bias[l]) return fail(ctx, AM_E_INVALID, "layer %d has no bias", l);
     }
 
     free_march(ctx);
@@ -396,17 +411,21 @@ am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
             for (int ks = 0; ks < ld / 4; ++ks)
                 for (int l = 0; l < 64; ++l) hf.push_back(Wp[(size_t)(mt * 16 + l % 16) * ld + ks * 4 + l / 16]);
     }
-    std::vector<double> hb(boff);
-    for (int l = 1; l < L2; ++l)
-        for (int k = 0; k < nd->width[l]; ++k) {
-            const double v = nd->bias[l][k];
-            if (!std::isfinite(v)) return fail(ctx, AM_E_INVALID, "bias of layer %d is not finite", l);
-            hb[dn.bias_off[l] + k] = v;
-        }
+    // bias table [S][boff]: the net's own biases, or one row per shape
+    std::vector<double> hb((size_t)n_shapes * boff);
+    for (int sh = 0; sh < n_shapes; ++sh)
+        for (int l = 1; l < L2; ++l)
+            for (int k = 0; k < nd->width[l]; ++k) {
+                const double v = shape_bias ? shape_bias[(size_t)sh * boff + dn.bias_off[l] + k] : nd->bias[l][k];
+                if (!std::isfinite(v)) return fail(ctx, AM_E_INVALID, "bias of shape %d layer %d is not finite", sh, l);
+                hb[(size_t)sh * boff + dn.bias_off[l] + k] = v;
+            }
+    dn.S = n_shapes;
+    dn.bias_stride = boff;
     std::vector<int> rou(N + M);
     for (int l = 1; l < L2; ++l)
         for (int k = 0; k < nd->width[l]; ++k) rou[dn.unit_off[l] + k] = dn.row_off[l] + k;
-    std::vector<uint64_t> zob(N + M);
+    std::vector<uint64_t> zob(N + M + n_shapes);
     uint64_t sm = 0x5eed0fa11c0de5ull;
     for (auto &z : zob) z = splitmix64(sm);
 
@@ -434,25 +453,28 @@ am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) {
     return AM_OK;
 }
 
-am_status am_net_dims(const am_ctx *ctx, int32_t *n_hidden, int32_t *n_heads, int32_t *code_words) {
+am_status am_net_dims(const am_ctx *ctx, int32_t *n_hidden, int32_t *n_heads, int32_t *code_words,
+                      int32_t *n_shapes) {
     if (!ctx || !ctx->loaded) return AM_E_STATE;
+    if (n_shapes) *n_shapes = ctx->dn.S;
     if (n_hidden) *n_hidden = ctx->dn.N;
     if (n_heads) *n_heads = ctx->dn.M;
     if (code_words) *code_words = ctx->dn.W;
     return AM_OK;
 }
 
-am_status am_codes(am_ctx *ctx, const double *pts, int64_t n, uint64_t *codes, int32_t *argmax, double *F) {
+am_status am_codes(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n, uint64_t *codes,
+                   int32_t *argmax, double *F) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n < 0 || (n > 0 && !pts)) return fail(ctx, AM_E_INVALID, "bad points");
     TRY(set_device(ctx));
-    launch_codes(ctx->dn, pts, n, codes, argmax, F, ctx->stream);
+    launch_codes(ctx->dn, pts, shape_id, n, codes, argmax, F, ctx->stream);
     HIPCHK(hipGetLastError());
     return AM_OK;
 }
 
-am_status am_chain(am_ctx *ctx, const uint64_t *codes, int64_t n, double *rows) {
+am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, int64_t n, double *rows) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n < 0 || (n > 0 && (!codes || !rows))) return fail(ctx, AM_E_INVALID, "bad arguments");
@@ -460,15 +482,15 @@ am_status am_chain(am_ctx *ctx, const uint64_t *codes, int64_t n, double *rows) 
     TRY(ensure_march(ctx, std::max<long long>(ctx->cap_cells, 1024)));
     for (long long lo = 0; lo < n; lo += ctx->chunk_cells) {
         const long long hi = std::min<long long>(n, lo + ctx->chunk_cells);
-        launch_chain(ctx->dn, codes, lo, hi, ctx->d_rows, ctx->stream);
+        launch_chain(ctx->dn, codes, shape_id, lo, hi, ctx->d_rows, ctx->stream);
         launch_rows_unpad(ctx->dn, hi - lo, ctx->d_rows, rows + lo * 4 * (ctx->dn.N + ctx->dn.M), ctx->stream);
     }
     HIPCHK(hipGetLastError());
     return AM_OK;
 }
 
-am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n, int32_t max_m,
-                   int32_t *m, int32_t *ids, double *verts, int32_t *flags) {
+am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id, int64_t n,
+                   int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n < 0 || max_m < 3 || max_m > kMaxPoly || (n > 0 && (!codes || !m || !ids || !verts)))
@@ -477,7 +499,7 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, in
     TRY(ensure_march(ctx, std::max<long long>(ctx->cap_cells, 1024)));
     for (long long lo = 0; lo < n; lo += ctx->chunk_cells) {
         const long long hi = std::min<long long>(n, lo + ctx->chunk_cells);
-        launch_chain(ctx->dn, codes, lo, hi, ctx->d_rows, ctx->stream);
+        launch_chain(ctx->dn, codes, shape_id, lo, hi, ctx->d_rows, ctx->stream);
         ClipOut out{};
         out.m = m;
         out.ids = ids;
@@ -499,19 +521,20 @@ static am_status ensure_seed_cap(am_ctx *ctx, long long n) {
     TRY(dalloc(ctx, ctx->d_seed_codes, (size_t)n * ctx->dn.W));
     TRY(dalloc(ctx, ctx->d_seed_am, n));
     TRY(dalloc(ctx, ctx->d_seed_status, n));
+    TRY(dalloc(ctx, ctx->d_seed_shape, n));
     ctx->seed_cap = n;
     return AM_OK;
 }
 
-am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, int64_t n_rays, int32_t max_iter,
-                       int32_t *status_out) {
+am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const int32_t *shape_id, int64_t n_rays,
+                       int32_t max_iter, int32_t *status_out) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n_rays <= 0 || !orig || !dir) return fail(ctx, AM_E_INVALID, "need at least one ray");
     TRY(set_device(ctx));
     TRY(ensure_seed_cap(ctx, n_rays));
-    launch_seed_rays(ctx->dn, orig, dir, n_rays, max_iter > 0 ? max_iter : 200, ctx->d_seed_codes,
-                     ctx->d_seed_am, ctx->d_seed_status, ctx->stream);
+    launch_seed_rays(ctx->dn, orig, dir, shape_id, n_rays, max_iter > 0 ? max_iter : 200, ctx->d_seed_codes,
+                     ctx->d_seed_am, ctx->d_seed_shape, ctx->d_seed_status, ctx->stream);
     if (status_out)
         HIPCHK(hipMemcpyAsync(status_out, ctx->d_seed_status, sizeof(int) * n_rays, hipMemcpyDeviceToDevice,
                               ctx->stream));
@@ -522,7 +545,8 @@ am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, int64
     return AM_OK;
 }
 
-am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, int64_t n) {
+am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
+                        int64_t n) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n <= 0 || !codes) return fail(ctx, AM_E_INVALID, "need at least one seed cell");
@@ -534,6 +558,10 @@ am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argma
         HIPCHK(hipMemcpyAsync(ctx->d_seed_am, argmax, sizeof(int) * n, hipMemcpyDeviceToDevice, ctx->stream));
     else
         HIPCHK(hipMemsetAsync(ctx->d_seed_am, 0, sizeof(int) * n, ctx->stream));
+    if (shape_id)
+        HIPCHK(hipMemcpyAsync(ctx->d_seed_shape, shape_id, sizeof(int) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    else
+        HIPCHK(hipMemsetAsync(ctx->d_seed_shape, 0, sizeof(int) * n, ctx->stream));
     ctx->n_seeds = n;
     ctx->seeds_have_status = false;
     ctx->have_result = false;
@@ -572,12 +600,14 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     const unsigned long long hmask = ctx->hcap - 1;
 
     // seeds -> cells 0..S-1 (deduplicated)
-    launch_seed_cands(net, ctx->d_seed_codes, ctx->d_seed_am, ctx->seeds_have_status ? ctx->d_seed_status : nullptr,
-                      ctx->n_seeds, ctx->cand, ctx->d_ctr, ctx->cand_cap, s);
-    launch_insert(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots, hmask,
-                  ctx->d_ctr, ctx->cand_cap, ctx->n_seeds, s);
-    launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_fm, ctx->d_seed_codes,
-                  ctx->d_seed_am, ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, ctx->n_seeds, s);
+    const CellArrays ca{ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape};
+    launch_seed_cands(net, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape,
+                      ctx->seeds_have_status ? ctx->d_seed_status : nullptr, ctx->n_seeds, ctx->cand, ctx->d_ctr,
+                      ctx->cand_cap, s);
+    launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, ctx->n_seeds, s);
+    launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints, ctx->d_fm,
+                  ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
+                  (unsigned long long)cap, ctx->n_seeds, s);
     HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
@@ -611,21 +641,20 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         const bool tk = o.time_kernels != 0;
         if (tk) HIPCHK(hipEventRecord(ctx->evk[0], s));
         if (fused) {
-            launch_fused(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells, out,
-                         ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
+            launch_fused(net, ctx->d_codes, ctx->d_shape, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells,
+                         out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
         } else {
-            launch_chain(net, ctx->d_codes, lo, lo + n, ctx->d_rows, s);
+            launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, ctx->d_rows, s);
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
             launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells, ctx->d_rows,
                         out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
         }
         if (tk) HIPCHK(hipEventRecord(ctx->evk[2], s));
         const long long nh = n * 6;
-        launch_insert(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots,
-                      hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
-        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_fm,
-                      ctx->d_seed_codes, ctx->d_seed_am, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
+        launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
+        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints, ctx->d_fm,
+                      ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
                       (unsigned long long)cap, nh, s);
         launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
         if (tk) HIPCHK(hipEventRecord(ctx->evk[3], s));
@@ -671,8 +700,9 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     // faces and empty seeds: count through the fetch scan
     TRY(ensure_scan(ctx, std::max<long long>(st.cells, 1)));
     HIPCHK(launch_fetch(net, st.cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
-                        ctx->d_am, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff, ctx->d_scan,
-                        ctx->scan_bytes, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+                        ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
+                        ctx->d_scan, ctx->scan_bytes, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, s));
     int last_idx = 0, last_has = 0;
     HIPCHK(hipMemcpyAsync(&last_idx, ctx->d_fidx + st.cells - 1, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&last_has, ctx->d_has + st.cells - 1, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -705,15 +735,15 @@ am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, 
 }
 
 am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr, uint64_t *codes,
-                   int32_t *argmax) {
+                   int32_t *argmax, int32_t *shape_id) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->have_result) return fail(ctx, AM_E_STATE, "no march result");
     TRY(set_device(ctx));
     TRY(ensure_scan(ctx, std::max<long long>(ctx->res_cells, 1)));
     HIPCHK(launch_fetch(ctx->dn, ctx->res_cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
-                        ctx->d_am, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff, ctx->d_scan,
-                        ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts, (long long *)nbr, codes,
-                        argmax, ctx->stream));
+                        ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
+                        ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
+                        (long long *)nbr, codes, argmax, shape_id, ctx->stream));
     return AM_OK;
 }
 

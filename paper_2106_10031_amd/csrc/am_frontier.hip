@@ -34,15 +34,18 @@ struct CodeRef {
     const uint64_t *base;
     int flip;     // unit to flip, -1 = none
     int am;
+    int shape;
 };
 
 __device__ __forceinline__ CodeRef cand_code(const DevNet &net, const Candidates &cand, long long t,
-                                             const uint64_t *codes, const int *argmax,
-                                             const uint64_t *seed_codes, const int *seed_am) {
+                                             const CellArrays &ca) {
     CodeRef r;
     const int p = cand.parent[t];
+    const uint64_t *codes = ca.codes;
+    const int *argmax = ca.argmax;
     if (p >= 0) {
         const int u = cand.unit[t];
+        r.shape = ca.shape[p];
         r.base = codes + (long long)p * net.W;
         if (u < net.N) {
             r.flip = u;
@@ -53,9 +56,10 @@ __device__ __forceinline__ CodeRef cand_code(const DevNet &net, const Candidates
         }
     } else {
         const long long s = -1LL - p;
-        r.base = seed_codes + s * net.W;
+        r.base = ca.seed_codes + s * net.W;
         r.flip = -1;
-        r.am = seed_am[s];
+        r.am = ca.seed_am[s];
+        r.shape = ca.seed_shape ? ca.seed_shape[s] : 0;
     }
     return r;
 }
@@ -67,7 +71,7 @@ __device__ __forceinline__ uint64_t code_word(const CodeRef &r, int w) {
 }
 
 __device__ __forceinline__ bool code_eq(int W, const CodeRef &a, const CodeRef &b) {
-    if (a.am != b.am) return false;
+    if (a.am != b.am || a.shape != b.shape) return false;
     for (int w = 0; w < W; ++w)
         if (code_word(a, w) != code_word(b, w)) return false;
     return true;
@@ -75,9 +79,7 @@ __device__ __forceinline__ bool code_eq(int W, const CodeRef &a, const CodeRef &
 
 // ------------------------------------------------------------------ insert
 
-__global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, const uint64_t *codes,
-                                                const int *argmax, const uint64_t *seed_codes,
-                                                const int *seed_am, unsigned long long *slots,
+__global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, CellArrays ca, unsigned long long *slots,
                                                 unsigned long long hmask, Counters *ctr,
                                                 unsigned long long cand_cap) {
     const unsigned long long n = min(ctr->n_cand, cand_cap);
@@ -85,7 +87,7 @@ __global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, con
          t += (unsigned long long)gridDim.x * blockDim.x) {
         const uint64_t h = cand.hash[t];
         const unsigned long long tag = slot_tag(h);
-        const CodeRef me = cand_code(net, cand, (long long)t, codes, argmax, seed_codes, seed_am);
+        const CodeRef me = cand_code(net, cand, (long long)t, ca);
         unsigned long long pos = h & hmask;
         int kind = kLost;
         long long ref = -1;
@@ -104,11 +106,12 @@ __global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, con
                 const long long other = (long long)(s & 0xffffffffull);
                 CodeRef o;
                 if (s & kPending) {
-                    o = cand_code(net, cand, other, codes, argmax, seed_codes, seed_am);
+                    o = cand_code(net, cand, other, ca);
                 } else {
-                    o.base = codes + other * net.W;
+                    o.base = ca.codes + other * net.W;
                     o.flip = -1;
-                    o.am = argmax[other];
+                    o.am = ca.argmax[other];
+                    o.shape = ca.shape[other];
                 }
                 if (code_eq(net.W, me, o)) {
                     kind = (s & kPending) ? kDup : kFound;
@@ -127,9 +130,9 @@ __global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, con
 // ------------------------------------------------------------------ commit
 
 __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uint64_t *codes, int *argmax,
-                                                uint64_t *cell_hash, int *hints, int *face_m,
+                                                int *shape, uint64_t *cell_hash, int *hints, int *face_m,
                                                 const uint64_t *seed_codes, const int *seed_am,
-                                                unsigned long long *slots, Counters *ctr,
+                                                const int *seed_shape, unsigned long long *slots, Counters *ctr,
                                                 unsigned long long cand_cap, unsigned long long cap_cells) {
     const unsigned long long n = min(ctr->n_cand, cand_cap);
     const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
@@ -146,10 +149,12 @@ __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uin
             cand.cell[t] = -1;
             continue;
         }
-        const CodeRef me = cand_code(net, cand, (long long)t, codes, argmax, seed_codes, seed_am);
+        const CellArrays ca{codes, argmax, shape, seed_codes, seed_am, seed_shape};
+        const CodeRef me = cand_code(net, cand, (long long)t, ca);
         uint64_t *dst = codes + (long long)id * net.W;
         for (int w = 0; w < net.W; ++w) dst[w] = code_word(me, w);
         argmax[id] = me.am;
+        shape[id] = me.shape;
         const uint64_t h = cand.hash[t];
         cell_hash[id] = h;
         const int p = cand.parent[t];
@@ -192,7 +197,9 @@ __global__ __launch_bounds__(256) void k_resolve(Candidates cand, int *face_nbr,
 // Forward pass of one point by a workgroup (Sec. 2.2).  act: LDS of
 // 3 + N + M doubles; code: LDS of W words.  Returns F = max over heads and
 // the argmax (lowest index on ties) to every thread.
-__device__ double wg_forward(const DevNet &net, const double x[3], double *act, uint64_t *code, int *am_out) {
+__device__ double wg_forward(const DevNet &net, int shape, const double x[3], double *act, uint64_t *code,
+                             int *am_out) {
+    const double *bias = net.bias + (long long)shape * net.bias_stride;
     const int tid = threadIdx.x, nt = blockDim.x;
     if (tid < 3) act[tid] = x[tid];
     for (int w = tid; w < net.W; w += nt) code[w] = 0;
@@ -202,7 +209,7 @@ __device__ double wg_forward(const DevNet &net, const double x[3], double *act, 
         const int nl = net.width[l];
         const int aoff = 3 + net.unit_off[l];
         for (int k = tid; k < nl; k += nt) {
-            double acc = net.bias[net.bias_off[l] + k];
+            double acc = bias[net.bias_off[l] + k];
             for (int b = 0; b < net.n_blocks; ++b) {
                 if (net.blk_dst[b] != l) continue;
                 const int j = net.blk_src[b];
@@ -233,20 +240,22 @@ __device__ double wg_forward(const DevNet &net, const double x[3], double *act, 
     return F;
 }
 
-__global__ __launch_bounds__(256) void k_codes(DevNet net, const double *pts, long long n, uint64_t *codes,
-                                               int *argmax, double *Fout) {
+__global__ __launch_bounds__(256) void k_codes(DevNet net, const double *pts, const int *shape_id, long long n,
+                                               uint64_t *codes, int *argmax, double *Fout) {
     extern __shared__ double lds[];
     double *act = lds;
     uint64_t *code = (uint64_t *)(lds + 3 + net.N + net.M);
     for (long long p = blockIdx.x; p < n; p += gridDim.x) {
         double x[3] = {pts[p * 3], pts[p * 3 + 1], pts[p * 3 + 2]};
         int am;
-        const double F = wg_forward(net, x, act, code, &am);
+        const int sh_in = shape_id ? shape_id[p] : 0;
+        const bool sh_ok = sh_in >= 0 && sh_in < net.S;   // a bad id reports argmax -1, F = NaN
+        const double F = wg_forward(net, sh_ok ? sh_in : 0, x, act, code, &am);
         if (codes)
             for (int w = threadIdx.x; w < net.W; w += blockDim.x) codes[p * net.W + w] = code[w];
         if (threadIdx.x == 0) {
-            if (argmax) argmax[p] = am;
-            if (Fout) Fout[p] = F;
+            if (argmax) argmax[p] = sh_ok ? am : -1;
+            if (Fout) Fout[p] = sh_ok ? F : __builtin_nan("");
         }
         __syncthreads();
     }
@@ -255,8 +264,9 @@ __global__ __launch_bounds__(256) void k_codes(DevNet net, const double *pts, lo
 // Dichotomy along o + t d, t in [0, 1]: keep a bracket with a sign change,
 // halve it until both ends share one code, then take the linear root.
 __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *orig, const double *dir,
-                                                   long long n_rays, int max_iter, uint64_t *seed_codes,
-                                                   int *seed_am, int *status) {
+                                                   const int *shape_id, long long n_rays, int max_iter,
+                                                   uint64_t *seed_codes, int *seed_am, int *seed_shape,
+                                                   int *status) {
     extern __shared__ double lds[];
     double *act = lds;
     uint64_t *c_lo = (uint64_t *)(lds + 3 + net.N + net.M);
@@ -268,15 +278,21 @@ __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *ori
         const double d[3] = {dir[r * 3], dir[r * 3 + 1], dir[r * 3 + 2]};
         int a_lo, a_hi, a_m;
         double x[3];
-        double f_lo = wg_forward(net, o, act, c_m, &a_lo);
+        const int sh_in = shape_id ? shape_id[r] : 0;
+        const bool sh_ok = sh_in >= 0 && sh_in < net.S;
+        const int sh = sh_ok ? sh_in : 0;
+        if (threadIdx.x == 0) seed_shape[r] = sh;
+        double f_lo = wg_forward(net, sh, o, act, c_m, &a_lo);
         for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_lo[w] = c_m[w];
         for (int i = 0; i < 3; ++i) x[i] = o[i] + d[i];
-        double f_hi = wg_forward(net, x, act, c_m, &a_hi);
+        double f_hi = wg_forward(net, sh, x, act, c_m, &a_hi);
         for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_hi[w] = c_m[w];
         __syncthreads();
         int st = 0;
         double t_lo = 0.0, t_hi = 1.0;
-        if ((f_lo > 0.0) == (f_hi > 0.0)) {
+        if (!sh_ok) {
+            st = 3;   // shape id out of range
+        } else if ((f_lo > 0.0) == (f_hi > 0.0)) {
             st = 1;
         } else {
             for (int it = 0;; ++it) {
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *ori
                 }
                 const double tm = 0.5 * (t_lo + t_hi);
                 for (int i = 0; i < 3; ++i) x[i] = o[i] + tm * d[i];
-                const double fm = wg_forward(net, x, act, c_m, &a_m);
+                const double fm = wg_forward(net, sh, x, act, c_m, &a_m);
                 if ((fm > 0.0) == (f_lo > 0.0)) {
                     t_lo = tm;
                     f_lo = fm;
@@ -312,7 +328,7 @@ __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *ori
         if (st == 0) {
             const double ts = t_lo - f_lo * (t_hi - t_lo) / (f_hi - f_lo);
             for (int i = 0; i < 3; ++i) x[i] = o[i] + ts * d[i];
-            wg_forward(net, x, act, c_m, &a_m);
+            wg_forward(net, sh, x, act, c_m, &a_m);
             for (int w = threadIdx.x; w < net.W; w += blockDim.x) seed_codes[r * net.W + w] = c_m[w];
             if (threadIdx.x == 0) seed_am[r] = a_m;
         } else {
@@ -326,12 +342,14 @@ __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *ori
 
 // Seeds with status 0 become candidates (parent = -(1 + seed index)).
 __global__ __launch_bounds__(256) void k_seed_cands(DevNet net, const uint64_t *seed_codes, const int *seed_am,
-                                                    const int *seed_ok, long long n, Candidates cand,
+                                                    const int *seed_shape, const int *seed_ok, long long n,
+                                                    Candidates cand,
                                                     Counters *ctr, unsigned long long cand_cap) {
     const long long n_round = (n + 63) & ~63LL;
     for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < n_round;
          s += (long long)gridDim.x * blockDim.x) {
-        const bool ok = s < n && (!seed_ok || seed_ok[s] == 0) && seed_am[s] >= 0 && seed_am[s] < net.M;
+        const bool ok = s < n && (!seed_ok || seed_ok[s] == 0) && seed_am[s] >= 0 && seed_am[s] < net.M &&
+                        seed_shape[s] >= 0 && seed_shape[s] < net.S;
         unsigned long long base;
         const unsigned long long idx = wave_reserve(&ctr->n_cand, ok, &base);
         if (!ok) continue;
@@ -339,7 +357,7 @@ __global__ __launch_bounds__(256) void k_seed_cands(DevNet net, const uint64_t *
             atomicAdd(&ctr->overflow_cand, 1ull);
             continue;
         }
-        uint64_t h = net.zobrist[net.N + seed_am[s]];
+        uint64_t h = net.zobrist[net.N + seed_am[s]] ^ net.zobrist[net.N + net.M + seed_shape[s]];
         for (int w = 0; w < net.W; ++w) {
             uint64_t x = seed_codes[s * net.W + w];
             while (x) {
@@ -369,8 +387,8 @@ __global__ void k_face_flags(const int *face_m, long long n, int *has, long long
 
 __global__ void k_fetch(const DevNet net, long long n, const int *face_m, const int *fidx, const long long *voff,
                         const int *ids, const double *verts, const int *nbr, const uint64_t *codes,
-                        const int *argmax, int stride, long long *o_off, int *o_ids, double *o_verts,
-                        long long *o_nbr, uint64_t *o_codes, int *o_am) {
+                        const int *argmax, const int *shape, int stride, long long *o_off, int *o_ids,
+                        double *o_verts, long long *o_nbr, uint64_t *o_codes, int *o_am, int *o_shape) {
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
         const int m = face_m[c];
@@ -381,6 +399,7 @@ __global__ void k_fetch(const DevNet net, long long n, const int *face_m, const 
         if (o_codes)
             for (int w = 0; w < net.W; ++w) o_codes[f * net.W + w] = codes[c * net.W + w];
         if (o_am) o_am[f] = argmax[c];
+        if (o_shape) o_shape[f] = shape[c];
         for (int i = 0; i < m; ++i) {
             const long long s = c * stride + i;
             if (o_ids) o_ids[o + i] = ids[s];
@@ -411,20 +430,18 @@ static unsigned grid_for(long long n, int block = 256, long long cap = 2048) {
     return (unsigned)b;
 }
 
-void launch_insert(const DevNet &net, const Candidates &cand, const uint64_t *codes, const int *argmax,
-                   const uint64_t *seed_codes, const int *seed_am, unsigned long long *slots,
+void launch_insert(const DevNet &net, const Candidates &cand, const CellArrays &ca, unsigned long long *slots,
                    unsigned long long hmask, Counters *ctr, unsigned long long cand_cap, long long n_hint,
                    hipStream_t st) {
-    hipLaunchKernelGGL(k_insert, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, codes, argmax,
-                       seed_codes, seed_am, slots, hmask, ctr, cand_cap);
+    hipLaunchKernelGGL(k_insert, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, ca, slots, hmask, ctr, cand_cap);
 }
 
-void launch_commit(const DevNet &net, const Candidates &cand, uint64_t *codes, int *argmax, uint64_t *cell_hash,
-                   int *hints, int *face_m, const uint64_t *seed_codes, const int *seed_am,
-                   unsigned long long *slots, Counters *ctr, unsigned long long cand_cap,
+void launch_commit(const DevNet &net, const Candidates &cand, uint64_t *codes, int *argmax, int *shape,
+                   uint64_t *cell_hash, int *hints, int *face_m, const uint64_t *seed_codes, const int *seed_am,
+                   const int *seed_shape, unsigned long long *slots, Counters *ctr, unsigned long long cand_cap,
                    unsigned long long cap_cells, long long n_hint, hipStream_t st) {
-    hipLaunchKernelGGL(k_commit, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, codes, argmax, cell_hash,
-                       hints, face_m, seed_codes, seed_am, slots, ctr, cand_cap, cap_cells);
+    hipLaunchKernelGGL(k_commit, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, codes, argmax, shape, cell_hash,
+                       hints, face_m, seed_codes, seed_am, seed_shape, slots, ctr, cand_cap, cap_cells);
 }
 
 void launch_resolve(const Candidates &cand, int *face_nbr, int stride, Counters *ctr, unsigned long long cand_cap,
@@ -437,26 +454,27 @@ size_t forward_lds_bytes(const DevNet &net, int code_bufs) {
     return sizeof(double) * (3 + net.N + net.M) + sizeof(uint64_t) * net.W * code_bufs;
 }
 
-void launch_codes(const DevNet &net, const double *pts, long long n, uint64_t *codes, int *argmax, double *F,
-                  hipStream_t st) {
+void launch_codes(const DevNet &net, const double *pts, const int *shape_id, long long n, uint64_t *codes,
+                  int *argmax, double *F, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_codes, dim3(grid_for(n, 1, 8192)), dim3(256), forward_lds_bytes(net, 1), st, net, pts,
-                       n, codes, argmax, F);
+                       shape_id, n, codes, argmax, F);
 }
 
-void launch_seed_rays(const DevNet &net, const double *orig, const double *dir, long long n, int max_iter,
-                      uint64_t *seed_codes, int *seed_am, int *status, hipStream_t st) {
+void launch_seed_rays(const DevNet &net, const double *orig, const double *dir, const int *shape_id, long long n,
+                      int max_iter, uint64_t *seed_codes, int *seed_am, int *seed_shape, int *status,
+                      hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_seed_rays, dim3(grid_for(n, 1, 8192)), dim3(256), forward_lds_bytes(net, 3), st, net,
-                       orig, dir, n, max_iter, seed_codes, seed_am, status);
+                       orig, dir, shape_id, n, max_iter, seed_codes, seed_am, seed_shape, status);
 }
 
-void launch_seed_cands(const DevNet &net, const uint64_t *seed_codes, const int *seed_am, const int *seed_ok,
-                       long long n, const Candidates &cand, Counters *ctr, unsigned long long cand_cap,
-                       hipStream_t st) {
+void launch_seed_cands(const DevNet &net, const uint64_t *seed_codes, const int *seed_am, const int *seed_shape,
+                       const int *seed_ok, long long n, const Candidates &cand, Counters *ctr,
+                       unsigned long long cand_cap, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_seed_cands, dim3(grid_for(n)), dim3(256), 0, st, net, seed_codes, seed_am, seed_ok, n,
-                       cand, ctr, cand_cap);
+    hipLaunchKernelGGL(k_seed_cands, dim3(grid_for(n)), dim3(256), 0, st, net, seed_codes, seed_am, seed_shape,
+                       seed_ok, n, cand, ctr, cand_cap);
 }
 
 // Compacts faces of cells 0..n-1 into CSR form.  tmp must hold scan_tmp_bytes(n).
@@ -470,10 +488,10 @@ hipError_t scan_tmp_bytes(long long n, size_t *bytes) {
 }
 
 hipError_t launch_fetch(const DevNet &net, long long n, const int *face_m, const int *ids, const double *verts,
-                        const int *nbr, const uint64_t *codes, const int *argmax, int stride, int *has, int *fidx,
-                        long long *mcount, long long *voff, void *tmp, size_t tmp_bytes, long long F,
-                        long long *o_off, int *o_ids, double *o_verts, long long *o_nbr, uint64_t *o_codes,
-                        int *o_am, hipStream_t st) {
+                        const int *nbr, const uint64_t *codes, const int *argmax, const int *shape, int stride,
+                        int *has, int *fidx, long long *mcount, long long *voff, void *tmp, size_t tmp_bytes,
+                        long long F, long long *o_off, int *o_ids, double *o_verts, long long *o_nbr,
+                        uint64_t *o_codes, int *o_am, int *o_shape, hipStream_t st) {
     if (n <= 0) {
         if (o_off) return hipMemsetAsync(o_off, 0, sizeof(long long), st);
         return hipSuccess;
@@ -486,7 +504,7 @@ hipError_t launch_fetch(const DevNet &net, long long n, const int *face_m, const
     e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, mcount, voff, (int)n, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fetch, dim3(grid_for(n)), dim3(256), 0, st, net, n, face_m, fidx, voff, ids, verts, nbr,
-                       codes, argmax, stride, o_off, o_ids, o_verts, o_nbr, o_codes, o_am);
+                       codes, argmax, shape, stride, o_off, o_ids, o_verts, o_nbr, o_codes, o_am, o_shape);
     hipLaunchKernelGGL(k_fetch_tail, dim3(1), dim3(64), 0, st, o_off, F, voff, face_m, n);
     return hipGetLastError();
 }

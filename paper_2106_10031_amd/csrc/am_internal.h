@@ -28,6 +28,8 @@ constexpr double kSquareHalf = 2.0;
 struct DevNet {
     int n_layers;              // L + 2
     int N, M, W;               // hidden units, heads, code words
+    int S;                     // shapes sharing the weights (1 for a single net)
+    int bias_stride;           // doubles per shape in `bias` (sum of widths of layers >= 1)
     int R;                     // padded rows per cell
     int width[kMaxLayers];
     int row_off[kMaxLayers];   // padded row offset (layers >= 1)
@@ -42,9 +44,9 @@ struct DevNet {
     // the same blocks as MFMA A fragments: for 16-row tile mt and K-step ks,
     // 64 doubles in lane order, lane l = W[16 mt + l % 16][4 ks + l / 16]
     const double *wfrag;
-    const double *bias;
+    const double *bias;        // [S][bias_stride]: shape s, layer l at s * bias_stride + bias_off[l]
     const int *row_of_unit;    // [N + M] padded row of global unit g
-    const uint64_t *zobrist;   // [N + M] keys of the cell fingerprint
+    const uint64_t *zobrist;   // [N + M + S] keys of the cell fingerprint (units, heads, shapes)
 };
 
 // Candidate neighbour cells produced by one marching step.
@@ -61,6 +63,16 @@ struct Candidates {
 };
 
 enum : int { kOwner = 0, kFound = 1, kDup = 2, kLost = 3 };
+
+// Per-cell and per-seed arrays the code of a candidate may come from.
+struct CellArrays {
+    const uint64_t *codes;
+    const int *argmax;
+    const int *shape;
+    const uint64_t *seed_codes;
+    const int *seed_am;
+    const int *seed_shape;
+};
 
 // Where the clip kernel writes faces.
 struct ClipOut {

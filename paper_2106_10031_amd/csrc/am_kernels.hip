@@ -52,8 +52,9 @@ constexpr int kMaxWords = kMaxHidden / 64;
 // tiles at a time (mt and mt + nwaves) so that one B value feeds two MFMAs,
 // and loads the operands of kKChunk K-steps before issuing their MFMAs.  The
 // four codes are staged in LDS (code_lds, 4 x W words).  Ends with a barrier.
-__device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes, long long c0, int ncell,
-                           double *zb, long long rs, long long cs, uint64_t *code_lds) {
+__device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes,
+                           const int *__restrict__ cell_shape, long long c0, int ncell, double *zb, long long rs,
+                           long long cs, uint64_t *code_lds, int *shape_lds) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -66,7 +67,13 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
         const int c = t / net.W;
         code_lds[t] = c < ncell ? codes[(c0 + c) * net.W + (t - c * net.W)] : 0ull;
     }
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        const int sh = (cell_shape && c < ncell) ? cell_shape[c0 + c] : 0;
+        shape_lds[c] = (sh >= 0 && sh < net.S) ? sh : 0;
+    }
     __syncthreads();
+    const long long bias_base = (long long)shape_lds[cl] * net.bias_stride;
     const uint64_t *code = code_lds + cl * net.W;
     double *zc = zb + cl * cs + q;
 
@@ -113,7 +120,7 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
                 }
             }
             if (cell_ok) {
-                const double *bias = net.bias + net.bias_off[l];
+                const double *bias = net.bias + bias_base + net.bias_off[l];
                 // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r of
                 // lane (kq * 16 + col)
                 double *z0 = zc + (long long)net.row_off[l] * rs;
@@ -498,12 +505,14 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
 
 // Unfused chain: rows of cells lo..hi-1 to the global buffer [cell][R][4].
 __global__ __launch_bounds__(256) void k_chain_f64(DevNet net, const uint64_t *__restrict__ codes,
-                                                   long long lo, long long hi, double *__restrict__ rows) {
+                                                   const int *__restrict__ cell_shape, long long lo, long long hi,
+                                                   double *__restrict__ rows) {
     __shared__ uint64_t code_lds[4 * kMaxWords];
+    __shared__ int shape_lds[4];
     const long long c0 = lo + 4LL * blockIdx.x;
     const int ncell = (int)min(4LL, hi - c0);
-    chain_tile(net, codes, c0, ncell, rows + (c0 - lo) * (long long)net.R * 4, 4, (long long)net.R * 4,
-               code_lds);
+    chain_tile(net, codes, cell_shape, c0, ncell, rows + (c0 - lo) * (long long)net.R * 4, 4,
+               (long long)net.R * 4, code_lds, shape_lds);
 }
 
 // Unfused clip: one wave per cell, four cells per workgroup.
@@ -527,6 +536,7 @@ __global__ __launch_bounds__(256) void k_clip_f64(DevNet net, const uint64_t *__
 // (16 consecutive doubles per row: conflict-free B loads and D stores), then
 // wave w clips cell w straight from LDS.  No row ever goes to HBM.
 __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t *__restrict__ codes,
+                                                     const int *__restrict__ cell_shape,
                                                      const int *__restrict__ argmax,
                                                      const uint64_t *__restrict__ cell_hash,
                                                      const int *__restrict__ hints, long long lo,
@@ -536,10 +546,11 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
     extern __shared__ double zl[];
     __shared__ PolyScratch scratch[4];
     __shared__ uint64_t code_lds[4 * kMaxWords];
+    __shared__ int shape_lds[4];
     const int wave = threadIdx.x >> 6;
     const long long c0 = lo + 4LL * blockIdx.x;
     const int ncell = (int)min(4LL, hi - c0);
-    chain_tile(net, codes, c0, ncell, zl, 16, 4, code_lds);
+    chain_tile(net, codes, cell_shape, c0, ncell, zl, 16, 4, code_lds, shape_lds);
     if (wave >= ncell) return;
     clip_cell(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zl + wave * 4, 16, scratch[wave], out,
               cand, cand_cap, ctr);
@@ -570,11 +581,11 @@ hipError_t prepare_fused(size_t bytes) {
                                (int)bytes);
 }
 
-void launch_chain(const DevNet &net, const uint64_t *codes, long long lo, long long hi, double *rows,
-                  hipStream_t st) {
+void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
+                  double *rows, hipStream_t st) {
     if (hi <= lo) return;
     const long long tiles = (hi - lo + 3) / 4;
-    hipLaunchKernelGGL(k_chain_f64, dim3((unsigned)tiles), dim3(256), 0, st, net, codes, lo, hi, rows);
+    hipLaunchKernelGGL(k_chain_f64, dim3((unsigned)tiles), dim3(256), 0, st, net, codes, cell_shape, lo, hi, rows);
 }
 
 void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
@@ -587,13 +598,14 @@ void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, co
                        lo, hi, n_seed_cells, rows, out, cand, cand_cap, ctr);
 }
 
-void launch_fused(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
+void launch_fused(const DevNet &net, const uint64_t *codes, const int *cell_shape, const int *argmax,
+                  const uint64_t *cell_hash,
                   const int *hints, long long lo, long long hi, long long n_seed_cells, const ClipOut &out,
                   const Candidates &cand, unsigned long long cand_cap, Counters *ctr, hipStream_t st) {
     if (hi <= lo) return;
     const long long blocks = (hi - lo + 3) / 4;
     hipLaunchKernelGGL(k_march_fused, dim3((unsigned)blocks), dim3(256), fused_lds_bytes(net), st, net, codes,
-                       argmax, cell_hash, hints, lo, hi, n_seed_cells, out, cand, cand_cap, ctr);
+                       cell_shape, argmax, cell_hash, hints, lo, hi, n_seed_cells, out, cand, cand_cap, ctr);
 }
 
 void launch_rows_unpad(const DevNet &net, long long n, const double *rows, double *out, hipStream_t st) {

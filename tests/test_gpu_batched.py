@@ -1,0 +1,95 @@
+"""Batched form: many shapes sharing weights, marched together in one frontier.
+
+Bar: every shape's part of the batched march equals (a) the oracle's march of
+that shape's own network and (b) the GPU's single-shape march of it (cell
+set, cycles, adjacency exact; vertices 1e-9).
+"""
+import numpy as np
+import pytest
+
+import meshcheck as MC
+from am_workloads import nets, seeds
+from gpu_common import HostMesh, compare_meshes, fetch_host, say
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_10031_amd import binding as B
+    return B
+
+
+def _split_by_shape(ctx):
+    from paper_2106_10031_amd.binding import mesh_to_host
+    h = mesh_to_host(ctx.fetch())
+    out = {}
+    shapes = h["shape"]
+    off = h["offsets"]
+    for s in np.unique(shapes):
+        fs = np.nonzero(shapes == s)[0]
+        remap = {int(f): i for i, f in enumerate(fs)}
+        offs, ids, verts, nbr = [0], [], [], []
+        for f in fs:
+            a, b = off[f], off[f + 1]
+            ids.append(h["ids"][a:b])
+            verts.append(h["verts"][a:b])
+            nbr.append([remap[int(g)] if g >= 0 else int(g) for g in h["nbr"][a:b]])
+            offs.append(offs[-1] + (b - a))
+        out[int(s)] = HostMesh(h["codes"][fs], h["argmax"][fs], np.asarray(offs), np.concatenate(ids),
+                               np.concatenate(verts), np.concatenate(nbr).astype(np.int64))
+    return out
+
+
+def _rays(S, per):
+    o, d, sh = [], [], []
+    for s in range(S):
+        a, b = seeds.random_rays(per, seed=100 + s)
+        o.append(a); d.append(b); sh.append(np.full(per, s, np.int32))
+    return np.concatenate(o), np.concatenate(d), np.concatenate(sh)
+
+
+@pytest.mark.parametrize("path", [1, 2], ids=["split", "fused"])
+def test_batched_equals_oracle_and_single_shape(binding, path):
+    sb = nets.latent_sphere_batch([16, 16, 16], reinject=3, latent_dim=8, n_shapes=6, seed=3)
+    o, d, sh = _rays(sb.n_shapes, 12)
+    say("batched march", sb.n_shapes, "shapes, path", path)
+    ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+    assert ctx.S == sb.n_shapes
+    ctx.seed_rays(o, d, shape_id=sh)
+    st = ctx.march(kernel_path=path)
+    got = _split_by_shape(ctx)
+    total = 0
+    for s in range(sb.n_shapes):
+        net = sb.shape_net(s)
+        on = O.OracleNet(net)
+        m = sh == s
+        codes, ams, _, _ = on.seed_rays(o[m], d[m])
+        ref = on.march(codes, ams)
+        compare_meshes(ref, got[s])
+        total += ref.n_faces
+        single = binding.Context(0).load_net(net)
+        single.seed_rays(o[m], d[m])
+        single.march(kernel_path=path)
+        compare_meshes(ref, fetch_host(single))
+        bad, _ = MC.edge_pairing(got[s], n_hidden=net.n_hidden)
+        assert bad == 0
+    assert st["faces"] == total
+
+
+def test_shape_ids_are_validated(binding):
+    sb = nets.latent_sphere_batch([8, 8], reinject=2, latent_dim=4, n_shapes=3, seed=5)
+    say("shape id validation")
+    ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+    o, d = seeds.random_rays(4, seed=1)
+    status = ctx.seed_rays(o, d, shape_id=np.array([0, 1, 7, -1], np.int32))
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert st[2] == 3 and st[3] == 3
+    codes, am, F = ctx.codes(o, shape_id=np.array([0, 2, 3, 1], np.int32))
+    torch.cuda.synchronize()
+    assert am.cpu().numpy()[2] == -1 and np.isnan(F.cpu().numpy()[2])
