@@ -364,10 +364,13 @@ int orc_face_from_rows(const orc_net *net, const uint64_t *code, int32_t argmax,
         for (int j = i + 1; j < m; j++)
             if (P[i].e == P[j].e) *flags |= ORC_FACE_DEGEN;
     }
+    /* twice the area, from the first vertex so that rounding scales with the
+     * polygon's own size (the absolute shoelace loses tiny faces) */
     double A2 = 0.0;
-    for (int i = 0; i < m; i++) {
-        int j = (i + 1) % m;
-        A2 += P[i].a * P[j].b - P[j].a * P[i].b;
+    for (int i = 1; i + 1 < m; i++) {
+        double ax = P[i].a - P[0].a, ay = P[i].b - P[0].b;
+        double bx = P[i + 1].a - P[0].a, by = P[i + 1].b - P[0].b;
+        A2 += ax * by - bx * ay;
     }
     *area = 0.5 * A2;
     if (!(A2 > 0.0)) { *flags |= ORC_FACE_EMPTY; return 0; }
