@@ -3,9 +3,10 @@
 The fitted nets stand in for the paper's per-shape SDF fits (the ShapeNet fits
 behind Tables 1-4 are not available).  Fitting is plain PyTorch on the CPU and
 has nothing to do with the meshing method; the resulting weights are frozen
-files under ``am_workloads/data`` whose SHA-256 is recorded in ``FIXTURES.txt``.
+files under ``am_workloads/data`` whose SHA-256 is recorded in ``FIXTURES.sha256``.
 
     python -m am_workloads.fit c2        # 3->[90]x6->1, 8 spheres, seed 1
+    python -m am_workloads.fit c3 --device cuda --out gpurun_out   # 3->[256]x8->1, superquadrics
 
 Recipe (one reading of the workload description, stated in the design doc):
     targets: union of 8 spheres (c ~ U[-0.5,0.5]^3, r ~ U[0.15,0.35]) or of 8
@@ -88,7 +89,8 @@ def make_samples(rng, kind, n_samples, prim):
     return x, y
 
 
-def fit(name: str, steps: int | None = None, threads: int | None = None, log_every: int = 100):
+def fit(name: str, steps: int | None = None, threads: int | None = None, log_every: int = 100,
+        device: str = "cpu", out_dir: str | None = None):
     import torch
     spec = SPECS[name]
     steps = spec["steps"] if steps is None else steps
@@ -98,12 +100,12 @@ def fit(name: str, steps: int | None = None, threads: int | None = None, log_eve
     Ws, bs = he_mlp(spec["hidden"], spec["seed"], 0.01)
     prim = sphere_params(rng) if spec["target"] == "spheres" else superquadric_params(rng)
     x, y = make_samples(rng, spec["target"], 1 << 18, prim)
-    X = torch.tensor(x, dtype=torch.float32)
-    Y = torch.tensor(y, dtype=torch.float32)
+    X = torch.tensor(x, dtype=torch.float32, device=device)
+    Y = torch.tensor(y, dtype=torch.float32, device=device)
     params = []
     for W, b in zip(Ws, bs):
-        params += [torch.tensor(W, dtype=torch.float32, requires_grad=True),
-                   torch.tensor(b, dtype=torch.float32, requires_grad=True)]
+        params += [torch.tensor(W, dtype=torch.float32, device=device, requires_grad=True),
+                   torch.tensor(b, dtype=torch.float32, device=device, requires_grad=True)]
     opt = torch.optim.Adam(params, lr=1e-4, betas=(0.9, 0.999))
     t0 = time.time()
     for it in range(steps):
@@ -117,13 +119,14 @@ def fit(name: str, steps: int | None = None, threads: int | None = None, log_eve
         opt.step()
         if it % log_every == 0 or it == steps - 1:
             print(f"[fit {name}] step {it} loss {loss.item():.5f} ({time.time() - t0:.0f}s)", flush=True)
-    Wf = [p.detach().numpy().astype(np.float64) for p in params[0::2]]
-    bf = [p.detach().numpy().astype(np.float64) for p in params[1::2]]
+    Wf = [p.detach().cpu().numpy().astype(np.float64) for p in params[0::2]]
+    bf = [p.detach().cpu().numpy().astype(np.float64) for p in params[1::2]]
     net = mlp_net(Wf, bf)
-    os.makedirs(DATA_DIR, exist_ok=True)
-    path = os.path.join(DATA_DIR, f"{name}.npz")
+    out_dir = out_dir or DATA_DIR
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, f"{name}.npz")
     net.save(path, dtype=np.float32)
-    meta = os.path.join(DATA_DIR, f"{name}_primitives.npz")
+    meta = os.path.join(out_dir, f"{name}_primitives.npz")
     np.savez(meta, **{f"p{i}": np.asarray(p) for i, p in enumerate(prim)})
     digest = hashlib.sha256(open(path, "rb").read()).hexdigest()
     print(f"[fit {name}] wrote {path} sha256 {digest} final loss {loss.item():.5f}", flush=True)
@@ -135,8 +138,10 @@ def main(argv=None):
     ap.add_argument("name", choices=sorted(SPECS))
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--threads", type=int, default=None)
+    ap.add_argument("--device", default="cpu")
+    ap.add_argument("--out", default=None, help="output folder (default: am_workloads/data)")
     a = ap.parse_args(argv)
-    fit(a.name, a.steps, a.threads)
+    fit(a.name, a.steps, a.threads, device=a.device, out_dir=a.out)
 
 
 if __name__ == "__main__":
