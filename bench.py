@@ -103,6 +103,7 @@ def main(argv=None):
     ap.add_argument("--max-cells", type=int, default=1 << 21)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="plain,bf16", help="forms to time besides the plain one")
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -120,26 +121,38 @@ def main(argv=None):
     d_d = torch.as_tensor(d, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
-    def step(time_kernels=False):
+    def step(time_kernels=False, precision=0):
         ctx.seed_rays(o_d, d_d)
-        st = ctx.march(max_cells=a.max_cells, time_kernels=time_kernels)
+        st = ctx.march(max_cells=a.max_cells, time_kernels=time_kernels, precision=precision)
         out = ctx.fetch()
         return st, out
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for _ in range(a.steps):
-        st, out = step()
-        stats.append(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    faces = stats[-1]["faces"]
-    assert all(s["faces"] == faces for s in stats), "face count changed between steps"
-    ms_per_step = (t1 - t0) * 1e3 / a.steps
-    value = faces * a.steps / (t1 - t0)
+    def timed(precision):
+        for _ in range(a.warmup):
+            step(precision=precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = []
+        for _ in range(a.steps):
+            st, out = step(precision=precision)
+            stats.append(st)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f = stats[-1]["faces"]
+        assert all(s["faces"] == f for s in stats), "face count changed between steps"
+        return f, (t1 - t0) * 1e3 / a.steps, f * a.steps / (t1 - t0), stats
+
+    faces, ms_per_step, value, stats = timed(0)
+    forms = {"plain": {"faces_per_s": round(value, 1), "ms_per_step": round(ms_per_step, 3),
+                       "precision": "FP64 chain (MFMA), FP64 clip and vertex solves"}}
+    if "bf16" in a.forms.split(","):
+        f16, ms16, v16, st16 = timed(1)
+        assert f16 == faces, "split-BF16 form changed the face count"
+        forms["bf16"] = {"faces_per_s": round(v16, 1), "ms_per_step": round(ms16, 3),
+                         "escalated_cells": st16[-1]["escalated"],
+                         "precision": "split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); "
+                                      "FP64 sign tests within margin 4e-6 + the vertex's error estimate and vertex solves; "
+                                      "uncertified cells redone in FP64"}
 
     # per-kernel durations (HIP events on the library's stream), separate pass
     kst, kout = step(time_kernels=True)
@@ -164,6 +177,7 @@ def main(argv=None):
     res = {"metric": METRIC, "value": round(value, 1), "unit": "faces/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "forms": forms,
            "config": {"workload": desc, "form": "plain", "faces": faces, "face_verts": stats[-1]["face_verts"],
                       "triangles": stats[-1]["triangles"], "cells": stats[-1]["cells"],
                       "march_steps": stats[-1]["steps"], "seeds": stats[-1]["seed_cells"],

@@ -80,7 +80,19 @@ typedef struct {
     int32_t time_kernels; /* 1: time each kernel class with HIP events on the stream */
     int32_t kernel_path;  /* 0: the library's choice; 1: split (chain rows through HBM, then
                              the clip); 2: fused chain+clip in LDS (AM_E_INVALID if too big) */
-    int32_t reserved[6];
+    int32_t precision;    /* 0: FP64 chain and clip.  1: split-BF16 chain on matrix cores
+                             (each operand = three BF16 terms, six products, FP32
+                             accumulation), clip and vertex solves in FP64 on the FP32 rows;
+                             a face is kept only if every vertex's estimated relative error
+                             is at most `vertex_tol` and no other constraint comes within
+                             `margin` + that estimate of a vertex (and no edge is that
+                             short), else its cell is redone by the FP64 chain and clip, so
+                             cells, cycles and adjacency equal the FP64 result */
+    int32_t reserved[5];
+    double margin;        /* relative sign-test margin of precision 1 (0: 4e-6) */
+    double vertex_tol;    /* precision 1: a cell is also redone in FP64 when a vertex's
+                             estimated relative error (1.2e-6 x its first-order sensitivity
+                             to the rows) exceeds this (0: 1e-5) */
 } am_march_opts;
 
 typedef struct {
@@ -106,7 +118,7 @@ typedef struct {
     int64_t hash_launches;
     int32_t fused;            /* 1 if the fused chain+clip kernel ran */
     int32_t pad;
-    double reserved[1];
+    int64_t escalated;        /* precision 1: cells redone in FP64 */
 } am_march_stats;
 
 /* Creates a context on `device` that enqueues its work on `hip_stream`
@@ -154,8 +166,11 @@ am_status am_codes(am_ctx *ctx, const double *pts, const int32_t *shape_id, int6
  * code, the rows Z[g] = (a, b, c, d) with pre_g(x) = a x + b y + c z + d
  * inside the cell, g = 0..N-1 hidden units then N..N+M-1 heads.  DEVICE
  * pointers: codes [n][W] u64 and shape_id [n] (NULL = shape 0) in;
- * rows [n][N+M][4] f64 out.  Enqueued. */
-am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, int64_t n, double *rows);
+ * rows [n][N+M][4] f64 out.  precision 0 = FP64 matrix cores, 1 = the
+ * split-BF16 chain of am_march_opts.precision (rows rounded to FP32).
+ * Enqueued. */
+am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, int64_t n, int32_t precision,
+                   double *rows);
 
 /* Analytic faces of n given cells (Eqn (AnalyticFace) clipped to the box,
  * vertices by Eqn (VertexEquationSystem)), without marching.  DEVICE

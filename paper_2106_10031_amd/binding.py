@@ -38,7 +38,8 @@ class NetDesc(C.Structure):
 
 class MarchOpts(C.Structure):
     _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
-                ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32 * 5), ("margin", C.c_double), ("vertex_tol", C.c_double)]
 
 
 class MarchStats(C.Structure):
@@ -49,7 +50,7 @@ class MarchStats(C.Structure):
                 ("march_ms", C.c_double), ("chain_ms", C.c_double), ("clip_ms", C.c_double),
                 ("hash_ms", C.c_double), ("chain_launches", C.c_int64), ("clip_launches", C.c_int64),
                 ("hash_launches", C.c_int64), ("fused", C.c_int32), ("pad", C.c_int32),
-                ("reserved", C.c_double * 1)]
+                ("escalated", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "pad")}
@@ -76,7 +77,7 @@ def lib(path: str = LIB_PATH):
     L.am_load_batch.argtypes = [vp, C.POINTER(NetDesc), i32, vp]
     L.am_net_dims.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     L.am_codes.argtypes = [vp, vp, vp, i64, vp, vp, vp]
-    L.am_chain.argtypes = [vp, vp, vp, i64, vp]
+    L.am_chain.argtypes = [vp, vp, vp, i64, i32, vp]
     L.am_faces.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
     L.am_seed_rays.argtypes = [vp, vp, vp, vp, i64, i32, vp]
     L.am_seed_cells.argtypes = [vp, vp, vp, vp, i64]
@@ -177,13 +178,14 @@ class Context:
         self._check(self.L.am_codes(self.h, _p(pts), _p(sh), n, _p(codes), _p(am), _p(F)))
         return codes, am, F
 
-    def chain(self, codes, shape_id=None):
+    def chain(self, codes, shape_id=None, precision=0):
         t = self.torch
         codes = self._dev(codes, t.int64).reshape(-1, self.W)
         n = codes.shape[0]
         sh = self._shape(shape_id)
         rows = t.empty((n, self.N + self.M, 4), dtype=t.float64, device=self.device)
-        self._check(self.L.am_chain(self.h, _p(codes), _p(sh), n, _p(rows)))
+        self._keep = (codes, sh)
+        self._check(self.L.am_chain(self.h, _p(codes), _p(sh), n, int(precision), _p(rows)))
         return rows
 
     def faces(self, codes, argmax=None, max_m=32, shape_id=None):
@@ -219,9 +221,12 @@ class Context:
         self._seed_keep = (codes, am, sh)   # the copy is enqueued on the stream
         self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), _p(sh), codes.shape[0]))
 
-    def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0):
+    def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
+              margin=0.0, vertex_tol=0.0):
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
-                         int(kernel_path))
+                         int(kernel_path), int(precision))
+        opts.margin = float(margin)
+        opts.vertex_tol = float(vertex_tol)
         stats = MarchStats()
         st = self.L.am_march(self.h, C.byref(opts), C.byref(stats))
         if st != AM_OK:

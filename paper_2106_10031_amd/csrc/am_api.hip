@@ -20,15 +20,20 @@
 
 namespace am {
 void launch_clip(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long, long long,
-                 long long, const double *, const ClipOut &, const Candidates &, unsigned long long, Counters *,
-                 hipStream_t);
-void launch_chain(const DevNet &, const uint64_t *, const int *, long long, long long, double *, hipStream_t);
+                 const int *, const unsigned long long *, long long, const double *, const ClipOut &,
+                 const Candidates &, unsigned long long, Counters *, hipStream_t);
+void launch_clip_f32(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long,
+                     long long, long long, const float *, const ClipOut &, const Candidates &, unsigned long long,
+                     Counters *, double, double, int *, unsigned long long *, hipStream_t);
+void launch_chain_bf16(const DevNet &, const uint64_t *, const int *, long long, long long, float *, hipStream_t);
+void launch_chain(const DevNet &, const uint64_t *, const int *, long long, long long, const int *,
+                  const unsigned long long *, double *, hipStream_t);
 void launch_fused(const DevNet &, const uint64_t *, const int *, const int *, const uint64_t *, const int *, long long,
                   long long, long long, const ClipOut &, const Candidates &, unsigned long long, Counters *,
                   hipStream_t);
 size_t fused_lds_bytes(const DevNet &);
 hipError_t prepare_fused(size_t);
-void launch_rows_unpad(const DevNet &, long long, const double *, double *, hipStream_t);
+void launch_rows_unpad(const DevNet &, long long, const void *, bool, double *, hipStream_t);
 void launch_insert(const DevNet &, const Candidates &, const CellArrays &, unsigned long long *, unsigned long long,
                    Counters *, unsigned long long, long long, hipStream_t);
 void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, int *, uint64_t *, int *, int *,
@@ -59,6 +64,9 @@ struct am_ctx {
     DevNet dn{};
     double *d_weights = nullptr;
     double *d_wfrag = nullptr;
+    uint16_t *d_wfrag16 = nullptr;
+    int *d_fb_list = nullptr;                 // cells the split-BF16 pass hands to FP64
+    unsigned long long *d_fb_count = nullptr;
     size_t lds_limit = 0;       // dynamic LDS a workgroup may use
     bool fused_ok = false;      // the fused kernel's rows fit in LDS
     bool prefer_fused = false;  // kernel_path 0 choice (the split path measured faster at width 90)
@@ -157,6 +165,22 @@ am_status dalloc(am_ctx *ctx, T *&p, size_t count) {
         if (s_ != AM_OK) return s_;  \
     } while (0)
 
+// BF16 bits of a float, rounded to nearest even.
+uint16_t bf16_bits(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
 uint64_t splitmix64(uint64_t &s) {
     uint64_t z = (s += 0x9e3779b97f4a7c15ull);
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -186,6 +210,8 @@ void free_march(am_ctx *c) {
     dfree(c->cand.hint_prev);
     dfree(c->cand.hint_next);
     dfree(c->d_rows);
+    dfree(c->d_fb_list);
+    dfree(c->d_fb_count);
     dfree(c->d_has);
     dfree(c->d_fidx);
     dfree(c->d_mcount);
@@ -202,6 +228,7 @@ void free_march(am_ctx *c) {
 void free_net(am_ctx *c) {
     dfree(c->d_weights);
     dfree(c->d_wfrag);
+    dfree(c->d_wfrag16);
     dfree(c->d_bias);
     dfree(c->d_row_of_unit);
     dfree(c->d_zobrist);
@@ -244,6 +271,8 @@ am_status ensure_march(am_ctx *ctx, long long cells) {
     chunk = (chunk + 3) & ~3LL;
     ctx->chunk_cells = chunk;
     TRY(dalloc(ctx, ctx->d_rows, (size_t)chunk * 4 * n.R));
+    TRY(dalloc(ctx, ctx->d_fb_list, chunk));
+    TRY(dalloc(ctx, ctx->d_fb_count, 1));
     ctx->rows_bytes = per_cell * chunk;
     // candidates: the seeds, or up to 16 edges per active cell on average
     ctx->cand_cap = (unsigned long long)std::max<long long>(16 * chunk, ctx->seed_cap + 64);
@@ -412,6 +441,31 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
                 for (int l = 0; l < 64; ++l) hf.push_back(Wp[(size_t)(mt * 16 + l % 16) * ld + ks * 4 + l / 16]);
     }
     // bias table [S][boff]: the net's own biases, or one row per shape
+    // split-BF16 fragments (blocks from the input are copies and get none)
+    std::vector<uint16_t> h16;
+    for (int b = 0; b < nd->n_blocks; ++b) {
+        const int d = dn.blk_dst[b], sr = dn.blk_src[b];
+        const int nd_ = nd->width[d], ns = nd->width[sr];
+        const int ld32 = (ns + 31) & ~31, rows16 = (nd_ + 15) & ~15;
+        dn.blk_ld32[b] = ld32;
+        dn.blk_frag16_off[b] = (long long)(h16.size() / 8);
+        if (sr == 0) continue;
+        const double *src = nd->blk_w[b];
+        for (int mt = 0; mt < rows16 / 16; ++mt)
+            for (int ks = 0; ks < ld32 / 32; ++ks)
+                for (int t = 0; t < 3; ++t)
+                    for (int l = 0; l < 64; ++l)
+                        for (int u = 0; u < 8; ++u) {
+                            const int i = mt * 16 + l % 16, k = ks * 32 + 8 * (l / 16) + u;
+                            double w = (i < nd_ && k < ns) ? src[(size_t)i * ns + k] : 0.0;
+                            uint16_t term = 0;
+                            for (int tt = 0; tt <= t; ++tt) {   // w = h + m + l, each the rounded remainder
+                                term = bf16_bits((float)w);
+                                w -= bf16_value(term);
+                            }
+                            h16.push_back(term);
+                        }
+    }
     std::vector<double> hb((size_t)n_shapes * boff);
     for (int sh = 0; sh < n_shapes; ++sh)
         for (int l = 1; l < L2; ++l)
@@ -431,6 +485,8 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
 
     TRY(dalloc(ctx, ctx->d_weights, hw.size()));
     TRY(dalloc(ctx, ctx->d_wfrag, hf.size()));
+    TRY(dalloc(ctx, ctx->d_wfrag16, h16.size()));
+    HIPCHK(hipMemcpy(ctx->d_wfrag16, h16.data(), sizeof(uint16_t) * h16.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_wfrag, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice));
     TRY(dalloc(ctx, ctx->d_bias, hb.size()));
     TRY(dalloc(ctx, ctx->d_row_of_unit, rou.size()));
@@ -441,6 +497,7 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     HIPCHK(hipMemcpy(ctx->d_zobrist, zob.data(), sizeof(uint64_t) * zob.size(), hipMemcpyHostToDevice));
     dn.weights = ctx->d_weights;
     dn.wfrag = ctx->d_wfrag;
+    dn.wfrag16 = ctx->d_wfrag16;
     dn.bias = ctx->d_bias;
     dn.row_of_unit = ctx->d_row_of_unit;
     dn.zobrist = ctx->d_zobrist;
@@ -474,16 +531,25 @@ am_status am_codes(am_ctx *ctx, const double *pts, const int32_t *shape_id, int6
     return AM_OK;
 }
 
-am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, int64_t n, double *rows) {
+am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, int64_t n, int32_t precision,
+                   double *rows) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
-    if (n < 0 || (n > 0 && (!codes || !rows))) return fail(ctx, AM_E_INVALID, "bad arguments");
+    if (n < 0 || (n > 0 && (!codes || !rows)) || precision < 0 || precision > 1)
+        return fail(ctx, AM_E_INVALID, "bad arguments");
     TRY(set_device(ctx));
     TRY(ensure_march(ctx, std::max<long long>(ctx->cap_cells, 1024)));
     for (long long lo = 0; lo < n; lo += ctx->chunk_cells) {
         const long long hi = std::min<long long>(n, lo + ctx->chunk_cells);
-        launch_chain(ctx->dn, codes, shape_id, lo, hi, ctx->d_rows, ctx->stream);
-        launch_rows_unpad(ctx->dn, hi - lo, ctx->d_rows, rows + lo * 4 * (ctx->dn.N + ctx->dn.M), ctx->stream);
+        if (precision == 1) {
+            launch_chain_bf16(ctx->dn, codes, shape_id, lo, hi, (float *)ctx->d_rows, ctx->stream);
+            launch_rows_unpad(ctx->dn, hi - lo, ctx->d_rows, true, rows + lo * 4 * (ctx->dn.N + ctx->dn.M),
+                              ctx->stream);
+        } else {
+            launch_chain(ctx->dn, codes, shape_id, lo, hi, nullptr, nullptr, ctx->d_rows, ctx->stream);
+            launch_rows_unpad(ctx->dn, hi - lo, ctx->d_rows, false, rows + lo * 4 * (ctx->dn.N + ctx->dn.M),
+                              ctx->stream);
+        }
     }
     HIPCHK(hipGetLastError());
     return AM_OK;
@@ -499,7 +565,7 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, co
     TRY(ensure_march(ctx, std::max<long long>(ctx->cap_cells, 1024)));
     for (long long lo = 0; lo < n; lo += ctx->chunk_cells) {
         const long long hi = std::min<long long>(n, lo + ctx->chunk_cells);
-        launch_chain(ctx->dn, codes, shape_id, lo, hi, ctx->d_rows, ctx->stream);
+        launch_chain(ctx->dn, codes, shape_id, lo, hi, nullptr, nullptr, ctx->d_rows, ctx->stream);
         ClipOut out{};
         out.m = m;
         out.ids = ids;
@@ -509,8 +575,8 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, co
         out.stride = max_m;
         out.out_base = 0;
         Candidates none{};
-        launch_clip(ctx->dn, codes, argmax, nullptr, nullptr, lo, hi, 0, ctx->d_rows, out, none, 0, nullptr,
-                    ctx->stream);
+        launch_clip(ctx->dn, codes, argmax, nullptr, nullptr, lo, hi, nullptr, nullptr, 0, ctx->d_rows, out, none, 0,
+                    nullptr, ctx->stream);
     }
     HIPCHK(hipGetLastError());
     return AM_OK;
@@ -584,10 +650,20 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         TRY(ensure_march(ctx, cap));
     }
     if (o.kernel_path < 0 || o.kernel_path > 2) return fail(ctx, AM_E_INVALID, "kernel_path must be 0, 1 or 2");
+    if (o.precision < 0 || o.precision > 1) return fail(ctx, AM_E_INVALID, "precision must be 0 or 1");
+    if (o.precision == 1 && o.kernel_path == 2)
+        return fail(ctx, AM_E_INVALID, "the split-BF16 form runs on the split path");
     if (o.kernel_path == 2 && !ctx->fused_ok)
         return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
                     fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
-    const bool fused = o.kernel_path == 2 || (o.kernel_path == 0 && ctx->prefer_fused && ctx->fused_ok);
+    const bool fused = o.precision == 0 && (o.kernel_path == 2 || (o.kernel_path == 0 && ctx->prefer_fused &&
+                                                                     ctx->fused_ok));
+    // default margin: the largest sign-test error of the split-BF16 rows at an
+    // exact vertex, relative to |c|_1 (1 + |v|_inf), was 1.3e-6 over 4,000
+    // vertices of the 6x90 sphere-union fit; each vertex adds its own error
+    // estimate to this margin
+    const double margin = o.margin > 0.0 ? o.margin : 4e-6;
+    const double vtol = o.vertex_tol > 0.0 ? o.vertex_tol : 1e-5;
     am_march_stats st{};
     st.fused = fused ? 1 : 0;
     hipStream_t s = ctx->stream;
@@ -644,11 +720,22 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             launch_fused(net, ctx->d_codes, ctx->d_shape, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells,
                          out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
-        } else {
-            launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, ctx->d_rows, s);
+        } else if (o.precision == 1) {
+            // split-BF16 chain; faces it cannot certify go to the FP64 chain and clip
+            HIPCHK(hipMemsetAsync(ctx->d_fb_count, 0, sizeof(unsigned long long), s));
+            launch_chain_bf16(net, ctx->d_codes, ctx->d_shape, lo, lo + n, (float *)ctx->d_rows, s);
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
-            launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells, ctx->d_rows,
-                        out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
+            launch_clip_f32(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells,
+                            (const float *)ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, margin, vtol,
+                            ctx->d_fb_list, ctx->d_fb_count, s);
+            launch_chain(net, ctx->d_codes, ctx->d_shape, 0, n, ctx->d_fb_list, ctx->d_fb_count, ctx->d_rows, s);
+            launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, 0, n, ctx->d_fb_list,
+                        ctx->d_fb_count, seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
+        } else {
+            launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, nullptr, nullptr, ctx->d_rows, s);
+            if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
+            launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, nullptr, nullptr,
+                        seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
         }
         if (tk) HIPCHK(hipEventRecord(ctx->evk[2], s));
         const long long nh = n * 6;
@@ -694,6 +781,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     st.cells = (long long)c.n_cells;
 
     st.domain_edges = (long long)c.domain_edges;
+    st.escalated = (long long)c.escalated;
     st.degenerate = (long long)c.degenerate;
     st.march_ms = ms;
 

@@ -44,6 +44,12 @@ struct DevNet {
     // the same blocks as MFMA A fragments: for 16-row tile mt and K-step ks,
     // 64 doubles in lane order, lane l = W[16 mt + l % 16][4 ks + l / 16]
     const double *wfrag;
+    // split-BF16 fragments for v_mfma_f32_16x16x32_bf16: per block, tile mt,
+    // K-step ks (32 wide) and term t (h, m, l: W = h + m + l), 64 lanes x 8
+    // BF16, lane l element u = term of W[16 mt + l % 16][32 ks + 8 (l / 16) + u]
+    const void *wfrag16;
+    long long blk_frag16_off[kMaxBlocks];   // in units of 8 BF16 (16 bytes)
+    int blk_ld32[kMaxBlocks];               // src width rounded up to 32
     const double *bias;        // [S][bias_stride]: shape s, layer l at s * bias_stride + bias_off[l]
     const int *row_of_unit;    // [N + M] padded row of global unit g
     const uint64_t *zobrist;   // [N + M + S] keys of the cell fingerprint (units, heads, shapes)
@@ -96,7 +102,8 @@ struct Counters {
     unsigned long long domain_edges;
     unsigned long long face_verts;
     unsigned long long too_big;
-    unsigned long long pad[7];
+    unsigned long long escalated;   // cells the split-BF16 pass handed to FP64
+    unsigned long long pad[6];
 };
 
 // ---------------------------------------------------------------- helpers

@@ -52,9 +52,30 @@ constexpr int kMaxWords = kMaxHidden / 64;
 // tiles at a time (mt and mt + nwaves) so that one B value feeds two MFMAs,
 // and loads the operands of kKChunk K-steps before issuing their MFMAs.  The
 // four codes are staged in LDS (code_lds, 4 x W words).  Ends with a barrier.
+// Cells of a tile: positions p0..p0+ncell-1 of the active range, i.e. cell
+// p0 + c, or list[p0 + c] when a cell list is given.
+__device__ __forceinline__ long long tile_cell(const int *list, long long p0, int c) {
+    return list ? (long long)list[p0 + c] : p0 + c;
+}
+
+// Stages the codes and shape ids of a tile's cells in LDS (ends with a barrier).
+__device__ void stage_tile(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ cell_shape,
+                           const int *list, long long p0, int ncell, uint64_t *code_lds, int *shape_lds) {
+    for (int t = threadIdx.x; t < 4 * net.W; t += blockDim.x) {
+        const int c = t / net.W;
+        code_lds[t] = c < ncell ? codes[tile_cell(list, p0, c) * net.W + (t - c * net.W)] : 0ull;
+    }
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        const int sh = (cell_shape && c < ncell) ? cell_shape[tile_cell(list, p0, c)] : 0;
+        shape_lds[c] = (sh >= 0 && sh < net.S) ? sh : 0;
+    }
+    __syncthreads();
+}
+
 __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes,
-                           const int *__restrict__ cell_shape, long long c0, int ncell, double *zb, long long rs,
-                           long long cs, uint64_t *code_lds, int *shape_lds) {
+                           const int *__restrict__ cell_shape, const int *list, long long c0, int ncell, double *zb,
+                           long long rs, long long cs, uint64_t *code_lds, int *shape_lds) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -63,16 +84,7 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
     const int q = col & 3;           // homogeneous component of this column
     const int cl = col >> 2;         // cell of this column within the tile
     const bool cell_ok = cl < ncell;
-    for (int t = threadIdx.x; t < 4 * net.W; t += blockDim.x) {
-        const int c = t / net.W;
-        code_lds[t] = c < ncell ? codes[(c0 + c) * net.W + (t - c * net.W)] : 0ull;
-    }
-    if (threadIdx.x < 4) {
-        const int c = threadIdx.x;
-        const int sh = (cell_shape && c < ncell) ? cell_shape[c0 + c] : 0;
-        shape_lds[c] = (sh >= 0 && sh < net.S) ? sh : 0;
-    }
-    __syncthreads();
+    stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds);
     const long long bias_base = (long long)shape_lds[cl] * net.bias_stride;
     const uint64_t *code = code_lds + cl * net.W;
     double *zc = zb + cl * cs + q;
@@ -137,11 +149,127 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
     }
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// x = h + m + l with h, m, l in BF16 (each the rounded remainder of the last):
+// 24 significant bits, as many as FP32 holds.
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+    h = (__bf16)x;
+    const float r1 = x - (float)h;
+    m = (__bf16)r1;
+    l = (__bf16)(r1 - (float)m);
+}
+
+// Affine chain of four cells in split-BF16 on matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Each operand is split into
+// three BF16 terms; the six products hh, hm, mh, mm, hl, lh are accumulated,
+// which keeps about 24 bits (terms below 2^-24 relative are dropped).  Rows
+// are FP32, element (row, cell, q) at zb[row * rs + cell * cs + q]; blocks
+// from the input are exact copies of W's x, y, z columns and bypass the
+// matrix cores.  Layout (16x16x32 BF16): A[i][k] in lane (i + 16 (k/8)),
+// element k % 8; B[k][j] in lane (j + 16 (k/8)); D[4 (l/16) + r][l % 16] in
+// register r of lane l.
+__device__ void chain_tile_bf16(const DevNet &net, const uint64_t *__restrict__ codes,
+                                const int *__restrict__ cell_shape, const int *list, long long c0, int ncell,
+                                float *zb, long long rs, long long cs, uint64_t *code_lds, int *shape_lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const int q = col & 3;
+    const int cl = col >> 2;
+    const bool cell_ok = cl < ncell;
+    stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds);
+    const long long bias_base = (long long)shape_lds[cl] * net.bias_stride;
+    const uint64_t *code = code_lds + cl * net.W;
+    float *zc = zb + cl * cs + q;
+
+    for (int l = 1; l < net.n_layers; ++l) {
+        const int nl = net.width[l];
+        const int mtiles = (nl + 15) >> 4;
+        for (int mt0 = wave; mt0 < mtiles; mt0 += 2 * nwaves) {
+            const int mt1 = mt0 + nwaves;
+            const bool two = mt1 < mtiles;
+            v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+            int b_in = -1;
+            for (int b = 0; b < net.n_blocks; ++b) {
+                if (net.blk_dst[b] != l) continue;
+                const int j = net.blk_src[b];
+                if (j == 0) {
+                    b_in = b;
+                    continue;
+                }
+                const int ks_n = net.blk_ld32[b] >> 5;
+                const int nj = net.width[j];
+                const v8bf *fr0 = reinterpret_cast<const v8bf *>(net.wfrag16) + net.blk_frag16_off[b] +
+                                  (long long)mt0 * ks_n * 3 * 64 + lane;
+                const v8bf *fr1 = fr0 + (long long)(mt1 - mt0) * ks_n * 3 * 64;
+                const int uoff = net.unit_off[j];
+                const float *zj = zc + (long long)net.row_off[j] * rs;
+                for (int ks = 0; ks < ks_n; ++ks) {
+                    const int kb = ks * 32 + 8 * kq;
+                    v8bf bh, bm, bl;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int k = kb + u;
+                        const float v = (k < nj && cell_ok && code_bit(code, uoff + k)) ? zj[k * rs] : 0.f;
+                        __bf16 h, m, lo;
+                        split3(v, h, m, lo);
+                        bh[u] = h;
+                        bm[u] = m;
+                        bl[u] = lo;
+                    }
+                    const v8bf ah = fr0[(ks * 3 + 0) * 64], am = fr0[(ks * 3 + 1) * 64], al = fr0[(ks * 3 + 2) * 64];
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc0, 0, 0, 0);
+                    if (two) {
+                        const v8bf ch = fr1[(ks * 3 + 0) * 64], cm = fr1[(ks * 3 + 1) * 64],
+                                   cl3 = fr1[(ks * 3 + 2) * 64];
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl3, bh, acc1, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, bl, acc1, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, bm, acc1, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cm, bh, acc1, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, bm, acc1, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch, bh, acc1, 0, 0, 0);
+                    }
+                }
+            }
+            if (cell_ok) {
+                const double *bias = net.bias + bias_base + net.bias_off[l];
+                float *z0 = zc + (long long)net.row_off[l] * rs;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i0 = mt0 * 16 + 4 * kq + r;
+                    const int i1 = mt1 * 16 + 4 * kq + r;
+                    if (i0 < nl) {
+                        double v = (double)acc0[r] + (q == 3 ? bias[i0] : 0.0);
+                        if (b_in >= 0 && q < 3) v += net.weights[net.blk_off[b_in] + (long long)i0 * net.blk_ld[b_in] + q];
+                        z0[i0 * rs] = (float)v;
+                    }
+                    if (two && i1 < nl) {
+                        double v = (double)acc1[r] + (q == 3 ? bias[i1] : 0.0);
+                        if (b_in >= 0 && q < 3) v += net.weights[net.blk_off[b_in] + (long long)i1 * net.blk_ld[b_in] + q];
+                        z0[i1 * rs] = (float)v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 struct PolyScratch {
     double a[kMaxPoly];
     double b[kMaxPoly];
     double r[kMaxPoly];
     int e[kMaxPoly];
+    int near[kWave];   // hidden lines the precision check must revisit
 };
 
 struct Poly {
@@ -212,9 +340,10 @@ __device__ bool sh_clip(Poly &P, double cu, double cv, double cw, double nrm, in
     return true;
 }
 
-// Oriented constraint row of id (feasible side <= 0).
+// Oriented constraint row of id (feasible side <= 0), widened to FP64.
+template <typename RowT>
 __device__ __forceinline__ void constraint_row(const DevNet &net, int id, const uint64_t *code, int am,
-                                               const double *rb, long long rs, double c[4]) {
+                                               const RowT *rb, long long rs, double c[4]) {
     if (id < 0) {
         const int t = -id - 1;
         const int ax = t >> 1;
@@ -222,21 +351,45 @@ __device__ __forceinline__ void constraint_row(const DevNet &net, int id, const 
         c[ax] = (t & 1) ? -1.0 : 1.0;
         c[3] = -1.0;
     } else if (id < net.N) {
-        const double *z = rb + (long long)net.row_of_unit[id] * rs;
+        const RowT *z = rb + (long long)net.row_of_unit[id] * rs;
         const double sg = code_bit(code, id) ? -1.0 : 1.0;
         c[0] = sg * z[0];
         c[1] = sg * z[1];
         c[2] = sg * z[2];
         c[3] = sg * z[3];
     } else {
-        const double *zi = rb + (long long)net.row_of_unit[id] * rs;
-        const double *zj = rb + (long long)net.row_of_unit[net.N + am] * rs;
+        const RowT *zi = rb + (long long)net.row_of_unit[id] * rs;
+        const RowT *zj = rb + (long long)net.row_of_unit[net.N + am] * rs;
         c[0] = zi[0] - zj[0];
         c[1] = zi[1] - zj[1];
         c[2] = zi[2] - zj[2];
         c[3] = zi[3] - zj[3];
     }
 }
+
+// Largest row sum of |A^-1| for a 3x3 matrix (adjugate / determinant).
+__device__ double inv_norm3(const double A[3][3]) {
+    const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    if (det == 0.0) return __builtin_inf();
+    const double i00 = c00, i01 = A[0][2] * A[2][1] - A[0][1] * A[2][2], i02 = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+    const double i10 = c01, i11 = A[0][0] * A[2][2] - A[0][2] * A[2][0], i12 = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+    const double i20 = c02, i21 = A[0][1] * A[2][0] - A[0][0] * A[2][1], i22 = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    const double r0 = fabs(i00) + fabs(i01) + fabs(i02);
+    const double r1 = fabs(i10) + fabs(i11) + fabs(i12);
+    const double r2 = fabs(i20) + fabs(i21) + fabs(i22);
+    return fmax(r0, fmax(r1, r2)) / fabs(det);
+}
+
+// Relative error of the split-BF16 rows per unit of first-order vertex
+// sensitivity, a calibrated constant (not a bound): the largest ratio of vertex
+// error to |A^-1|_inf max_k (|A_k|_1 |x|_inf + |r_k|) / max(1, |x|_inf),
+// measured against FP64 rows with no vertex redone, was 3.6e-7 over all
+// 1,887,520 vertices of the 6x90 sphere-union fit and 8.4e-7 over all
+// 33,049,480 vertices of the 8x256 superquadric fit; 1.2e-6 is used.
+constexpr double kSplitRowEps = 1.2e-6;
 
 // Solves A x = r (3x3) by elimination with row pivoting; false if singular.
 __device__ bool solve3(double A[3][3], double r[3], double x[3]) {
@@ -271,12 +424,74 @@ __device__ bool solve3(double A[3][3], double r[3], double x[3]) {
     return true;
 }
 
+// Cells whose face the split-BF16 path cannot certify, for the FP64 path.
+struct Fallback {
+    int *list;
+    unsigned long long *count;
+    unsigned long long cap;
+};
+
+// Precision check of a face computed from approximate rows: true when a
+// constraint that is not an edge of the polygon comes within margin + est_i
+// of vertex i (relative to |c|_1 (1 + |v|_inf); est_i is the vertex's own
+// estimated relative error, held by lane i), or when an edge is that short;
+// then the exact face may differ and the cell must be redone in FP64.  The
+// hidden lines checked are the n_near ones the clip listed in `near`: every
+// other hidden line stayed farther than that from an intermediate polygon,
+// which contains the final one.  Max-pool and box lines are all checked.
+template <typename RowT>
+__device__ bool margin_ambiguous(const DevNet &net, const uint64_t *code, int am, const RowT *rb, long long rs,
+                                 int m, int e, double vx, double vy, double vz, double est, double margin,
+                                 const int *near, int n_near) {
+    const int lane = lane_id();
+    bool amb = false;
+    const int jn = lane + 1 >= m ? 0 : lane + 1;
+    const double wx = shfl(vx, jn), wy = shfl(vy, jn), wz = shfl(vz, jn);
+    const double west = shfl(est, jn);
+    if (lane < m) {
+        const double sc = 1.0 + fmax(fabs(vx), fmax(fabs(vy), fabs(vz)));
+        if (fmax(fabs(wx - vx), fmax(fabs(wy - vy), fabs(wz - vz))) <= (margin + est + west) * sc) amb = true;
+    }
+    const int total = n_near + net.M + 6;
+    for (int base = 0; base < total; base += kWave) {
+        const int t = base + lane;
+        bool valid = t < total;
+        int id;
+        if (t < n_near) {
+            id = near[t];
+        } else if (t < n_near + net.M) {
+            id = net.N + (t - n_near);
+            if (t - n_near == am) valid = false;
+        } else {
+            id = -1 - (t - n_near - net.M);
+        }
+        bool isedge = false;
+        for (int k = 0; k < m; ++k) isedge |= bcast(e, k) == id;
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+        const bool test = valid && !isedge;
+        if (test) constraint_row(net, id, code, am, rb, rs, c);
+        const double cn = fabs(c[0]) + fabs(c[1]) + fabs(c[2]) + fabs(c[3]);
+        for (int i = 0; i < m; ++i) {
+            const double xi = bcast(vx, i), yi = bcast(vy, i), zi = bcast(vz, i);
+            const double ti = margin + bcast(est, i);
+            const double d = c[0] * xi + c[1] * yi + c[2] * zi + c[3];
+            const double sc = 1.0 + fmax(fabs(xi), fmax(fabs(yi), fabs(zi)));
+            if (test && d > -ti * cn * sc) amb = true;
+        }
+    }
+    return ballot(amb) != 0;
+}
+
 // Clips the face of one cell (one wave) and writes it; rows of the cell's
-// chain are read as rb[row * rs + q].
+// chain are read as rb[row * rs + q] (FP64, or FP32 from the split-BF16
+// chain).  margin > 0 (FP32 rows): faces that margin_ambiguous flags, and
+// empty or degenerate results, are not written but appended to fb.
+template <typename RowT>
 __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ argmax,
                           const uint64_t *__restrict__ cell_hash, const int *__restrict__ hints, long long cell,
-                          long long n_seed_cells, const double *rb, long long rs, PolyScratch &S, const ClipOut &out,
-                          const Candidates &cand, unsigned long long cand_cap, Counters *ctr) {
+                          long long n_seed_cells, const RowT *rb, long long rs, PolyScratch &S, const ClipOut &out,
+                          const Candidates &cand, unsigned long long cand_cap, Counters *ctr, double margin,
+                          double vertex_tol, const Fallback &fb) {
     const int lane = lane_id();
     const uint64_t *code = codes + cell * net.W;
     const int am_in = argmax ? argmax[cell] : 0;
@@ -284,9 +499,14 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
     const int am = am_ok ? am_in : 0;
     const long long oi = cell - out.out_base;
     int flags = 0;
+    // precision check: a hidden line that stays farther than near_tol (x |c|_1)
+    // from every vertex of an intermediate polygon clears margin + est (est <=
+    // vertex_tol, vertex scale <= 2 in the box) at the final vertices
+    const double near_tol = margin > 0.0 ? 2.5 * (margin + vertex_tol) : 0.0;
+    int n_near = 0;
 
     // ---- plane frame: n = a_F[0:3], foot point p0, orthonormal u, v with u x v = n/|n|
-    const double *aF = rb + (long long)net.row_of_unit[net.N + am] * rs;
+    const RowT *aF = rb + (long long)net.row_of_unit[net.N + am] * rs;
     const double fx = aF[0], fy = aF[1], fz = aF[2], fw = aF[3];
     const double nn = fx * fx + fy * fy + fz * fz;
     Poly P;
@@ -341,20 +561,31 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         for (int base = 0; base < net.N && P.m > 0; base += kWave) {
             const int g = base + lane;
             const bool valid = g < net.N;
-            double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0;
-            bool cuts = false;
+            double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0, cn = 0.0;
+            bool cuts = false, close = false;
             if (valid) {
-                const double *z = rb + (long long)net.row_of_unit[g] * rs;
+                const RowT *z = rb + (long long)net.row_of_unit[g] * rs;
                 const double sg = code_bit(code, g) ? -1.0 : 1.0;
                 const double c0 = sg * z[0], c1 = sg * z[1], c2 = sg * z[2], c3 = sg * z[3];
                 cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
                 cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
                 cw = c0 * p0[0] + c1 * p0[1] + c2 * p0[2] + c3;
                 nrm = sqrt(cu * cu + cv * cv);
+                cn = fabs(c0) + fabs(c1) + fabs(c2) + fabs(c3);
             }
             for (int i = 0; i < P.m; ++i) {
                 const double ai = bcast(P.a, i), bi = bcast(P.b, i), ri = bcast(P.r, i);
-                cuts |= (cu * ai + cv * bi + cw) > kTau * (nrm * ri + fabs(cw));
+                const double d = cu * ai + cv * bi + cw;
+                cuts |= d > kTau * (nrm * ri + fabs(cw));
+                close |= d > -near_tol * cn;
+            }
+            if (near_tol > 0.0) {
+                // lines that cut, or pass within near_tol of this polygon,
+                // are the only hidden lines the precision check revisits
+                const uint64_t nm = ballot(valid && close);
+                const int at = n_near + __popcll(nm & ((1ull << lane) - 1ull));
+                if (valid && close && at < kWave) S.near[at] = g;
+                n_near += __popcll(nm);
             }
             uint64_t mask = ballot(valid && cuts);
             while (mask) {
@@ -369,7 +600,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
             const bool valid = hd < net.M && hd != am;
             double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0;
             if (valid) {
-                const double *zi = rb + (long long)net.row_of_unit[net.N + hd] * rs;
+                const RowT *zi = rb + (long long)net.row_of_unit[net.N + hd] * rs;
                 const double c0 = zi[0] - fx, c1 = zi[1] - fy, c2 = zi[2] - fz, c3 = zi[3] - fw;
                 cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
                 cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
@@ -399,9 +630,13 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
     int m = P.m;
     const bool act = lane < m;
     if (m >= 3) {
+        // twice the area as a fan from vertex 0, so that rounding scales with
+        // the polygon's own size (an absolute shoelace loses tiny faces)
         const int j = (lane + 1 >= m) ? 0 : lane + 1;
         const double ja = shfl(P.a, j), jb = shfl(P.b, j);
-        const double area2 = wave_sum(act ? (P.a * jb - ja * P.b) : 0.0);
+        const double a0 = bcast(P.a, 0), b0 = bcast(P.b, 0);
+        const bool fan = lane >= 1 && lane + 1 < m;
+        const double area2 = wave_sum(fan ? ((P.a - a0) * (jb - b0) - (ja - a0) * (P.b - b0)) : 0.0);
         bool dup = false;
         for (int k = 0; k < m; ++k) {
             const int ek = bcast(P.e, k);
@@ -426,6 +661,8 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
     }
 
     int e_out = 0;
+    double x[3] = {0.0, 0.0, 0.0};
+    double vsens_a = 0.0, vsens_b = 0.0, vsens_r = 0.0;
     if (m > 0) {
         // rotate so that the smallest edge id comes first
         const int minid = wave_min(lane < m ? P.e : 0x7fffffff);
@@ -437,25 +674,59 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         const int eprev = shfl(e, lane == 0 ? m - 1 : lane - 1);
         e_out = e;
         if (lane < m) {
-            // vertex i = [c_{e(i-1)}; c_{e(i)}; a_F] x = -[...]
+            // vertex i = [c_{e(i-1)}; c_{e(i)}; a_F] x = -[...], in FP64
             double ca[4], cb[4];
             constraint_row(net, eprev, code, am, rb, rs, ca);
             constraint_row(net, e, code, am, rb, rs, cb);
             double A[3][3] = {{ca[0], ca[1], ca[2]}, {cb[0], cb[1], cb[2]}, {fx, fy, fz}};
             double rr[3] = {-ca[3], -cb[3], -fw};
-            double x[3];
+            if (margin > 0.0) {
+                // estimated vertex error from the approximate rows
+                const double an = inv_norm3(A);
+                const double s0 = fabs(A[0][0]) + fabs(A[0][1]) + fabs(A[0][2]);
+                const double s1 = fabs(A[1][0]) + fabs(A[1][1]) + fabs(A[1][2]);
+                const double s2 = fabs(A[2][0]) + fabs(A[2][1]) + fabs(A[2][2]);
+                vsens_a = an;
+                vsens_b = fmax(s0, fmax(s1, s2));
+                vsens_r = fmax(fabs(rr[0]), fmax(fabs(rr[1]), fabs(rr[2])));
+            }
             if (!solve3(A, rr, x)) {
                 flags |= kFlagSingular;
                 x[0] = x[1] = x[2] = __builtin_nan("");
             }
-            const long long o = oi * out.stride + lane;
-            out.ids[o] = e;
-            out.verts[o * 3 + 0] = x[0];
-            out.verts[o * 3 + 1] = x[1];
-            out.verts[o * 3 + 2] = x[2];
-            if (out.nbr) out.nbr[o] = -1;
         }
         for (int o = 32; o > 0; o >>= 1) flags |= __shfl_xor(flags, o, kWave);
+    }
+    if (margin > 0.0) {
+        // split-BF16 rows: keep the face only if FP64 could not decide otherwise
+        wave_lds_sync();   // the near list was written by other lanes
+        bool shaky = false;
+        double est = 0.0;
+        if (lane < m) {
+            const double xm = fmax(fabs(x[0]), fmax(fabs(x[1]), fabs(x[2])));
+            est = kSplitRowEps * vsens_a * (vsens_b * xm + vsens_r) / fmax(1.0, xm);
+            shaky = !(est <= vertex_tol);
+        }
+        const bool redo = m == 0 || flags != 0 || n_near > kWave || ballot(shaky) != 0 ||
+                          margin_ambiguous(net, code, am, rb, rs, m, e_out, x[0], x[1], x[2], est, margin, S.near,
+                                           n_near);
+        if (redo) {
+            if (lane == 0) {
+                const unsigned long long k = atomicAdd(fb.count, 1ull);
+                if (k < fb.cap) fb.list[k] = (int)cell;
+                out.m[oi] = 0;
+                if (ctr) atomicAdd(&ctr->escalated, 1ull);
+            }
+            return;
+        }
+    }
+    if (m > 0 && lane < m) {
+        const long long o = oi * out.stride + lane;
+        out.ids[o] = e_out;
+        out.verts[o * 3 + 0] = x[0];
+        out.verts[o * 3 + 1] = x[1];
+        out.verts[o * 3 + 2] = x[2];
+        if (out.nbr) out.nbr[o] = -1;
     }
     if (lane == 0) {
         out.m[oi] = m;
@@ -503,33 +774,64 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
 
 
 
-// Unfused chain: rows of cells lo..hi-1 to the global buffer [cell][R][4].
+// Positions 0..count-1 of a step: cell lo + p, or list[p] (count read on the
+// device from *list_count, at most cap).
+struct CellRange {
+    long long lo, hi;
+    const int *list;
+    const unsigned long long *list_count;
+    unsigned long long cap;
+    __device__ long long count() const {
+        if (!list) return hi - lo;
+        const unsigned long long c = *list_count;
+        return (long long)(c < cap ? c : cap);
+    }
+    __device__ long long cell(long long p) const { return list ? (long long)list[p] : lo + p; }
+    __device__ long long tile_base(long long p) const { return list ? p : lo + p; }
+};
+
+// Unfused FP64 chain: rows of position p go to rows[p][R][4].
 __global__ __launch_bounds__(256) void k_chain_f64(DevNet net, const uint64_t *__restrict__ codes,
-                                                   const int *__restrict__ cell_shape, long long lo, long long hi,
+                                                   const int *__restrict__ cell_shape, CellRange rg,
                                                    double *__restrict__ rows) {
     __shared__ uint64_t code_lds[4 * kMaxWords];
     __shared__ int shape_lds[4];
-    const long long c0 = lo + 4LL * blockIdx.x;
-    const int ncell = (int)min(4LL, hi - c0);
-    chain_tile(net, codes, cell_shape, c0, ncell, rows + (c0 - lo) * (long long)net.R * 4, 4,
+    const long long p0 = 4LL * blockIdx.x;
+    const long long n = rg.count();
+    if (p0 >= n) return;
+    const int ncell = (int)min(4LL, n - p0);
+    chain_tile(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, rows + p0 * (long long)net.R * 4, 4,
                (long long)net.R * 4, code_lds, shape_lds);
 }
 
-// Unfused clip: one wave per cell, four cells per workgroup.
-__global__ __launch_bounds__(256) void k_clip_f64(DevNet net, const uint64_t *__restrict__ codes,
-                                                  const int *__restrict__ argmax,
-                                                  const uint64_t *__restrict__ cell_hash,
-                                                  const int *__restrict__ hints, long long lo,
-                                                  long long hi, long long n_seed_cells,
-                                                  const double *__restrict__ rows, ClipOut out,
-                                                  Candidates cand, unsigned long long cand_cap,
-                                                  Counters *ctr) {
+// Split-BF16 chain: FP32 rows of position p go to rows[p][R][4].
+__global__ __launch_bounds__(256) void k_chain_bf16(DevNet net, const uint64_t *__restrict__ codes,
+                                                    const int *__restrict__ cell_shape, CellRange rg,
+                                                    float *__restrict__ rows) {
+    __shared__ uint64_t code_lds[4 * kMaxWords];
+    __shared__ int shape_lds[4];
+    const long long p0 = 4LL * blockIdx.x;
+    const long long n = rg.count();
+    if (p0 >= n) return;
+    const int ncell = (int)min(4LL, n - p0);
+    chain_tile_bf16(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, rows + p0 * (long long)net.R * 4, 4,
+                    (long long)net.R * 4, code_lds, shape_lds);
+}
+
+// Unfused clip: one wave per position, four per workgroup.
+template <typename RowT>
+__global__ __launch_bounds__(256) void k_clip(DevNet net, const uint64_t *__restrict__ codes,
+                                              const int *__restrict__ argmax, const uint64_t *__restrict__ cell_hash,
+                                              const int *__restrict__ hints, CellRange rg, long long n_seed_cells,
+                                              const RowT *__restrict__ rows, ClipOut out, Candidates cand,
+                                              unsigned long long cand_cap, Counters *ctr, double margin,
+                                              double vertex_tol, Fallback fb) {
     __shared__ PolyScratch scratch[4];
     const int wave = threadIdx.x >> 6;
-    const long long cell = lo + 4LL * blockIdx.x + wave;
-    if (cell >= hi) return;
-    clip_cell(net, codes, argmax, cell_hash, hints, cell, n_seed_cells, rows + (cell - lo) * (long long)net.R * 4,
-              4, scratch[wave], out, cand, cand_cap, ctr);
+    const long long p = 4LL * blockIdx.x + wave;
+    if (p >= rg.count()) return;
+    clip_cell<RowT>(net, codes, argmax, cell_hash, hints, rg.cell(p), n_seed_cells, rows + p * (long long)net.R * 4,
+                    4, scratch[wave], out, cand, cand_cap, ctr, margin, vertex_tol, fb);
 }
 
 // Fused step: the chain of four cells lands in LDS as [row][cell][4]
@@ -550,22 +852,23 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
     const int wave = threadIdx.x >> 6;
     const long long c0 = lo + 4LL * blockIdx.x;
     const int ncell = (int)min(4LL, hi - c0);
-    chain_tile(net, codes, cell_shape, c0, ncell, zl, 16, 4, code_lds, shape_lds);
+    chain_tile(net, codes, cell_shape, nullptr, c0, ncell, zl, 16, 4, code_lds, shape_lds);
     if (wave >= ncell) return;
-    clip_cell(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zl + wave * 4, 16, scratch[wave], out,
-              cand, cand_cap, ctr);
+    const Fallback none{nullptr, nullptr, 0};
+    clip_cell<double>(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zl + wave * 4, 16,
+                      scratch[wave], out, cand, cand_cap, ctr, 0.0, 0.0, none);
 }
 
-// Repacks padded per-cell rows into the dense [n][N+M][4] layout of am_chain.
-__global__ void k_rows_unpad(DevNet net, long long n, const double *__restrict__ rows,
-                             double *__restrict__ out) {
+// Repacks padded per-cell rows into the dense [n][N+M][4] FP64 layout of am_chain.
+template <typename RowT>
+__global__ void k_rows_unpad(DevNet net, long long n, const RowT *__restrict__ rows, double *__restrict__ out) {
     const int G = net.N + net.M;
     const long long total = n * G;
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
          t += (long long)gridDim.x * blockDim.x) {
         const long long c = t / G;
         const int g = (int)(t % G);
-        const double *src = rows + (c * net.R + net.row_of_unit[g]) * 4;
+        const RowT *src = rows + (c * net.R + net.row_of_unit[g]) * 4;
         double *dst = out + t * 4;
         dst[0] = src[0];
         dst[1] = src[1];
@@ -581,21 +884,58 @@ hipError_t prepare_fused(size_t bytes) {
                                (int)bytes);
 }
 
+static CellRange range_of(long long lo, long long hi, const int *list, const unsigned long long *count,
+                          unsigned long long cap) {
+    CellRange r;
+    r.lo = lo;
+    r.hi = hi;
+    r.list = list;
+    r.list_count = count;
+    r.cap = cap;
+    return r;
+}
+
+// Positions [0, hi - lo) of cells lo..hi-1, or (list != NULL) the first
+// *count entries of list, launched for up to hi - lo positions.
 void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
-                  double *rows, hipStream_t st) {
+                  const int *list, const unsigned long long *count, double *rows, hipStream_t st) {
     if (hi <= lo) return;
     const long long tiles = (hi - lo + 3) / 4;
-    hipLaunchKernelGGL(k_chain_f64, dim3((unsigned)tiles), dim3(256), 0, st, net, codes, cell_shape, lo, hi, rows);
+    hipLaunchKernelGGL(k_chain_f64, dim3((unsigned)tiles), dim3(256), 0, st, net, codes, cell_shape,
+                       range_of(lo, hi, list, count, (unsigned long long)(hi - lo)), rows);
+}
+
+void launch_chain_bf16(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
+                       float *rows, hipStream_t st) {
+    if (hi <= lo) return;
+    const long long tiles = (hi - lo + 3) / 4;
+    hipLaunchKernelGGL(k_chain_bf16, dim3((unsigned)tiles), dim3(256), 0, st, net, codes, cell_shape,
+                       range_of(lo, hi, nullptr, nullptr, 0), rows);
 }
 
 void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
-                 const int *hints, long long lo, long long hi, long long n_seed_cells, const double *rows,
-                 const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, Counters *ctr,
-                 hipStream_t st) {
+                 const int *hints, long long lo, long long hi, const int *list, const unsigned long long *count,
+                 long long n_seed_cells, const double *rows, const ClipOut &out, const Candidates &cand,
+                 unsigned long long cand_cap, Counters *ctr, hipStream_t st) {
     if (hi <= lo) return;
     const long long blocks = (hi - lo + 3) / 4;
-    hipLaunchKernelGGL(k_clip_f64, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints,
-                       lo, hi, n_seed_cells, rows, out, cand, cand_cap, ctr);
+    const Fallback none{nullptr, nullptr, 0};
+    hipLaunchKernelGGL(k_clip<double>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints,
+                       range_of(lo, hi, list, count, (unsigned long long)(hi - lo)), n_seed_cells, rows, out, cand,
+                       cand_cap, ctr, 0.0, 0.0, none);
+}
+
+void launch_clip_f32(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
+                     const int *hints, long long lo, long long hi, long long n_seed_cells, const float *rows,
+                     const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, Counters *ctr,
+                     double margin, double vertex_tol, int *fb_list, unsigned long long *fb_count,
+                     hipStream_t st) {
+    if (hi <= lo) return;
+    const long long blocks = (hi - lo + 3) / 4;
+    const Fallback fb{fb_list, fb_count, (unsigned long long)(hi - lo)};
+    hipLaunchKernelGGL(k_clip<float>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints,
+                       range_of(lo, hi, nullptr, nullptr, 0), n_seed_cells, rows, out, cand, cand_cap, ctr, margin,
+                       vertex_tol, fb);
 }
 
 void launch_fused(const DevNet &net, const uint64_t *codes, const int *cell_shape, const int *argmax,
@@ -608,12 +948,17 @@ void launch_fused(const DevNet &net, const uint64_t *codes, const int *cell_shap
                        cell_shape, argmax, cell_hash, hints, lo, hi, n_seed_cells, out, cand, cand_cap, ctr);
 }
 
-void launch_rows_unpad(const DevNet &net, long long n, const double *rows, double *out, hipStream_t st) {
+void launch_rows_unpad(const DevNet &net, long long n, const void *rows, bool f32, double *out, hipStream_t st) {
     if (n <= 0) return;
     const long long total = n * (net.N + net.M);
     long long blocks = (total + 255) / 256;
     if (blocks > 65535) blocks = 65535;
-    hipLaunchKernelGGL(k_rows_unpad, dim3((unsigned)blocks), dim3(256), 0, st, net, n, rows, out);
+    if (f32)
+        hipLaunchKernelGGL(k_rows_unpad<float>, dim3((unsigned)blocks), dim3(256), 0, st, net, n,
+                           (const float *)rows, out);
+    else
+        hipLaunchKernelGGL(k_rows_unpad<double>, dim3((unsigned)blocks), dim3(256), 0, st, net, n,
+                           (const double *)rows, out);
 }
 
 }  // namespace am

@@ -53,3 +53,44 @@ def compare_meshes(ref, got, vtol=1e-9):
         worst = max(worst, float(err))
     assert worst <= vtol, worst
     return worst
+
+
+def canonical(mesh):
+    """Faces sorted by (code words, argmax); neighbour indices remapped.
+
+    Returns (codes, argmax, m, ids, verts, nbr) with the per-edge arrays
+    concatenated in sorted face order.  Vectorised, for meshes with millions
+    of faces.
+    """
+    codes = np.asarray(mesh.codes, np.uint64)
+    am = np.asarray(mesh.argmax)
+    keys = [am] + [codes[:, w] for w in range(codes.shape[1] - 1, -1, -1)]
+    order = np.lexsort(keys)
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    off = np.asarray(mesh.offsets, np.int64)
+    m = np.diff(off)
+    ms = m[order]
+    starts = off[:-1][order]
+    # edge index list in sorted face order
+    rel = np.arange(ms.sum()) - np.repeat(np.cumsum(ms) - ms, ms)
+    idx = np.repeat(starts, ms) + rel
+    nbr = np.asarray(mesh.nbr, np.int64)[idx]
+    nbr = np.where(nbr >= 0, inv[np.maximum(nbr, 0)], nbr)
+    return codes[order], am[order], ms, np.asarray(mesh.ids)[idx], np.asarray(mesh.verts)[idx], nbr
+
+
+def compare_meshes_fast(ref, got, vtol=1e-9):
+    """compare_meshes for large meshes: same bar, vectorised."""
+    rc, ra, rm, ri, rv, rn = canonical(ref)
+    gc, ga, gm, gi, gv, gn = canonical(got)
+    assert rc.shape == gc.shape, (rc.shape, gc.shape)
+    assert np.array_equal(rc, gc) and np.array_equal(ra, ga), "face sets differ"
+    assert np.array_equal(rm, gm), "polygon sizes differ"
+    assert np.array_equal(ri, gi), "edge id cycles differ"
+    assert np.array_equal(rn, gn), "adjacency differs"
+    scale = np.maximum(1.0, np.repeat(np.abs(rv).reshape(-1, 3).max(axis=1), 1))
+    err = np.abs(gv - rv).max(axis=1) / np.maximum(1.0, np.abs(rv).max(axis=1))
+    worst = float(err.max()) if len(err) else 0.0
+    assert worst <= vtol, worst
+    return worst
