@@ -88,7 +88,15 @@ typedef struct {
                              `margin` + that estimate of a vertex (and no edge is that
                              short), else its cell is redone by the FP64 chain and clip, so
                              cells, cycles and adjacency equal the FP64 result */
-    int32_t reserved[5];
+    int32_t propose;      /* learned form (not in the paper, which sorts planes by distance
+                             in its pivoting routine, Sec. 4.2.1): before the every-line clip,
+                             clip the best k hidden lines near the edge the cell was entered
+                             by.  0: off; 1: ranked by the scorer of am_prop_set; 2: ranked
+                             by distance to that edge's midpoint; 3: off, but count cuts.
+                             The every-line pass decides the face, so results equal
+                             propose 0.  Cells without an entry edge (seeds) are not
+                             proposed for. */
+    int32_t reserved[4];
     double margin;        /* relative sign-test margin of precision 1 (0: 4e-6) */
     double vertex_tol;    /* precision 1: a cell is also redone in FP64 when a vertex's
                              estimated relative error (1.2e-6 x its first-order sensitivity
@@ -119,6 +127,11 @@ typedef struct {
     int32_t fused;            /* 1 if the fused chain+clip kernel ran */
     int32_t pad;
     int64_t escalated;        /* precision 1: cells redone in FP64 */
+    /* propose != 0, over cells with an entry edge: */
+    int64_t prop_cells;       /* such cells */
+    int64_t prop_accepted;    /* ... whose every-line pass cut nothing (the proposals and
+                                 entry lines already gave the face) */
+    int64_t prop_cuts;        /* lines that cut in their every-line passes */
 } am_march_stats;
 
 /* Creates a context on `device` that enqueues its work on `hip_stream`
@@ -217,6 +230,57 @@ am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, 
  * may be NULL to skip that output.  Enqueued. */
 am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                    uint64_t *codes, int32_t *argmax, int32_t *shape_id);
+
+/* ---- Learned form: constraint-proposal scorer.
+ *
+ * The scorer is a ReLU MLP  x (32 features, 8 used) -> 128 -> 128 -> 1 that
+ * gives each hidden line near a cell's entry edge a logit; the best k are
+ * clipped first (opts.propose = 1).  Parameters are FP32, flat, in the order
+ *   W1 [128][32], b1 [128], W2 [128][128], b2 [128], w3 [128], b3
+ * (am_prop_param_count() of them).  The features of a line, in the plane
+ * frame of the cell, relative to the entry edge (the crossed line's segment
+ * between the parent's two neighbouring edges, length h): its signed distance
+ * from the edge's midpoint and from both endpoints, in units of h (clamped to
+ * +-16); the cosine and sine of its normal against the edge direction; its
+ * layer / L; its unit's state bit; log2(h) / 16.  Candidates are the lines
+ * whose midpoint distance is at most rho h. */
+
+/* Number of scorer parameters. */
+int64_t am_prop_param_count(void);
+
+/* Loads the scorer used by propose = 1: params is a HOST array of
+ * am_prop_param_count() FP32 values (copied; matrices stored as FP16 on the
+ * device).  k (1..16) lines are proposed per cell among candidates within
+ * rho (> 0) entry lengths.  AM_E_INVALID on a wrong count or a non-finite
+ * value. */
+am_status am_prop_set(am_ctx *ctx, const float *params, int64_t n_params, int32_t k, float rho);
+
+/* Training samples: every later march of this context appends, for each cell
+ * with an entry edge and a face, one row per candidate line (within rho entry
+ * lengths): samples [cap][32] FP32 features, labels [cap] u8 (1 if the line
+ * carries an edge of the face).  DEVICE buffers owned by the caller; rows
+ * beyond cap are dropped (am_prop_collected reports the total wanted).
+ * NULL buffers or cap <= 0 turn collection off.  Resets the count. */
+am_status am_prop_collect(am_ctx *ctx, float *samples, uint8_t *labels, int64_t cap, float rho);
+
+/* Rows wanted by the marches since am_prop_collect (may exceed cap). */
+am_status am_prop_collected(am_ctx *ctx, int64_t *n);
+
+/* Mean binary cross-entropy of the scorer's logits on n rows (X [n][32] FP32,
+ * y [n] u8, DEVICE) and its gradient: params and grad are DEVICE arrays of
+ * am_prop_param_count() FP32.  FP32 arithmetic, partial sums in FP64.  loss
+ * (HOST, may be NULL) receives the mean loss; then the call synchronises. */
+am_status am_prop_grad(am_ctx *ctx, const float *X, const uint8_t *y, int64_t n, const float *params,
+                       float *grad, double *loss);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected, step >= 1) on
+ * DEVICE arrays params, grad, m, v of am_prop_param_count() FP32.  Enqueued. */
+am_status am_prop_adam(am_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step, float lr);
+
+/* Logits of n feature rows (X [n][32] FP32, DEVICE) by the loaded scorer as
+ * the proposing clip computes them (FP16 operands on matrix cores, FP32
+ * accumulation) into z [n] FP32 (DEVICE).  Enqueued. */
+am_status am_prop_score(am_ctx *ctx, const float *X, int64_t n, float *z);
 
 #ifdef __cplusplus
 }

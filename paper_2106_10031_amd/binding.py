@@ -21,7 +21,9 @@ STATUS_NAMES = {0: "AM_OK", 1: "AM_E_INVALID", 2: "AM_E_OOM", 3: "AM_E_CAPACITY"
 
 # every symbol include/am.h declares
 EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_batch", "am_net_dims", "am_codes",
-           "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch"]
+           "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch",
+           "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
+           "am_prop_adam", "am_prop_score"]
 
 
 class AmError(RuntimeError):
@@ -39,7 +41,8 @@ class NetDesc(C.Structure):
 class MarchOpts(C.Structure):
     _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
                 ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32 * 5), ("margin", C.c_double), ("vertex_tol", C.c_double)]
+                ("propose", C.c_int32), ("reserved", C.c_int32 * 4), ("margin", C.c_double),
+                ("vertex_tol", C.c_double)]
 
 
 class MarchStats(C.Structure):
@@ -50,7 +53,8 @@ class MarchStats(C.Structure):
                 ("march_ms", C.c_double), ("chain_ms", C.c_double), ("clip_ms", C.c_double),
                 ("hash_ms", C.c_double), ("chain_launches", C.c_int64), ("clip_launches", C.c_int64),
                 ("hash_launches", C.c_int64), ("fused", C.c_int32), ("pad", C.c_int32),
-                ("escalated", C.c_int64)]
+                ("escalated", C.c_int64), ("prop_cells", C.c_int64), ("prop_accepted", C.c_int64),
+                ("prop_cuts", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "pad")}
@@ -84,8 +88,17 @@ def lib(path: str = LIB_PATH):
     L.am_march.argtypes = [vp, C.POINTER(MarchOpts), C.POINTER(MarchStats)]
     L.am_get_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.am_prop_param_count.argtypes = []
+    L.am_prop_set.argtypes = [vp, vp, i64, i32, C.c_float]
+    L.am_prop_collect.argtypes = [vp, vp, vp, i64, C.c_float]
+    L.am_prop_collected.argtypes = [vp, C.POINTER(i64)]
+    L.am_prop_grad.argtypes = [vp, vp, vp, i64, vp, vp, C.POINTER(C.c_double)]
+    L.am_prop_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float]
+    L.am_prop_score.argtypes = [vp, vp, i64, vp]
     for name in EXPORTS:
-        if name not in ("am_destroy", "am_last_error"):
+        if name == "am_prop_param_count":
+            L.am_prop_param_count.restype = C.c_int64
+        elif name not in ("am_destroy", "am_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -222,9 +235,9 @@ class Context:
         self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), _p(sh), codes.shape[0]))
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
-              margin=0.0, vertex_tol=0.0):
+              margin=0.0, vertex_tol=0.0, propose=0):
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
-                         int(kernel_path), int(precision))
+                         int(kernel_path), int(precision), int(propose))
         opts.margin = float(margin)
         opts.vertex_tol = float(vertex_tol)
         stats = MarchStats()
@@ -234,6 +247,50 @@ class Context:
             err.stats = stats.as_dict()
             raise err
         return stats.as_dict()
+
+    # ------------------------------------------------------------ learned form
+    def prop_param_count(self):
+        return int(self.L.am_prop_param_count())
+
+    def prop_set(self, params, k=16, rho=6.0):
+        """Loads the proposal scorer (host FP32 parameters, flat)."""
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        self._check(self.L.am_prop_set(self.h, p.ctypes.data_as(C.c_void_p), p.size, int(k), float(rho)))
+
+    def prop_collect(self, samples, labels, rho=6.0):
+        """Later marches append training rows to the device tensors samples
+        [cap][32] float32 and labels [cap] uint8 (None: stop collecting)."""
+        if samples is None:
+            self._check(self.L.am_prop_collect(self.h, None, None, 0, float(rho)))
+            return
+        assert samples.dtype == self.torch.float32 and samples.shape[1] == 32 and labels.dtype == self.torch.uint8
+        assert samples.is_contiguous() and labels.is_contiguous() and labels.shape[0] == samples.shape[0]
+        self._check(self.L.am_prop_collect(self.h, _p(samples), _p(labels), samples.shape[0], float(rho)))
+
+    def prop_collected(self):
+        n = C.c_int64()
+        self._check(self.L.am_prop_collected(self.h, C.byref(n)))
+        return n.value
+
+    def prop_grad(self, X, y, params, grad):
+        """Mean BCE loss (returned) and its gradient into `grad` (device tensors)."""
+        loss = C.c_double()
+        n = X.shape[0]
+        assert X.dtype == self.torch.float32 and X.shape[1] == 32 and X.is_contiguous()
+        assert y.dtype == self.torch.uint8 and y.shape[0] == n and params.is_contiguous() and grad.is_contiguous()
+        self._check(self.L.am_prop_grad(self.h, _p(X), _p(y), n, _p(params), _p(grad), C.byref(loss)))
+        return loss.value
+
+    def prop_adam(self, params, grad, m, v, step, lr):
+        self._check(self.L.am_prop_adam(self.h, _p(params), _p(grad), _p(m), _p(v), int(step), float(lr)))
+
+    def prop_score(self, X):
+        """Logits of the rows of X (device float32 [n][32]) by the loaded scorer."""
+        assert X.dtype == self.torch.float32 and X.shape[1] == 32 and X.is_contiguous()
+        z = self.torch.empty(X.shape[0], dtype=self.torch.float32, device=self.device)
+        self._check(self.L.am_prop_score(self.h, _p(X), X.shape[0], _p(z)))
+        return z
 
     def counts(self):
         f, v, c = C.c_int64(), C.c_int64(), C.c_int64()

@@ -21,10 +21,16 @@
 namespace am {
 void launch_clip(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long, long long,
                  const int *, const unsigned long long *, long long, const double *, const ClipOut &,
-                 const Candidates &, unsigned long long, Counters *, hipStream_t);
+                 const Candidates &, unsigned long long, Counters *, const PropArgs &, hipStream_t);
 void launch_clip_f32(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long,
                      long long, long long, const float *, const ClipOut &, const Candidates &, unsigned long long,
-                     Counters *, double, double, int *, unsigned long long *, hipStream_t);
+                     Counters *, double, double, int *, unsigned long long *, const PropArgs &, hipStream_t);
+void launch_prop_score(const PropNet &, const float *, long long, float *, hipStream_t);
+long long prop_param_count();
+int prop_grad_blocks();
+void launch_prop_grad(const float *, const unsigned char *, long long, const float *, float *, float *, double *,
+                      hipStream_t);
+void launch_prop_adam(float *, const float *, float *, float *, int, float, hipStream_t);
 void launch_chain_bf16(const DevNet &, const uint64_t *, const int *, long long, long long, float *, hipStream_t);
 void launch_chain(const DevNet &, const uint64_t *, const int *, long long, long long, const int *,
                   const unsigned long long *, double *, hipStream_t);
@@ -115,6 +121,17 @@ struct am_ctx {
     char *d_scan = nullptr;
     size_t scan_bytes = 0;
     long long scan_n = 0;
+
+    // learned form: scorer weights (FP16 matrices, FP32 vectors), counters,
+    // collection buffers (caller-owned) and training scratch
+    bool prop_loaded = false;
+    PropArgs prop{};
+    char *d_prop_w = nullptr;
+    unsigned long long *d_prop_stats = nullptr;
+    unsigned long long *d_prop_nsamp = nullptr;
+    float *d_prop_scratch = nullptr;
+    double *d_prop_loss = nullptr;
+    double *h_prop_loss = nullptr;
 
     // last result
     bool have_result = false;
@@ -327,6 +344,8 @@ am_status am_create(am_ctx **out, int device, void *hip_stream) {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
     ctx->lds_limit = (size_t)lds;
+    ctx->prop.k = kPropK;
+    ctx->prop.rho = 6.f;
     *out = ctx;
     return AM_OK;
 }
@@ -338,6 +357,12 @@ void am_destroy(am_ctx *ctx) {
     else (void)hipDeviceSynchronize();
     free_march(ctx);
     free_net(ctx);
+    dfree(ctx->d_prop_w);
+    dfree(ctx->d_prop_stats);
+    dfree(ctx->d_prop_nsamp);
+    dfree(ctx->d_prop_scratch);
+    dfree(ctx->d_prop_loss);
+    if (ctx->h_prop_loss) (void)hipHostFree(ctx->h_prop_loss);
     dfree(ctx->d_ctr);
     if (ctx->h_ctr) (void)hipHostFree(ctx->h_ctr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -576,7 +601,7 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, co
         out.out_base = 0;
         Candidates none{};
         launch_clip(ctx->dn, codes, argmax, nullptr, nullptr, lo, hi, nullptr, nullptr, 0, ctx->d_rows, out, none, 0,
-                    nullptr, ctx->stream);
+                    nullptr, PropArgs{}, ctx->stream);
     }
     HIPCHK(hipGetLastError());
     return AM_OK;
@@ -656,8 +681,23 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     if (o.kernel_path == 2 && !ctx->fused_ok)
         return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
                     fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
-    const bool fused = o.precision == 0 && (o.kernel_path == 2 || (o.kernel_path == 0 && ctx->prefer_fused &&
-                                                                     ctx->fused_ok));
+    if (o.propose < 0 || o.propose > 3) return fail(ctx, AM_E_INVALID, "propose must be 0..3");
+    if (o.propose == 1 && !ctx->prop_loaded) return fail(ctx, AM_E_STATE, "no proposal scorer loaded");
+    const bool collecting = ctx->prop.samples != nullptr;
+    if ((o.propose != 0 || collecting) && o.kernel_path == 2)
+        return fail(ctx, AM_E_INVALID, "proposals and sample collection run on the split path");
+    const bool fused = o.precision == 0 && o.propose == 0 && !collecting &&
+                       (o.kernel_path == 2 || (o.kernel_path == 0 && ctx->prefer_fused && ctx->fused_ok));
+    PropArgs pa = ctx->prop;
+    pa.mode = o.propose;
+    if (o.propose != 0) {
+        if (!ctx->d_prop_stats) TRY(dalloc(ctx, ctx->d_prop_stats, (size_t)kPropStats * kPropSlots));
+        pa.stats = ctx->d_prop_stats;
+        HIPCHK(hipMemsetAsync(ctx->d_prop_stats, 0, sizeof(unsigned long long) * kPropStats * kPropSlots,
+                              ctx->stream));
+    } else {
+        pa.stats = nullptr;
+    }
     // default margin: the largest sign-test error of the split-BF16 rows at an
     // exact vertex, relative to |c|_1 (1 + |v|_inf), was 1.3e-6 over 4,000
     // vertices of the 6x90 sphere-union fit; each vertex adds its own error
@@ -727,15 +767,15 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
             launch_clip_f32(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells,
                             (const float *)ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, margin, vtol,
-                            ctx->d_fb_list, ctx->d_fb_count, s);
+                            ctx->d_fb_list, ctx->d_fb_count, pa, s);
             launch_chain(net, ctx->d_codes, ctx->d_shape, 0, n, ctx->d_fb_list, ctx->d_fb_count, ctx->d_rows, s);
             launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, 0, n, ctx->d_fb_list,
-                        ctx->d_fb_count, seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
+                        ctx->d_fb_count, seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, pa, s);
         } else {
             launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, nullptr, nullptr, ctx->d_rows, s);
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
             launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, nullptr, nullptr,
-                        seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, s);
+                        seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, pa, s);
         }
         if (tk) HIPCHK(hipEventRecord(ctx->evk[2], s));
         const long long nh = n * 6;
@@ -782,6 +822,16 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
 
     st.domain_edges = (long long)c.domain_edges;
     st.escalated = (long long)c.escalated;
+    if (o.propose != 0) {
+        unsigned long long ps[kPropStats * kPropSlots];
+        HIPCHK(hipMemcpy(ps, ctx->d_prop_stats, sizeof ps, hipMemcpyDeviceToHost));
+        long long sum[kPropStats] = {0, 0, 0};
+        for (int i = 0; i < kPropStats; ++i)
+            for (int j = 0; j < kPropSlots; ++j) sum[i] += (long long)ps[i * kPropSlots + j];
+        st.prop_cells = sum[0];
+        st.prop_accepted = sum[1];
+        st.prop_cuts = sum[2];
+    }
     st.degenerate = (long long)c.degenerate;
     st.march_ms = ms;
 
@@ -832,6 +882,121 @@ am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, i
                         ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
                         ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
                         (long long *)nbr, codes, argmax, shape_id, ctx->stream));
+    return AM_OK;
+}
+
+// ---- learned form
+
+int64_t am_prop_param_count(void) { return prop_param_count(); }
+
+am_status am_prop_set(am_ctx *ctx, const float *params, int64_t n_params, int32_t k, float rho) {
+    if (!ctx) return AM_E_INVALID;
+    if (!params || n_params != prop_param_count())
+        return fail(ctx, AM_E_INVALID, "the scorer has %lld parameters", prop_param_count());
+    if (k < 1 || k > kPropK) return fail(ctx, AM_E_INVALID, "k must be 1..%d", kPropK);
+    if (!(rho > 0.f) || !(rho < 1e6f)) return fail(ctx, AM_E_INVALID, "rho must be positive and finite");
+    for (int64_t i = 0; i < n_params; ++i)
+        if (!std::isfinite(params[i])) return fail(ctx, AM_E_INVALID, "non-finite scorer parameter %lld", (long long)i);
+    TRY(set_device(ctx));
+    const int H = kPropH, D = kPropD;
+    // device image: W1 (FP16), W2 (FP16), b1, b2, w3 (FP32)
+    std::vector<_Float16> w1((size_t)H * D), w2((size_t)H * H);
+    for (int i = 0; i < H * D; ++i) w1[i] = (_Float16)params[i];
+    const float *b1 = params + H * D, *W2 = b1 + H, *b2 = W2 + H * H, *w3 = b2 + H;
+    for (int i = 0; i < H * H; ++i) w2[i] = (_Float16)W2[i];
+    const size_t o_w2 = w1.size() * 2, o_b1 = o_w2 + w2.size() * 2, o_b2 = o_b1 + H * 4, o_w3 = o_b2 + H * 4,
+                 total = o_w3 + H * 4;
+    if (!ctx->d_prop_w) TRY(dalloc(ctx, ctx->d_prop_w, total));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(ctx->d_prop_w, w1.data(), w1.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_prop_w + o_w2, w2.data(), w2.size() * 2, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_prop_w + o_b1, b1, H * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_prop_w + o_b2, b2, H * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_prop_w + o_w3, w3, H * 4, hipMemcpyHostToDevice));
+    PropNet &P = ctx->prop.net;
+    P.W1 = (const _Float16 *)ctx->d_prop_w;
+    P.W2 = (const _Float16 *)(ctx->d_prop_w + o_w2);
+    P.b1 = (const float *)(ctx->d_prop_w + o_b1);
+    P.b2 = (const float *)(ctx->d_prop_w + o_b2);
+    P.w3 = (const float *)(ctx->d_prop_w + o_w3);
+    P.b3 = w3[H];
+    ctx->prop.k = k;
+    ctx->prop.rho = rho;
+    ctx->prop_loaded = true;
+    return AM_OK;
+}
+
+am_status am_prop_collect(am_ctx *ctx, float *samples, uint8_t *labels, int64_t cap, float rho) {
+    if (!ctx) return AM_E_INVALID;
+    TRY(set_device(ctx));
+    if (!samples || !labels || cap <= 0) {
+        ctx->prop.samples = nullptr;
+        ctx->prop.labels = nullptr;
+        ctx->prop.cap = 0;
+        return AM_OK;
+    }
+    if (!(rho > 0.f) || !(rho < 1e6f)) return fail(ctx, AM_E_INVALID, "rho must be positive and finite");
+    if (!ctx->d_prop_nsamp) TRY(dalloc(ctx, ctx->d_prop_nsamp, 1));
+    HIPCHK(hipMemsetAsync(ctx->d_prop_nsamp, 0, sizeof(unsigned long long), ctx->stream));
+    ctx->prop.samples = samples;
+    ctx->prop.labels = labels;
+    ctx->prop.cap = (unsigned long long)cap;
+    ctx->prop.n_samples = ctx->d_prop_nsamp;
+    if (!ctx->prop_loaded) ctx->prop.rho = rho;
+    else if (rho != ctx->prop.rho) return fail(ctx, AM_E_INVALID, "rho differs from the loaded scorer's");
+    return AM_OK;
+}
+
+am_status am_prop_collected(am_ctx *ctx, int64_t *n) {
+    if (!ctx || !n) return AM_E_INVALID;
+    *n = 0;
+    if (!ctx->d_prop_nsamp) return AM_OK;
+    TRY(set_device(ctx));
+    unsigned long long v = 0;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(&v, ctx->d_prop_nsamp, sizeof v, hipMemcpyDeviceToHost));
+    *n = (int64_t)v;
+    return AM_OK;
+}
+
+am_status am_prop_grad(am_ctx *ctx, const float *X, const uint8_t *y, int64_t n, const float *params, float *grad,
+                       double *loss) {
+    if (!ctx) return AM_E_INVALID;
+    if (n <= 0 || !X || !y || !params || !grad) return fail(ctx, AM_E_INVALID, "bad arguments");
+    TRY(set_device(ctx));
+    const long long P = prop_param_count();
+    if (!ctx->d_prop_scratch) TRY(dalloc(ctx, ctx->d_prop_scratch, (size_t)prop_grad_blocks() * P + kPropH * kPropH));
+    if (!ctx->d_prop_loss) TRY(dalloc(ctx, ctx->d_prop_loss, (size_t)prop_grad_blocks()));
+    if (!ctx->h_prop_loss) HIPCHK(hipHostMalloc((void **)&ctx->h_prop_loss, sizeof(double) * prop_grad_blocks()));
+    launch_prop_grad(X, y, n, params, grad, ctx->d_prop_scratch, ctx->d_prop_loss, ctx->stream);
+    HIPCHK(hipGetLastError());
+    if (loss) {
+        HIPCHK(hipMemcpyAsync(ctx->h_prop_loss, ctx->d_prop_loss, sizeof(double) * prop_grad_blocks(),
+                              hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        double sum = 0.0;
+        for (int b = 0; b < prop_grad_blocks(); ++b) sum += ctx->h_prop_loss[b];
+        *loss = sum / (double)n;
+    }
+    return AM_OK;
+}
+
+am_status am_prop_adam(am_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step, float lr) {
+    if (!ctx) return AM_E_INVALID;
+    if (!params || !grad || !m || !v || step < 1 || !(lr > 0.f)) return fail(ctx, AM_E_INVALID, "bad arguments");
+    TRY(set_device(ctx));
+    launch_prop_adam(params, grad, m, v, step, lr, ctx->stream);
+    HIPCHK(hipGetLastError());
+    return AM_OK;
+}
+
+am_status am_prop_score(am_ctx *ctx, const float *X, int64_t n, float *z) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->prop_loaded) return fail(ctx, AM_E_STATE, "no proposal scorer loaded");
+    if (n < 0 || (n > 0 && (!X || !z))) return fail(ctx, AM_E_INVALID, "bad arguments");
+    TRY(set_device(ctx));
+    if (n > 0) launch_prop_score(ctx->prop.net, X, n, z, ctx->stream);
+    HIPCHK(hipGetLastError());
     return AM_OK;
 }
 

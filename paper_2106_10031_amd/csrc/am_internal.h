@@ -55,6 +55,37 @@ struct DevNet {
     const uint64_t *zobrist;   // [N + M + S] keys of the cell fingerprint (units, heads, shapes)
 };
 
+// ---- learned form: a scorer ranks the constraint lines near the edge a
+// cell was entered by; the best ones are clipped first, then every line is
+// checked (the plain clip), so the face never depends on the scorer.
+constexpr int kPropD = 32;       // features per line, zero padded (one MFMA K-step)
+constexpr int kPropF = 8;        // features in use
+constexpr int kPropH = 128;      // hidden width of the scorer
+constexpr int kPropK = 16;       // most proposals per cell
+constexpr int kPropSlots = 32;   // counters spread over this many slots
+constexpr int kPropStats = 3;    // cells proposed, cells accepted, cuts in the check pass
+
+struct PropNet {
+    const _Float16 *W1;          // [kPropH][kPropD]
+    const float *b1;             // [kPropH]
+    const _Float16 *W2;          // [kPropH][kPropH]
+    const float *b2;             // [kPropH]
+    const float *w3;             // [kPropH]
+    float b3;
+};
+
+struct PropArgs {
+    int mode;                    // 0 off, 1 scorer, 2 distance order, 3 off but count cuts
+    int k;                       // proposals per cell (<= kPropK)
+    float rho;                   // candidates: distance to the entry midpoint <= rho x entry length
+    PropNet net;
+    float *samples;              // collection (nullptr: off): [cap][kPropD] features
+    unsigned char *labels;       // [cap] 1 if the line carries an edge of the face
+    unsigned long long cap;
+    unsigned long long *n_samples;
+    unsigned long long *stats;   // [kPropStats][kPropSlots]
+};
+
 // Candidate neighbour cells produced by one marching step.
 struct Candidates {
     int *parent;       // cell the candidate was found from; < 0: seed -(1+index)

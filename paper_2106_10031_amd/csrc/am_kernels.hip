@@ -482,16 +482,285 @@ __device__ bool margin_ambiguous(const DevNet &net, const uint64_t *code, int am
     return ballot(amb) != 0;
 }
 
+// ---------------------------------------------------------------- learned form
+
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+// The edge a cell was entered by, in its plane frame: the crossed line and the
+// parent's two edges beside it bound this face too, so their intersections are
+// two vertices of it (generic position).  Uniform over the wave.
+struct EntryEdge {
+    double v1a, v1b, v2a, v2b;   // endpoints
+    double qa, qb;               // midpoint
+    double ta, tb;               // unit direction v1 -> v2
+    double h;                    // length
+    int id[3];                   // the three lines (entry, previous, next)
+};
+
+// Unit-normal 2-D line of constraint `id` in the frame: a x + b y + o <= 0 inside.
+template <typename RowT>
+__device__ bool frame_line(const DevNet &net, int id, const uint64_t *code, int am, const RowT *rb, long long rs,
+                           const double u[3], const double v[3], const double p0[3], double &a, double &b,
+                           double &o) {
+    double c[4];
+    constraint_row(net, id, code, am, rb, rs, c);
+    const double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+    const double cv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
+    const double cw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
+    const double n = sqrt(cu * cu + cv * cv);
+    if (!(n > 0.0)) return false;
+    a = cu / n;
+    b = cv / n;
+    o = cw / n;
+    return true;
+}
+
+template <typename RowT>
+__device__ bool entry_edge(const DevNet &net, const int *hints, long long cell, const uint64_t *code, int am,
+                           const RowT *rb, long long rs, const double u[3], const double v[3], const double p0[3],
+                           EntryEdge &E) {
+    if (!hints) return false;
+    double a[3], b[3], o[3];
+    for (int h = 0; h < 3; ++h) {
+        const int id = hints[cell * 3 + h];
+        if (id < 0 || id >= net.N + net.M || id == net.N + am) return false;
+        E.id[h] = id;
+        if (!frame_line(net, id, code, am, rb, rs, u, v, p0, a[h], b[h], o[h])) return false;
+    }
+    const double d1 = a[0] * b[1] - a[1] * b[0], d2 = a[0] * b[2] - a[2] * b[0];
+    if (fabs(d1) < 1e-9 || fabs(d2) < 1e-9) return false;
+    E.v1a = (b[0] * o[1] - b[1] * o[0]) / d1;
+    E.v1b = (a[1] * o[0] - a[0] * o[1]) / d1;
+    E.v2a = (b[0] * o[2] - b[2] * o[0]) / d2;
+    E.v2b = (a[2] * o[0] - a[0] * o[2]) / d2;
+    const double da = E.v2a - E.v1a, db = E.v2b - E.v1b;
+    E.h = sqrt(da * da + db * db);
+    if (!(E.h > 1e-12) || !(E.h < 8.0)) return false;
+    E.ta = da / E.h;
+    E.tb = db / E.h;
+    E.qa = 0.5 * (E.v1a + E.v2a);
+    E.qb = 0.5 * (E.v1b + E.v2b);
+    return true;
+}
+
+__device__ __forceinline__ float clamp16(double x) { return (float)fmin(16.0, fmax(-16.0, x)); }
+
+// Features of the unit-normal line (a, b, o) of hidden unit g, relative to the
+// entry edge: signed distances of its midpoint and endpoints in entry lengths,
+// the line's direction against the edge, the unit's depth and state, and the
+// edge length.  Returns the midpoint distance in entry lengths.
+__device__ double line_features(const DevNet &net, const EntryEdge &E, int g, int bit, double a, double b, double o,
+                                float f[kPropF]) {
+    const double ih = 1.0 / E.h;
+    const double s = (a * E.qa + b * E.qb + o) * ih;
+    int layer = 1;
+    while (layer + 1 < net.n_layers - 1 && g >= net.unit_off[layer + 1]) ++layer;
+    f[0] = clamp16(s);
+    f[1] = clamp16((a * E.v1a + b * E.v1b + o) * ih);
+    f[2] = clamp16((a * E.v2a + b * E.v2b + o) * ih);
+    f[3] = (float)(a * E.ta + b * E.tb);
+    f[4] = (float)(b * E.ta - a * E.tb);
+    f[5] = (float)layer / (float)(net.n_layers - 2);
+    f[6] = (float)bit;
+    f[7] = (float)(log2(E.h) * (1.0 / 16.0));
+    return s;
+}
+
+__device__ __forceinline__ float wave_max_f(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+
+// Logits of the first `rows` rows of feats [64][kPropD] (FP16) by the scorer
+// relu(W1 x + b1) -> relu(W2 . + b2) -> w3 . + b3, on v_mfma_f32_16x16x32_f16
+// with FP32 accumulation; hs is [16][kPropH] FP16 LDS scratch.  Lane r gets
+// row r's logit (rows >= `rows`: unspecified).
+__device__ float prop_score(const PropNet &P, const _Float16 *feats, _Float16 *hs, int rows) {
+    const int lane = lane_id();
+    const int r16 = lane & 15, q = lane >> 4;
+    float z = 0.f;
+    for (int c = 0; c * 16 < rows; ++c) {
+        const v8h bx = *(const v8h *)(feats + (16 * c + r16) * kPropD + 8 * q);
+#pragma unroll
+        for (int i = 0; i < kPropH / 16; ++i) {
+            const v8h aw = *(const v8h *)(P.W1 + (16 * i + r16) * kPropD + 8 * q);
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(aw, bx, acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int h = 16 * i + 4 * q + r;   // D[4 q + r][r16] of tile i
+                hs[r16 * kPropH + h] = (_Float16)fmaxf(acc[r] + P.b1[h], 0.f);
+            }
+        }
+        wave_lds_sync();
+        float part = 0.f;
+#pragma unroll 2
+        for (int i = 0; i < kPropH / 16; ++i) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < kPropH / 32; ++ks) {
+                const v8h aw = *(const v8h *)(P.W2 + (16 * i + r16) * kPropH + 32 * ks + 8 * q);
+                const v8h bh = *(const v8h *)(hs + r16 * kPropH + 32 * ks + 8 * q);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(aw, bh, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int h = 16 * i + 4 * q + r;
+                part += P.w3[h] * fmaxf(acc[r] + P.b2[h], 0.f);
+            }
+        }
+        wave_lds_sync();
+        part += __shfl_xor(part, 16, kWave);
+        part += __shfl_xor(part, 32, kWave);
+        if (q == c) z = part + P.b3;
+    }
+    return z;
+}
+
+// Per-wave LDS of the proposing clip.
+struct alignas(16) PropScratch {
+    _Float16 feats[kWave * kPropD];
+    _Float16 hs[16 * kPropH];
+    int ids[kWave];
+};
+
+// Merges this lane's candidate (s, id; s = -inf for none) into the running
+// top-k list held by lanes 0..k-1 (tk_s, tk_id), best first.
+__device__ void topk_merge(float s, int id, float &tk_s, int &tk_id, int k) {
+    const int lane = lane_id();
+    float s2 = lane < k ? tk_s : -INFINITY;
+    const int id2 = tk_id;
+    float ns = -INFINITY;
+    int nid = -1;
+    for (int t = 0; t < k; ++t) {
+        const float m = wave_max_f(fmaxf(s, s2));
+        if (m == -INFINITY) break;
+        const uint64_t w1 = ballot(s == m), w2 = ballot(s2 == m);
+        int pick_id;
+        if (w1) {
+            const int src = __builtin_ctzll(w1);
+            pick_id = __builtin_amdgcn_readlane(id, src);
+            if (lane == src) s = -INFINITY;
+        } else {
+            const int src = __builtin_ctzll(w2);
+            pick_id = __builtin_amdgcn_readlane(id2, src);
+            if (lane == src) s2 = -INFINITY;
+        }
+        if (lane == t) {
+            ns = m;
+            nid = pick_id;
+        }
+    }
+    tk_s = ns;
+    tk_id = nid;
+}
+
+// Proposal pass: ranks the hidden lines near the entry edge (distance to its
+// midpoint <= rho entry lengths, the entry lines themselves excluded) by the
+// scorer (mode 1) or by that distance (mode 2, the order the paper's pivoting
+// routine sorts planes in) and returns the best k ids in lanes 0..k-1
+// (-1: none).
+template <typename RowT>
+__device__ int propose_lines(const DevNet &net, const PropArgs &pa, PropScratch *ps, const EntryEdge &E,
+                             const uint64_t *code, int am, const RowT *rb, long long rs, const double u[3],
+                             const double v[3], const double p0[3]) {
+    const int lane = lane_id();
+    float tk_s = -INFINITY;
+    int tk_id = -1;
+    int nbuf = 0;
+    for (int base = 0; base < net.N; base += kWave) {
+        const int g = base + lane;
+        bool cand = false;
+        float f[kPropF];
+        double sd = 0.0;
+        if (g < net.N && g != E.id[0] && g != E.id[1] && g != E.id[2]) {
+            const RowT *z = rb + (long long)net.row_of_unit[g] * rs;
+            const int bit = code_bit(code, g);
+            const double sg = bit ? -1.0 : 1.0;
+            const double c0 = sg * z[0], c1 = sg * z[1], c2 = sg * z[2], c3 = sg * z[3];
+            const double cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
+            const double cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
+            const double cw = c0 * p0[0] + c1 * p0[1] + c2 * p0[2] + c3;
+            const double n = sqrt(cu * cu + cv * cv);
+            if (n > 0.0) {
+                sd = line_features(net, E, g, bit, cu / n, cv / n, cw / n, f);
+                cand = fabs(sd) <= (double)pa.rho;
+            }
+        }
+        if (pa.mode == 2) {
+            topk_merge(cand ? (float)(-fabs(sd)) : -INFINITY, g, tk_s, tk_id, pa.k);
+            continue;
+        }
+        const uint64_t cm = ballot(cand);
+        const int nc = __popcll(cm);
+        if (nc == 0) continue;
+        if (nbuf + nc > kWave) {
+            const float zz = prop_score(pa.net, ps->feats, ps->hs, nbuf);
+            topk_merge(lane < nbuf ? zz : -INFINITY, ps->ids[lane], tk_s, tk_id, pa.k);
+            nbuf = 0;
+            wave_lds_sync();
+        }
+        if (cand) {
+            const int at = nbuf + __popcll(cm & lanemask_lt());
+            _Float16 *row = ps->feats + at * kPropD;
+#pragma unroll
+            for (int j = 0; j < kPropF; ++j) row[j] = (_Float16)f[j];
+#pragma unroll
+            for (int j = kPropF; j < kPropD; ++j) row[j] = (_Float16)0.f;
+            ps->ids[at] = g;
+        }
+        nbuf += nc;
+        wave_lds_sync();
+    }
+    if (pa.mode == 1 && nbuf > 0) {
+        // rows nbuf..63 of the last 16-row group are stale: their logits are dropped
+        const float zz = prop_score(pa.net, ps->feats, ps->hs, nbuf);
+        topk_merge(lane < nbuf ? zz : -INFINITY, ps->ids[lane], tk_s, tk_id, pa.k);
+        wave_lds_sync();
+    }
+    return tk_id;
+}
+
+// Training samples of one finished cell: features of its candidate lines and
+// whether each carries an edge of the face (ids e of lanes < m).
+template <typename RowT>
+__device__ void collect_samples(const DevNet &net, const PropArgs &pa, const EntryEdge &E, const uint64_t *code,
+                                int am, const RowT *rb, long long rs, const double u[3], const double v[3],
+                                const double p0[3], int m, int e) {
+    const int lane = lane_id();
+    for (int base = 0; base < net.N; base += kWave) {
+        const int g = base + lane;
+        bool cand = false;
+        float f[kPropF];
+        if (g < net.N && g != E.id[0] && g != E.id[1] && g != E.id[2]) {
+            double a, b, o;
+            if (frame_line(net, g, code, am, rb, rs, u, v, p0, a, b, o)) {
+                const double sd = line_features(net, E, g, code_bit(code, g), a, b, o, f);
+                cand = fabs(sd) <= (double)pa.rho;
+            }
+        }
+        bool edge = false;
+        for (int k = 0; k < m; ++k) edge |= bcast(e, k) == g;
+        unsigned long long basev;
+        const unsigned long long idx = wave_reserve(pa.n_samples, cand, &basev);
+        if (cand && idx < pa.cap) {
+            float *row = pa.samples + idx * kPropD;
+            for (int j = 0; j < kPropD; ++j) row[j] = j < kPropF ? f[j] : 0.f;
+            pa.labels[idx] = edge ? 1 : 0;
+        }
+    }
+}
+
 // Clips the face of one cell (one wave) and writes it; rows of the cell's
 // chain are read as rb[row * rs + q] (FP64, or FP32 from the split-BF16
 // chain).  margin > 0 (FP32 rows): faces that margin_ambiguous flags, and
 // empty or degenerate results, are not written but appended to fb.
-template <typename RowT>
+template <typename RowT, bool Learn>
 __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ argmax,
                           const uint64_t *__restrict__ cell_hash, const int *__restrict__ hints, long long cell,
                           long long n_seed_cells, const RowT *rb, long long rs, PolyScratch &S, const ClipOut &out,
                           const Candidates &cand, unsigned long long cand_cap, Counters *ctr, double margin,
-                          double vertex_tol, const Fallback &fb) {
+                          double vertex_tol, const Fallback &fb, const PropArgs &pa, PropScratch *ps) {
     const int lane = lane_id();
     const uint64_t *code = codes + cell * net.W;
     const int am_in = argmax ? argmax[cell] : 0;
@@ -504,6 +773,10 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
     // vertex_tol, vertex scale <= 2 in the box) at the final vertices
     const double near_tol = margin > 0.0 ? 2.5 * (margin + vertex_tol) : 0.0;
     int n_near = 0;
+    EntryEdge E;
+    bool have_entry = false;
+    int ncuts = 0;   // lines that cut in the every-line pass
+    (void)ps;
 
     // ---- plane frame: n = a_F[0:3], foot point p0, orthonormal u, v with u x v = n/|n|
     const RowT *aF = rb + (long long)net.row_of_unit[net.N + am] * rs;
@@ -557,6 +830,25 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
                 sh_clip(P, hu, hv, hw, sqrt(hu * hu + hv * hv), id, S, flags);
             }
         }
+        // learned form: clip the proposed lines next; the pass below still
+        // tests every line, so the face does not depend on the proposals
+        if constexpr (Learn) {
+        if ((pa.mode != 0 || pa.samples) && P.m > 0)
+            have_entry = entry_edge(net, hints, cell, code, am, rb, rs, u, v, p0, E);
+        if (have_entry && ((pa.mode == 1 && ps) || pa.mode == 2)) {
+            const int pid = propose_lines(net, pa, ps, E, code, am, rb, rs, u, v, p0);
+            for (int t = 0; t < pa.k && P.m > 0; ++t) {
+                const int id = bcast(pid, t);
+                if (id < 0) break;
+                double c[4];
+                constraint_row(net, id, code, am, rb, rs, c);
+                const double hu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+                const double hv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
+                const double hw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
+                sh_clip(P, hu, hv, hw, sqrt(hu * hu + hv * hv), id, S, flags);
+            }
+        }
+        }
         // hidden units, 64 lines per pass
         for (int base = 0; base < net.N && P.m > 0; base += kWave) {
             const int g = base + lane;
@@ -588,6 +880,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
                 n_near += __popcll(nm);
             }
             uint64_t mask = ballot(valid && cuts);
+            ncuts += __popcll(mask);
             while (mask) {
                 const int t = __builtin_ctzll(mask);
                 mask &= mask - 1;
@@ -733,6 +1026,17 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         if (out.flags) out.flags[oi] = flags;
     }
 
+    if constexpr (Learn) {
+        if (pa.stats && pa.mode != 0 && have_entry && lane == 0) {
+            const int slot = (int)(cell % kPropSlots);
+            atomicAdd(&pa.stats[0 * kPropSlots + slot], 1ull);
+            if (ncuts == 0) atomicAdd(&pa.stats[1 * kPropSlots + slot], 1ull);
+            atomicAdd(&pa.stats[2 * kPropSlots + slot], (unsigned long long)ncuts);
+        }
+        if (pa.samples && have_entry && m > 0)
+            collect_samples(net, pa, E, code, am, rb, rs, u, v, p0, m, e_out);
+    }
+
     if (ctr && lane == 0) {
         if (m == 0) {
             if (cell >= n_seed_cells) atomicAdd(&ctr->degenerate, 1ull);
@@ -825,13 +1129,34 @@ __global__ __launch_bounds__(256) void k_clip(DevNet net, const uint64_t *__rest
                                               const int *__restrict__ hints, CellRange rg, long long n_seed_cells,
                                               const RowT *__restrict__ rows, ClipOut out, Candidates cand,
                                               unsigned long long cand_cap, Counters *ctr, double margin,
-                                              double vertex_tol, Fallback fb) {
+                                              double vertex_tol, Fallback fb, PropArgs pa) {
     __shared__ PolyScratch scratch[4];
     const int wave = threadIdx.x >> 6;
     const long long p = 4LL * blockIdx.x + wave;
     if (p >= rg.count()) return;
-    clip_cell<RowT>(net, codes, argmax, cell_hash, hints, rg.cell(p), n_seed_cells, rows + p * (long long)net.R * 4,
-                    4, scratch[wave], out, cand, cand_cap, ctr, margin, vertex_tol, fb);
+    clip_cell<RowT, false>(net, codes, argmax, cell_hash, hints, rg.cell(p), n_seed_cells,
+                           rows + p * (long long)net.R * 4, 4, scratch[wave], out, cand, cand_cap, ctr, margin,
+                           vertex_tol, fb, pa, nullptr);
+}
+
+// The clip with the learned form's steps (proposals, counting, sample
+// collection) and the scorer's LDS.
+template <typename RowT>
+__global__ __launch_bounds__(256) void k_clip_prop(DevNet net, const uint64_t *__restrict__ codes,
+                                                   const int *__restrict__ argmax,
+                                                   const uint64_t *__restrict__ cell_hash,
+                                                   const int *__restrict__ hints, CellRange rg, long long n_seed_cells,
+                                                   const RowT *__restrict__ rows, ClipOut out, Candidates cand,
+                                                   unsigned long long cand_cap, Counters *ctr, double margin,
+                                                   double vertex_tol, Fallback fb, PropArgs pa) {
+    __shared__ PolyScratch scratch[4];
+    __shared__ PropScratch pscr[4];
+    const int wave = threadIdx.x >> 6;
+    const long long p = 4LL * blockIdx.x + wave;
+    if (p >= rg.count()) return;
+    clip_cell<RowT, true>(net, codes, argmax, cell_hash, hints, rg.cell(p), n_seed_cells,
+                          rows + p * (long long)net.R * 4, 4, scratch[wave], out, cand, cand_cap, ctr, margin,
+                          vertex_tol, fb, pa, &pscr[wave]);
 }
 
 // Fused step: the chain of four cells lands in LDS as [row][cell][4]
@@ -855,8 +1180,28 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
     chain_tile(net, codes, cell_shape, nullptr, c0, ncell, zl, 16, 4, code_lds, shape_lds);
     if (wave >= ncell) return;
     const Fallback none{nullptr, nullptr, 0};
-    clip_cell<double>(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zl + wave * 4, 16,
-                      scratch[wave], out, cand, cand_cap, ctr, 0.0, 0.0, none);
+    const PropArgs off{};
+    clip_cell<double, false>(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zl + wave * 4, 16,
+                             scratch[wave], out, cand, cand_cap, ctr, 0.0, 0.0, none, off, nullptr);
+}
+
+// Logits of n feature rows (FP32 [n][kPropD]) by the scorer the proposing
+// clip uses (FP16 operands, FP32 accumulation); one wave per 64 rows.
+__global__ __launch_bounds__(256) void k_prop_score(PropNet P, const float *__restrict__ X, long long n,
+                                                    float *__restrict__ z) {
+    __shared__ PropScratch ps[4];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const long long r0 = (4LL * blockIdx.x + wave) * kWave;
+    if (r0 >= n) return;
+    const int rows = (int)min((long long)kWave, n - r0);
+    for (int i = lane; i < kWave * kPropD; i += kWave) {
+        const int r = i / kPropD;
+        ps[wave].feats[i] = (_Float16)(r < rows ? X[(r0 + r) * kPropD + (i % kPropD)] : 0.f);
+    }
+    wave_lds_sync();
+    const float zz = prop_score(P, ps[wave].feats, ps[wave].hs, rows);
+    if (lane < rows) z[r0 + lane] = zz;
 }
 
 // Repacks padded per-cell rows into the dense [n][N+M][4] FP64 layout of am_chain.
@@ -916,26 +1261,36 @@ void launch_chain_bf16(const DevNet &net, const uint64_t *codes, const int *cell
 void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
                  const int *hints, long long lo, long long hi, const int *list, const unsigned long long *count,
                  long long n_seed_cells, const double *rows, const ClipOut &out, const Candidates &cand,
-                 unsigned long long cand_cap, Counters *ctr, hipStream_t st) {
+                 unsigned long long cand_cap, Counters *ctr, const PropArgs &pa, hipStream_t st) {
     if (hi <= lo) return;
     const long long blocks = (hi - lo + 3) / 4;
     const Fallback none{nullptr, nullptr, 0};
-    hipLaunchKernelGGL(k_clip<double>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints,
-                       range_of(lo, hi, list, count, (unsigned long long)(hi - lo)), n_seed_cells, rows, out, cand,
-                       cand_cap, ctr, 0.0, 0.0, none);
+    if (pa.mode != 0 || pa.samples)
+        hipLaunchKernelGGL(k_clip_prop<double>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax,
+                           cell_hash, hints, range_of(lo, hi, list, count, (unsigned long long)(hi - lo)),
+                           n_seed_cells, rows, out, cand, cand_cap, ctr, 0.0, 0.0, none, pa);
+    else
+        hipLaunchKernelGGL(k_clip<double>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash,
+                           hints, range_of(lo, hi, list, count, (unsigned long long)(hi - lo)), n_seed_cells, rows,
+                           out, cand, cand_cap, ctr, 0.0, 0.0, none, pa);
 }
 
 void launch_clip_f32(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
                      const int *hints, long long lo, long long hi, long long n_seed_cells, const float *rows,
                      const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, Counters *ctr,
                      double margin, double vertex_tol, int *fb_list, unsigned long long *fb_count,
-                     hipStream_t st) {
+                     const PropArgs &pa, hipStream_t st) {
     if (hi <= lo) return;
     const long long blocks = (hi - lo + 3) / 4;
     const Fallback fb{fb_list, fb_count, (unsigned long long)(hi - lo)};
-    hipLaunchKernelGGL(k_clip<float>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints,
-                       range_of(lo, hi, nullptr, nullptr, 0), n_seed_cells, rows, out, cand, cand_cap, ctr, margin,
-                       vertex_tol, fb);
+    if (pa.mode != 0 || pa.samples)
+        hipLaunchKernelGGL(k_clip_prop<float>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax,
+                           cell_hash, hints, range_of(lo, hi, nullptr, nullptr, 0), n_seed_cells, rows, out, cand,
+                           cand_cap, ctr, margin, vertex_tol, fb, pa);
+    else
+        hipLaunchKernelGGL(k_clip<float>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash,
+                           hints, range_of(lo, hi, nullptr, nullptr, 0), n_seed_cells, rows, out, cand, cand_cap,
+                           ctr, margin, vertex_tol, fb, pa);
 }
 
 void launch_fused(const DevNet &net, const uint64_t *codes, const int *cell_shape, const int *argmax,
@@ -959,6 +1314,11 @@ void launch_rows_unpad(const DevNet &net, long long n, const void *rows, bool f3
     else
         hipLaunchKernelGGL(k_rows_unpad<double>, dim3((unsigned)blocks), dim3(256), 0, st, net, n,
                            (const double *)rows, out);
+}
+
+void launch_prop_score(const PropNet &P, const float *X, long long n, float *z, hipStream_t st) {
+    const long long blocks = (n + 4 * kWave - 1) / (4 * kWave);
+    hipLaunchKernelGGL(k_prop_score, dim3((unsigned)blocks), dim3(256), 0, st, P, X, n, z);
 }
 
 }  // namespace am
