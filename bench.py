@@ -120,14 +120,45 @@ def cpu_baseline(net, o, d, budget_s: float):
                       f"workload, single-threaded C oracle, FP64"}
 
 
-def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells):
+def train_scorer(B, dev, max_cells):
+    """Trains the proposal scorer on the GPU on rows the clip writes while
+    marching the C1 net, the 6x90 fit and the 8x256 fit (at most 2^20 rows
+    each); returns (params, info)."""
+    import torch
+    from am_workloads import seeds
+    from paper_2106_10031_amd import learn
+    t0 = time.perf_counter()
+    Xs, ys = [], []
+    for name in ("c1", "c2", "c3"):
+        net, o, d, _ = workload(name)
+        if name == "c1":
+            o, d = seeds.random_rays(64, seed=11)
+        ctx = B.Context(0).load_net(net)
+        X, y = learn.collect(ctx, torch.as_tensor(o, device=dev), torch.as_tensor(d, device=dev), cap=1 << 20,
+                             max_cells=max_cells)
+        Xs.append(X.clone())
+        ys.append(y.clone())
+        ctx.close()
+    X, y = torch.cat(Xs), torch.cat(ys)
+    t1 = time.perf_counter()
+    ctx = B.Context(0)
+    params, losses = learn.train(ctx, X, y, steps=150, lr=3e-3)
+    ctx.close()
+    t2 = time.perf_counter()
+    return params, {"rows": int(X.shape[0]), "positive_rate": round(float(y.float().mean()), 4),
+                    "loss_first": round(losses[0], 4), "loss_last": round(losses[-1], 4),
+                    "collect_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+                    "steps": 150, "scorer": "8 features (padded 32) -> 128 -> 128 -> 1, FP16 weights on MFMA"}
+
+
+def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0):
     """Times `steps` full passes (seed + march + fetch) after `warmup` passes.
     Kernel-class durations come from HIP events on the library's stream."""
     import torch
 
     def step():
         ctx.seed_rays(o_d, d_d)
-        st = ctx.march(max_cells=max_cells, time_kernels=True, precision=precision)
+        st = ctx.march(max_cells=max_cells, time_kernels=True, precision=precision, propose=propose)
         out = ctx.fetch()
         return st, out
 
@@ -159,8 +190,9 @@ def main(argv=None):
     ap.add_argument("--max-cells", type=int, default=1 << 24)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="bf16,c3,c3_bf16",
-                    help="other forms to time: bf16 (same net), c3, c3_bf16 (8x256 fit); empty for none")
+    ap.add_argument("--forms", default="bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16",
+                    help="other forms to time on the same net (bf16, distance, learned, learned_bf16) and on "
+                         "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16); empty for none")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the bench, copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args(argv)
@@ -184,7 +216,14 @@ def main(argv=None):
         torch.cuda.synchronize()
         return net, o, d, desc, ctx, o_d, d_d
 
+    learned_forms = [f for f in forms_req if "learned" in f]
+    scorer, train_info = (train_scorer(B, dev, a.max_cells) if learned_forms else (None, None))
+    if scorer is not None:
+        print(f"[bench] scorer trained: {train_info}", file=sys.stderr, flush=True)
+
     net, o, d, desc, ctx, o_d, d_d = prepare(a.workload)
+    if scorer is not None:
+        ctx.prop_set(scorer, k=16, rho=6.0)
     main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells)
     print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step",
           file=sys.stderr, flush=True)
@@ -193,13 +232,29 @@ def main(argv=None):
                                      "precision": "FP64 chain (MFMA), FP64 clip and vertex solves"}}
     bf16_desc = ("split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and vertex solves on "
                  "the FP32 rows; cells whose combinatorics or vertices (1e-5) are not certified are redone in FP64")
-    if "bf16" in forms_req:
-        r = time_form(ctx, o_d, d_d, 1, a.steps, a.warmup, a.max_cells)
-        assert r["faces"] == main_run["faces"], "split-BF16 form changed the face count"
-        forms[f"{a.workload}_bf16"] = {"faces_per_s": round(r["faces_per_s"], 1),
-                                       "ms_per_step": round(r["ms_per_step"], 3),
-                                       "escalated_cells": r["stats"]["escalated"], "precision": bf16_desc}
-        print(f"[bench] {a.workload} bf16: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    variants = {"bf16": (1, 0), "distance": (0, 2), "learned": (0, 1), "learned_bf16": (1, 1)}
+    prop_desc = {0: None, 1: "top-16 lines by the trained scorer clipped before the every-line pass",
+                 2: "top-16 lines by distance to the entry edge clipped before the every-line pass"}
+
+    def record(key, r, precision, propose):
+        e = {"faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
+             "faces": r["faces"], "precision": bf16_desc if precision else "FP64 chain (MFMA), FP64 clip"}
+        if precision:
+            e["escalated_cells"] = r["stats"]["escalated"]
+        if propose:
+            st = r["stats"]
+            e["proposals"] = prop_desc[propose]
+            e["accept_rate"] = round(st["prop_accepted"] / max(1, st["prop_cells"]), 4)
+            e["cuts_per_cell_in_check_pass"] = round(st["prop_cuts"] / max(1, st["prop_cells"]), 3)
+        forms[key] = e
+        print(f"[bench] {key}: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+
+    for v, (precision, propose) in variants.items():
+        if v not in forms_req:
+            continue
+        r = time_form(ctx, o_d, d_d, precision, a.steps, a.warmup, a.max_cells, propose=propose)
+        assert r["faces"] == main_run["faces"], f"{v} form changed the face count"
+        record(f"{a.workload}_{v}", r, precision, propose)
 
     # roofline of the dominant kernel of the timed plain steps
     kst = main_run["kernels"]
@@ -225,26 +280,24 @@ def main(argv=None):
     ctx.close()
 
     for name in ("c3",):
-        want_plain, want_bf16 = name in forms_req, f"{name}_bf16" in forms_req
-        if name == a.workload or not (want_plain or want_bf16):
+        todo = [(v, pv) for v, pv in [("plain", (0, 0))] + list(variants.items())
+                if (name if v == "plain" else f"{name}_{v}") in forms_req]
+        if name == a.workload or not todo:
             continue
         net3, _, _, _, ctx3, o3, d3 = prepare(name)
+        if scorer is not None:
+            ctx3.prop_set(scorer, k=16, rho=6.0)
         steps3 = max(1, min(a.steps, 3))
         base = None
-        if want_plain:
-            r = time_form(ctx3, o3, d3, 0, steps3, 1, a.max_cells)
-            base = r["faces"]
-            forms[f"{name}_plain"] = {"faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
-                                      "faces": r["faces"], "precision": "FP64 chain (MFMA), FP64 clip and vertex solves"}
-            print(f"[bench] {name} plain: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
-        if want_bf16:
-            r = time_form(ctx3, o3, d3, 1, steps3, 1, a.max_cells)
-            assert base is None or r["faces"] == base, "split-BF16 form changed the face count"
-            forms[f"{name}_bf16"] = {"faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
-                                     "faces": r["faces"], "escalated_cells": r["stats"]["escalated"],
-                                     "precision": bf16_desc}
-            print(f"[bench] {name} bf16: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+        for v, (precision, propose) in todo:
+            r = time_form(ctx3, o3, d3, precision, steps3, 1, a.max_cells, propose=propose)
+            if base is None:
+                base = r["faces"]
+            assert r["faces"] == base, f"{name} {v} form changed the face count"
+            record(f"{name}_{v}", r, precision, propose)
         ctx3.close()
+    if train_info:
+        forms["scorer_training"] = train_info
 
     st = main_run["stats"]
     res = {"metric": METRIC, "value": round(main_run["faces_per_s"], 1), "unit": "faces/s", "n_gpus": 1,
