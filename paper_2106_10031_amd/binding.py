@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "AM_OK", 1: "AM_E_INVALID", 2: "AM_E_OOM", 3: "AM_E_CAPACITY"
 EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_batch", "am_net_dims", "am_codes",
            "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch",
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
-           "am_prop_adam", "am_prop_score"]
+           "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups"]
 
 
 class AmError(RuntimeError):
@@ -41,7 +41,8 @@ class NetDesc(C.Structure):
 class MarchOpts(C.Structure):
     _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
                 ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("precision", C.c_int32),
-                ("propose", C.c_int32), ("reserved", C.c_int32 * 4), ("margin", C.c_double),
+                ("propose", C.c_int32), ("chain_groups", C.c_int32), ("reserved", C.c_int32 * 3),
+                ("margin", C.c_double),
                 ("vertex_tol", C.c_double)]
 
 
@@ -95,6 +96,9 @@ def lib(path: str = LIB_PATH):
     L.am_prop_grad.argtypes = [vp, vp, vp, i64, vp, vp, C.POINTER(C.c_double)]
     L.am_prop_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float]
     L.am_prop_score.argtypes = [vp, vp, i64, vp]
+    L.am_tune_chain.argtypes = [vp, i32, vp]
+    L.am_set_chain_groups.argtypes = [vp, vp]
+    L.am_get_chain_groups.argtypes = [vp, vp]
     for name in EXPORTS:
         if name == "am_prop_param_count":
             L.am_prop_param_count.restype = C.c_int64
@@ -235,9 +239,9 @@ class Context:
         self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), _p(sh), codes.shape[0]))
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
-              margin=0.0, vertex_tol=0.0, propose=0):
+              margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0):
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
-                         int(kernel_path), int(precision), int(propose))
+                         int(kernel_path), int(precision), int(propose), int(chain_groups))
         opts.margin = float(margin)
         opts.vertex_tol = float(vertex_tol)
         stats = MarchStats()
@@ -247,6 +251,27 @@ class Context:
             err.stats = stats.as_dict()
             raise err
         return stats.as_dict()
+
+    # ------------------------------------------------------------ chain tiles
+    def tune_chain(self, reps=5):
+        """Times the chain tiles on the last march's cells and keeps the
+        fastest per launch size; returns (groups[4], ms[4][3])."""
+        import numpy as np
+        ms = np.zeros(12, dtype=np.float32)
+        self._check(self.L.am_tune_chain(self.h, int(reps), ms.ctypes.data_as(C.c_void_p)))
+        return self.chain_groups(), ms.reshape(4, 3)
+
+    def chain_groups(self):
+        import numpy as np
+        g = np.zeros(4, dtype=np.int32)
+        self._check(self.L.am_get_chain_groups(self.h, g.ctypes.data_as(C.c_void_p)))
+        return [int(x) for x in g]
+
+    def set_chain_groups(self, groups):
+        import numpy as np
+        g = np.ascontiguousarray(np.asarray(groups, dtype=np.int32))
+        assert g.shape == (4,)
+        self._check(self.L.am_set_chain_groups(self.h, g.ctypes.data_as(C.c_void_p)))
 
     # ------------------------------------------------------------ learned form
     def prop_param_count(self):

@@ -33,7 +33,7 @@ void launch_prop_grad(const float *, const unsigned char *, long long, const flo
 void launch_prop_adam(float *, const float *, float *, float *, int, float, hipStream_t);
 void launch_chain_bf16(const DevNet &, const uint64_t *, const int *, long long, long long, float *, hipStream_t);
 void launch_chain(const DevNet &, const uint64_t *, const int *, long long, long long, const int *,
-                  const unsigned long long *, double *, hipStream_t);
+                  const unsigned long long *, double *, int, hipStream_t);
 void launch_fused(const DevNet &, const uint64_t *, const int *, const int *, const uint64_t *, const int *, long long,
                   long long, long long, const ClipOut &, const Candidates &, unsigned long long, Counters *,
                   hipStream_t);
@@ -122,6 +122,10 @@ struct am_ctx {
     size_t scan_bytes = 0;
     long long scan_n = 0;
 
+    // chain tile: column groups per workgroup by launch size (< 2^11, < 2^13,
+    // < 2^15, larger), set by am_tune_chain or am_set_chain_groups
+    int chain_g[4] = {1, 1, 1, 1};
+
     // learned form: scorer weights (FP16 matrices, FP32 vectors), counters,
     // collection buffers (caller-owned) and training scratch
     bool prop_loaded = false;
@@ -139,6 +143,15 @@ struct am_ctx {
 };
 
 namespace {
+
+constexpr long long kChainBucket[3] = {1LL << 11, 1LL << 13, 1LL << 15};
+
+int chain_groups(const am_ctx *ctx, long long n, int forced) {
+    if (forced > 0) return forced;
+    int b = 0;
+    while (b < 3 && n >= kChainBucket[b]) ++b;
+    return ctx->chain_g[b];
+}
 
 am_status fail(am_ctx *c, am_status s, const char *fmt, ...) {
     char buf[512];
@@ -571,7 +584,8 @@ am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, 
             launch_rows_unpad(ctx->dn, hi - lo, ctx->d_rows, true, rows + lo * 4 * (ctx->dn.N + ctx->dn.M),
                               ctx->stream);
         } else {
-            launch_chain(ctx->dn, codes, shape_id, lo, hi, nullptr, nullptr, ctx->d_rows, ctx->stream);
+            launch_chain(ctx->dn, codes, shape_id, lo, hi, nullptr, nullptr, ctx->d_rows,
+                     chain_groups(ctx, hi - lo, 0), ctx->stream);
             launch_rows_unpad(ctx->dn, hi - lo, ctx->d_rows, false, rows + lo * 4 * (ctx->dn.N + ctx->dn.M),
                               ctx->stream);
         }
@@ -590,7 +604,8 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, co
     TRY(ensure_march(ctx, std::max<long long>(ctx->cap_cells, 1024)));
     for (long long lo = 0; lo < n; lo += ctx->chunk_cells) {
         const long long hi = std::min<long long>(n, lo + ctx->chunk_cells);
-        launch_chain(ctx->dn, codes, shape_id, lo, hi, nullptr, nullptr, ctx->d_rows, ctx->stream);
+        launch_chain(ctx->dn, codes, shape_id, lo, hi, nullptr, nullptr, ctx->d_rows,
+                     chain_groups(ctx, hi - lo, 0), ctx->stream);
         ClipOut out{};
         out.m = m;
         out.ids = ids;
@@ -682,6 +697,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
                     fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
     if (o.propose < 0 || o.propose > 3) return fail(ctx, AM_E_INVALID, "propose must be 0..3");
+    if (o.chain_groups != 0 && o.chain_groups != 1 && o.chain_groups != 2 && o.chain_groups != 4)
+        return fail(ctx, AM_E_INVALID, "chain_groups must be 0, 1, 2 or 4");
     if (o.propose == 1 && !ctx->prop_loaded) return fail(ctx, AM_E_STATE, "no proposal scorer loaded");
     const bool collecting = ctx->prop.samples != nullptr;
     if ((o.propose != 0 || collecting) && o.kernel_path == 2)
@@ -768,11 +785,13 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             launch_clip_f32(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells,
                             (const float *)ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, margin, vtol,
                             ctx->d_fb_list, ctx->d_fb_count, pa, s);
-            launch_chain(net, ctx->d_codes, ctx->d_shape, 0, n, ctx->d_fb_list, ctx->d_fb_count, ctx->d_rows, s);
+            launch_chain(net, ctx->d_codes, ctx->d_shape, 0, n, ctx->d_fb_list, ctx->d_fb_count, ctx->d_rows,
+                         chain_groups(ctx, n, o.chain_groups), s);
             launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, 0, n, ctx->d_fb_list,
                         ctx->d_fb_count, seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, pa, s);
         } else {
-            launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, nullptr, nullptr, ctx->d_rows, s);
+            launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, nullptr, nullptr, ctx->d_rows,
+                         chain_groups(ctx, n, o.chain_groups), s);
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
             launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, nullptr, nullptr,
                         seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, pa, s);
@@ -882,6 +901,57 @@ am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, i
                         ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
                         ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
                         (long long *)nbr, codes, argmax, shape_id, ctx->stream));
+    return AM_OK;
+}
+
+// ---- chain tile autotuner
+
+am_status am_set_chain_groups(am_ctx *ctx, const int32_t *groups) {
+    if (!ctx || !groups) return AM_E_INVALID;
+    for (int b = 0; b < 4; ++b)
+        if (groups[b] != 1 && groups[b] != 2 && groups[b] != 4)
+            return fail(ctx, AM_E_INVALID, "column groups must be 1, 2 or 4");
+    for (int b = 0; b < 4; ++b) ctx->chain_g[b] = groups[b];
+    return AM_OK;
+}
+
+am_status am_get_chain_groups(const am_ctx *ctx, int32_t *groups) {
+    if (!ctx || !groups) return AM_E_INVALID;
+    for (int b = 0; b < 4; ++b) groups[b] = ctx->chain_g[b];
+    return AM_OK;
+}
+
+am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->have_result || ctx->res_cells <= 0) return fail(ctx, AM_E_STATE, "tuning needs a finished march");
+    if (reps < 1 || reps > 100) return fail(ctx, AM_E_INVALID, "reps must be 1..100");
+    TRY(set_device(ctx));
+    const int gs[3] = {1, 2, 4};
+    const long long sizes[4] = {1LL << 10, 1LL << 12, 1LL << 14, 1LL << 16};
+    hipStream_t s = ctx->stream;
+    for (int b = 0; b < 4; ++b) {
+        const long long n = std::min<long long>({sizes[b], ctx->res_cells, ctx->chunk_cells});
+        float best = 0.f;
+        int best_g = 1;
+        for (int gi = 0; gi < 3; ++gi) {
+            launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, gs[gi], s);
+            HIPCHK(hipEventRecord(ctx->evk[0], s));
+            for (int r = 0; r < reps; ++r)
+                launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, gs[gi], s);
+            HIPCHK(hipEventRecord(ctx->evk[1], s));
+            HIPCHK(hipEventSynchronize(ctx->evk[1]));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->evk[0], ctx->evk[1]));
+            ms /= (float)reps;
+            if (ms_out) ms_out[b * 3 + gi] = ms;
+            if (gi == 0 || ms < best) {
+                best = ms;
+                best_g = gs[gi];
+            }
+        }
+        ctx->chain_g[b] = best_g;
+    }
+    HIPCHK(hipGetLastError());
     return AM_OK;
 }
 

@@ -58,14 +58,16 @@ __device__ __forceinline__ long long tile_cell(const int *list, long long p0, in
     return list ? (long long)list[p0 + c] : p0 + c;
 }
 
-// Stages the codes and shape ids of a tile's cells in LDS (ends with a barrier).
+// Stages the codes and shape ids of a tile's ncell (<= nmax) cells in LDS
+// (ends with a barrier).
 __device__ void stage_tile(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ cell_shape,
-                           const int *list, long long p0, int ncell, uint64_t *code_lds, int *shape_lds) {
-    for (int t = threadIdx.x; t < 4 * net.W; t += blockDim.x) {
+                           const int *list, long long p0, int ncell, uint64_t *code_lds, int *shape_lds,
+                           int nmax = 4) {
+    for (int t = threadIdx.x; t < nmax * net.W; t += blockDim.x) {
         const int c = t / net.W;
         code_lds[t] = c < ncell ? codes[tile_cell(list, p0, c) * net.W + (t - c * net.W)] : 0ull;
     }
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < nmax) {
         const int c = threadIdx.x;
         const int sh = (cell_shape && c < ncell) ? cell_shape[tile_cell(list, p0, c)] : 0;
         shape_lds[c] = (sh >= 0 && sh < net.S) ? sh : 0;
@@ -73,6 +75,14 @@ __device__ void stage_tile(const DevNet &net, const uint64_t *__restrict__ codes
     __syncthreads();
 }
 
+// Affine chain of the 4 G cells c0..c0+ncell-1 of a tile: G groups of 16 MFMA
+// columns (cell = 4 g + col / 4, homogeneous component q = col % 4).  Element
+// (row, cell, q) of the rows is zb[row * rs + cell * cs + q].  Each wave takes
+// two 16-row output tiles at a time (mt and mt + nwaves), so that every A
+// fragment (weights) feeds 2 G MFMAs and every B value feeds two: a tile of
+// 4 G cells streams each weight block from L2 once.  Operands of KC K-steps
+// are loaded before their MFMAs issue.  Ends with a barrier.
+template <int G, int KC>
 __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes,
                            const int *__restrict__ cell_shape, const int *list, long long c0, int ncell, double *zb,
                            long long rs, long long cs, uint64_t *code_lds, int *shape_lds) {
@@ -82,12 +92,20 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
     const int col = lane & 15;       // MFMA column (B, D) / row within the tile (A)
     const int kq = lane >> 4;        // k within the K-step of 4 (A, B) / row offset (D)
     const int q = col & 3;           // homogeneous component of this column
-    const int cl = col >> 2;         // cell of this column within the tile
-    const bool cell_ok = cl < ncell;
-    stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds);
-    const long long bias_base = (long long)shape_lds[cl] * net.bias_stride;
-    const uint64_t *code = code_lds + cl * net.W;
-    double *zc = zb + cl * cs + q;
+    const int cl = col >> 2;         // cell of this column within its group
+    stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds, 4 * G);
+    long long bias_base[G];
+    const uint64_t *code[G];
+    double *zc[G];
+    bool cell_ok[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int c = 4 * g + cl;
+        cell_ok[g] = c < ncell;
+        bias_base[g] = (long long)shape_lds[c] * net.bias_stride;
+        code[g] = code_lds + c * net.W;
+        zc[g] = zb + c * cs + q;
+    }
 
     for (int l = 1; l < net.n_layers; ++l) {
         const int nl = net.width[l];
@@ -95,7 +113,12 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
         for (int mt0 = wave; mt0 < mtiles; mt0 += 2 * nwaves) {
             const int mt1 = mt0 + nwaves;
             const bool two = mt1 < mtiles;
-            v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+            v4d acc0[G], acc1[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                acc0[g] = v4d{0.0, 0.0, 0.0, 0.0};
+                acc1[g] = v4d{0.0, 0.0, 0.0, 0.0};
+            }
             for (int b = 0; b < net.n_blocks; ++b) {
                 if (net.blk_dst[b] != l) continue;
                 const int j = net.blk_src[b];
@@ -107,41 +130,53 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
                 if (j == 0) {
                     // Z_0 = [I | 0]: one K-step; row k of B is e_k for k < 3
                     const double bv = (kq < 3 && kq == q) ? 1.0 : 0.0;
-                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fr0[0], bv, acc0, 0, 0, 0);
-                    if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fr1[0], bv, acc1, 0, 0, 0);
+                    const double a0 = fr0[0], a1 = two ? fr1[0] : 0.0;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        acc0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0[g], 0, 0, 0);
+                        if (two) acc1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1[g], 0, 0, 0);
+                    }
                     continue;
                 }
                 const int uoff = net.unit_off[j];
-                const double *zj = zc + (long long)net.row_off[j] * rs;
-                for (int ks0 = 0; ks0 < ks_n; ks0 += kKChunk) {
-                    double a0[kKChunk], a1[kKChunk], bv[kKChunk];
+                const long long roff = (long long)net.row_off[j] * rs;
+                for (int ks0 = 0; ks0 < ks_n; ks0 += KC) {
+                    double a0[KC], a1[KC], bv[G][KC];
 #pragma unroll
-                    for (int u = 0; u < kKChunk; ++u) {
+                    for (int u = 0; u < KC; ++u) {
                         const int ks = ks0 + u;
                         const bool kv = ks < ks_n;
                         const int k = ks * 4 + kq;
                         a0[u] = kv ? fr0[ks * 64] : 0.0;
                         a1[u] = (kv && two) ? fr1[ks * 64] : 0.0;
-                        bv[u] = (kv && k < nj && cell_ok && code_bit(code, uoff + k)) ? zj[k * rs] : 0.0;
+#pragma unroll
+                        for (int g = 0; g < G; ++g)
+                            bv[g][u] = (kv && k < nj && cell_ok[g] && code_bit(code[g], uoff + k))
+                                           ? zc[g][roff + k * rs] : 0.0;
                     }
 #pragma unroll
-                    for (int u = 0; u < kKChunk; ++u) {
-                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc0, 0, 0, 0);
-                        if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc1, 0, 0, 0);
+                    for (int u = 0; u < KC; ++u) {
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            acc0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[g][u], acc0[g], 0, 0, 0);
+                            if (two) acc1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[g][u], acc1[g], 0, 0, 0);
+                        }
                     }
                 }
             }
-            if (cell_ok) {
-                const double *bias = net.bias + bias_base + net.bias_off[l];
-                // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r of
-                // lane (kq * 16 + col)
-                double *z0 = zc + (long long)net.row_off[l] * rs;
+            // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r of
+            // lane (kq * 16 + col)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (!cell_ok[g]) continue;
+                const double *bias = net.bias + bias_base[g] + net.bias_off[l];
+                double *z0 = zc[g] + (long long)net.row_off[l] * rs;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i0 = mt0 * 16 + kq + 4 * r;
-                    if (i0 < nl) z0[i0 * rs] = acc0[r] + (q == 3 ? bias[i0] : 0.0);
+                    if (i0 < nl) z0[i0 * rs] = acc0[g][r] + (q == 3 ? bias[i0] : 0.0);
                     const int i1 = mt1 * 16 + kq + 4 * r;
-                    if (two && i1 < nl) z0[i1 * rs] = acc1[r] + (q == 3 ? bias[i1] : 0.0);
+                    if (two && i1 < nl) z0[i1 * rs] = acc1[g][r] + (q == 3 ? bias[i1] : 0.0);
                 }
             }
         }
@@ -1094,18 +1129,20 @@ struct CellRange {
     __device__ long long tile_base(long long p) const { return list ? p : lo + p; }
 };
 
-// Unfused FP64 chain: rows of position p go to rows[p][R][4].
+// Unfused FP64 chain, 4 G cells per workgroup: rows of position p go to
+// rows[p][R][4].
+template <int G, int KC>
 __global__ __launch_bounds__(256) void k_chain_f64(DevNet net, const uint64_t *__restrict__ codes,
                                                    const int *__restrict__ cell_shape, CellRange rg,
                                                    double *__restrict__ rows) {
-    __shared__ uint64_t code_lds[4 * kMaxWords];
-    __shared__ int shape_lds[4];
-    const long long p0 = 4LL * blockIdx.x;
+    __shared__ uint64_t code_lds[4 * G * kMaxWords];
+    __shared__ int shape_lds[4 * G];
+    const long long p0 = 4LL * G * blockIdx.x;
     const long long n = rg.count();
     if (p0 >= n) return;
-    const int ncell = (int)min(4LL, n - p0);
-    chain_tile(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, rows + p0 * (long long)net.R * 4, 4,
-               (long long)net.R * 4, code_lds, shape_lds);
+    const int ncell = (int)min(4LL * G, n - p0);
+    chain_tile<G, KC>(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, rows + p0 * (long long)net.R * 4,
+                      4, (long long)net.R * 4, code_lds, shape_lds);
 }
 
 // Split-BF16 chain: FP32 rows of position p go to rows[p][R][4].
@@ -1177,7 +1214,7 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
     const int wave = threadIdx.x >> 6;
     const long long c0 = lo + 4LL * blockIdx.x;
     const int ncell = (int)min(4LL, hi - c0);
-    chain_tile(net, codes, cell_shape, nullptr, c0, ncell, zl, 16, 4, code_lds, shape_lds);
+    chain_tile<1, kKChunk>(net, codes, cell_shape, nullptr, c0, ncell, zl, 16, 4, code_lds, shape_lds);
     if (wave >= ncell) return;
     const Fallback none{nullptr, nullptr, 0};
     const PropArgs off{};
@@ -1242,12 +1279,21 @@ static CellRange range_of(long long lo, long long hi, const int *list, const uns
 
 // Positions [0, hi - lo) of cells lo..hi-1, or (list != NULL) the first
 // *count entries of list, launched for up to hi - lo positions.
+// g: column groups per workgroup (1, 2 or 4; 4 g cells per workgroup).
 void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
-                  const int *list, const unsigned long long *count, double *rows, hipStream_t st) {
+                  const int *list, const unsigned long long *count, double *rows, int g, hipStream_t st) {
     if (hi <= lo) return;
-    const long long tiles = (hi - lo + 3) / 4;
-    hipLaunchKernelGGL(k_chain_f64, dim3((unsigned)tiles), dim3(256), 0, st, net, codes, cell_shape,
-                       range_of(lo, hi, list, count, (unsigned long long)(hi - lo)), rows);
+    const CellRange rg = range_of(lo, hi, list, count, (unsigned long long)(hi - lo));
+    const long long n = hi - lo;
+    if (g >= 4)
+        hipLaunchKernelGGL((k_chain_f64<4, 4>), dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, net, codes,
+                           cell_shape, rg, rows);
+    else if (g == 2)
+        hipLaunchKernelGGL((k_chain_f64<2, 4>), dim3((unsigned)((n + 7) / 8)), dim3(256), 0, st, net, codes,
+                           cell_shape, rg, rows);
+    else
+        hipLaunchKernelGGL((k_chain_f64<1, kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net, codes,
+                           cell_shape, rg, rows);
 }
 
 void launch_chain_bf16(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,

@@ -1,0 +1,92 @@
+"""Chain tiles of 4, 8 and 16 cells per workgroup, and the tile autotuner.
+
+Bar: each tile width reproduces the oracle's mesh (cells, cycles, adjacency
+exact; vertices 1e-9) on nets with shortcuts, max-pooled heads and per-shape
+biases, and the 6x90 fit's mesh is identical across widths and after tuning.
+"""
+import numpy as np
+import pytest
+
+from am_workloads import nets, seeds
+from gpu_common import compare_meshes, compare_meshes_fast, fetch_host, say
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_10031_amd import binding as B
+    return B
+
+
+NETS = {
+    "c1": nets.c1_net,
+    "maxpool_cube": nets.maxpool_cube_net,
+    "sphere_like_2x24": lambda: nets.random_sphere_like([24, 24], seed=5, radius=0.6, scale=0.4),
+    "shortcut_cube_mlp": lambda: nets.shortcut_cube_mlp([20, 20], seed=2),
+}
+
+
+@pytest.mark.parametrize("groups", [2, 4])
+@pytest.mark.parametrize("name", list(NETS))
+def test_tile_widths_match_oracle(binding, name, groups):
+    net = NETS[name]()
+    o, d = seeds.random_rays(16, seed=4)
+    on = O.OracleNet(net)
+    codes, ams, _, _ = on.seed_rays(o, d)
+    ref = on.march(codes, ams)
+    say("chain tile", name, "groups", groups, ref.n_faces, "faces")
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    st = ctx.march(kernel_path=1, chain_groups=groups)
+    assert st["faces"] == ref.n_faces
+    compare_meshes(ref, fetch_host(ctx))
+    ctx.close()
+
+
+@pytest.mark.parametrize("groups", [2, 4])
+def test_tile_widths_batched(binding, groups):
+    sb = nets.latent_sphere_batch([16, 16, 16], reinject=3, latent_dim=8, n_shapes=6, seed=3)
+    o, d, sh = [], [], []
+    for s in range(sb.n_shapes):
+        a, b = seeds.random_rays(12, seed=100 + s)
+        o.append(a); d.append(b); sh.append(np.full(12, s, np.int32))
+    o, d, sh = np.concatenate(o), np.concatenate(d), np.concatenate(sh)
+    say("batched chain tile groups", groups)
+    ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+    ctx.seed_rays(o, d, shape_id=sh)
+    ctx.march(kernel_path=1, chain_groups=1)
+    ref = fetch_host(ctx)
+    ctx.seed_rays(o, d, shape_id=sh)
+    ctx.march(kernel_path=1, chain_groups=groups)
+    compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+    ctx.close()
+
+
+def test_tuner_keeps_the_mesh(binding):
+    net = nets.load_fitted("c2")
+    prim = np.load(nets.DATA_DIR + "/c2_primitives.npz")
+    o, d = seeds.centre_rays(prim["p0"], 128)
+    say("c2 tiles and tuner")
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    ctx.march(max_cells=1 << 21, chain_groups=1)
+    ref = fetch_host(ctx)
+    for g in (2, 4):
+        ctx.seed_rays(o, d)
+        ctx.march(max_cells=1 << 21, chain_groups=g)
+        compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+    groups, ms = ctx.tune_chain(reps=3)
+    say("tuned groups", groups, "ms", np.round(ms, 4).tolist())
+    assert all(g in (1, 2, 4) for g in groups)
+    assert np.all(ms > 0)
+    ctx.seed_rays(o, d)
+    ctx.march(max_cells=1 << 21)
+    compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+    with pytest.raises(binding.AmError):
+        ctx.set_chain_groups([1, 3, 1, 1])
+    ctx.close()
