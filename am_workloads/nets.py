@@ -372,14 +372,15 @@ class ShapeBatch:
 
 
 def latent_sphere_batch(hidden: Sequence[int], reinject: int, latent_dim: int, n_shapes: int, seed: int,
-                        latent_std: float = 0.3, radius=(0.4, 0.8), scale: float = 0.4) -> ShapeBatch:
+                        latent_std: float = 0.3, radius=(0.4, 0.8), scale: float = 0.4,
+                        log_radii: bool = False) -> ShapeBatch:
     """A latent-conditioned decoder ``scale * MLP([x; z]) + |x|_1 - r_s``.
 
     The MLP takes [x; z] at layer 1 and again at layer ``reinject`` (a linear
     shortcut from the input, Sec. 5.1); the latent terms W_z z_s are folded
     into the biases of those layers.  Shape s has latent z_s ~ N(0, latent_std^2)
-    and radius r_s spread over ``radius`` (so the shapes' sizes, and cell
-    counts, differ).  The L1 norm uses |t| = 2 relu(t) - t (three extra units
+    and radius r_s spread over ``radius``, evenly or (log_radii) geometrically,
+    so the shapes' sizes, and cell counts, differ.  The L1 norm uses |t| = 2 relu(t) - t (three extra units
     of layer 1 and an input shortcut to the head).
     """
     rng = np.random.default_rng(seed)
@@ -401,7 +402,7 @@ def latent_sphere_batch(hidden: Sequence[int], reinject: int, latent_dim: int, n
     Wout = rng.normal(0.0, np.sqrt(2.0 / hidden[-1]), (1, hidden[-1]))
     bout = rng.normal(0.0, 0.05, 1)
     Z = rng.normal(0.0, latent_std, (n_shapes, latent_dim))
-    radii = np.linspace(radius[0], radius[1], n_shapes)
+    radii = (np.geomspace if log_radii else np.linspace)(radius[0], radius[1], n_shapes)
 
     widths = [3, hidden[0] + 3] + list(hidden[1:]) + [1]
     B10 = np.zeros((hidden[0] + 3, 3)); B10[:hidden[0]] = Wx[0]; B10[hidden[0]:] = np.eye(3)
@@ -443,3 +444,19 @@ def latent_sphere_batch(hidden: Sequence[int], reinject: int, latent_dim: int, n
     shape_bias = np.asarray(rows)
     base = [shape_bias[0][o:o + w] for o, w in zip(np.cumsum([0] + widths[1:-1]), widths[1:])]
     return ShapeBatch(Net(widths, blocks, base), shape_bias)
+
+
+def c4_batch(n_shapes: int = 64, radius=(0.008, 0.35)) -> ShapeBatch:
+    """The batched workload: 64 shapes of one latent-conditioned decoder.
+
+    [x; z] (3 + 256) -> [512] x 8 -> 1 ReLU MLP with [x; z] entering layer 1
+    and again layer 4 (fan-in 512 + 259), He-normal weights, biases
+    N(0, 0.05^2), latents z_i ~ N(0, 0.01^2), seed 3; the output is
+    0.01 * MLP + |x|_1 - r_i with radii geometrically spaced over `radius`, so
+    that per-shape cell counts run from about 1e3 to 1e6 (measured: cells grow
+    like r^1.85).  The decoder is untrained; the radius term sets each
+    shape's size.
+    """
+    return latent_sphere_batch([512] * 8, reinject=4, latent_dim=256, n_shapes=n_shapes, seed=3,
+                               latent_std=0.01, radius=radius, scale=0.01, log_radii=True)
+

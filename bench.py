@@ -181,6 +181,55 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0):
             "stats": stats[-1], "kernels": agg, "out": out}
 
 
+def c4_forms(B, dev, steps, max_cells):
+    """The 64-shape decoder batch: one batched march (all shapes in one
+    frontier, chain tiles autotuned on it) against one march per shape."""
+    import torch
+    from am_workloads import nets, seeds
+    sb = nets.c4_batch()
+    o1, d1 = seeds.centre_rays(np.zeros((1, 3)), 16)
+    S = sb.n_shapes
+    o = torch.as_tensor(np.tile(o1, (S, 1)), device=dev)
+    d = torch.as_tensor(np.tile(d1, (S, 1)), device=dev)
+    sh_np = np.repeat(np.arange(S, dtype=np.int32), len(o1))
+    sh = torch.as_tensor(sh_np, device=dev)
+    ctx = B.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+
+    def batched():
+        ctx.seed_rays(o, d, shape_id=sh)
+        return ctx.march(max_cells=max_cells, time_kernels=True)
+
+    st = batched()
+    groups, _ = ctx.tune_chain(reps=3)
+    batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = batched()
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    counts = np.bincount(ctx.fetch()["shape"].cpu().numpy(), minlength=S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    faces_single = 0
+    for s in range(S):
+        m = sh_np == s
+        ctx.seed_rays(o[m], d[m], shape_id=sh[m])
+        faces_single += ctx.march(max_cells=max_cells)["faces"]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    assert faces_single == st["faces"], "batched and per-shape marches differ"
+    ctx.close()
+    desc = ("64 shapes of one decoder [x; z] (3+256) -> [512]x8 -> 1 with [x; z] re-entering layer 4, "
+            "0.01*MLP + |x|_1 - r_i, radii 0.008..0.35 geometric, 16 rays per shape")
+    return {"c4_batched": {"faces_per_s": round(st["faces"] / t_b, 1), "ms_per_step": round(t_b * 1e3, 3),
+                           "faces": st["faces"], "march_steps": st["steps"],
+                           "faces_per_shape_min_max": [int(counts.min()), int(counts.max())],
+                           "chain_groups_tuned": groups, "workload": desc},
+            "c4_per_shape": {"faces_per_s": round(faces_single / t_s, 1), "ms_per_step": round(t_s * 1e3, 3),
+                             "faces": faces_single, "note": "one march per shape, same context, one pass"}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,9 +239,11 @@ def main(argv=None):
     ap.add_argument("--max-cells", type=int, default=1 << 24)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16",
-                    help="other forms to time on the same net (bf16, distance, learned, learned_bf16) and on "
-                         "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16); empty for none")
+    ap.add_argument("--forms",
+                    default="bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16,c4",
+                    help="other forms to time on the same net (bf16, distance, learned, learned_bf16), on "
+                         "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
+                         "batch (c4); empty for none")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the bench, copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args(argv)
@@ -296,6 +347,10 @@ def main(argv=None):
             assert r["faces"] == base, f"{name} {v} form changed the face count"
             record(f"{name}_{v}", r, precision, propose)
         ctx3.close()
+    if "c4" in forms_req:
+        forms.update(c4_forms(B, dev, max(1, min(a.steps, 2)), a.max_cells))
+        print(f"[bench] c4: {forms['c4_batched']['ms_per_step']:.1f} ms batched, "
+              f"{forms['c4_per_shape']['ms_per_step']:.1f} ms per-shape", file=sys.stderr, flush=True)
     if train_info:
         forms["scorer_training"] = train_info
 

@@ -9,7 +9,7 @@ namespace am {
 
 constexpr int kMaxLayers = 40;
 constexpr int kMaxBlocks = 64;
-constexpr int kMaxHidden = 4096;
+constexpr int kMaxHidden = 8192;
 constexpr int kMaxHeads = 64;
 constexpr int kWave = 64;
 constexpr int kMaxPoly = 64;      // polygon vertices held by one wave (one per lane)

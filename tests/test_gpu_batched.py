@@ -93,3 +93,30 @@ def test_shape_ids_are_validated(binding):
     codes, am, F = ctx.codes(o, shape_id=np.array([0, 2, 3, 1], np.int32))
     torch.cuda.synchronize()
     assert am.cpu().numpy()[2] == -1 and np.isnan(F.cpu().numpy()[2])
+
+
+def test_wide_decoder_batch_equals_single_shape_marches(binding):
+    """The 64-shape decoder's first 12 shapes (the smallest): each shape's part
+    of one batched march equals that shape's own GPU march (cells, cycles,
+    adjacency exact; vertices bit-equal: same rows, same solves)."""
+    from gpu_common import compare_meshes_fast
+    sb = nets.c4_batch()
+    keep = 12
+    o1, d1 = seeds.centre_rays(np.zeros((1, 3)), 16)
+    o = np.tile(o1, (keep, 1)); d = np.tile(d1, (keep, 1))
+    sh = np.repeat(np.arange(keep, dtype=np.int32), len(o1))
+    say("c4 batch of", keep, "shapes")
+    ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+    ctx.seed_rays(o, d, shape_id=sh)
+    st = ctx.march(max_cells=1 << 20)
+    got = _split_by_shape(ctx)
+    total = 0
+    for s in range(keep):
+        m = sh == s
+        ctx.seed_rays(o[m], d[m], shape_id=sh[m])
+        ctx.march(max_cells=1 << 20)
+        one = fetch_host(ctx)
+        compare_meshes_fast(one, got[s], vtol=0.0)
+        total += one.n_faces
+    assert st["faces"] == total
+    ctx.close()
