@@ -96,9 +96,12 @@ typedef struct {
                              The every-line pass decides the face, so results equal
                              propose 0.  Cells without an entry edge (seeds) are not
                              proposed for. */
-    int32_t chain_groups; /* affine-chain tile: 0 = the context's table (am_tune_chain), else
-                             1, 2 or 4 column groups of 16 (4, 8 or 16 cells per workgroup;
-                             more cells share each streamed weight fragment) */
+    int32_t chain_groups; /* affine-chain tile: 0 = the context's table (am_tune_chain); 1, 2
+                             or 4 column groups of 16 (4, 8 or 16 cells per workgroup; more
+                             cells share each streamed weight fragment); 5 = four cells whose
+                             K loop runs only over the source units active in any of them
+                             (sources of at most 1024 units; rows then differ from the dense
+                             sum in the last bits) */
     int32_t reserved[3];
     double margin;        /* relative sign-test margin of precision 1 (0: 4e-6) */
     double vertex_tol;    /* precision 1: a cell is also redone in FP64 when a vertex's
@@ -234,20 +237,22 @@ am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, 
 am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                    uint64_t *codes, int32_t *argmax, int32_t *shape_id);
 
-/* ---- Affine-chain tile autotuner.  The chain kernel takes 4 g cells per
- * workgroup (g = 1, 2 or 4 column groups of the 16-column FP64 MFMA tile);
- * larger g streams each weight block once for more cells, smaller g fills
- * the chip at small frontiers.  The context keeps one g per launch-size
- * bucket (fewer than 2^11 cells, 2^13, 2^15, more); all start at 1. */
+/* ---- Affine-chain tile autotuner.  The chain kernel has four tile
+ * variants (opts.chain_groups): 4, 8 or 16 cells per workgroup (1, 2 or 4
+ * column groups of the 16-column FP64 MFMA tile; more cells share each
+ * streamed weight fragment, fewer fill the chip at small frontiers), and 5:
+ * four cells whose K loop skips the units that are off in all of them.  The
+ * context keeps one variant per launch-size bucket (fewer than 2^11 cells,
+ * 2^13, 2^15, more); all start at 1. */
 
 /* Times the chain kernel on the first 2^10, 2^12, 2^14 and 2^16 cells of the
- * last march (fewer if it has fewer) for each g, `reps` launches each, and
- * keeps the fastest g per bucket.  ms_out (HOST, may be NULL) receives the
- * 4 x 3 average launch times (bucket-major, g = 1, 2, 4).  AM_E_STATE
- * without a finished march. */
+ * last march (fewer if it has fewer) for each variant, `reps` launches each,
+ * and keeps the fastest per bucket.  ms_out (HOST, may be NULL) receives the
+ * 4 x 4 average launch times (bucket-major; variants 1, 2, 4, 5).
+ * AM_E_STATE without a finished march. */
 am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out);
 
-/* Sets / reads the 4 per-bucket g values (each 1, 2 or 4; HOST arrays). */
+/* Sets / reads the 4 per-bucket variants (each 1, 2, 4 or 5; HOST arrays). */
 am_status am_set_chain_groups(am_ctx *ctx, const int32_t *groups);
 am_status am_get_chain_groups(const am_ctx *ctx, int32_t *groups);
 

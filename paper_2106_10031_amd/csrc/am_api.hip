@@ -42,9 +42,12 @@ hipError_t prepare_fused(size_t);
 void launch_rows_unpad(const DevNet &, long long, const void *, bool, double *, hipStream_t);
 void launch_insert(const DevNet &, const Candidates &, const CellArrays &, unsigned long long *, unsigned long long,
                    Counters *, unsigned long long, long long, hipStream_t);
-void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, int *, uint64_t *, int *, int *,
+void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, int *, uint64_t *, int *, unsigned *, int *,
                    const uint64_t *, const int *, const int *, unsigned long long *, Counters *, unsigned long long,
                    unsigned long long, long long, hipStream_t);
+hipError_t sort_tmp_bytes(long long, size_t *);
+hipError_t launch_sort_cells(const unsigned *, long long, long long, unsigned *, int *, int *, void *, size_t,
+                             hipStream_t);
 void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t);
 void launch_codes(const DevNet &, const double *, const int *, long long, uint64_t *, int *, double *, hipStream_t);
 void launch_seed_rays(const DevNet &, const double *, const double *, const int *, long long, int, uint64_t *, int *,
@@ -70,6 +73,7 @@ struct am_ctx {
     DevNet dn{};
     double *d_weights = nullptr;
     double *d_wfrag = nullptr;
+    double *d_wcol = nullptr;
     uint16_t *d_wfrag16 = nullptr;
     int *d_fb_list = nullptr;                 // cells the split-BF16 pass hands to FP64
     unsigned long long *d_fb_count = nullptr;
@@ -96,6 +100,12 @@ struct am_ctx {
     int *d_shape = nullptr;
     uint64_t *d_hash = nullptr;
     int *d_hints = nullptr;     // [cap][3] lines to clip first (entry edge and its neighbours)
+    unsigned *d_cell_key = nullptr;   // [cap] Morton key of each cell's entry edge midpoint
+    unsigned *d_key_sorted = nullptr; // [chunk] scratch of the step sort
+    int *d_order = nullptr;           // [chunk] a step's cells in key order
+    int *d_ids = nullptr;             // [chunk] scratch of the step sort
+    char *d_sort_tmp = nullptr;
+    size_t sort_tmp = 0;
     int *d_fm = nullptr;
     int *d_fids = nullptr;
     double *d_fverts = nullptr;
@@ -239,6 +249,12 @@ void free_march(am_ctx *c) {
     dfree(c->cand.cell);
     dfree(c->cand.hint_prev);
     dfree(c->cand.hint_next);
+    dfree(c->cand.key);
+    dfree(c->d_cell_key);
+    dfree(c->d_key_sorted);
+    dfree(c->d_order);
+    dfree(c->d_ids);
+    dfree(c->d_sort_tmp);
     dfree(c->d_rows);
     dfree(c->d_fb_list);
     dfree(c->d_fb_count);
@@ -258,6 +274,7 @@ void free_march(am_ctx *c) {
 void free_net(am_ctx *c) {
     dfree(c->d_weights);
     dfree(c->d_wfrag);
+    dfree(c->d_wcol);
     dfree(c->d_wfrag16);
     dfree(c->d_bias);
     dfree(c->d_row_of_unit);
@@ -315,6 +332,17 @@ am_status ensure_march(am_ctx *ctx, long long cells) {
     TRY(dalloc(ctx, ctx->cand.cell, ctx->cand_cap));
     TRY(dalloc(ctx, ctx->cand.hint_prev, ctx->cand_cap));
     TRY(dalloc(ctx, ctx->cand.hint_next, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->cand.key, ctx->cand_cap));
+    TRY(dalloc(ctx, ctx->d_cell_key, (size_t)cells));
+    TRY(dalloc(ctx, ctx->d_key_sorted, (size_t)chunk));
+    TRY(dalloc(ctx, ctx->d_order, (size_t)chunk));
+    TRY(dalloc(ctx, ctx->d_ids, (size_t)chunk));
+    {
+        size_t b = 0;
+        HIPCHK(sort_tmp_bytes(chunk, &b));
+        TRY(dalloc(ctx, ctx->d_sort_tmp, b));
+        ctx->sort_tmp = b;
+    }
     ctx->cap_cells = cells;
     return AM_OK;
 }
@@ -478,6 +506,15 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
             for (int ks = 0; ks < ld / 4; ++ks)
                 for (int l = 0; l < 64; ++l) hf.push_back(Wp[(size_t)(mt * 16 + l % 16) * ld + ks * 4 + l / 16]);
     }
+    // column-major copy of every block (rows padded to 16) for the gathered chain
+    std::vector<double> hc;
+    for (int b = 0; b < nd->n_blocks; ++b) {
+        const int ld = dn.blk_ld[b], rows = (nd->width[dn.blk_dst[b]] + 15) & ~15, ns = nd->width[dn.blk_src[b]];
+        const double *Wp = hw.data() + dn.blk_off[b];
+        dn.blk_col_off[b] = (long long)hc.size();
+        for (int k = 0; k < ns; ++k)
+            for (int i = 0; i < rows; ++i) hc.push_back(Wp[(size_t)i * ld + k]);
+    }
     // bias table [S][boff]: the net's own biases, or one row per shape
     // split-BF16 fragments (blocks from the input are copies and get none)
     std::vector<uint16_t> h16;
@@ -523,6 +560,8 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
 
     TRY(dalloc(ctx, ctx->d_weights, hw.size()));
     TRY(dalloc(ctx, ctx->d_wfrag, hf.size()));
+    TRY(dalloc(ctx, ctx->d_wcol, hc.size()));
+    HIPCHK(hipMemcpy(ctx->d_wcol, hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice));
     TRY(dalloc(ctx, ctx->d_wfrag16, h16.size()));
     HIPCHK(hipMemcpy(ctx->d_wfrag16, h16.data(), sizeof(uint16_t) * h16.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_wfrag, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice));
@@ -535,6 +574,7 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     HIPCHK(hipMemcpy(ctx->d_zobrist, zob.data(), sizeof(uint64_t) * zob.size(), hipMemcpyHostToDevice));
     dn.weights = ctx->d_weights;
     dn.wfrag = ctx->d_wfrag;
+    dn.wcol = ctx->d_wcol;
     dn.wfrag16 = ctx->d_wfrag16;
     dn.bias = ctx->d_bias;
     dn.row_of_unit = ctx->d_row_of_unit;
@@ -697,8 +737,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
                     fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
     if (o.propose < 0 || o.propose > 3) return fail(ctx, AM_E_INVALID, "propose must be 0..3");
-    if (o.chain_groups != 0 && o.chain_groups != 1 && o.chain_groups != 2 && o.chain_groups != 4)
-        return fail(ctx, AM_E_INVALID, "chain_groups must be 0, 1, 2 or 4");
+    if (o.chain_groups < 0 || o.chain_groups > 5 || o.chain_groups == 3)
+        return fail(ctx, AM_E_INVALID, "chain_groups must be 0, 1, 2, 4 or 5");
     if (o.propose == 1 && !ctx->prop_loaded) return fail(ctx, AM_E_STATE, "no proposal scorer loaded");
     const bool collecting = ctx->prop.samples != nullptr;
     if ((o.propose != 0 || collecting) && o.kernel_path == 2)
@@ -738,7 +778,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
                       ctx->seeds_have_status ? ctx->d_seed_status : nullptr, ctx->n_seeds, ctx->cand, ctx->d_ctr,
                       ctx->cand_cap, s);
     launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, ctx->n_seeds, s);
-    launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints, ctx->d_fm,
+    launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
+                  ctx->d_cell_key, ctx->d_fm,
                   ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
                   (unsigned long long)cap, ctx->n_seeds, s);
     HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -790,16 +831,25 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, 0, n, ctx->d_fb_list,
                         ctx->d_fb_count, seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, pa, s);
         } else {
-            launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, nullptr, nullptr, ctx->d_rows,
-                         chain_groups(ctx, n, o.chain_groups), s);
+            // the gathered chain skips units off in all four cells of a tile:
+            // order the step's cells by position first, so that tiles are local
+            const int variant = chain_groups(ctx, n, o.chain_groups);
+            const int *order = nullptr;
+            if (variant == 5) {
+                HIPCHK(launch_sort_cells(ctx->d_cell_key, lo, n, ctx->d_key_sorted, ctx->d_ids, ctx->d_order,
+                                         ctx->d_sort_tmp, ctx->sort_tmp, s));
+                order = ctx->d_order;
+            }
+            launch_chain(net, ctx->d_codes, ctx->d_shape, lo, lo + n, order, nullptr, ctx->d_rows, variant, s);
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
-            launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, nullptr, nullptr,
+            launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, order, nullptr,
                         seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, pa, s);
         }
         if (tk) HIPCHK(hipEventRecord(ctx->evk[2], s));
         const long long nh = n * 6;
         launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
-        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints, ctx->d_fm,
+        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
+                  ctx->d_cell_key, ctx->d_fm,
                       ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
                       (unsigned long long)cap, nh, s);
         launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
@@ -909,8 +959,8 @@ am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, i
 am_status am_set_chain_groups(am_ctx *ctx, const int32_t *groups) {
     if (!ctx || !groups) return AM_E_INVALID;
     for (int b = 0; b < 4; ++b)
-        if (groups[b] != 1 && groups[b] != 2 && groups[b] != 4)
-            return fail(ctx, AM_E_INVALID, "column groups must be 1, 2 or 4");
+        if (groups[b] != 1 && groups[b] != 2 && groups[b] != 4 && groups[b] != 5)
+            return fail(ctx, AM_E_INVALID, "chain tile variants are 1, 2, 4 and 5");
     for (int b = 0; b < 4; ++b) ctx->chain_g[b] = groups[b];
     return AM_OK;
 }
@@ -926,14 +976,14 @@ am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out) {
     if (!ctx->have_result || ctx->res_cells <= 0) return fail(ctx, AM_E_STATE, "tuning needs a finished march");
     if (reps < 1 || reps > 100) return fail(ctx, AM_E_INVALID, "reps must be 1..100");
     TRY(set_device(ctx));
-    const int gs[3] = {1, 2, 4};
+    const int gs[4] = {1, 2, 4, 5};
     const long long sizes[4] = {1LL << 10, 1LL << 12, 1LL << 14, 1LL << 16};
     hipStream_t s = ctx->stream;
     for (int b = 0; b < 4; ++b) {
         const long long n = std::min<long long>({sizes[b], ctx->res_cells, ctx->chunk_cells});
         float best = 0.f;
         int best_g = 1;
-        for (int gi = 0; gi < 3; ++gi) {
+        for (int gi = 0; gi < 4; ++gi) {
             launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, gs[gi], s);
             HIPCHK(hipEventRecord(ctx->evk[0], s));
             for (int r = 0; r < reps; ++r)
@@ -943,7 +993,7 @@ am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, ctx->evk[0], ctx->evk[1]));
             ms /= (float)reps;
-            if (ms_out) ms_out[b * 3 + gi] = ms;
+            if (ms_out) ms_out[b * 4 + gi] = ms;
             if (gi == 0 || ms < best) {
                 best = ms;
                 best_g = gs[gi];

@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256) void k_insert(DevNet net, Candidates cand, Cel
 // ------------------------------------------------------------------ commit
 
 __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uint64_t *codes, int *argmax,
-                                                int *shape, uint64_t *cell_hash, int *hints, int *face_m,
+                                                int *shape, uint64_t *cell_hash, int *hints, unsigned *cell_key,
+                                                int *face_m,
                                                 const uint64_t *seed_codes, const int *seed_am,
                                                 const int *seed_shape, unsigned long long *slots, Counters *ctr,
                                                 unsigned long long cand_cap, unsigned long long cap_cells) {
@@ -168,6 +169,7 @@ __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uin
         hints[id * 3 + 0] = entry;
         hints[id * 3 + 1] = hp;
         hints[id * 3 + 2] = hn;
+        if (cell_key) cell_key[id] = (p >= 0 && cand.key) ? cand.key[t] : 0u;
         face_m[id] = 0;
         slots[cand.ref[t]] = ((unsigned long long)slot_tag(h) << 32) | id;
         cand.cell[t] = (int)id;
@@ -437,11 +439,30 @@ void launch_insert(const DevNet &net, const Candidates &cand, const CellArrays &
 }
 
 void launch_commit(const DevNet &net, const Candidates &cand, uint64_t *codes, int *argmax, int *shape,
-                   uint64_t *cell_hash, int *hints, int *face_m, const uint64_t *seed_codes, const int *seed_am,
-                   const int *seed_shape, unsigned long long *slots, Counters *ctr, unsigned long long cand_cap,
-                   unsigned long long cap_cells, long long n_hint, hipStream_t st) {
+                   uint64_t *cell_hash, int *hints, unsigned *cell_key, int *face_m, const uint64_t *seed_codes,
+                   const int *seed_am, const int *seed_shape, unsigned long long *slots, Counters *ctr,
+                   unsigned long long cand_cap, unsigned long long cap_cells, long long n_hint, hipStream_t st) {
     hipLaunchKernelGGL(k_commit, dim3(grid_for(n_hint)), dim3(256), 0, st, net, cand, codes, argmax, shape, cell_hash,
-                       hints, face_m, seed_codes, seed_am, seed_shape, slots, ctr, cand_cap, cap_cells);
+                       hints, cell_key, face_m, seed_codes, seed_am, seed_shape, slots, ctr, cand_cap, cap_cells);
+}
+
+// Orders cells lo..lo+n-1 by their Morton keys: order[p] = the p-th cell.
+// tmp must hold sort_tmp_bytes(n); keys_out and ids are n words of scratch.
+__global__ void k_iota(int *ids, long long lo, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ids[i] = (int)(lo + i);
+}
+
+hipError_t sort_tmp_bytes(long long n, size_t *bytes) {
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const unsigned *)nullptr, (unsigned *)nullptr,
+                                              (const int *)nullptr, (int *)nullptr, (int)n, 0, 30);
+}
+
+hipError_t launch_sort_cells(const unsigned *cell_key, long long lo, long long n, unsigned *keys_out, int *ids,
+                             int *order, void *tmp, size_t tmp_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ids, lo, n);
+    size_t tb = tmp_bytes;
+    return hipcub::DeviceRadixSort::SortPairs(tmp, tb, cell_key + lo, keys_out, ids, order, (int)n, 0, 30, st);
 }
 
 void launch_resolve(const Candidates &cand, int *face_nbr, int stride, Counters *ctr, unsigned long long cand_cap,

@@ -50,6 +50,10 @@ struct DevNet {
     const void *wfrag16;
     long long blk_frag16_off[kMaxBlocks];   // in units of 8 BF16 (16 bytes)
     int blk_ld32[kMaxBlocks];               // src width rounded up to 32
+    // the same blocks column-major, rows padded to 16: element (i, k) at
+    // wcol[blk_col_off + k * 16 ceil(n_dst / 16) + i] (gathered chain)
+    const double *wcol;
+    long long blk_col_off[kMaxBlocks];
     const double *bias;        // [S][bias_stride]: shape s, layer l at s * bias_stride + bias_off[l]
     const int *row_of_unit;    // [N + M] padded row of global unit g
     const uint64_t *zobrist;   // [N + M + S] keys of the cell fingerprint (units, heads, shapes)
@@ -97,6 +101,7 @@ struct Candidates {
     int *cell;         // resolved cell id
     int *hint_prev;    // the parent's edges next to the crossed one (clip-order hints)
     int *hint_next;
+    unsigned *key;     // Morton key of the crossed edge's midpoint (step ordering)
 };
 
 enum : int { kOwner = 0, kFound = 1, kDup = 2, kLost = 3 };

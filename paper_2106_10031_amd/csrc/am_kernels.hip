@@ -184,6 +184,165 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
     }
 }
 
+// ---- gathered chain: a tile's four cells share the MFMA columns, so a unit
+// that is off in all four contributes only zeros.  For source layers of at
+// most kListMax units the tile first lists the units active in any of its
+// cells (LDS, ascending, padded with -1 to a multiple of 4) and the K loop
+// runs over that list, loading A from the column-major weights (four
+// 128-byte columns per K-step).  Products are summed in list order, so rows
+// may differ from the dense kernel's in the last bits.
+constexpr int kListMax = 1024;
+constexpr int kListBlocks = 2;
+
+// Builds the union list of source layer j over the tile's ncell cells;
+// returns its length.  All threads; ends with a barrier.
+__device__ int union_list(const DevNet &net, int j, const uint64_t *code_lds, int ncell, short *list,
+                          int *cnt_lds) {
+    const int nj = net.width[j], uoff = net.unit_off[j];
+    const int nchunks = (nj + 63) >> 6;
+    const int t = threadIdx.x;
+    uint64_t mask = 0;
+    if (t < nchunks) {
+        const int u0 = uoff + t * 64;
+        const int w = u0 >> 6, sh = u0 & 63;
+        for (int c = 0; c < ncell; ++c) {
+            const uint64_t *code = code_lds + c * net.W;
+            mask |= code[w] >> sh;
+            if (sh && w + 1 < net.W) mask |= code[w + 1] << (64 - sh);
+        }
+        const int rem = nj - t * 64;
+        if (rem < 64) mask &= (1ull << rem) - 1ull;
+        cnt_lds[t] = __popcll(mask);
+    }
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int c = 0; c < nchunks; ++c) {
+        const int v = cnt_lds[c];
+        if (c < t) base += v;
+        total += v;
+    }
+    if (t < nchunks) {
+        int at = base;
+        while (mask) {
+            const int bit = __builtin_ctzll(mask);
+            mask &= mask - 1ull;
+            list[at++] = (short)(t * 64 + bit);
+        }
+    }
+    if (t < 4 && total + t < ((total + 3) & ~3)) list[total + t] = -1;
+    __syncthreads();
+    return total;
+}
+
+template <int KC>
+__device__ void chain_tile_gather(const DevNet &net, const uint64_t *__restrict__ codes,
+                                  const int *__restrict__ cell_shape, const int *list, long long c0, int ncell,
+                                  double *zb, long long rs, long long cs, uint64_t *code_lds, int *shape_lds,
+                                  short *lists, int *cnt_lds) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const int q = col & 3;
+    const int cl = col >> 2;
+    const bool cell_ok = cl < ncell;
+    stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds);
+    const long long bias_base = (long long)shape_lds[cl] * net.bias_stride;
+    const uint64_t *code = code_lds + cl * net.W;
+    double *zc = zb + cl * cs + q;
+
+    for (int l = 1; l < net.n_layers; ++l) {
+        const int nl = net.width[l];
+        const int mtiles = (nl + 15) >> 4;
+        const int rows16 = mtiles * 16;
+        int lb[kListBlocks], lcount[kListBlocks], nlist = 0;
+        for (int b = 0; b < net.n_blocks; ++b) {
+            const int j = net.blk_src[b];
+            if (net.blk_dst[b] != l || j == 0 || net.width[j] > kListMax || nlist == kListBlocks) continue;
+            lcount[nlist] = union_list(net, j, code_lds, ncell, lists + nlist * (kListMax + 4), cnt_lds);
+            lb[nlist++] = b;
+        }
+        for (int mt0 = wave; mt0 < mtiles; mt0 += 2 * nwaves) {
+            const int mt1 = mt0 + nwaves;
+            const bool two = mt1 < mtiles;
+            v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < net.n_blocks; ++b) {
+                if (net.blk_dst[b] != l) continue;
+                const int j = net.blk_src[b];
+                const int ks_n = net.blk_ld[b] >> 2;
+                const int nj = net.width[j];
+                const double *fr0 = net.wfrag + net.blk_frag_off[b] + (long long)mt0 * ks_n * 64 + lane;
+                const double *fr1 = fr0 + (long long)(mt1 - mt0) * ks_n * 64;
+                if (j == 0) {
+                    const double bv = (kq < 3 && kq == q) ? 1.0 : 0.0;
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fr0[0], bv, acc0, 0, 0, 0);
+                    if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fr1[0], bv, acc1, 0, 0, 0);
+                    continue;
+                }
+                const int uoff = net.unit_off[j];
+                const double *zj = zc + (long long)net.row_off[j] * rs;
+                int li = -1;
+                for (int t = 0; t < nlist; ++t)
+                    if (lb[t] == b) li = t;
+                if (li >= 0) {
+                    const short *kl = lists + li * (kListMax + 4);
+                    const int ksn = (lcount[li] + 3) >> 2;
+                    const double *wc = net.wcol + net.blk_col_off[b] + mt0 * 16 + col;
+                    const long long d1 = (long long)(mt1 - mt0) * 16;
+                    for (int ks0 = 0; ks0 < ksn; ks0 += KC) {
+                        double a0[KC], a1[KC], bv[KC];
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) {
+                            const int ks = ks0 + u;
+                            const int k = ks < ksn ? (int)kl[ks * 4 + kq] : -1;
+                            const long long wo = (long long)k * rows16;
+                            a0[u] = k >= 0 ? wc[wo] : 0.0;
+                            a1[u] = (k >= 0 && two) ? wc[wo + d1] : 0.0;
+                            bv[u] = (k >= 0 && cell_ok && code_bit(code, uoff + k)) ? zj[k * rs] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) {
+                            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc0, 0, 0, 0);
+                            if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc1, 0, 0, 0);
+                        }
+                    }
+                    continue;
+                }
+                for (int ks0 = 0; ks0 < ks_n; ks0 += KC) {
+                    double a0[KC], a1[KC], bv[KC];
+#pragma unroll
+                    for (int u = 0; u < KC; ++u) {
+                        const int ks = ks0 + u;
+                        const bool kv = ks < ks_n;
+                        const int k = ks * 4 + kq;
+                        a0[u] = kv ? fr0[ks * 64] : 0.0;
+                        a1[u] = (kv && two) ? fr1[ks * 64] : 0.0;
+                        bv[u] = (kv && k < nj && cell_ok && code_bit(code, uoff + k)) ? zj[k * rs] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < KC; ++u) {
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc0, 0, 0, 0);
+                        if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc1, 0, 0, 0);
+                    }
+                }
+            }
+            if (cell_ok) {
+                const double *bias = net.bias + bias_base + net.bias_off[l];
+                double *z0 = zc + (long long)net.row_off[l] * rs;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i0 = mt0 * 16 + kq + 4 * r;
+                    if (i0 < nl) z0[i0 * rs] = acc0[r] + (q == 3 ? bias[i0] : 0.0);
+                    const int i1 = mt1 * 16 + kq + 4 * r;
+                    if (two && i1 < nl) z0[i1 * rs] = acc1[r] + (q == 3 ? bias[i1] : 0.0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
@@ -515,6 +674,24 @@ __device__ bool margin_ambiguous(const DevNet &net, const uint64_t *code, int am
         }
     }
     return ballot(amb) != 0;
+}
+
+// 30-bit Morton key of a point of [-1, 1]^3 (10 bits per axis), used to order
+// a step's cells so that the four cells of a chain tile lie close together.
+__device__ __forceinline__ unsigned spread10(unsigned v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ __forceinline__ unsigned morton_key(double x, double y, double z) {
+    auto q = [](double t) {
+        const double u = fmin(1.0, fmax(0.0, 0.5 * (t + 1.0)));
+        return (unsigned)fmin(1023.0, u * 1024.0);
+    };
+    return spread10(q(x)) | (spread10(q(y)) << 1) | (spread10(q(z)) << 2);
 }
 
 // ---------------------------------------------------------------- learned form
@@ -1086,6 +1263,9 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         const bool want = lane < m && e_out >= 0;
         const int e_prev = shfl(e_out, lane == 0 ? m - 1 : lane - 1);
         const int e_next = shfl(e_out, lane + 1 >= m ? 0 : lane + 1);
+        // edge i runs from vertex i to vertex i + 1
+        const int vn = lane + 1 >= m ? 0 : lane + 1;
+        const double nx = shfl(x[0], vn), ny = shfl(x[1], vn), nz = shfl(x[2], vn);
         if (ctr) {
             const uint64_t dm = ballot(lane < m && e_out < 0);
             if (lane == 0 && dm) atomicAdd(&ctr->domain_edges, (unsigned long long)__popcll(dm));
@@ -1104,6 +1284,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
                 cand.hash[idx] = hn;
                 cand.hint_prev[idx] = e_prev;
                 cand.hint_next[idx] = e_next;
+                if (cand.key) cand.key[idx] = morton_key(0.5 * (x[0] + nx), 0.5 * (x[1] + ny), 0.5 * (x[2] + nz));
             } else {
                 atomicAdd(&ctr->overflow_cand, 1ull);
             }
@@ -1121,7 +1302,7 @@ struct CellRange {
     const unsigned long long *list_count;
     unsigned long long cap;
     __device__ long long count() const {
-        if (!list) return hi - lo;
+        if (!list || !list_count) return hi - lo;
         const unsigned long long c = *list_count;
         return (long long)(c < cap ? c : cap);
     }
@@ -1143,6 +1324,24 @@ __global__ __launch_bounds__(256) void k_chain_f64(DevNet net, const uint64_t *_
     const int ncell = (int)min(4LL * G, n - p0);
     chain_tile<G, KC>(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, rows + p0 * (long long)net.R * 4,
                       4, (long long)net.R * 4, code_lds, shape_lds);
+}
+
+// Gathered FP64 chain, four cells per workgroup.
+template <int KC>
+__global__ __launch_bounds__(256) void k_chain_f64_gather(DevNet net, const uint64_t *__restrict__ codes,
+                                                          const int *__restrict__ cell_shape, CellRange rg,
+                                                          double *__restrict__ rows) {
+    __shared__ uint64_t code_lds[4 * kMaxWords];
+    __shared__ int shape_lds[4];
+    __shared__ short lists[kListBlocks * (kListMax + 4)];
+    __shared__ int cnt_lds[kListMax / 64];
+    const long long p0 = 4LL * blockIdx.x;
+    const long long n = rg.count();
+    if (p0 >= n) return;
+    const int ncell = (int)min(4LL, n - p0);
+    chain_tile_gather<KC>(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell,
+                          rows + p0 * (long long)net.R * 4, 4, (long long)net.R * 4, code_lds, shape_lds, lists,
+                          cnt_lds);
 }
 
 // Split-BF16 chain: FP32 rows of position p go to rows[p][R][4].
@@ -1279,13 +1478,17 @@ static CellRange range_of(long long lo, long long hi, const int *list, const uns
 
 // Positions [0, hi - lo) of cells lo..hi-1, or (list != NULL) the first
 // *count entries of list, launched for up to hi - lo positions.
-// g: column groups per workgroup (1, 2 or 4; 4 g cells per workgroup).
+// g: tile variant: 1, 2 or 4 column groups per workgroup (4 g cells), or 5:
+// four cells with the K loop over the units active in any of them.
 void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
                   const int *list, const unsigned long long *count, double *rows, int g, hipStream_t st) {
     if (hi <= lo) return;
     const CellRange rg = range_of(lo, hi, list, count, (unsigned long long)(hi - lo));
     const long long n = hi - lo;
-    if (g >= 4)
+    if (g == 5)
+        hipLaunchKernelGGL((k_chain_f64_gather<kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net,
+                           codes, cell_shape, rg, rows);
+    else if (g >= 4)
         hipLaunchKernelGGL((k_chain_f64<4, 4>), dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, net, codes,
                            cell_shape, rg, rows);
     else if (g == 2)

@@ -1,8 +1,11 @@
-"""Chain tiles of 4, 8 and 16 cells per workgroup, and the tile autotuner.
+"""Chain tiles of 4, 8 and 16 cells per workgroup, the gathered tile (K loop
+over the units active in any of its four cells), and the tile autotuner.
 
-Bar: each tile width reproduces the oracle's mesh (cells, cycles, adjacency
+Bar: each variant reproduces the oracle's mesh (cells, cycles, adjacency
 exact; vertices 1e-9) on nets with shortcuts, max-pooled heads and per-shape
-biases, and the 6x90 fit's mesh is identical across widths and after tuning.
+biases; on the 6x90 fit the dense widths give identical meshes and the
+gathered tile the same cells, cycles and adjacency (vertices 1e-9: its sums
+run in another order).
 """
 import numpy as np
 import pytest
@@ -31,7 +34,7 @@ NETS = {
 }
 
 
-@pytest.mark.parametrize("groups", [2, 4])
+@pytest.mark.parametrize("groups", [2, 4, 5])
 @pytest.mark.parametrize("name", list(NETS))
 def test_tile_widths_match_oracle(binding, name, groups):
     net = NETS[name]()
@@ -48,7 +51,7 @@ def test_tile_widths_match_oracle(binding, name, groups):
     ctx.close()
 
 
-@pytest.mark.parametrize("groups", [2, 4])
+@pytest.mark.parametrize("groups", [2, 4, 5])
 def test_tile_widths_batched(binding, groups):
     sb = nets.latent_sphere_batch([16, 16, 16], reinject=3, latent_dim=8, n_shapes=6, seed=3)
     o, d, sh = [], [], []
@@ -63,7 +66,7 @@ def test_tile_widths_batched(binding, groups):
     ref = fetch_host(ctx)
     ctx.seed_rays(o, d, shape_id=sh)
     ctx.march(kernel_path=1, chain_groups=groups)
-    compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+    compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0 if groups != 5 else 1e-9)
     ctx.close()
 
 
@@ -76,17 +79,17 @@ def test_tuner_keeps_the_mesh(binding):
     ctx.seed_rays(o, d)
     ctx.march(max_cells=1 << 21, chain_groups=1)
     ref = fetch_host(ctx)
-    for g in (2, 4):
+    for g in (2, 4, 5):
         ctx.seed_rays(o, d)
         ctx.march(max_cells=1 << 21, chain_groups=g)
-        compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+        compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0 if g != 5 else 1e-9)
     groups, ms = ctx.tune_chain(reps=3)
-    say("tuned groups", groups, "ms", np.round(ms, 4).tolist())
-    assert all(g in (1, 2, 4) for g in groups)
+    say("tuned variants", groups, "ms", np.round(ms, 4).tolist())
+    assert all(g in (1, 2, 4, 5) for g in groups)
     assert np.all(ms > 0)
     ctx.seed_rays(o, d)
     ctx.march(max_cells=1 << 21)
-    compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+    compare_meshes_fast(ref, fetch_host(ctx), vtol=1e-9)
     with pytest.raises(binding.AmError):
         ctx.set_chain_groups([1, 3, 1, 1])
     ctx.close()
