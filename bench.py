@@ -151,18 +151,24 @@ def train_scorer(B, dev, max_cells):
                     "steps": 150, "scorer": "8 features (padded 32) -> 128 -> 128 -> 1, FP16 weights on MFMA"}
 
 
-def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0):
-    """Times `steps` full passes (seed + march + fetch) after `warmup` passes.
-    Kernel-class durations come from HIP events on the library's stream."""
+def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tune=False, graph_steps=0):
+    """Times `steps` full passes (seed + march + fetch) after `warmup` passes
+    (and, with tune, the chain-tile autotuner run on the warm-up's cells).
+    Kernel-class durations come from HIP events recorded on the library's
+    stream (host-driven steps only: graph replays are timed as a whole)."""
     import torch
 
     def step():
         ctx.seed_rays(o_d, d_d)
-        st = ctx.march(max_cells=max_cells, time_kernels=True, precision=precision, propose=propose)
+        st = ctx.march(max_cells=max_cells, time_kernels=graph_steps == 0, precision=precision, propose=propose,
+                       graph_steps=graph_steps)
         out = ctx.fetch()
         return st, out
 
-    for _ in range(warmup):
+    for _ in range(max(1, warmup) if tune else warmup):
+        step()
+    if tune:
+        ctx.tune_chain(reps=3)
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -244,6 +250,8 @@ def main(argv=None):
                     help="other forms to time on the same net (bf16, distance, learned, learned_bf16), on "
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
                          "batch (c4); empty for none")
+    ap.add_argument("--graph-steps", type=int, default=8,
+                    help="marching steps per captured HIP graph for the plain form (0: host-driven steps)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the bench, copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args(argv)
@@ -275,12 +283,22 @@ def main(argv=None):
     net, o, d, desc, ctx, o_d, d_d = prepare(a.workload)
     if scorer is not None:
         ctx.prop_set(scorer, k=16, rho=6.0)
-    main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells)
+    main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=True)
+    chain_tiles = {a.workload: ctx.chain_groups()}
     print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step",
           file=sys.stderr, flush=True)
     forms = {f"{a.workload}_plain": {"faces_per_s": round(main_run["faces_per_s"], 1),
                                      "ms_per_step": round(main_run["ms_per_step"], 3),
-                                     "precision": "FP64 chain (MFMA), FP64 clip and vertex solves"}}
+                                     "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
+                                     "launch": "host-driven steps, HIP events around every kernel class"}}
+    if a.graph_steps > 0:
+        r = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, graph_steps=a.graph_steps)
+        assert r["faces"] == main_run["faces"], "graph-launched form changed the face count"
+        forms[f"{a.workload}_plain_graph"] = {
+            "faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
+            "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
+            "launch": f"device-driven steps, {a.graph_steps} per HIP graph replay, no kernel timing"}
+        print(f"[bench] {a.workload}_plain_graph: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     bf16_desc = ("split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and vertex solves on "
                  "the FP32 rows; cells whose combinatorics or vertices (1e-5) are not certified are redone in FP64")
     variants = {"bf16": (1, 0), "distance": (0, 2), "learned": (0, 1), "learned_bf16": (1, 1)}
@@ -340,8 +358,9 @@ def main(argv=None):
             ctx3.prop_set(scorer, k=16, rho=6.0)
         steps3 = max(1, min(a.steps, 3))
         base = None
-        for v, (precision, propose) in todo:
-            r = time_form(ctx3, o3, d3, precision, steps3, 1, a.max_cells, propose=propose)
+        for i, (v, (precision, propose)) in enumerate(todo):
+            r = time_form(ctx3, o3, d3, precision, steps3, 1, a.max_cells, propose=propose, tune=(i == 0))
+            chain_tiles[name] = ctx3.chain_groups()
             if base is None:
                 base = r["faces"]
             assert r["faces"] == base, f"{name} {v} form changed the face count"
@@ -353,6 +372,7 @@ def main(argv=None):
               f"{forms['c4_per_shape']['ms_per_step']:.1f} ms per-shape", file=sys.stderr, flush=True)
     if train_info:
         forms["scorer_training"] = train_info
+    forms["chain_tiles_tuned"] = {k: v for k, v in chain_tiles.items()}
 
     st = main_run["stats"]
     res = {"metric": METRIC, "value": round(main_run["faces_per_s"], 1), "unit": "faces/s", "n_gpus": 1,

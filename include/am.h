@@ -102,7 +102,14 @@ typedef struct {
                              K loop runs only over the source units active in any of them
                              (sources of at most 1024 units; rows then differ from the dense
                              sum in the last bits) */
-    int32_t reserved[3];
+    int32_t graph_steps;  /* > 0 (<= 64): device-driven steps, this many captured in one HIP
+                             graph (built once per context and shape of the march, then
+                             replayed) and one counter read per replay instead of per step.
+                             Each step takes up to 16384 cells from the device-side frontier.
+                             Plain FP64 form on the split path only (AM_E_INVALID with
+                             precision, propose, sample collection, kernel_path 2 or
+                             time_kernels); the gathered chain tile is replaced by 4 cells */
+    int32_t reserved[2];
     double margin;        /* relative sign-test margin of precision 1 (0: 4e-6) */
     double vertex_tol;    /* precision 1: a cell is also redone in FP64 when a vertex's
                              estimated relative error (1.2e-6 x its first-order sensitivity
@@ -138,6 +145,7 @@ typedef struct {
     int64_t prop_accepted;    /* ... whose every-line pass cut nothing (the proposals and
                                  entry lines already gave the face) */
     int64_t prop_cuts;        /* lines that cut in their every-line passes */
+    int64_t graph_launches;   /* graph_steps > 0: graph replays */
 } am_march_stats;
 
 /* Creates a context on `device` that enqueues its work on `hip_stream`

@@ -41,7 +41,8 @@ class NetDesc(C.Structure):
 class MarchOpts(C.Structure):
     _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
                 ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("precision", C.c_int32),
-                ("propose", C.c_int32), ("chain_groups", C.c_int32), ("reserved", C.c_int32 * 3),
+                ("propose", C.c_int32), ("chain_groups", C.c_int32), ("graph_steps", C.c_int32),
+                ("reserved", C.c_int32 * 2),
                 ("margin", C.c_double),
                 ("vertex_tol", C.c_double)]
 
@@ -55,7 +56,7 @@ class MarchStats(C.Structure):
                 ("hash_ms", C.c_double), ("chain_launches", C.c_int64), ("clip_launches", C.c_int64),
                 ("hash_launches", C.c_int64), ("fused", C.c_int32), ("pad", C.c_int32),
                 ("escalated", C.c_int64), ("prop_cells", C.c_int64), ("prop_accepted", C.c_int64),
-                ("prop_cuts", C.c_int64)]
+                ("prop_cuts", C.c_int64), ("graph_launches", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "pad")}
@@ -239,9 +240,9 @@ class Context:
         self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), _p(sh), codes.shape[0]))
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
-              margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0):
+              margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0, graph_steps=0):
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
-                         int(kernel_path), int(precision), int(propose), int(chain_groups))
+                         int(kernel_path), int(precision), int(propose), int(chain_groups), int(graph_steps))
         opts.margin = float(margin)
         opts.vertex_tol = float(vertex_tol)
         stats = MarchStats()

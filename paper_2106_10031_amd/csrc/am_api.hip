@@ -46,6 +46,13 @@ void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, int *,
                    const uint64_t *, const int *, const int *, unsigned long long *, Counters *, unsigned long long,
                    unsigned long long, long long, hipStream_t);
 hipError_t sort_tmp_bytes(long long, size_t *);
+void launch_step_begin(Counters *, long long, long long, hipStream_t);
+void launch_step_end(Counters *, hipStream_t);
+void launch_chain_dev(const DevNet &, const uint64_t *, const int *, Counters *, long long, double *, int,
+                      hipStream_t);
+void launch_clip_dev(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, Counters *,
+                     long long, long long, const double *, const ClipOut &, const Candidates &, unsigned long long,
+                     hipStream_t);
 hipError_t launch_sort_cells(const unsigned *, long long, long long, unsigned *, int *, int *, void *, size_t,
                              hipStream_t);
 void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t);
@@ -131,6 +138,11 @@ struct am_ctx {
     char *d_scan = nullptr;
     size_t scan_bytes = 0;
     long long scan_n = 0;
+
+    // graph of device-driven steps (opts.graph_steps), rebuilt when its key changes
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<long long> graph_key;
 
     // chain tile: column groups per workgroup by launch size (< 2^11, < 2^13,
     // < 2^15, larger), set by am_tune_chain or am_set_chain_groups
@@ -396,6 +408,8 @@ void am_destroy(am_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     free_march(ctx);
     free_net(ctx);
     dfree(ctx->d_prop_w);
@@ -739,6 +753,10 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     if (o.propose < 0 || o.propose > 3) return fail(ctx, AM_E_INVALID, "propose must be 0..3");
     if (o.chain_groups < 0 || o.chain_groups > 5 || o.chain_groups == 3)
         return fail(ctx, AM_E_INVALID, "chain_groups must be 0, 1, 2, 4 or 5");
+    if (o.graph_steps < 0 || o.graph_steps > 64) return fail(ctx, AM_E_INVALID, "graph_steps must be 0..64");
+    if (o.graph_steps > 0 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2 ||
+                              o.time_kernels))
+        return fail(ctx, AM_E_INVALID, "graph steps run the plain FP64 split path without kernel timing");
     if (o.propose == 1 && !ctx->prop_loaded) return fail(ctx, AM_E_STATE, "no proposal scorer loaded");
     const bool collecting = ctx->prop.samples != nullptr;
     if ((o.propose != 0 || collecting) && o.kernel_path == 2)
@@ -807,6 +825,73 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     out.stride = kFaceSlots;
     out.out_base = 0;
     const long long seed_cells = hi;
+    if (o.graph_steps > 0) {
+        // device-driven steps, graph_steps per graph launch, one counter read
+        // per launch (plain FP64 form, dense chain tiles)
+        const long long gchunk = std::min<long long>(ctx->chunk_cells, 1LL << 14);
+        int variant = chain_groups(ctx, gchunk, o.chain_groups);
+        if (variant == 5) variant = 1;
+        const std::vector<long long> key = {(long long)o.graph_steps, gchunk, variant, (long long)ctx->d_codes,
+                                            (long long)ctx->d_rows, (long long)ctx->cand.parent,
+                                            (long long)ctx->d_slots, (long long)hmask, (long long)ctx->d_fm,
+                                            (long long)net.wfrag, (long long)net.bias, cap, seed_cells,
+                                            (long long)ctx->cand_cap};
+        if (!ctx->graph_exec || ctx->graph_key != key) {
+            if (ctx->graph_exec) {
+                HIPCHK(hipGraphExecDestroy(ctx->graph_exec));
+                ctx->graph_exec = nullptr;
+            }
+            if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            hipStream_t cs = ctx->cap_stream;
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < o.graph_steps; ++k) {
+                launch_step_begin(ctx->d_ctr, gchunk, cap, cs);
+                launch_chain_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_ctr, gchunk, ctx->d_rows, variant, cs);
+                launch_clip_dev(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_ctr, gchunk,
+                                seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, cs);
+                const long long nh = gchunk * 6;
+                launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, nh, cs);
+                launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
+                              ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape,
+                              ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, cs);
+                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, cs);
+                launch_step_end(ctx->d_ctr, cs);
+            }
+            const hipError_t ce = hipStreamEndCapture(cs, &g);
+            if (ce != hipSuccess) return fail(ctx, AM_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+            const hipError_t ie = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                ctx->graph_exec = nullptr;
+                return fail(ctx, AM_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+            }
+            ctx->graph_key = key;
+        }
+        long long launches = 0;
+        for (;;) {
+            HIPCHK(hipGraphLaunch(ctx->graph_exec, s));
+            HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipGetLastError());
+            ++launches;
+            const Counters &c = *ctx->h_ctr;
+            if (c.overflow_cells || c.overflow_cand || c.overflow_hash) {
+                st.required_cells = (long long)c.n_cells;
+                st.cells = std::min<long long>((long long)c.n_cells, cap);
+                st.steps = (long long)c.steps_run;
+                if (stats) *stats = st;
+                return fail(ctx, AM_E_CAPACITY,
+                            "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu)",
+                            c.n_cells, cap, c.overflow_cand, c.overflow_hash);
+            }
+            if (c.step_lo >= c.n_cells) break;
+            if (o.max_steps > 0 && (long long)c.steps_run >= o.max_steps) break;
+        }
+        st.steps = (long long)ctx->h_ctr->steps_run;
+        st.graph_launches = launches;
+        lo = hi = 0;
+    }
     while (lo < hi) {
         if (o.max_steps > 0 && st.steps >= o.max_steps) break;
         const long long n = std::min<long long>(hi - lo, ctx->chunk_cells);

@@ -139,7 +139,12 @@ struct Counters {
     unsigned long long face_verts;
     unsigned long long too_big;
     unsigned long long escalated;   // cells the split-BF16 pass handed to FP64
-    unsigned long long pad[6];
+    // device-driven steps (graph launch): first cell and cell count of the
+    // current step (adjacent: read as a pair), steps run
+    unsigned long long step_lo;
+    unsigned long long step_n;
+    unsigned long long steps_run;
+    unsigned long long pad[3];
 };
 
 // ---------------------------------------------------------------- helpers

@@ -1296,18 +1296,23 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
 
 // Positions 0..count-1 of a step: cell lo + p, or list[p] (count read on the
 // device from *list_count, at most cap).
+// With dev set (device-driven steps), the range is cells dev[0] ..
+// dev[0] + dev[1] - 1, read on the device (lo, hi unused).
 struct CellRange {
     long long lo, hi;
     const int *list;
     const unsigned long long *list_count;
     unsigned long long cap;
+    const unsigned long long *dev;
+    __device__ long long base() const { return dev ? (long long)dev[0] : lo; }
     __device__ long long count() const {
+        if (dev) return (long long)dev[1];
         if (!list || !list_count) return hi - lo;
         const unsigned long long c = *list_count;
         return (long long)(c < cap ? c : cap);
     }
-    __device__ long long cell(long long p) const { return list ? (long long)list[p] : lo + p; }
-    __device__ long long tile_base(long long p) const { return list ? p : lo + p; }
+    __device__ long long cell(long long p) const { return list ? (long long)list[p] : base() + p; }
+    __device__ long long tile_base(long long p) const { return list ? p : base() + p; }
 };
 
 // Unfused FP64 chain, 4 G cells per workgroup: rows of position p go to
@@ -1466,8 +1471,9 @@ hipError_t prepare_fused(size_t bytes) {
 }
 
 static CellRange range_of(long long lo, long long hi, const int *list, const unsigned long long *count,
-                          unsigned long long cap) {
+                          unsigned long long cap, const unsigned long long *dev = nullptr) {
     CellRange r;
+    r.dev = dev;
     r.lo = lo;
     r.hi = hi;
     r.list = list;
@@ -1568,6 +1574,61 @@ void launch_rows_unpad(const DevNet &net, long long n, const void *rows, bool f3
 void launch_prop_score(const PropNet &P, const float *X, long long n, float *z, hipStream_t st) {
     const long long blocks = (n + 4 * kWave - 1) / (4 * kWave);
     hipLaunchKernelGGL(k_prop_score, dim3((unsigned)blocks), dim3(256), 0, st, P, X, n, z);
+}
+
+// ---- device-driven steps: the step's range lives in the counters, so a fixed
+// sequence of steps can be captured in a graph and replayed without the host.
+
+// Opens a step: up to `chunk` cells from step_lo (none after an overflow),
+// and clears the candidate count.
+__global__ void k_step_begin(Counters *c, unsigned long long chunk, unsigned long long cap_cells) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long cells = c->n_cells < cap_cells ? c->n_cells : cap_cells;
+    const bool bad = c->overflow_cells || c->overflow_cand || c->overflow_hash;
+    const unsigned long long lo = c->step_lo;
+    unsigned long long n = (!bad && cells > lo) ? cells - lo : 0ull;
+    if (n > chunk) n = chunk;
+    c->step_n = n;
+    c->n_cand = 0ull;
+}
+
+__global__ void k_step_end(Counters *c) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    c->step_lo += c->step_n;
+    if (c->step_n) c->steps_run += 1ull;
+}
+
+void launch_step_begin(Counters *ctr, long long chunk, long long cap_cells, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, st, ctr, (unsigned long long)chunk,
+                       (unsigned long long)cap_cells);
+}
+
+void launch_step_end(Counters *ctr, hipStream_t st) { hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, ctr); }
+
+// Chain (dense variants 1, 2, 4) and clip of the device-driven step; grids
+// cover `chunk` cells, workgroups past the step's count exit at once.
+void launch_chain_dev(const DevNet &net, const uint64_t *codes, const int *cell_shape, Counters *ctr, long long chunk,
+                      double *rows, int g, hipStream_t st) {
+    const CellRange rg = range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo);
+    if (g >= 4)
+        hipLaunchKernelGGL((k_chain_f64<4, 4>), dim3((unsigned)((chunk + 15) / 16)), dim3(256), 0, st, net, codes,
+                           cell_shape, rg, rows);
+    else if (g == 2)
+        hipLaunchKernelGGL((k_chain_f64<2, 4>), dim3((unsigned)((chunk + 7) / 8)), dim3(256), 0, st, net, codes,
+                           cell_shape, rg, rows);
+    else
+        hipLaunchKernelGGL((k_chain_f64<1, kKChunk>), dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, net,
+                           codes, cell_shape, rg, rows);
+}
+
+void launch_clip_dev(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
+                     const int *hints, Counters *ctr, long long chunk, long long n_seed_cells, const double *rows,
+                     const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, hipStream_t st) {
+    const Fallback none{nullptr, nullptr, 0};
+    const PropArgs off{};
+    hipLaunchKernelGGL(k_clip<double>, dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, net, codes, argmax,
+                       cell_hash, hints, range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo), n_seed_cells, rows,
+                       out, cand, cand_cap, ctr, 0.0, 0.0, none, off);
 }
 
 }  // namespace am

@@ -1,0 +1,117 @@
+"""Device-driven marching steps replayed from a captured HIP graph.
+
+Bar: the graph march reproduces the oracle's mesh on small nets and batched
+shapes (cells, cycles, adjacency exact; vertices 1e-9) and the host-driven
+march's mesh on the 6x90 fit exactly; replays reuse the captured graph;
+capacity errors surface as AM_E_CAPACITY and a retry with room succeeds.
+"""
+import numpy as np
+import pytest
+
+from am_workloads import nets, seeds
+from gpu_common import compare_meshes, compare_meshes_fast, fetch_host, say
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_10031_amd import binding as B
+    return B
+
+
+NETS = {
+    "c1": nets.c1_net,
+    "maxpool_cube": nets.maxpool_cube_net,
+    "sphere_like_2x24": lambda: nets.random_sphere_like([24, 24], seed=5, radius=0.6, scale=0.4),
+}
+
+
+@pytest.mark.parametrize("k", [1, 8])
+@pytest.mark.parametrize("name", list(NETS))
+def test_graph_march_matches_oracle(binding, name, k):
+    net = NETS[name]()
+    o, d = seeds.random_rays(16, seed=4)
+    on = O.OracleNet(net)
+    codes, ams, _, _ = on.seed_rays(o, d)
+    ref = on.march(codes, ams)
+    say("graph march", name, "steps per graph", k)
+    ctx = binding.Context(0).load_net(net)
+    for _ in range(2):                         # second march replays the same graph
+        ctx.seed_rays(o, d)
+        st = ctx.march(graph_steps=k)
+        assert st["faces"] == ref.n_faces and st["cells"] == ref.stats["cells"]
+        compare_meshes(ref, fetch_host(ctx))
+    ctx.close()
+
+
+def test_graph_march_batched(binding):
+    sb = nets.latent_sphere_batch([16, 16, 16], reinject=3, latent_dim=8, n_shapes=6, seed=3)
+    o, d, sh = [], [], []
+    for s in range(sb.n_shapes):
+        a, b = seeds.random_rays(12, seed=100 + s)
+        o.append(a); d.append(b); sh.append(np.full(12, s, np.int32))
+    o, d, sh = np.concatenate(o), np.concatenate(d), np.concatenate(sh)
+    say("graph march batched")
+    ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+    ctx.seed_rays(o, d, shape_id=sh)
+    ctx.march()
+    ref = fetch_host(ctx)
+    ctx.seed_rays(o, d, shape_id=sh)
+    ctx.march(graph_steps=8)
+    compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+    ctx.close()
+
+
+def test_graph_march_c2_equals_host_driven(binding):
+    net = nets.load_fitted("c2")
+    prim = np.load(nets.DATA_DIR + "/c2_primitives.npz")
+    o, d = seeds.centre_rays(prim["p0"], 128)
+    say("graph march c2")
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    ctx.march(max_cells=1 << 21)
+    ref = fetch_host(ctx)
+    for k in (4, 16):
+        ctx.seed_rays(o, d)
+        st = ctx.march(max_cells=1 << 21, graph_steps=k)
+        assert st["faces"] == 471884
+        compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
+    ctx.close()
+
+
+def test_graph_march_capacity_then_retry(binding):
+    net = nets.c1_net()
+    o, d = seeds.random_rays(16, seed=4)
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    with pytest.raises(binding.AmError) as e:
+        ctx.march(max_cells=2000, graph_steps=4)
+    assert "AM_E_CAPACITY" in str(e.value)
+    ctx.seed_rays(o, d)
+    st = ctx.march(max_cells=1 << 16, graph_steps=4)
+    assert st["faces"] > 2000
+    with pytest.raises(binding.AmError):
+        ctx.march(graph_steps=4, precision=1)
+    ctx.close()
+
+
+
+def test_graph_march_counts_replays(binding):
+    net = nets.c1_net()
+    o, d = seeds.random_rays(16, seed=4)
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    ref = ctx.march()
+    ctx.seed_rays(o, d)
+    st = ctx.march(graph_steps=8)
+    say("graph replays", st["steps"], st["graph_launches"])
+    assert st["faces"] == ref["faces"]
+    assert st["graph_launches"] == (st["steps"] + 7) // 8 or st["graph_launches"] == (st["steps"] + 7) // 8 + 1
+    with pytest.raises(binding.AmError):
+        ctx.march(graph_steps=8, time_kernels=True)
+    ctx.close()
