@@ -44,12 +44,13 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2106_10031_amd", "csrc", f)
 
 def workload(name: str):
     from am_workloads import nets, seeds
-    if name in ("c2", "c3"):
+    if name in ("c2", "c3", "c5"):
         net = nets.load_fitted(name)
         prim = np.load(os.path.join(nets.DATA_DIR, f"{name}_primitives.npz"))
         o, d = seeds.centre_rays(prim["p0"], 128)
         desc = {"c2": "3->[90]x6->1 ReLU SDF fit of 8 random spheres (FP32 weights, FP64 geometry), 1024 dichotomy rays",
-                "c3": "3->[256]x8->1 ReLU SDF fit of 8 random superquadrics (FP32 weights), 1024 dichotomy rays"}[name]
+                "c3": "3->[256]x8->1 ReLU SDF fit of 8 random superquadrics (FP32 weights), 1024 dichotomy rays",
+                "c5": "3->[512]x8->1 ReLU SDF fit of 8 random spheres (FP32 weights), 1024 dichotomy rays"}[name]
         return net, o, d, desc
     if name == "c1":
         net = nets.c1_net()
@@ -169,7 +170,8 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tun
         step()
     if tune:
         ctx.tune_chain(reps=3)
-        step()
+        if warmup > 0:
+            step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -241,12 +243,13 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--max-cells", type=int, default=1 << 24)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
-                    default="bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16,c4",
+                    default="bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16,c4,"
+                            "c5,c5_learned",
                     help="other forms to time on the same net (bf16, distance, learned, learned_bf16), on "
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
                          "batch (c4); empty for none")
@@ -348,7 +351,7 @@ def main(argv=None):
         roofline["dominant_by_time"] = "k_clip_f64"
     ctx.close()
 
-    for name in ("c3",):
+    for name in ("c3", "c5"):
         todo = [(v, pv) for v, pv in [("plain", (0, 0))] + list(variants.items())
                 if (name if v == "plain" else f"{name}_{v}") in forms_req]
         if name == a.workload or not todo:
@@ -356,10 +359,12 @@ def main(argv=None):
         net3, _, _, _, ctx3, o3, d3 = prepare(name)
         if scorer is not None:
             ctx3.prop_set(scorer, k=16, rho=6.0)
-        steps3 = max(1, min(a.steps, 3))
+        steps3 = max(1, min(a.steps, 3 if name == "c3" else 1))
         base = None
         for i, (v, (precision, propose)) in enumerate(todo):
-            r = time_form(ctx3, o3, d3, precision, steps3, 1, a.max_cells, propose=propose, tune=(i == 0))
+            r = time_form(ctx3, o3, d3, precision, steps3, 1 if name == "c3" else 0,
+                          a.max_cells if name == "c3" else max(a.max_cells, 1 << 26), propose=propose,
+                          tune=(i == 0))
             chain_tiles[name] = ctx3.chain_groups()
             if base is None:
                 base = r["faces"]

@@ -98,10 +98,12 @@ typedef struct {
                              proposed for. */
     int32_t chain_groups; /* affine-chain tile: 0 = the context's table (am_tune_chain); 1, 2
                              or 4 column groups of 16 (4, 8 or 16 cells per workgroup; more
-                             cells share each streamed weight fragment); 5 = four cells whose
-                             K loop runs only over the source units active in any of them
-                             (sources of at most 1024 units; rows then differ from the dense
-                             sum in the last bits) */
+                             cells share each streamed weight fragment); 3 = four cells with
+                             the previous layer's rows (at most 128 units) also kept in LDS
+                             for the next layer's B operand; 5 = four cells whose K loop runs
+                             only over the source units active in any of them (sources of at
+                             most 1024 units; rows then differ from the dense sum in the last
+                             bits) */
     int32_t graph_steps;  /* > 0 (<= 64): device-driven steps, this many captured in one HIP
                              graph (built once per context and shape of the march, then
                              replayed) and one counter read per replay instead of per step.
@@ -245,22 +247,23 @@ am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, 
 am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                    uint64_t *codes, int32_t *argmax, int32_t *shape_id);
 
-/* ---- Affine-chain tile autotuner.  The chain kernel has four tile
+/* ---- Affine-chain tile autotuner.  The chain kernel has five tile
  * variants (opts.chain_groups): 4, 8 or 16 cells per workgroup (1, 2 or 4
  * column groups of the 16-column FP64 MFMA tile; more cells share each
- * streamed weight fragment, fewer fill the chip at small frontiers), and 5:
- * four cells whose K loop skips the units that are off in all of them.  The
- * context keeps one variant per launch-size bucket (fewer than 2^11 cells,
- * 2^13, 2^15, more); all start at 1. */
+ * streamed weight fragment, fewer fill the chip at small frontiers); 3: four
+ * cells reading the previous layer from LDS; 5: four cells whose K loop
+ * skips the units that are off in all of them.  The context keeps one
+ * variant per launch-size bucket (fewer than 2^11 cells, 2^13, 2^15, more);
+ * all start at 1. */
 
 /* Times the chain kernel on the first 2^10, 2^12, 2^14 and 2^16 cells of the
  * last march (fewer if it has fewer) for each variant, `reps` launches each,
  * and keeps the fastest per bucket.  ms_out (HOST, may be NULL) receives the
- * 4 x 4 average launch times (bucket-major; variants 1, 2, 4, 5).
+ * 4 x 5 average launch times (bucket-major; variants 1, 2, 3, 4, 5).
  * AM_E_STATE without a finished march. */
 am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out);
 
-/* Sets / reads the 4 per-bucket variants (each 1, 2, 4 or 5; HOST arrays). */
+/* Sets / reads the 4 per-bucket variants (each 1..5; HOST arrays). */
 am_status am_set_chain_groups(am_ctx *ctx, const int32_t *groups);
 am_status am_get_chain_groups(const am_ctx *ctx, int32_t *groups);
 

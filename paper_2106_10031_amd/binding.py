@@ -256,11 +256,11 @@ class Context:
     # ------------------------------------------------------------ chain tiles
     def tune_chain(self, reps=5):
         """Times the chain tiles on the last march's cells and keeps the
-        fastest per launch size; returns (variants[4], ms[4][4])."""
+        fastest per launch size; returns (variants[4], ms[4][5])."""
         import numpy as np
-        ms = np.zeros(16, dtype=np.float32)
+        ms = np.zeros(20, dtype=np.float32)
         self._check(self.L.am_tune_chain(self.h, int(reps), ms.ctypes.data_as(C.c_void_p)))
-        return self.chain_groups(), ms.reshape(4, 4)
+        return self.chain_groups(), ms.reshape(4, 5)
 
     def chain_groups(self):
         import numpy as np

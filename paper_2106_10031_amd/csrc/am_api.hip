@@ -751,8 +751,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
                     fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
     if (o.propose < 0 || o.propose > 3) return fail(ctx, AM_E_INVALID, "propose must be 0..3");
-    if (o.chain_groups < 0 || o.chain_groups > 5 || o.chain_groups == 3)
-        return fail(ctx, AM_E_INVALID, "chain_groups must be 0, 1, 2, 4 or 5");
+    if (o.chain_groups < 0 || o.chain_groups > 5)
+        return fail(ctx, AM_E_INVALID, "chain_groups must be 0..5");
     if (o.graph_steps < 0 || o.graph_steps > 64) return fail(ctx, AM_E_INVALID, "graph_steps must be 0..64");
     if (o.graph_steps > 0 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2 ||
                               o.time_kernels))
@@ -1044,8 +1044,8 @@ am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, i
 am_status am_set_chain_groups(am_ctx *ctx, const int32_t *groups) {
     if (!ctx || !groups) return AM_E_INVALID;
     for (int b = 0; b < 4; ++b)
-        if (groups[b] != 1 && groups[b] != 2 && groups[b] != 4 && groups[b] != 5)
-            return fail(ctx, AM_E_INVALID, "chain tile variants are 1, 2, 4 and 5");
+        if (groups[b] < 1 || groups[b] > 5)
+            return fail(ctx, AM_E_INVALID, "chain tile variants are 1..5");
     for (int b = 0; b < 4; ++b) ctx->chain_g[b] = groups[b];
     return AM_OK;
 }
@@ -1061,14 +1061,14 @@ am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out) {
     if (!ctx->have_result || ctx->res_cells <= 0) return fail(ctx, AM_E_STATE, "tuning needs a finished march");
     if (reps < 1 || reps > 100) return fail(ctx, AM_E_INVALID, "reps must be 1..100");
     TRY(set_device(ctx));
-    const int gs[4] = {1, 2, 4, 5};
+    const int gs[5] = {1, 2, 3, 4, 5};
     const long long sizes[4] = {1LL << 10, 1LL << 12, 1LL << 14, 1LL << 16};
     hipStream_t s = ctx->stream;
     for (int b = 0; b < 4; ++b) {
         const long long n = std::min<long long>({sizes[b], ctx->res_cells, ctx->chunk_cells});
         float best = 0.f;
         int best_g = 1;
-        for (int gi = 0; gi < 4; ++gi) {
+        for (int gi = 0; gi < 5; ++gi) {
             launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, gs[gi], s);
             HIPCHK(hipEventRecord(ctx->evk[0], s));
             for (int r = 0; r < reps; ++r)
@@ -1078,7 +1078,7 @@ am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, ctx->evk[0], ctx->evk[1]));
             ms /= (float)reps;
-            if (ms_out) ms_out[b * 4 + gi] = ms;
+            if (ms_out) ms_out[b * 5 + gi] = ms;
             if (gi == 0 || ms < best) {
                 best = ms;
                 best_g = gs[gi];

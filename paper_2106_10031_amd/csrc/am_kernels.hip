@@ -82,10 +82,15 @@ __device__ void stage_tile(const DevNet &net, const uint64_t *__restrict__ codes
 // fragment (weights) feeds 2 G MFMAs and every B value feeds two: a tile of
 // 4 G cells streams each weight block from L2 once.  Operands of KC K-steps
 // are loaded before their MFMAs issue.  Ends with a barrier.
+// With zl (LDS, 2 x kLdsRows x 16 doubles, G = 1), the rows of each layer of
+// at most kLdsRows units are also kept in LDS (ping-pong by layer parity) and
+// the next layer reads its B operand there instead of from global memory.
+constexpr int kLdsRows = 128;
+
 template <int G, int KC>
 __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes,
                            const int *__restrict__ cell_shape, const int *list, long long c0, int ncell, double *zb,
-                           long long rs, long long cs, uint64_t *code_lds, int *shape_lds) {
+                           long long rs, long long cs, uint64_t *code_lds, int *shape_lds, double *zl = nullptr) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -140,6 +145,9 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
                 }
                 const int uoff = net.unit_off[j];
                 const long long roff = (long long)net.row_off[j] * rs;
+                // B from LDS: the previous layer, kept there when it fits
+                const double *zin = (zl && j == l - 1 && nj <= kLdsRows) ? zl + (j & 1) * kLdsRows * 16 + col
+                                                                         : nullptr;
                 for (int ks0 = 0; ks0 < ks_n; ks0 += KC) {
                     double a0[KC], a1[KC], bv[G][KC];
 #pragma unroll
@@ -152,7 +160,7 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
 #pragma unroll
                         for (int g = 0; g < G; ++g)
                             bv[g][u] = (kv && k < nj && cell_ok[g] && code_bit(code[g], uoff + k))
-                                           ? zc[g][roff + k * rs] : 0.0;
+                                           ? (zin ? zin[k * 16] : zc[g][roff + k * rs]) : 0.0;
                     }
 #pragma unroll
                     for (int u = 0; u < KC; ++u) {
@@ -166,6 +174,7 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
             }
             // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r of
             // lane (kq * 16 + col)
+            double *zout = (zl && nl <= kLdsRows) ? zl + (l & 1) * kLdsRows * 16 + col : nullptr;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (!cell_ok[g]) continue;
@@ -174,9 +183,17 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i0 = mt0 * 16 + kq + 4 * r;
-                    if (i0 < nl) z0[i0 * rs] = acc0[g][r] + (q == 3 ? bias[i0] : 0.0);
+                    if (i0 < nl) {
+                        const double v = acc0[g][r] + (q == 3 ? bias[i0] : 0.0);
+                        z0[i0 * rs] = v;
+                        if (zout) zout[i0 * 16] = v;
+                    }
                     const int i1 = mt1 * 16 + kq + 4 * r;
-                    if (two && i1 < nl) z0[i1 * rs] = acc1[g][r] + (q == 3 ? bias[i1] : 0.0);
+                    if (two && i1 < nl) {
+                        const double v = acc1[g][r] + (q == 3 ? bias[i1] : 0.0);
+                        z0[i1 * rs] = v;
+                        if (zout) zout[i1 * 16] = v;
+                    }
                 }
             }
         }
@@ -1331,6 +1348,22 @@ __global__ __launch_bounds__(256) void k_chain_f64(DevNet net, const uint64_t *_
                       4, (long long)net.R * 4, code_lds, shape_lds);
 }
 
+// Dense FP64 chain, four cells per workgroup, the previous layer's rows in LDS.
+template <int KC>
+__global__ __launch_bounds__(256) void k_chain_f64_lds(DevNet net, const uint64_t *__restrict__ codes,
+                                                       const int *__restrict__ cell_shape, CellRange rg,
+                                                       double *__restrict__ rows) {
+    __shared__ uint64_t code_lds[4 * kMaxWords];
+    __shared__ int shape_lds[4];
+    __shared__ double zl[2 * kLdsRows * 16];
+    const long long p0 = 4LL * blockIdx.x;
+    const long long n = rg.count();
+    if (p0 >= n) return;
+    const int ncell = (int)min(4LL, n - p0);
+    chain_tile<1, KC>(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, rows + p0 * (long long)net.R * 4, 4,
+                      (long long)net.R * 4, code_lds, shape_lds, zl);
+}
+
 // Gathered FP64 chain, four cells per workgroup.
 template <int KC>
 __global__ __launch_bounds__(256) void k_chain_f64_gather(DevNet net, const uint64_t *__restrict__ codes,
@@ -1484,8 +1517,9 @@ static CellRange range_of(long long lo, long long hi, const int *list, const uns
 
 // Positions [0, hi - lo) of cells lo..hi-1, or (list != NULL) the first
 // *count entries of list, launched for up to hi - lo positions.
-// g: tile variant: 1, 2 or 4 column groups per workgroup (4 g cells), or 5:
-// four cells with the K loop over the units active in any of them.
+// g: tile variant: 1, 2 or 4 column groups per workgroup (4 g cells); 3: four
+// cells with the previous layer's rows in LDS; 5: four cells with the K loop
+// over the units active in any of them.
 void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
                   const int *list, const unsigned long long *count, double *rows, int g, hipStream_t st) {
     if (hi <= lo) return;
@@ -1494,6 +1528,9 @@ void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shap
     if (g == 5)
         hipLaunchKernelGGL((k_chain_f64_gather<kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net,
                            codes, cell_shape, rg, rows);
+    else if (g == 3)
+        hipLaunchKernelGGL((k_chain_f64_lds<kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net, codes,
+                           cell_shape, rg, rows);
     else if (g >= 4)
         hipLaunchKernelGGL((k_chain_f64<4, 4>), dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, net, codes,
                            cell_shape, rg, rows);
@@ -1605,12 +1642,15 @@ void launch_step_begin(Counters *ctr, long long chunk, long long cap_cells, hipS
 
 void launch_step_end(Counters *ctr, hipStream_t st) { hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, ctr); }
 
-// Chain (dense variants 1, 2, 4) and clip of the device-driven step; grids
+// Chain (dense variants 1, 2, 3, 4) and clip of the device-driven step; grids
 // cover `chunk` cells, workgroups past the step's count exit at once.
 void launch_chain_dev(const DevNet &net, const uint64_t *codes, const int *cell_shape, Counters *ctr, long long chunk,
                       double *rows, int g, hipStream_t st) {
     const CellRange rg = range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo);
-    if (g >= 4)
+    if (g == 3)
+        hipLaunchKernelGGL((k_chain_f64_lds<kKChunk>), dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, net,
+                           codes, cell_shape, rg, rows);
+    else if (g >= 4)
         hipLaunchKernelGGL((k_chain_f64<4, 4>), dim3((unsigned)((chunk + 15) / 16)), dim3(256), 0, st, net, codes,
                            cell_shape, rg, rows);
     else if (g == 2)

@@ -34,7 +34,7 @@ NETS = {
 }
 
 
-@pytest.mark.parametrize("groups", [2, 4, 5])
+@pytest.mark.parametrize("groups", [2, 3, 4, 5])
 @pytest.mark.parametrize("name", list(NETS))
 def test_tile_widths_match_oracle(binding, name, groups):
     net = NETS[name]()
@@ -51,7 +51,7 @@ def test_tile_widths_match_oracle(binding, name, groups):
     ctx.close()
 
 
-@pytest.mark.parametrize("groups", [2, 4, 5])
+@pytest.mark.parametrize("groups", [2, 3, 4, 5])
 def test_tile_widths_batched(binding, groups):
     sb = nets.latent_sphere_batch([16, 16, 16], reinject=3, latent_dim=8, n_shapes=6, seed=3)
     o, d, sh = [], [], []
@@ -79,17 +79,17 @@ def test_tuner_keeps_the_mesh(binding):
     ctx.seed_rays(o, d)
     ctx.march(max_cells=1 << 21, chain_groups=1)
     ref = fetch_host(ctx)
-    for g in (2, 4, 5):
+    for g in (2, 3, 4, 5):
         ctx.seed_rays(o, d)
         ctx.march(max_cells=1 << 21, chain_groups=g)
         compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0 if g != 5 else 1e-9)
     groups, ms = ctx.tune_chain(reps=3)
     say("tuned variants", groups, "ms", np.round(ms, 4).tolist())
-    assert all(g in (1, 2, 4, 5) for g in groups)
+    assert all(g in (1, 2, 3, 4, 5) for g in groups)
     assert np.all(ms > 0)
     ctx.seed_rays(o, d)
     ctx.march(max_cells=1 << 21)
     compare_meshes_fast(ref, fetch_host(ctx), vtol=1e-9)
     with pytest.raises(binding.AmError):
-        ctx.set_chain_groups([1, 3, 1, 1])
+        ctx.set_chain_groups([1, 6, 1, 1])
     ctx.close()
