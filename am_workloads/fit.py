@@ -6,9 +6,9 @@ has nothing to do with the meshing method; the resulting weights are frozen
 files under ``am_workloads/data`` whose SHA-256 is recorded in ``FIXTURES.sha256``.
 
     python -m am_workloads.fit c2        # 3->[90]x6->1, 8 spheres, seed 1
-    python -m am_workloads.fit c3 --device cuda --out gpurun_out   # 3->[256]x8->1, superquadrics
+    python -m am_workloads.fit c3 --device cuda --out /tmp/fits   # 3->[256]x8->1, superquadrics
 
-Recipe (one reading of the workload description, stated in the design doc):
+Recipe (one reading of the workload description):
     targets: union of 8 spheres (c ~ U[-0.5,0.5]^3, r ~ U[0.15,0.35]) or of 8
     superquadrics; 2^18 samples, half uniform in [-1,1]^3 and half near the
     surface (random primitive, random direction, radial jitter N(0, 0.05^2));

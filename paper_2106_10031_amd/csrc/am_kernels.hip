@@ -36,22 +36,12 @@ namespace am {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Affine chain of up to four cells c0..c0+ncell-1 (16 MFMA columns: cell =
-// col / 4, homogeneous component q = col % 4).  Element (row, cell, q) of the
-// rows is zb[row * rs + cell * cs + q].  Every wave of the workgroup takes
-// the 16-row output tiles wave, wave + nwaves, ...  Ends with a barrier.
 #ifndef AM_KCHUNK
 #define AM_KCHUNK 8
 #endif
 constexpr int kKChunk = AM_KCHUNK;     // K-steps whose operands are loaded before their MFMAs issue
 constexpr int kMaxWords = kMaxHidden / 64;
 
-// Affine chain of up to four cells c0..c0+ncell-1 (16 MFMA columns: cell =
-// col / 4, homogeneous component q = col % 4).  Element (row, cell, q) of the
-// rows is zb[row * rs + cell * cs + q].  Each wave takes two 16-row output
-// tiles at a time (mt and mt + nwaves) so that one B value feeds two MFMAs,
-// and loads the operands of kKChunk K-steps before issuing their MFMAs.  The
-// four codes are staged in LDS (code_lds, 4 x W words).  Ends with a barrier.
 // Cells of a tile: positions p0..p0+ncell-1 of the active range, i.e. cell
 // p0 + c, or list[p0 + c] when a cell list is given.
 __device__ __forceinline__ long long tile_cell(const int *list, long long p0, int c) {
