@@ -458,6 +458,63 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
+/* sphere-tracing seeding (Sec. 4.3.1, Eqn (SphereTracing))             */
+/* ------------------------------------------------------------------ */
+
+/* From x0, repeats x <- x - F(x) g / |g|^2, where g is the gradient of F in
+ * the cell of x (the xyz part of the selected head's row of the cell's affine
+ * chain); for an exact SDF |g| = 1 and this is the paper's update with step
+ * size 1.  It stops when a step lands in the cell it started from: that point
+ * lies on the cell's zero plane, so it is a surface point of that cell.
+ * Returns 0 on success (x, code, argmax and *iters set), 1 if max_iter steps
+ * do not settle, 2 if the gradient vanishes, 3 if the settled point lies
+ * outside [-1, 1]^3.  A start point with F exactly 0 is returned as it is. */
+int orc_seed_st(const orc_net *net, const double *x0, int max_iter, double *x, uint64_t *code,
+                int32_t *argmax, int32_t *iters) {
+    int W = orc_code_words(net), N = n_hidden(net), M = n_heads(net);
+    uint64_t *cc = (uint64_t *)malloc(8 * W), *cn = (uint64_t *)malloc(8 * W);
+    double *rows = (double *)malloc(sizeof(double) * 4 * (N + M));
+    double p[3] = {x0[0], x0[1], x0[2]}, q[3];
+    int32_t ac, an;
+    int st = 1, it = 0;
+    double F = orc_code(net, p, cc, &ac);
+    if (F == 0.0) {
+        st = 0;
+        goto settled;
+    }
+    for (it = 0; it < max_iter; it++) {
+        orc_chain(net, cc, rows);
+        const double *g = rows + 4 * (N + (ORC_MUTATE == 12 ? 0 : ac));
+        double gg = ORC_MUTATE == 11 ? 1.0 : g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        if (!(gg > 0.0)) { st = 2; goto done; }
+        for (int i = 0; i < 3; i++) q[i] = p[i] - F * g[i] / gg;
+        double Fq = orc_code(net, q, cn, &an);
+        for (int i = 0; i < 3; i++) p[i] = q[i];
+        if (an == ac && memcmp(cn, cc, 8 * W) == 0) {
+            it++;
+            st = 0;
+            goto settled;
+        }
+        memcpy(cc, cn, 8 * W);
+        ac = an;
+        F = Fq;
+    }
+    goto done;
+settled:
+    for (int i = 0; i < 3; i++)
+        if (fabs(p[i]) > 1.0) st = 3;
+    for (int i = 0; i < 3; i++) x[i] = p[i];
+    memcpy(code, cc, 8 * W);
+    *argmax = ac;
+    *iters = it;
+done:
+    free(cc);
+    free(cn);
+    free(rows);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
 /* marching (Algorithm 1)                                               */
 /* ------------------------------------------------------------------ */
 

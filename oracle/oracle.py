@@ -67,6 +67,9 @@ def lib(path: str = LIB_PATH):
         L.orc_seed_ray.argtypes = [P(_Net), P(C.c_double), P(C.c_double), C.c_int,
                                    P(C.c_double), P(C.c_uint64), P(C.c_int32)]
         L.orc_seed_ray.restype = C.c_int
+        L.orc_seed_st.argtypes = [P(_Net), P(C.c_double), C.c_int, P(C.c_double), P(C.c_uint64),
+                                  P(C.c_int32), P(C.c_int32)]
+        L.orc_seed_st.restype = C.c_int
         L.orc_march.argtypes = [P(_Net), P(C.c_uint64), P(C.c_int32), C.c_int64, C.c_int64]
         L.orc_march.restype = C.c_void_p
         L.orc_result_free.argtypes = [C.c_void_p]
@@ -152,6 +155,17 @@ class OracleNet:
                                 int(max_iter), _ptr(x, C.c_double), _ptr(code, C.c_uint64),
                                 C.byref(am))
         return st, x, code, am.value
+
+    def seed_st(self, x0, max_iter=64):
+        """Sphere-tracing seed from x0: (status, x, code, argmax, iterations)."""
+        x0 = np.ascontiguousarray(x0, np.float64)
+        x = np.zeros(3)
+        code = np.zeros(self.W, np.uint64)
+        am = C.c_int32()
+        it = C.c_int32()
+        st = self._L.orc_seed_st(C.byref(self.s), _ptr(x0, C.c_double), int(max_iter), _ptr(x, C.c_double),
+                                 _ptr(code, C.c_uint64), C.byref(am), C.byref(it))
+        return st, x, code, am.value, it.value
 
     def seed_rays(self, origins, dirs, max_iter=200):
         """Seeds for a batch of rays; returns (codes[S,W], argmax[S], points[S,3], status[R])."""

@@ -4,7 +4,8 @@ Each mutant is the oracle compiled with one planted mistake (ORC_MUTATE=k in
 oracle/am_oracle.c): a dropped bias, a flipped constraint orientation, a
 missing ReLU mask, dropped shortcut blocks, a reversed max-pool comparison, a
 wrong edge pair in the vertex solve, the wrong tie rule, a wrong neighbour
-flip, a transposed weight block, and ON vertices treated as outside.  The
+flip, a transposed weight block, ON vertices treated as outside, and two
+sphere-tracing seeding mistakes (no gradient normalisation, wrong head).  The
 test runs a battery of the pins (closed-form nets, brute force, Lemma 1,
 closedness) against every mutant and asserts that at least one pin fails.
 """
@@ -14,6 +15,7 @@ import numpy as np
 import pytest
 
 import meshcheck as MC
+import test_oracle_seed_st as ST
 from am_workloads import nets
 from oracle import brute
 from oracle import oracle as O
@@ -29,6 +31,8 @@ MUTANTS = {
     8: "neighbour flips the wrong unit",
     9: "square weight blocks transposed",
     10: "ON vertices treated as outside",
+    11: "sphere-tracing step not divided by |grad F|^2",
+    12: "sphere-tracing gradient taken from head 0, not the argmax head",
 }
 
 
@@ -120,6 +124,9 @@ def _battery(lib_path):
         ("brute_maxpool", lambda: _pin_brute(lib_path, _net_maxpool())),
         ("brute_cube", lambda: _pin_brute(lib_path, nets.shortcut_cube_mlp([4, 4], 301, 0.3))),
         ("c1_closed", lambda: _pin_c1_closed(lib_path)),
+        ("st_cube", lambda: ST.cube_pin(lib_path)),
+        ("st_maxpool_cube", lambda: ST.cube_pin(lib_path, nets.maxpool_cube_net)),
+        ("st_octahedron", lambda: ST.octahedron_pin(lib_path)),
     ]
     failed = []
     for name, fn in pins:
