@@ -189,6 +189,37 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tun
             "stats": stats[-1], "kernels": agg, "out": out}
 
 
+def seeding_forms(ctx, o, d, max_cells, reps=5):
+    """Triggering (Sec. 4.3): dichotomy along the 1,024 rays against sphere
+    tracing from their midpoints, each timed alone, and the faces marched
+    from the sphere-tracing seeds."""
+    import torch
+    dev = ctx.device
+    o_d = torch.as_tensor(o, dtype=torch.float64, device=dev)
+    d_d = torch.as_tensor(d, dtype=torch.float64, device=dev)
+    mid = (o_d + 0.5 * d_d).contiguous()
+    out = {}
+    for name in ("dichotomy", "sphere_tracing"):
+        for rep in range(reps + 1):
+            if rep == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if name == "dichotomy":
+                status = ctx.seed_rays(o_d, d_d)
+            else:
+                status, iters, _ = ctx.seed_points_st(mid)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        st = status.cpu().numpy()
+        e = {"ms": round(ms, 3), "points": int(len(st)), "seeded": int((st == 0).sum())}
+        if name == "sphere_tracing":
+            it = iters.cpu().numpy()[st == 0]
+            e["mean_steps"] = round(float(it.mean()), 2) if len(it) else None
+            e["faces_marched_from_seeds"] = ctx.march(max_cells=max_cells)["faces"]
+        out[name] = e
+    return out
+
+
 def c4_forms(B, dev, steps, max_cells):
     """The 64-shape decoder batch: one batched march (all shapes in one
     frontier, chain tiles autotuned on it) against one march per shape."""
@@ -248,9 +279,9 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
-                    default="bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16,c4,"
-                            "c5,c5_learned",
-                    help="other forms to time on the same net (bf16, distance, learned, learned_bf16), on "
+                    default="seeding,bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16,"
+                            "c4,c5,c5_learned",
+                    help="other forms to time on the same net (seeding, bf16, distance, learned, learned_bf16), on "
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
                          "batch (c4); empty for none")
     ap.add_argument("--graph-steps", type=int, default=8,
@@ -304,6 +335,9 @@ def main(argv=None):
         print(f"[bench] {a.workload}_plain_graph: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     bf16_desc = ("split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and vertex solves on "
                  "the FP32 rows; cells whose combinatorics or vertices (1e-5) are not certified are redone in FP64")
+    if "seeding" in forms_req:
+        forms[f"{a.workload}_seeding"] = seeding_forms(ctx, o, d, a.max_cells)
+        print(f"[bench] seeding: {forms[a.workload + '_seeding']}", file=sys.stderr, flush=True)
     variants = {"bf16": (1, 0), "distance": (0, 2), "learned": (0, 1), "learned_bf16": (1, 1)}
     prop_desc = {0: None, 1: "top-16 lines by the trained scorer clipped before the every-line pass",
                  2: "top-16 lines by distance to the entry edge clipped before the every-line pass"}

@@ -229,6 +229,20 @@ am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const
 am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
                         int64_t n);
 
+/* Sphere-tracing seeds (Sec. 4.3.1, Eqn (SphereTracing)), for SDF networks:
+ * from each start point pts[i] (DEVICE [n][3] f64; shape_id DEVICE [n] i32 or
+ * NULL), repeats x <- x - F(x) g / |g|^2 with g the gradient of F in the cell
+ * of x (the paper's update with step size 1 when |g| = 1) until a step lands
+ * in the cell it started from; that point lies on the cell's zero plane and
+ * its code is the seed.  max_iter steps at most (0: 64).  Optional DEVICE
+ * outputs: status_out [n] i32 (0 settled, 1 not within max_iter, 2 zero
+ * gradient, 3 settled outside [-1,1]^3, 4 shape id out of range), iters_out
+ * [n] i32, x_out [n][3] f64 (the last iterate).  Seeds with status != 0 are
+ * skipped by the march.  AM_E_INVALID if the network needs more LDS than a
+ * workgroup has (2 (3 + N + M) doubles + 2 W words).  Enqueued. */
+am_status am_seed_points_st(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n, int32_t max_iter,
+                            int32_t *status_out, int32_t *iters_out, double *x_out);
+
 /* Marches from the current seeds (Algorithm 1, all active cells at once)
  * until the active set is empty.  Blocks until done.  opts may be NULL.
  * Returns AM_E_CAPACITY (stats->required_cells set) when max_cells is too

@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "AM_OK", 1: "AM_E_INVALID", 2: "AM_E_OOM", 3: "AM_E_CAPACITY"
 EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_batch", "am_net_dims", "am_codes",
            "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch",
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
-           "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups"]
+           "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups",
+           "am_seed_points_st"]
 
 
 class AmError(RuntimeError):
@@ -98,6 +99,7 @@ def lib(path: str = LIB_PATH):
     L.am_prop_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float]
     L.am_prop_score.argtypes = [vp, vp, i64, vp]
     L.am_tune_chain.argtypes = [vp, i32, vp]
+    L.am_seed_points_st.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
     L.am_set_chain_groups.argtypes = [vp, vp]
     L.am_get_chain_groups.argtypes = [vp, vp]
     for name in EXPORTS:
@@ -238,6 +240,19 @@ class Context:
         sh = self._shape(shape_id)
         self._seed_keep = (codes, am, sh)   # the copy is enqueued on the stream
         self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), _p(sh), codes.shape[0]))
+
+    def seed_points_st(self, pts, max_iter=64, shape_id=None):
+        """Sphere-tracing seeds from start points; returns (status, iters, x) device tensors."""
+        t = self.torch
+        P = self._dev(pts, t.float64).reshape(-1, 3)
+        sh = self._shape(shape_id)
+        n = P.shape[0]
+        status = t.empty(n, dtype=t.int32, device=self.device)
+        iters = t.empty(n, dtype=t.int32, device=self.device)
+        x = t.empty((n, 3), dtype=t.float64, device=self.device)
+        self._seed_keep = (P, sh)           # the kernel reads them on the stream
+        self._check(self.L.am_seed_points_st(self.h, _p(P), _p(sh), n, int(max_iter), _p(status), _p(iters), _p(x)))
+        return status, iters, x
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
               margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0, graph_steps=0):

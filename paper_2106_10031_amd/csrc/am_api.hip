@@ -59,6 +59,9 @@ void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long lo
 void launch_codes(const DevNet &, const double *, const int *, long long, uint64_t *, int *, double *, hipStream_t);
 void launch_seed_rays(const DevNet &, const double *, const double *, const int *, long long, int, uint64_t *, int *,
                       int *, int *, hipStream_t);
+void launch_seed_st(const DevNet &, const double *, const int *, long long, int, uint64_t *, int *, int *, int *,
+                    int *, double *, hipStream_t);
+size_t seed_st_lds_bytes(const DevNet &);
 void launch_seed_cands(const DevNet &, const uint64_t *, const int *, const int *, const int *, long long,
                        const Candidates &, Counters *, unsigned long long, hipStream_t);
 hipError_t scan_tmp_bytes(long long, size_t *);
@@ -700,6 +703,29 @@ am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const
                               ctx->stream));
     HIPCHK(hipGetLastError());
     ctx->n_seeds = n_rays;
+    ctx->seeds_have_status = true;
+    ctx->have_result = false;
+    return AM_OK;
+}
+
+am_status am_seed_points_st(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n, int32_t max_iter,
+                            int32_t *status_out, int32_t *iters_out, double *x_out) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n <= 0 || !pts) return fail(ctx, AM_E_INVALID, "need at least one start point");
+    if (max_iter < 0 || max_iter > 100000) return fail(ctx, AM_E_INVALID, "max_iter must be 0..100000");
+    if (seed_st_lds_bytes(ctx->dn) > ctx->lds_limit)
+        return fail(ctx, AM_E_INVALID, "sphere tracing needs %zu bytes of LDS (limit %zu)",
+                    seed_st_lds_bytes(ctx->dn), ctx->lds_limit);
+    TRY(set_device(ctx));
+    TRY(ensure_seed_cap(ctx, n));
+    launch_seed_st(ctx->dn, pts, shape_id, n, max_iter > 0 ? max_iter : 64, ctx->d_seed_codes, ctx->d_seed_am,
+                   ctx->d_seed_shape, ctx->d_seed_status, iters_out, x_out, ctx->stream);
+    if (status_out)
+        HIPCHK(hipMemcpyAsync(status_out, ctx->d_seed_status, sizeof(int) * n, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+    HIPCHK(hipGetLastError());
+    ctx->n_seeds = n;
     ctx->seeds_have_status = true;
     ctx->have_result = false;
     return AM_OK;

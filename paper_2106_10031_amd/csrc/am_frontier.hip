@@ -342,6 +342,118 @@ __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *ori
     }
 }
 
+// Gradient of the selected head in the cell of `code` by a reverse pass:
+// the head's adjoint goes down through every block (l <- j), masked by the
+// ReLU states of layer l's units (hidden layers only).  adj: LDS of
+// 3 + N + M doubles.  Returns the xyz gradient to every thread.
+__device__ void wg_grad(const DevNet &net, const uint64_t *code, int am, double *adj, double g[3]) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int total = 3 + net.N + net.M;
+    for (int i = tid; i < total; i += nt) adj[i] = 0.0;
+    __syncthreads();
+    if (tid == 0) adj[3 + net.N + am] = 1.0;
+    __syncthreads();
+    const int L2 = net.n_layers;
+    for (int l = L2 - 1; l >= 1; --l) {
+        const int nl = net.width[l];
+        const double *al = adj + 3 + net.unit_off[l];
+        const bool hidden = l < L2 - 1;
+        for (int b = 0; b < net.n_blocks; ++b) {
+            if (net.blk_dst[b] != l) continue;
+            const int j = net.blk_src[b];
+            const int nj = net.width[j];
+            double *aj = adj + (j == 0 ? 0 : 3 + net.unit_off[j]);
+            const double *Wb = net.weights + net.blk_off[b];
+            const int ld = net.blk_ld[b];
+            for (int q = tid; q < nj; q += nt) {
+                double acc = 0.0;
+                for (int k = 0; k < nl; ++k) {
+                    const double a = al[k];
+                    if (a == 0.0 || (hidden && !code_bit(code, net.unit_off[l] + k))) continue;
+                    acc += Wb[(long long)k * ld + q] * a;
+                }
+                aj[q] += acc;
+            }
+        }
+        __syncthreads();
+    }
+    g[0] = adj[0];
+    g[1] = adj[1];
+    g[2] = adj[2];
+    __syncthreads();
+}
+
+// Sphere-tracing seeds (Sec. 4.3.1, Eqn (SphereTracing)): from each start
+// point, x <- x - F g / |g|^2 with g the gradient of F in the current cell
+// (the paper's step of size 1 when |g| = 1), until a step lands in the cell
+// it started from.  Status 0 settled, 1 max_iter steps without settling,
+// 2 zero gradient, 3 settled outside [-1, 1]^3, 4 shape id out of range.
+__global__ __launch_bounds__(256) void k_seed_st(DevNet net, const double *pts, const int *shape_id, long long n,
+                                                 int max_iter, uint64_t *seed_codes, int *seed_am,
+                                                 int *seed_shape, int *status, int *iters, double *x_out) {
+    extern __shared__ double lds[];
+    double *act = lds;
+    double *adj = lds + 3 + net.N + net.M;
+    uint64_t *c_cur = (uint64_t *)(adj + 3 + net.N + net.M);
+    uint64_t *c_new = c_cur + net.W;
+    __shared__ int s_eq;
+    for (long long r = blockIdx.x; r < n; r += gridDim.x) {
+        double x[3] = {pts[r * 3], pts[r * 3 + 1], pts[r * 3 + 2]};
+        const int sh_in = shape_id ? shape_id[r] : 0;
+        const bool sh_ok = sh_in >= 0 && sh_in < net.S;
+        const int sh = sh_ok ? sh_in : 0;
+        int a_cur = 0, a_new = 0, st = 1, it = 0;
+        double F = wg_forward(net, sh, x, act, c_cur, &a_cur);
+        if (!sh_ok) {
+            st = 4;
+        } else if (F == 0.0) {
+            st = 0;
+        } else {
+            for (it = 0; it < max_iter;) {
+                double g[3];
+                wg_grad(net, c_cur, a_cur, adj, g);
+                const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+                if (!(gg > 0.0)) {
+                    st = 2;
+                    break;
+                }
+                for (int i = 0; i < 3; ++i) x[i] -= F * g[i] / gg;
+                const double Fq = wg_forward(net, sh, x, act, c_new, &a_new);
+                ++it;
+                if (threadIdx.x == 0) s_eq = (a_new == a_cur);
+                __syncthreads();
+                for (int w = threadIdx.x; w < net.W; w += blockDim.x)
+                    if (c_new[w] != c_cur[w]) s_eq = 0;
+                __syncthreads();
+                const int eq = s_eq;
+                __syncthreads();
+                if (eq) {
+                    st = 0;
+                    break;
+                }
+                for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_cur[w] = c_new[w];
+                a_cur = a_new;
+                F = Fq;
+                __syncthreads();
+            }
+        }
+        if (st == 0 && (fabs(x[0]) > 1.0 || fabs(x[1]) > 1.0 || fabs(x[2]) > 1.0)) st = 3;
+        for (int w = threadIdx.x; w < net.W; w += blockDim.x) seed_codes[r * net.W + w] = st == 0 ? c_cur[w] : 0ull;
+        if (threadIdx.x == 0) {
+            seed_am[r] = st == 0 ? a_cur : 0;
+            seed_shape[r] = sh;
+            if (status) status[r] = st;
+            if (iters) iters[r] = it;
+            if (x_out) {
+                x_out[r * 3] = x[0];
+                x_out[r * 3 + 1] = x[1];
+                x_out[r * 3 + 2] = x[2];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Seeds with status 0 become candidates (parent = -(1 + seed index)).
 __global__ __launch_bounds__(256) void k_seed_cands(DevNet net, const uint64_t *seed_codes, const int *seed_am,
                                                     const int *seed_shape, const int *seed_ok, long long n,
@@ -488,6 +600,19 @@ void launch_seed_rays(const DevNet &net, const double *orig, const double *dir, 
     if (n <= 0) return;
     hipLaunchKernelGGL(k_seed_rays, dim3(grid_for(n, 1, 8192)), dim3(256), forward_lds_bytes(net, 3), st, net,
                        orig, dir, shape_id, n, max_iter, seed_codes, seed_am, seed_shape, status);
+}
+
+void launch_seed_st(const DevNet &net, const double *pts, const int *shape_id, long long n, int max_iter,
+                    uint64_t *seed_codes, int *seed_am, int *seed_shape, int *status, int *iters, double *x_out,
+                    hipStream_t st) {
+    if (n <= 0) return;
+    const size_t lds = sizeof(double) * 2 * (3 + net.N + net.M) + sizeof(uint64_t) * 2 * net.W;
+    hipLaunchKernelGGL(k_seed_st, dim3(grid_for(n, 1, 8192)), dim3(256), lds, st, net, pts, shape_id, n, max_iter,
+                       seed_codes, seed_am, seed_shape, status, iters, x_out);
+}
+
+size_t seed_st_lds_bytes(const DevNet &net) {
+    return sizeof(double) * 2 * (3 + net.N + net.M) + sizeof(uint64_t) * 2 * net.W;
 }
 
 void launch_seed_cands(const DevNet &net, const uint64_t *seed_codes, const int *seed_am, const int *seed_shape,
