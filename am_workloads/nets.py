@@ -460,3 +460,52 @@ def c4_batch(n_shapes: int = 64, radius=(0.008, 0.35)) -> ShapeBatch:
     return latent_sphere_batch([512] * 8, reinject=4, latent_dim=256, n_shapes=n_shapes, seed=3,
                                latent_std=0.01, radius=radius, scale=0.01, log_radii=True)
 
+
+
+def shifted(net: Net, c) -> Net:
+    """The network x -> net(x - c): every block from the input gives its
+    destination layer the extra bias -W c."""
+    c = np.asarray(c, np.float64)
+    bias = [b.copy() for b in net.bias]
+    for d, s, W in net.blocks:
+        if s == 0:
+            bias[d - 1] = bias[d - 1] - W @ c
+    return Net(list(net.widths), [(d, s, W.copy()) for d, s, W in net.blocks], bias)
+
+
+def negated_head(net: Net) -> Net:
+    """The network -net(x) (single head): head blocks and bias change sign."""
+    L = len(net.widths) - 1
+    blocks = [(d, s, -W if d == L else W.copy()) for d, s, W in net.blocks]
+    bias = [b.copy() for b in net.bias]
+    bias[-1] = -bias[-1]
+    return Net(list(net.widths), blocks, bias)
+
+
+def ensemble_net(n_sub: int = 4, depth: int = 4, width: int = 32, seed: int = 5) -> Net:
+    """A max-pooled ensemble in the form of the paper's local decoders (Sec. 5.2,
+    Table 7: 4 sub-networks of depth 4 and width 32 joined by a max).
+
+    Sub-network i is an occupancy-style logit, positive inside:
+    r_i - |x - c_i|_1 - 0.3 MLP_i(x - c_i), with MLP_i a He-normal ReLU MLP of
+    `depth` hidden layers of `width` units (seed + i), centre c_i ~ U[-0.35, 0.35]^3
+    and radius r_i ~ U[0.25, 0.45] (drawn in that order from seed); the max of
+    the logits is positive on the union of the insides.  Untrained: a synthetic
+    stand-in for the paper's trained decoders.
+    """
+    subs = []
+    for i, (c, r) in enumerate(ensemble_centres(n_sub, seed)):
+        sub = random_sphere_like([width] * depth, seed=seed + i, radius=r, scale=0.3)
+        subs.append(negated_head(shifted(sub, c)))
+    return maxpool_of(subs)
+
+
+def ensemble_centres(n_sub: int = 4, seed: int = 5):
+    """(centre, radius) of each sub-network of ensemble_net (same draws)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_sub):
+        c = rng.uniform(-0.35, 0.35, 3)
+        r = float(rng.uniform(0.25, 0.45))
+        out.append((c, r))
+    return out

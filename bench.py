@@ -220,6 +220,23 @@ def seeding_forms(ctx, o, d, max_cells, reps=5):
     return out
 
 
+def ensemble_form(B, dev, steps):
+    """Max-pooled ensemble of 4 depth-4 width-32 sub-networks (Sec. 5.2)."""
+    import torch
+    from am_workloads import nets, seeds
+    net = nets.ensemble_net()
+    cs = np.array([c for c, r in nets.ensemble_centres()])
+    o, d = seeds.centre_rays(cs, 32)
+    ctx = B.Context(0).load_net(net)
+    r = time_form(ctx, torch.as_tensor(o, device=dev), torch.as_tensor(d, device=dev), 0, steps, 1, 1 << 21,
+                  tune=True)
+    ctx.close()
+    return {"faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
+            "faces": r["faces"],
+            "workload": "max over 4 logits r_i - |x - c_i|_1 - 0.3 MLP_i(x - c_i), MLP_i 4 x 32 ReLU "
+                        "(untrained), 128 rays from the centres"}
+
+
 def c4_forms(B, dev, steps, max_cells):
     """The 64-shape decoder batch: one batched march (all shapes in one
     frontier, chain tiles autotuned on it) against one march per shape."""
@@ -280,7 +297,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
                     default="seeding,bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16,"
-                            "c4,c5,c5_learned",
+                            "ensemble,c4,c5,c5_learned",
                     help="other forms to time on the same net (seeding, bf16, distance, learned, learned_bf16), on "
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
                          "batch (c4); empty for none")
@@ -405,6 +422,10 @@ def main(argv=None):
             assert r["faces"] == base, f"{name} {v} form changed the face count"
             record(f"{name}_{v}", r, precision, propose)
         ctx3.close()
+    if "ensemble" in forms_req:
+        forms["ensemble_4x_d4w32"] = ensemble_form(B, dev, a.steps)
+        print(f"[bench] ensemble: {forms['ensemble_4x_d4w32']['ms_per_step']:.2f} ms/step", file=sys.stderr,
+              flush=True)
     if "c4" in forms_req:
         forms.update(c4_forms(B, dev, max(1, min(a.steps, 2)), a.max_cells))
         print(f"[bench] c4: {forms['c4_batched']['ms_per_step']:.1f} ms batched, "
