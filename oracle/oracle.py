@@ -230,3 +230,83 @@ class Mesh:
     def face(self, f):
         a, b = self.offsets[f], self.offsets[f + 1]
         return self.ids[a:b], self.verts[a:b], self.nbr[a:b]
+
+
+# ------------------------------------------------------------- welded mesh
+
+def weld(mesh, n_hidden: int, _mutate: int = 0):
+    """Shared vertices of a march's mesh: the output Z = {V, {P}} of Sec. 3.
+
+    Corner i of face f is entry offsets[f] + i; it starts edge i, so edge i
+    runs from corner i to corner i+1 (cyclic).  Across edge i (to face
+    g = nbr[i], where the same edge is edge j of g: same constraint, or for a
+    max-pool comparison edge N + k of f the row N + argmax[f] of g) the two
+    faces traverse the edge in opposite directions, so corner i of f is
+    corner j+1 of g and corner i+1 of f is corner j of g.  The vertices are
+    the classes of the equivalence these identifications generate (union-find
+    over the corners).  Vertex ids follow each class's smallest corner; a
+    vertex's position is that corner's.
+
+    Returns (corner_vertex [corners] int64, vxyz [V][3] float64, unpaired).
+    ``_mutate`` plants a mistake for the checks of the checks
+    (1: corner i of f joined to corner j of g instead of j+1).
+    """
+    off = np.asarray(mesh.offsets, np.int64)
+    ids = np.asarray(mesh.ids)
+    nbr = np.asarray(mesh.nbr, np.int64)
+    am = np.asarray(mesh.argmax)
+    n = int(off[-1])
+    parent = list(range(n))
+
+    def find(a):
+        root = a
+        while parent[root] != root:
+            root = parent[root]
+        while parent[a] != root:
+            parent[a], a = root, parent[a]
+        return root
+
+    def union(a, b):
+        a, b = find(a), find(b)
+        if a != b:
+            parent[max(a, b)] = min(a, b)
+
+    unpaired = 0
+    for f in range(len(off) - 1):
+        a0, m = int(off[f]), int(off[f + 1] - off[f])
+        for i in range(m):
+            g = int(nbr[a0 + i])
+            if g < 0:
+                continue
+            e = int(ids[a0 + i])
+            twin = e if e < n_hidden else n_hidden + int(am[f])
+            b0, mg = int(off[g]), int(off[g + 1] - off[g])
+            js = [k for k in range(mg) if ids[b0 + k] == twin and nbr[b0 + k] == f]
+            if len(js) != 1:
+                unpaired += 1
+                continue
+            j = js[0]
+            if _mutate == 1:
+                union(a0 + i, b0 + j)
+                union(a0 + (i + 1) % m, b0 + (j + 1) % mg)
+            else:
+                union(a0 + i, b0 + (j + 1) % mg)
+                union(a0 + (i + 1) % m, b0 + j)
+    roots = np.array([find(a) for a in range(n)], np.int64)
+    is_root = roots == np.arange(n)
+    vid = np.cumsum(is_root) - 1
+    corner_vertex = vid[roots]
+    vxyz = np.asarray(mesh.verts, np.float64).reshape(-1, 3)[is_root]
+    return corner_vertex.astype(np.int64), vxyz, unpaired
+
+
+def fan_triangles(offsets, corner_vertex):
+    """Triangles (c0, ck, ck+1), k = 1..m-2, of each convex polygon in order."""
+    off = np.asarray(offsets, np.int64)
+    cv = np.asarray(corner_vertex, np.int64)
+    out = []
+    for f in range(len(off) - 1):
+        a0, m = int(off[f]), int(off[f + 1] - off[f])
+        for k in range(1, m - 1):
+            out.append((cv[a0], cv[a0 + k], cv[a0 + k + 1]))
+    return np.array(out, np.int64).reshape(-1, 3)
