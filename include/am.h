@@ -261,6 +261,42 @@ am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, 
 am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                    uint64_t *codes, int32_t *argmax, int32_t *shape_id);
 
+/* ---- Welded mesh: the output Z = {V, {P}} of Sec. 3, a shared vertex
+ * array plus polygons that index it.  A march emits each face with its own
+ * copy of its vertices; across a shared edge (edge i of face f, edge j of
+ * face g = nbr[i], on the same constraint, or for a max-pool comparison edge
+ * the neighbour's row N + argmax[f], N = hidden units of the loaded net)
+ * the start of edge i is the end of edge j and vice versa.  Welding puts
+ * corners joined that way into one vertex, by connectivity alone, so a
+ * vertex where many faces meet is still one vertex.  Vertex ids run in the
+ * order of each vertex's smallest corner index.
+ *
+ * DEVICE in: the am_fetch layout for `faces` faces and `corners` corners
+ * (offsets [faces+1] with offsets[faces] == corners, ids [corners],
+ * nbr [corners], argmax [faces] or NULL when the net has no max-pool, verts
+ * [corners][3], needed only for vxyz).  DEVICE out (NULL to skip):
+ * corner_vertex [corners] i64 vertex id of each corner; vxyz [vxyz_rows][3]
+ * f64 vertex positions, taken from each vertex's smallest corner.  HOST
+ * out: n_vertices; n_unpaired = edges whose neighbour lists no matching
+ * edge back, plus faces with malformed offsets (0 for a march's mesh).
+ * At most 2^31 - 1 corners.  Synchronises.  AM_E_INVALID when
+ * offsets[faces] != corners or vxyz_rows < n_vertices (corner_vertex and
+ * n_vertices are still valid then; the first vxyz_rows rows are written). */
+am_status am_weld(am_ctx *ctx, int64_t faces, const int64_t *offsets, const int32_t *ids,
+                  const int64_t *nbr, const int32_t *argmax, const double *verts, int64_t corners,
+                  int64_t *corner_vertex, double *vxyz, int64_t vxyz_rows, int64_t *n_vertices,
+                  int64_t *n_unpaired);
+
+/* Fan triangulation of the welded polygons: face f with corners c0..c(m-1)
+ * gives triangles (c0, ck, ck+1), k = 1..m-2, in face order, as vertex ids
+ * from corner_vertex.  DEVICE: offsets [faces+1] (offsets[0] == 0),
+ * corner_vertex [offsets[faces]] i64, tri [tri_rows][3] i64 out; tri_rows =
+ * corners - 2 faces holds them all (rows past tri_rows are not written).
+ * The polygons are convex (Sec. 3), so the fan covers each exactly.
+ * Enqueued after a synchronous read of the two offset ends. */
+am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets,
+                       const int64_t *corner_vertex, int64_t *tri, int64_t tri_rows);
+
 /* ---- Affine-chain tile autotuner.  The chain kernel has five tile
  * variants (opts.chain_groups): 4, 8 or 16 cells per workgroup (1, 2 or 4
  * column groups of the 16-column FP64 MFMA tile; more cells share each

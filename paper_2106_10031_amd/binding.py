@@ -24,7 +24,7 @@ EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_b
            "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch",
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
            "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups",
-           "am_seed_points_st"]
+           "am_seed_points_st", "am_weld", "am_triangles"]
 
 
 class AmError(RuntimeError):
@@ -102,6 +102,8 @@ def lib(path: str = LIB_PATH):
     L.am_seed_points_st.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
     L.am_set_chain_groups.argtypes = [vp, vp]
     L.am_get_chain_groups.argtypes = [vp, vp]
+    L.am_weld.argtypes = [vp, i64, vp, vp, vp, vp, vp, i64, vp, vp, i64, C.POINTER(i64), C.POINTER(i64)]
+    L.am_triangles.argtypes = [vp, i64, vp, vp, vp, i64]
     for name in EXPORTS:
         if name == "am_prop_param_count":
             L.am_prop_param_count.restype = C.c_int64
@@ -350,6 +352,34 @@ class Context:
         self._check(self.L.am_fetch(self.h, _p(out["offsets"]), _p(out["ids"]), _p(out["verts"]), _p(out["nbr"]),
                                     _p(out["codes"]), _p(out["argmax"]), _p(out["shape"])))
         return out
+
+
+    def weld(self, mesh, positions=True):
+        """Shared vertices of a fetched mesh (the dict fetch() returns).
+
+        Returns (corner_vertex [corners] int64, vxyz [V][3] float64 or None,
+        n_unpaired), all on the device but n_unpaired.
+        """
+        t = self.torch
+        F = mesh["offsets"].shape[0] - 1
+        n = mesh["ids"].shape[0]
+        cv = t.empty(n, dtype=t.int64, device=self.device)
+        vx = t.empty((max(n, 1), 3), dtype=t.float64, device=self.device) if positions else None
+        nv, unp = C.c_int64(), C.c_int64()
+        am = mesh.get("argmax")
+        self._check(self.L.am_weld(self.h, F, _p(mesh["offsets"]), _p(mesh["ids"]), _p(mesh["nbr"]), _p(am),
+                                   _p(mesh["verts"]), n, _p(cv), _p(vx), vx.shape[0] if positions else 0,
+                                   C.byref(nv), C.byref(unp)))
+        return cv, (vx[:nv.value] if positions else None), unp.value
+
+    def triangles(self, offsets, corner_vertex):
+        """Fan triangles [corners - 2 faces][3] int64 (device) of welded polygons."""
+        t = self.torch
+        F = offsets.shape[0] - 1
+        T = max(corner_vertex.shape[0] - 2 * F, 0)
+        tri = t.empty((max(T, 1), 3), dtype=t.int64, device=self.device)
+        self._check(self.L.am_triangles(self.h, F, _p(offsets), _p(corner_vertex), _p(tri), T))
+        return tri[:T]
 
 
 def mesh_to_host(out):

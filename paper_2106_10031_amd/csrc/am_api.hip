@@ -69,6 +69,12 @@ hipError_t launch_fetch(const DevNet &, long long, const int *, const int *, con
                         const uint64_t *, const int *, const int *, int, int *, int *, long long *, long long *,
                         void *, size_t, long long, long long *, int *, double *, long long *, uint64_t *, int *,
                         int *, hipStream_t);
+hipError_t weld_tmp_bytes(long long, size_t *);
+hipError_t launch_weld(long long, long long, const long long *, const int *, const long long *, const int *,
+                       const double *, int, long long, long long *, int *, int *, void *, size_t,
+                       unsigned long long *, long long *, double *, hipStream_t);
+void launch_triangles(long long, long long, const long long *, const long long *, long long *, long long,
+                      hipStream_t);
 }  // namespace am
 
 using namespace am;
@@ -161,6 +167,15 @@ struct am_ctx {
     float *d_prop_scratch = nullptr;
     double *d_prop_loss = nullptr;
     double *h_prop_loss = nullptr;
+
+    // weld scratch: union-find parents, root flags, vertex ids, scan space
+    long long *d_weld_parent = nullptr;
+    int *d_weld_root = nullptr;
+    int *d_weld_vid = nullptr;
+    char *d_weld_tmp = nullptr;
+    size_t weld_tmp = 0;
+    long long weld_n = 0;
+    unsigned long long *d_weld_unpaired = nullptr;
 
     // last result
     bool have_result = false;
@@ -420,6 +435,11 @@ void am_destroy(am_ctx *ctx) {
     dfree(ctx->d_prop_nsamp);
     dfree(ctx->d_prop_scratch);
     dfree(ctx->d_prop_loss);
+    dfree(ctx->d_weld_parent);
+    dfree(ctx->d_weld_root);
+    dfree(ctx->d_weld_vid);
+    dfree(ctx->d_weld_tmp);
+    dfree(ctx->d_weld_unpaired);
     if (ctx->h_prop_loss) (void)hipHostFree(ctx->h_prop_loss);
     dfree(ctx->d_ctr);
     if (ctx->h_ctr) (void)hipHostFree(ctx->h_ctr);
@@ -1062,6 +1082,80 @@ am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, i
                         ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
                         ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
                         (long long *)nbr, codes, argmax, shape_id, ctx->stream));
+    return AM_OK;
+}
+
+// ---- welded mesh
+
+am_status am_weld(am_ctx *ctx, int64_t faces, const int64_t *offsets, const int32_t *ids, const int64_t *nbr,
+                  const int32_t *argmax, const double *verts, int64_t corners, int64_t *corner_vertex,
+                  double *vxyz, int64_t vxyz_rows, int64_t *n_vertices, int64_t *n_unpaired) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (faces < 0 || corners < 0 || vxyz_rows < 0) return fail(ctx, AM_E_INVALID, "negative size");
+    if (corners >= (1LL << 31)) return fail(ctx, AM_E_INVALID, "at most 2^31 - 1 corners");
+    if (faces > 0 && (!offsets || !ids || !nbr)) return fail(ctx, AM_E_INVALID, "offsets, ids and nbr are required");
+    if (vxyz && !verts && corners > 0) return fail(ctx, AM_E_INVALID, "vxyz needs verts");
+    if (corners > 0 && faces == 0) return fail(ctx, AM_E_INVALID, "corners without faces");
+    TRY(set_device(ctx));
+    if (faces > 0) {
+        long long last = 0;   // the CSR end must be the corner count
+        HIPCHK(hipMemcpy(&last, offsets + faces, sizeof(long long), hipMemcpyDeviceToHost));
+        if (last != corners) return fail(ctx, AM_E_INVALID, "offsets[faces] = %lld, corners = %lld", last, corners);
+    }
+    if (corners > ctx->weld_n || !ctx->d_weld_parent) {
+        const long long n = std::max<long long>(corners, 1);
+        TRY(dalloc(ctx, ctx->d_weld_parent, n));
+        TRY(dalloc(ctx, ctx->d_weld_root, n));
+        TRY(dalloc(ctx, ctx->d_weld_vid, n));
+        size_t b = 0;
+        HIPCHK(weld_tmp_bytes(n, &b));
+        TRY(dalloc(ctx, ctx->d_weld_tmp, b));
+        ctx->weld_tmp = b;
+        ctx->weld_n = n;
+    }
+    if (!ctx->d_weld_unpaired) TRY(dalloc(ctx, ctx->d_weld_unpaired, 1));
+    HIPCHK(hipMemsetAsync(ctx->d_weld_unpaired, 0, sizeof(unsigned long long), ctx->stream));
+    HIPCHK(launch_weld(faces, corners, (const long long *)offsets, ids, (const long long *)nbr, argmax, verts,
+                       ctx->dn.N, vxyz ? vxyz_rows : 0, (long long *)ctx->d_weld_parent, ctx->d_weld_root,
+                       ctx->d_weld_vid, ctx->d_weld_tmp, ctx->weld_tmp, ctx->d_weld_unpaired,
+                       (long long *)corner_vertex, vxyz, ctx->stream));
+    HIPCHK(hipGetLastError());
+    long long V = 0;
+    unsigned long long unp = 0;
+    if (corners > 0) {
+        int tail[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(&tail[0], ctx->d_weld_vid + corners - 1, sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->stream));
+        HIPCHK(hipMemcpyAsync(&tail[1], ctx->d_weld_root + corners - 1, sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->stream));
+        HIPCHK(hipMemcpyAsync(&unp, ctx->d_weld_unpaired, sizeof(unp), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        V = (long long)tail[0] + tail[1];
+    }
+    if (n_vertices) *n_vertices = V;
+    if (n_unpaired) *n_unpaired = (int64_t)unp;
+    if (vxyz && V > vxyz_rows)
+        return fail(ctx, AM_E_INVALID, "vxyz has %lld rows, the mesh has %lld vertices", (long long)vxyz_rows, V);
+    return AM_OK;
+}
+
+am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets, const int64_t *corner_vertex,
+                       int64_t *tri, int64_t tri_rows) {
+    if (!ctx) return AM_E_INVALID;
+    if (faces < 0 || tri_rows < 0) return fail(ctx, AM_E_INVALID, "negative size");
+    if (faces > 0 && (!offsets || !corner_vertex || !tri))
+        return fail(ctx, AM_E_INVALID, "offsets, corner_vertex and tri are required");
+    TRY(set_device(ctx));
+    if (faces > 0) {
+        long long ends[2] = {0, 0};
+        HIPCHK(hipMemcpy(&ends[0], offsets, sizeof(long long), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(&ends[1], offsets + faces, sizeof(long long), hipMemcpyDeviceToHost));
+        if (ends[0] != 0 || ends[1] < 0) return fail(ctx, AM_E_INVALID, "offsets must start at 0");
+        launch_triangles(faces, ends[1], (const long long *)offsets, (const long long *)corner_vertex,
+                         (long long *)tri, tri_rows, ctx->stream);
+    }
+    HIPCHK(hipGetLastError());
     return AM_OK;
 }
 

@@ -55,6 +55,19 @@ def compare_meshes(ref, got, vtol=1e-9):
     return worst
 
 
+def canonical_order(mesh):
+    """(face order, corner order) that sort faces by (code words, argmax)."""
+    codes = np.asarray(mesh.codes, np.uint64)
+    am = np.asarray(mesh.argmax)
+    keys = [am] + [codes[:, w] for w in range(codes.shape[1] - 1, -1, -1)]
+    order = np.lexsort(keys)
+    off = np.asarray(mesh.offsets, np.int64)
+    ms = np.diff(off)[order]
+    starts = off[:-1][order]
+    rel = np.arange(ms.sum()) - np.repeat(np.cumsum(ms) - ms, ms)
+    return order, np.repeat(starts, ms) + rel
+
+
 def canonical(mesh):
     """Faces sorted by (code words, argmax); neighbour indices remapped.
 
@@ -64,17 +77,10 @@ def canonical(mesh):
     """
     codes = np.asarray(mesh.codes, np.uint64)
     am = np.asarray(mesh.argmax)
-    keys = [am] + [codes[:, w] for w in range(codes.shape[1] - 1, -1, -1)]
-    order = np.lexsort(keys)
+    order, idx = canonical_order(mesh)
     inv = np.empty_like(order)
     inv[order] = np.arange(len(order))
-    off = np.asarray(mesh.offsets, np.int64)
-    m = np.diff(off)
-    ms = m[order]
-    starts = off[:-1][order]
-    # edge index list in sorted face order
-    rel = np.arange(ms.sum()) - np.repeat(np.cumsum(ms) - ms, ms)
-    idx = np.repeat(starts, ms) + rel
+    ms = np.diff(np.asarray(mesh.offsets, np.int64))[order]
     nbr = np.asarray(mesh.nbr, np.int64)[idx]
     nbr = np.where(nbr >= 0, inv[np.maximum(nbr, 0)], nbr)
     return codes[order], am[order], ms, np.asarray(mesh.ids)[idx], np.asarray(mesh.verts)[idx], nbr
