@@ -27,6 +27,8 @@
  *     an edge on unit k has code s XOR e_k (Sec. 3.1, Fig. 2), the neighbour
  *     across a max-pool comparison edge i has the same sub-codes and argmax i
  *     (Eqn (StateFuntionalMaxPoolingOperation)).
+ *   - pivoting enumeration of one face (Sec. 4.2.1, Alg. 2): a second,
+ *     independent face routine, used to cross-check the clipping one.
  *   - seeding: dichotomy along a ray (Sec. 4.3.2), stopped once both ends of
  *     the bracket share one code, then the linear root inside that cell.
  *
@@ -409,6 +411,206 @@ int orc_face(const orc_net *net, const uint64_t *code, int32_t argmax, int max_m
     orc_chain(net, code, rows);
     int m = orc_face_from_rows(net, code, argmax, rows, max_m, ids, verts, area, flags);
     free(rows);
+    return m;
+}
+
+/* ------------------------------------------------------------------ */
+/* pivoting enumeration of a face (Sec. 4.2.1, Alg. 2)                  */
+/* ------------------------------------------------------------------ */
+
+/* Constraint value and its on-plane tolerance at x (the TAU reading). */
+static double row_value(const double *c, const double *x, double *tol) {
+    double d = c[0] * x[0] + c[1] * x[1] + c[2] * x[2] + c[3];
+    double xn = fmax(fabs(x[0]), fmax(fabs(x[1]), fabs(x[2])));
+    *tol = TAU * ((fabs(c[0]) + fabs(c[1]) + fabs(c[2])) * (1.0 + xn) + fabs(c[3]));
+    return d;
+}
+
+/* Candidate vertex of planes a and b on the zero plane aF. */
+static int pair_vertex(const double *ca, const double *cb, const double *aF, double *x) {
+    double A[3][3] = {{ca[0], ca[1], ca[2]}, {cb[0], cb[1], cb[2]}, {aF[0], aF[1], aF[2]}};
+    double r[3] = {-ca[3], -cb[3], -aF[3]};
+    return solve3(A, r, x);
+}
+
+/* The boundary condition of the cell, Eqn (AnalyticCellSystem), with the box
+ * and comparison rows: every oriented row is <= its tolerance at x. */
+static int point_valid(const double *C, int nl, const double *x) {
+    for (int k = 0; k < nl; k++) {
+        double tol, d = row_value(C + 4 * k, x, &tol);
+        if (d > tol) return 0;
+    }
+    return 1;
+}
+
+static int same_point(const double *x, const double *y) {
+    double s = 1.0 + fmax(fabs(x[0]), fmax(fabs(x[1]), fabs(x[2])));
+    return fabs(x[0] - y[0]) <= 1e-12 * s && fabs(x[1] - y[1]) <= 1e-12 * s && fabs(x[2] - y[2]) <= 1e-12 * s;
+}
+
+/* Plane b carries a valid vertex other than v (with some plane other than
+ * itself): the segment of the face on b has positive length. */
+static int carries_edge(const double *C, int nl, int b, const double *aF, const double *v) {
+    for (int k = 0; k < nl; k++) {
+        if (k == b) continue;
+        double x[3];
+        if (pair_vertex(C + 4 * b, C + 4 * k, aF, x) != 0) continue;
+        if (!same_point(x, v) && point_valid(C, nl, x)) return 1;
+    }
+    return 0;
+}
+
+typedef struct {
+    double dist;
+    int k;
+} orc_order;
+
+static int cmp_order(const void *pa, const void *pb) {
+    const orc_order *a = (const orc_order *)pa, *b = (const orc_order *)pb;
+    if (a->dist < b->dist) return -1;
+    if (a->dist > b->dist) return 1;
+    return a->k - b->k;
+}
+
+/* Face of the cell (code, argmax) by pivoting from a true boundary plane
+ * start_id through the point xs on the face's edge on that plane.
+ *
+ * The planes are ordered by their distance from xs.  Phase 1 takes the
+ * first plane t'' in that order whose vertex with the start plane satisfies
+ * the cell's boundary condition; phase 2 repeats from the newest plane,
+ * scanning the order again each time, until the accepted plane is the start
+ * plane.  Readings where the paper is silent:
+ *   - the plane list holds the hidden units, the comparison rows of other
+ *     heads and the six box planes (the face is clipped to the box);
+ *   - a candidate equal to the current vertex (up to 1e-12 relative) is not
+ *     a new vertex, so a vertex where several planes meet is visited once;
+ *   - a plane is accepted only if it also carries a valid vertex other than
+ *     the candidate, i.e. the face has an edge of positive length on it
+ *     (otherwise a plane that only touches the face at the candidate could
+ *     be taken and the walk would stall);
+ *   - the walk may go either way round; the cycle is then oriented
+ *     counter-clockwise seen from +grad F and rotated to start at the
+ *     smallest id, and vertices are re-solved from consecutive ids, as in
+ *     the clipping routine.
+ * Returns m (0 on failure, flags set as for orc_face). */
+int orc_face_pivot(const orc_net *net, const uint64_t *code, int32_t argmax, int32_t start_id,
+                   const double *xs, int max_m, int32_t *ids, double *verts, int32_t *flags) {
+    int N = n_hidden(net), M = n_heads(net);
+    double *rows = (double *)malloc(sizeof(double) * 4 * (N + M));
+    orc_chain(net, code, rows);
+    const double *aF = rows + 4 * (int64_t)(N + argmax);
+    *flags = 0;
+    int nl_max = 6 + N + M;
+    double *C = (double *)malloc(sizeof(double) * 4 * nl_max);
+    int *cid = (int *)malloc(sizeof(int) * nl_max);
+    orc_order *ord = (orc_order *)malloc(sizeof(orc_order) * nl_max);
+    int32_t *walk = (int32_t *)malloc(sizeof(int32_t) * (max_m + 1));
+    double *wv = (double *)malloc(sizeof(double) * 3 * (max_m + 1));
+    int nl = 0, star = -1, m = 0;
+    for (int t = 0; t < nl_max; t++) {
+        int id;
+        if (t < 6) id = -1 - t;
+        else if (t < 6 + N) id = t - 6;
+        else {
+            int i = t - 6 - N;
+            if (i == argmax) continue;
+            id = N + i;
+        }
+        constraint_row(id, N, code, argmax, rows, C + 4 * nl);
+        cid[nl] = id;
+        if (id == start_id) star = nl;
+        double nrm = sqrt(C[4 * nl] * C[4 * nl] + C[4 * nl + 1] * C[4 * nl + 1] + C[4 * nl + 2] * C[4 * nl + 2]);
+        double d = C[4 * nl] * xs[0] + C[4 * nl + 1] * xs[1] + C[4 * nl + 2] * xs[2] + C[4 * nl + 3];
+        ord[nl].dist = nrm > 0.0 ? fabs(d) / nrm : INFINITY;
+        ord[nl].k = nl;
+        nl++;
+    }
+    if (star < 0) { *flags = ORC_FACE_EMPTY; goto done; }
+    qsort(ord, nl, sizeof(orc_order), cmp_order);
+
+    int t = star, tp = -1;
+    double cur[3] = {0.0, 0.0, 0.0};
+    int have_cur = 0;
+    for (;;) {
+        int accepted = -1;
+        double v[3];
+        for (int q = 0; q < nl; q++) {
+            int k = ord[q].k;
+            if (k == t || k == tp) continue;
+            if (pair_vertex(C + 4 * t, C + 4 * k, aF, v) != 0) continue;
+            if (!point_valid(C, nl, v)) continue;
+            if (have_cur && same_point(v, cur)) continue;
+            if (ORC_MUTATE != 13 && !carries_edge(C, nl, k, aF, v)) continue;
+            accepted = k;
+            break;
+        }
+        if (accepted < 0 || m >= max_m) { *flags = accepted < 0 ? ORC_FACE_EMPTY : ORC_FACE_TOOBIG; m = 0; goto done; }
+        /* the vertex joins the edge on t and the edge on the accepted plane */
+        walk[m] = accepted;
+        wv[3 * m] = v[0]; wv[3 * m + 1] = v[1]; wv[3 * m + 2] = v[2];
+        m++;
+        cur[0] = v[0]; cur[1] = v[1]; cur[2] = v[2];
+        have_cur = 1;
+        if (accepted == star) break;
+        tp = t;
+        t = accepted;
+    }
+    /* walk order: vertex i (i < m-1) starts the edge on walk[i]; the last
+     * vertex lies on the start plane and starts the edge back to vertex 0 */
+    {
+        double nx = 0.0, ny = 0.0, nz = 0.0;
+        for (int i = 1; i + 1 < m; i++) {
+            double ax = wv[3 * i] - wv[0], ay = wv[3 * i + 1] - wv[1], az = wv[3 * i + 2] - wv[2];
+            double bx = wv[3 * i + 3] - wv[0], by = wv[3 * i + 4] - wv[1], bz = wv[3 * i + 5] - wv[2];
+            nx += ay * bz - az * by;
+            ny += az * bx - ax * bz;
+            nz += ax * by - ay * bx;
+        }
+        int32_t *e = (int32_t *)malloc(sizeof(int32_t) * (m + 1));
+        for (int i = 0; i < m; i++) e[i] = cid[walk[i]];   /* edge starting at walk vertex i */
+        /* walk[m-1] is the start plane: vertex m-1 starts the edge on it */
+        int ccw = nx * aF[0] + ny * aF[1] + nz * aF[2] > 0.0;
+        if (ORC_MUTATE == 14) ccw = 1;
+        int32_t *cyc = (int32_t *)malloc(sizeof(int32_t) * (m + 1));
+        if (ccw) {
+            for (int i = 0; i < m; i++) cyc[i] = e[i];
+        } else {
+            /* reversed: vertex i (from the end) starts the edge that ended there */
+            for (int i = 0; i < m; i++) cyc[i] = e[(2 * m - 2 - i) % m];
+        }
+        free(e);
+        if (m < 3) { *flags = ORC_FACE_EMPTY; free(cyc); m = 0; goto done; }
+        for (int i = 0; i < m; i++)
+            for (int j = i + 1; j < m; j++)
+                if (cyc[i] == cyc[j]) *flags |= ORC_FACE_DEGEN;
+        int r = 0;
+        for (int i = 1; i < m; i++)
+            if (cyc[i] < cyc[r]) r = i;
+        for (int i = 0; i < m; i++) {
+            int ea = cyc[(i + r + m - 1) % m], eb = cyc[(i + r) % m];
+            double ca[4], cb[4], x[3];
+            constraint_row(ea, N, code, argmax, rows, ca);
+            constraint_row(eb, N, code, argmax, rows, cb);
+            double A[3][3] = {{ca[0], ca[1], ca[2]}, {cb[0], cb[1], cb[2]}, {aF[0], aF[1], aF[2]}};
+            double rr[3] = {-ca[3], -cb[3], -aF[3]};
+            if (solve3(A, rr, x) != 0) {
+                *flags |= ORC_FACE_SINGULAR;
+                x[0] = x[1] = x[2] = NAN;
+            }
+            ids[i] = eb;
+            verts[3 * i] = x[0];
+            verts[3 * i + 1] = x[1];
+            verts[3 * i + 2] = x[2];
+        }
+        free(cyc);
+    }
+done:
+    free(rows);
+    free(C);
+    free(cid);
+    free(ord);
+    free(walk);
+    free(wv);
     return m;
 }
 

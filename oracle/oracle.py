@@ -64,6 +64,9 @@ def lib(path: str = LIB_PATH):
         L.orc_face.argtypes = [P(_Net), P(C.c_uint64), C.c_int32, C.c_int, P(C.c_int32),
                                P(C.c_double), P(C.c_double), P(C.c_int32)]
         L.orc_face.restype = C.c_int
+        L.orc_face_pivot.argtypes = [P(_Net), P(C.c_uint64), C.c_int32, C.c_int32, P(C.c_double), C.c_int,
+                                     P(C.c_int32), P(C.c_double), P(C.c_int32)]
+        L.orc_face_pivot.restype = C.c_int
         L.orc_seed_ray.argtypes = [P(_Net), P(C.c_double), P(C.c_double), C.c_int,
                                    P(C.c_double), P(C.c_uint64), P(C.c_int32)]
         L.orc_seed_ray.restype = C.c_int
@@ -144,6 +147,19 @@ class OracleNet:
                            _ptr(ids, C.c_int32), _ptr(verts, C.c_double), C.byref(area),
                            C.byref(flags))
         return ids[:m].copy(), verts[:m].copy(), area.value, flags.value
+
+    def face_pivot(self, code, argmax, start_id, xs, max_m=128):
+        """Face by pivoting enumeration (Alg. 2) from plane start_id through
+        the point xs on the face's edge there: (ids, verts, flags)."""
+        code = np.ascontiguousarray(code, np.uint64)
+        xs = np.ascontiguousarray(xs, np.float64)
+        ids = np.zeros(max_m, np.int32)
+        verts = np.zeros((max_m, 3))
+        flags = C.c_int32()
+        m = self._L.orc_face_pivot(C.byref(self.s), _ptr(code, C.c_uint64), int(argmax), int(start_id),
+                                   _ptr(xs, C.c_double), max_m, _ptr(ids, C.c_int32), _ptr(verts, C.c_double),
+                                   C.byref(flags))
+        return ids[:m].copy(), verts[:m].copy(), flags.value
 
     def seed_ray(self, o, d, max_iter=200):
         o = np.ascontiguousarray(o, np.float64)

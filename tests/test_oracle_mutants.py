@@ -4,8 +4,9 @@ Each mutant is the oracle compiled with one planted mistake (ORC_MUTATE=k in
 oracle/am_oracle.c): a dropped bias, a flipped constraint orientation, a
 missing ReLU mask, dropped shortcut blocks, a reversed max-pool comparison, a
 wrong edge pair in the vertex solve, the wrong tie rule, a wrong neighbour
-flip, a transposed weight block, ON vertices treated as outside, and two
-sphere-tracing seeding mistakes (no gradient normalisation, wrong head).  The
+flip, a transposed weight block, ON vertices treated as outside, two
+sphere-tracing seeding mistakes (no gradient normalisation, wrong head) and
+two pivoting mistakes (no positive-length-edge rule, no orientation fix).  The
 test runs a battery of the pins (closed-form nets, brute force, Lemma 1,
 closedness) against every mutant and asserts that at least one pin fails.
 """
@@ -15,6 +16,7 @@ import numpy as np
 import pytest
 
 import meshcheck as MC
+import test_oracle_pivot as PV
 import test_oracle_seed_st as ST
 from am_workloads import nets
 from oracle import brute
@@ -33,6 +35,8 @@ MUTANTS = {
     10: "ON vertices treated as outside",
     11: "sphere-tracing step not divided by |grad F|^2",
     12: "sphere-tracing gradient taken from head 0, not the argmax head",
+    13: "pivoting accepts a plane without a positive-length edge on it",
+    14: "pivoting keeps the walk's orientation",
 }
 
 
@@ -127,6 +131,9 @@ def _battery(lib_path):
         ("st_cube", lambda: ST.cube_pin(lib_path)),
         ("st_maxpool_cube", lambda: ST.cube_pin(lib_path, nets.maxpool_cube_net)),
         ("st_octahedron", lambda: ST.octahedron_pin(lib_path)),
+        ("pivot_cube", lambda: PV.pin_exact(lib_path, nets.cube_net)),
+        ("pivot_octahedron_split", lambda: PV.pin_exact(lib_path, nets.octahedron_split_net)),
+        ("pivot_brute", lambda: PV.pin_brute(lib_path, _net_mlp_square())),
     ]
     failed = []
     for name, fn in pins:
