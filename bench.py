@@ -152,7 +152,8 @@ def train_scorer(B, dev, max_cells):
                     "steps": 150, "scorer": "8 features (padded 32) -> 128 -> 128 -> 1, FP16 weights on MFMA"}
 
 
-def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tune=False, graph_steps=0):
+def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tune=False, graph_steps=0,
+              face_routine=0):
     """Times `steps` full passes (seed + march + fetch) after `warmup` passes
     (and, with tune, the chain-tile autotuner run on the warm-up's cells).
     Kernel-class durations come from HIP events recorded on the library's
@@ -162,7 +163,7 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tun
     def step():
         ctx.seed_rays(o_d, d_d)
         st = ctx.march(max_cells=max_cells, time_kernels=graph_steps == 0, precision=precision, propose=propose,
-                       graph_steps=graph_steps)
+                       graph_steps=graph_steps, face_routine=face_routine)
         out = ctx.fetch()
         return st, out
 
@@ -186,7 +187,25 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tun
     agg = {k: sum(s[k] for s in stats) for k in ("chain_ms", "clip_ms", "hash_ms", "march_ms",
                                                "chain_launches", "clip_launches")}
     return {"faces": faces, "ms_per_step": (t1 - t0) * 1e3 / steps, "faces_per_s": faces * steps / (t1 - t0),
-            "stats": stats[-1], "kernels": agg, "out": out}
+            "stats": stats[-1], "kernels": agg, "out": out, "steps": steps}
+
+
+def mesh_form(ctx, mesh, reps=5):
+    """The welded output Z = {V, {P}} (Sec. 3) of a fetched march: shared
+    vertices (am_weld) and fan triangles (am_triangles), timed together."""
+    import torch
+    for rep in range(reps + 1):
+        if rep == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        cv, vx, unp = ctx.weld(mesh)
+        tri = ctx.triangles(mesh["offsets"], cv)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    F = mesh["offsets"].shape[0] - 1
+    return {"ms": round(ms, 3), "faces": int(F), "corners": int(cv.shape[0]), "vertices": int(vx.shape[0]),
+            "triangles": int(tri.shape[0]), "unpaired_edges": int(unp),
+            "faces_per_s": round(F / (ms * 1e-3), 1) if ms > 0 else None}
 
 
 def seeding_forms(ctx, o, d, max_cells, reps=5):
@@ -296,9 +315,10 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
-                    default="seeding,bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned,c3_learned_bf16,"
-                            "ensemble,c4,c5,c5_learned",
-                    help="other forms to time on the same net (seeding, bf16, distance, learned, learned_bf16), on "
+                    default="seeding,mesh,pivot,bf16,distance,learned,learned_bf16,c3,c3_pivot,c3_bf16,c3_learned,"
+                            "c3_learned_bf16,ensemble,c4,c5,c5_learned",
+                    help="other forms to time on the same net (seeding, mesh, pivot, bf16, distance, learned, "
+                         "learned_bf16), on "
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
                          "batch (c4); empty for none")
     ap.add_argument("--graph-steps", type=int, default=8,
@@ -352,16 +372,28 @@ def main(argv=None):
         print(f"[bench] {a.workload}_plain_graph: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     bf16_desc = ("split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and vertex solves on "
                  "the FP32 rows; cells whose combinatorics or vertices (1e-5) are not certified are redone in FP64")
+    if "mesh" in forms_req:
+        forms[f"{a.workload}_mesh"] = mesh_form(ctx, main_run["out"])
+        print(f"[bench] mesh: {forms[a.workload + '_mesh']}", file=sys.stderr, flush=True)
     if "seeding" in forms_req:
         forms[f"{a.workload}_seeding"] = seeding_forms(ctx, o, d, a.max_cells)
         print(f"[bench] seeding: {forms[a.workload + '_seeding']}", file=sys.stderr, flush=True)
-    variants = {"bf16": (1, 0), "distance": (0, 2), "learned": (0, 1), "learned_bf16": (1, 1)}
+    variants = {"pivot": (0, 0, 1), "bf16": (1, 0, 0), "distance": (0, 2, 0), "learned": (0, 1, 0),
+                "learned_bf16": (1, 1, 0)}
     prop_desc = {0: None, 1: "top-16 lines by the trained scorer clipped before the every-line pass",
                  2: "top-16 lines by distance to the entry edge clipped before the every-line pass"}
 
-    def record(key, r, precision, propose):
+    def record(key, r, precision, propose, routine=0):
         e = {"faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
              "faces": r["faces"], "precision": bf16_desc if precision else "FP64 chain (MFMA), FP64 clip"}
+        if routine:
+            st = r["stats"]
+            e["precision"] = "FP64 chain (MFMA), FP64 pivoting walk"
+            e["face_routine"] = ("pivoting (Sec. 4.2.1): each face traced from its entry edge, one ratio test "
+                                 "over every line per vertex; seeds clipped")
+            e["walked_cells"] = st["pivot_cells"]
+            e["clipped_cells"] = st["pivot_fallback"]
+            e["clip_ms_per_step"] = round(r["kernels"]["clip_ms"] / r["steps"], 3)
         if precision:
             e["escalated_cells"] = r["stats"]["escalated"]
         if propose:
@@ -372,12 +404,13 @@ def main(argv=None):
         forms[key] = e
         print(f"[bench] {key}: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
 
-    for v, (precision, propose) in variants.items():
+    for v, (precision, propose, routine) in variants.items():
         if v not in forms_req:
             continue
-        r = time_form(ctx, o_d, d_d, precision, a.steps, a.warmup, a.max_cells, propose=propose)
+        r = time_form(ctx, o_d, d_d, precision, a.steps, a.warmup, a.max_cells, propose=propose,
+                      face_routine=routine)
         assert r["faces"] == main_run["faces"], f"{v} form changed the face count"
-        record(f"{a.workload}_{v}", r, precision, propose)
+        record(f"{a.workload}_{v}", r, precision, propose, routine)
 
     # roofline of the dominant kernel of the timed plain steps
     kst = main_run["kernels"]
@@ -403,7 +436,7 @@ def main(argv=None):
     ctx.close()
 
     for name in ("c3", "c5"):
-        todo = [(v, pv) for v, pv in [("plain", (0, 0))] + list(variants.items())
+        todo = [(v, pv) for v, pv in [("plain", (0, 0, 0))] + list(variants.items())
                 if (name if v == "plain" else f"{name}_{v}") in forms_req]
         if name == a.workload or not todo:
             continue
@@ -412,15 +445,15 @@ def main(argv=None):
             ctx3.prop_set(scorer, k=16, rho=6.0)
         steps3 = max(1, min(a.steps, 3 if name == "c3" else 1))
         base = None
-        for i, (v, (precision, propose)) in enumerate(todo):
+        for i, (v, (precision, propose, routine)) in enumerate(todo):
             r = time_form(ctx3, o3, d3, precision, steps3, 1 if name == "c3" else 0,
                           a.max_cells if name == "c3" else max(a.max_cells, 1 << 26), propose=propose,
-                          tune=(i == 0))
+                          tune=(i == 0), face_routine=routine)
             chain_tiles[name] = ctx3.chain_groups()
             if base is None:
                 base = r["faces"]
             assert r["faces"] == base, f"{name} {v} form changed the face count"
-            record(f"{name}_{v}", r, precision, propose)
+            record(f"{name}_{v}", r, precision, propose, routine)
         ctx3.close()
     if "ensemble" in forms_req:
         forms["ensemble_4x_d4w32"] = ensemble_form(B, dev, a.steps)

@@ -111,7 +111,14 @@ typedef struct {
                              Plain FP64 form on the split path only (AM_E_INVALID with
                              precision, propose, sample collection, kernel_path 2 or
                              time_kernels); the gathered chain tile is replaced by 4 cells */
-    int32_t reserved[2];
+    int32_t face_routine; /* 0: halfplane clipping; 1: pivoting (Sec. 4.2.1): each face with
+                             an entry edge from its parent is traced vertex by vertex from
+                             that edge (a ratio test over every line per vertex); seeds and
+                             cells entered across a box or comparison edge are clipped.  The
+                             faces are the same.  Plain FP64 form on the split path only
+                             (AM_E_INVALID with precision, propose, sample collection,
+                             kernel_path 2 or graph_steps) */
+    int32_t reserved;
     double margin;        /* relative sign-test margin of precision 1 (0: 4e-6) */
     double vertex_tol;    /* precision 1: a cell is also redone in FP64 when a vertex's
                              estimated relative error (1.2e-6 x its first-order sensitivity
@@ -148,6 +155,8 @@ typedef struct {
                                  entry lines already gave the face) */
     int64_t prop_cuts;        /* lines that cut in their every-line passes */
     int64_t graph_launches;   /* graph_steps > 0: graph replays */
+    int64_t pivot_cells;      /* face_routine 1: faces traced by pivoting */
+    int64_t pivot_fallback;   /* face_routine 1: cells clipped instead (no usable entry edge) */
 } am_march_stats;
 
 /* Creates a context on `device` that enqueues its work on `hip_stream`

@@ -43,7 +43,7 @@ class MarchOpts(C.Structure):
     _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
                 ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("precision", C.c_int32),
                 ("propose", C.c_int32), ("chain_groups", C.c_int32), ("graph_steps", C.c_int32),
-                ("reserved", C.c_int32 * 2),
+                ("face_routine", C.c_int32), ("reserved", C.c_int32),
                 ("margin", C.c_double),
                 ("vertex_tol", C.c_double)]
 
@@ -57,7 +57,8 @@ class MarchStats(C.Structure):
                 ("hash_ms", C.c_double), ("chain_launches", C.c_int64), ("clip_launches", C.c_int64),
                 ("hash_launches", C.c_int64), ("fused", C.c_int32), ("pad", C.c_int32),
                 ("escalated", C.c_int64), ("prop_cells", C.c_int64), ("prop_accepted", C.c_int64),
-                ("prop_cuts", C.c_int64), ("graph_launches", C.c_int64)]
+                ("prop_cuts", C.c_int64), ("graph_launches", C.c_int64), ("pivot_cells", C.c_int64),
+                ("pivot_fallback", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "pad")}
@@ -257,9 +258,10 @@ class Context:
         return status, iters, x
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
-              margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0, graph_steps=0):
+              margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0, graph_steps=0, face_routine=0):
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
-                         int(kernel_path), int(precision), int(propose), int(chain_groups), int(graph_steps))
+                         int(kernel_path), int(precision), int(propose), int(chain_groups), int(graph_steps),
+                         int(face_routine))
         opts.margin = float(margin)
         opts.vertex_tol = float(vertex_tol)
         stats = MarchStats()

@@ -803,6 +803,10 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     if (o.graph_steps > 0 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2 ||
                               o.time_kernels))
         return fail(ctx, AM_E_INVALID, "graph steps run the plain FP64 split path without kernel timing");
+    if (o.face_routine < 0 || o.face_routine > 1) return fail(ctx, AM_E_INVALID, "face_routine must be 0 or 1");
+    if (o.face_routine == 1 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2 ||
+                                o.graph_steps > 0))
+        return fail(ctx, AM_E_INVALID, "pivoting runs the plain FP64 split path with host-driven steps");
     if (o.propose == 1 && !ctx->prop_loaded) return fail(ctx, AM_E_STATE, "no proposal scorer loaded");
     const bool collecting = ctx->prop.samples != nullptr;
     if ((o.propose != 0 || collecting) && o.kernel_path == 2)
@@ -811,6 +815,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
                        (o.kernel_path == 2 || (o.kernel_path == 0 && ctx->prefer_fused && ctx->fused_ok));
     PropArgs pa = ctx->prop;
     pa.mode = o.propose;
+    pa.face_routine = o.face_routine;
     if (o.propose != 0) {
         if (!ctx->d_prop_stats) TRY(dalloc(ctx, ctx->d_prop_stats, (size_t)kPropStats * kPropSlots));
         pa.stats = ctx->d_prop_stats;
@@ -1022,6 +1027,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
 
     st.domain_edges = (long long)c.domain_edges;
     st.escalated = (long long)c.escalated;
+    st.pivot_cells = (long long)c.pivot_cells;
+    st.pivot_fallback = (long long)c.pivot_fallback;
     if (o.propose != 0) {
         unsigned long long ps[kPropStats * kPropSlots];
         HIPCHK(hipMemcpy(ps, ctx->d_prop_stats, sizeof ps, hipMemcpyDeviceToHost));

@@ -80,6 +80,7 @@ struct PropNet {
 
 struct PropArgs {
     int mode;                    // 0 off, 1 scorer, 2 distance order, 3 off but count cuts
+    int face_routine;            // 0 clipping, 1 pivoting walk from the entry edge (FP64 rows)
     int k;                       // proposals per cell (<= kPropK)
     float rho;                   // candidates: distance to the entry midpoint <= rho x entry length
     PropNet net;
@@ -144,7 +145,9 @@ struct Counters {
     unsigned long long step_lo;
     unsigned long long step_n;
     unsigned long long steps_run;
-    unsigned long long pad[3];
+    unsigned long long pivot_cells;      // pivoting form: faces traced by the walk
+    unsigned long long pivot_fallback;   // ... and cells clipped instead
+    unsigned long long pad;
 };
 
 // ---------------------------------------------------------------- helpers

@@ -974,7 +974,166 @@ __device__ void collect_samples(const DevNet &net, const PropArgs &pa, const Ent
 // chain are read as rb[row * rs + q] (FP64, or FP32 from the split-BF16
 // chain).  margin > 0 (FP32 rows): faces that margin_ambiguous flags, and
 // empty or degenerate results, are not written but appended to fb.
-template <typename RowT, bool Learn>
+// 2-D line of constraint slot l of a cell (0..N-1 hidden units, N..N+M-1
+// comparisons with the other heads, then the six box planes) in the plane
+// frame: cu a + cv b + cw <= 0 inside.  False for the cell's own head.
+template <typename RowT>
+__device__ __forceinline__ bool slot_line(const DevNet &net, int l, const uint64_t *code, int am, const RowT *rb,
+                                          long long rs, const double u[3], const double v[3], const double p0[3],
+                                          const double aF[4], double &cu, double &cv, double &cw, int &id) {
+    double c[4];
+    if (l < net.N) {
+        const RowT *z = rb + (long long)net.row_of_unit[l] * rs;
+        const double sg = code_bit(code, l) ? -1.0 : 1.0;
+        c[0] = sg * z[0];
+        c[1] = sg * z[1];
+        c[2] = sg * z[2];
+        c[3] = sg * z[3];
+        id = l;
+    } else if (l < net.N + net.M) {
+        const int hd = l - net.N;
+        if (hd == am) return false;
+        const RowT *z = rb + (long long)net.row_of_unit[l] * rs;
+        c[0] = z[0] - aF[0];
+        c[1] = z[1] - aF[1];
+        c[2] = z[2] - aF[2];
+        c[3] = z[3] - aF[3];
+        id = l;
+    } else {
+        const int t = l - net.N - net.M;
+        const int axb = t >> 1;
+        const double sg = (t & 1) ? -1.0 : 1.0;
+        cu = sg * u[axb];
+        cv = sg * v[axb];
+        cw = sg * p0[axb] - 1.0;
+        id = -1 - t;
+        return true;
+    }
+    cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+    cv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
+    cw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
+    return true;
+}
+
+// Wave-wide minimum of (key, id), smaller id on equal keys.
+__device__ __forceinline__ void wave_argmin(double &key, int &id) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double k2 = __shfl_xor(key, o, kWave);
+        const int i2 = __shfl_xor(id, o, kWave);
+        if (k2 < key || (k2 == key && i2 < id)) {
+            key = k2;
+            id = i2;
+        }
+    }
+}
+
+// Pivoting (Sec. 4.2.1): the face traced vertex by vertex from its entry
+// edge.  From a point on the current boundary line the walk moves along it,
+// the face on its left; the next vertex is where the first line ahead is
+// met (a ratio test over every line, one wave-wide minimum per vertex, in
+// place of testing candidate vertices one by one in distance order).  Where
+// several lines meet that vertex (within 2^-38 relative) the face goes on
+// along the one that turns furthest, the only one that leaves the face on
+// its inner side.  The walk ends when the entry line is met again.  Builds P
+// counter-clockwise with edge ids as the clip does; false (P unusable) when
+// the walk cannot finish within max_m vertices or meets no line ahead.
+template <typename RowT>
+__device__ bool pivot_poly(const DevNet &net, const uint64_t *code, int am, const RowT *rb, long long rs,
+                           const double u[3], const double v[3], const double p0[3], const double aF[4],
+                           const EntryEdge &E, int max_m, Poly &P) {
+    const int lane = lane_id();
+    const int L = net.N + net.M + 6;
+    const int start = E.id[0];
+    double na, nb, no;
+    if (!frame_line(net, start, code, am, rb, rs, u, v, p0, na, nb, no)) return false;
+    int cur = start;
+    double ya = E.qa, yb = E.qb;
+    int m = 0;
+    P.m = 0;
+    for (int step = 0; step < max_m + 8; ++step) {
+        const double da = -nb, db = na;   // along the line, the inside on the left
+        double s1 = __builtin_inf(), s2 = __builtin_inf();
+        int id1 = 0x7fffffff;
+        for (int l = lane; l < L; l += kWave) {
+            double cu, cv, cw;
+            int id;
+            if (!slot_line(net, l, code, am, rb, rs, u, v, p0, aF, cu, cv, cw, id) || id == cur) continue;
+            const double den = cu * da + cv * db;
+            if (!(den > 1e-13 * sqrt(cu * cu + cv * cv))) continue;   // parallel, or behind
+            const double s = -(cu * ya + cv * yb + cw) / den;
+            if (s < s1 || (s == s1 && id < id1)) {
+                s2 = s1;
+                s1 = s;
+                id1 = id;
+            } else if (s < s2) {
+                s2 = s;
+            }
+        }
+        double g = s1;
+        int gid = id1;
+        wave_argmin(g, gid);
+        if (!(g < 1e300)) return false;
+        const double tol = 0x1p-38 * (1.0 + fabs(ya) + fabs(yb) + fabs(g));
+        const uint64_t near = ballot(s1 <= g + tol);
+        const bool tie = __popcll(near) > 1 || ballot(s2 <= g + tol) != 0;
+        int nid = gid;
+        if (tie) {
+            // the lines through the next vertex: the one turning furthest left
+            double key = __builtin_inf();
+            int kid = 0x7fffffff;
+            for (int l = lane; l < L; l += kWave) {
+                double cu, cv, cw;
+                int id;
+                if (!slot_line(net, l, code, am, rb, rs, u, v, p0, aF, cu, cv, cw, id) || id == cur) continue;
+                const double nrm = sqrt(cu * cu + cv * cv);
+                const double den = cu * da + cv * db;
+                if (!(den > 1e-13 * nrm)) continue;
+                const double s = -(cu * ya + cv * yb + cw) / den;
+                if (!(s <= g + tol)) continue;
+                // cosine between the walk and the line's own direction (-cv, cu)
+                const double c = (da * -cv + db * cu) / nrm;
+                if (c < key || (c == key && id < kid)) {
+                    key = c;
+                    kid = id;
+                }
+            }
+            wave_argmin(key, kid);
+            nid = kid;
+        }
+        double ma, mb, mo;
+        if (!frame_line(net, nid, code, am, rb, rs, u, v, p0, ma, mb, mo)) return false;
+        const double det = na * mb - nb * ma;
+        if (!(fabs(det) > 1e-300)) return false;
+        const double xa = (nb * mo - no * mb) / det;
+        const double xb = (ma * no - na * mo) / det;
+        if (m > 0 && g <= tol) {
+            // no length on the current line: the last vertex's edge is the new line
+            if (lane == m - 1) P.e = nid;
+        } else {
+            if (m >= max_m) return false;
+            if (lane == m) {
+                P.a = xa;
+                P.b = xb;
+                P.r = 1.0 + sqrt(xa * xa + xb * xb);
+                P.e = nid;
+            }
+            ++m;
+        }
+        if (nid == start) {
+            P.m = m;
+            return m >= 3;
+        }
+        cur = nid;
+        na = ma;
+        nb = mb;
+        no = mo;
+        ya = xa;
+        yb = xb;
+    }
+    return false;
+}
+
+template <typename RowT, bool Learn, bool Pivot = false>
 __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ argmax,
                           const uint64_t *__restrict__ cell_hash, const int *__restrict__ hints, long long cell,
                           long long n_seed_cells, const RowT *rb, long long rs, PolyScratch &S, const ClipOut &out,
@@ -1033,6 +1192,20 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         P.r = 1.0 + sqrt(P.a * P.a + P.b * P.b);
         P.e = -7 - li;
         P.m = 4;
+        bool walked = false;
+        if constexpr (Pivot) {
+            // pivoting form: trace the face from the entry edge; cells
+            // without one (seeds, box or comparison entries) are clipped
+            EntryEdge E0;
+            if (entry_edge(net, hints, cell, code, am, rb, rs, u, v, p0, E0)) {
+                const double aFd[4] = {fx, fy, fz, fw};
+                Poly W;
+                walked = pivot_poly(net, code, am, rb, rs, u, v, p0, aFd, E0, kMaxPoly, W);
+                if (walked) P = W;
+            }
+            if (lane == 0 && ctr) atomicAdd(walked ? &ctr->pivot_cells : &ctr->pivot_fallback, 1ull);
+        }
+        if (!walked) {
         // lines the parent's face says bound this one: the entry edge and the
         // parent's edges on either side of it (the cells around a cell edge
         // share both planes).  Any order gives the same polygon; these first
@@ -1136,6 +1309,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
             sh_clip(P, sg * u[axb], sg * v[axb], sg * p0[axb] - 1.0, sqrt(u[axb] * u[axb] + v[axb] * v[axb]), -1 - t,
                     S, flags);
         }
+        }   // !walked
     }
 
     // ---- validity: >= 3 vertices, positive area, distinct ids, no frame edge
@@ -1405,6 +1579,23 @@ __global__ __launch_bounds__(256) void k_clip(DevNet net, const uint64_t *__rest
 
 // The clip with the learned form's steps (proposals, counting, sample
 // collection) and the scorer's LDS.
+__global__ __launch_bounds__(256) void k_clip_pivot(DevNet net, const uint64_t *__restrict__ codes,
+                                                    const int *__restrict__ argmax,
+                                                    const uint64_t *__restrict__ cell_hash,
+                                                    const int *__restrict__ hints, CellRange rg,
+                                                    long long n_seed_cells, const double *__restrict__ rows,
+                                                    ClipOut out, Candidates cand, unsigned long long cand_cap,
+                                                    Counters *ctr, PropArgs pa) {
+    __shared__ PolyScratch scratch[4];
+    const int wave = threadIdx.x >> 6;
+    const long long p = 4LL * blockIdx.x + wave;
+    if (p >= rg.count()) return;
+    const Fallback none{nullptr, nullptr, 0};
+    clip_cell<double, false, true>(net, codes, argmax, cell_hash, hints, rg.cell(p), n_seed_cells,
+                                   rows + p * (long long)net.R * 4, 4, scratch[wave], out, cand, cand_cap, ctr, 0.0,
+                                   0.0, none, pa, nullptr);
+}
+
 template <typename RowT>
 __global__ __launch_bounds__(256) void k_clip_prop(DevNet net, const uint64_t *__restrict__ codes,
                                                    const int *__restrict__ argmax,
@@ -1547,7 +1738,11 @@ void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, co
     if (hi <= lo) return;
     const long long blocks = (hi - lo + 3) / 4;
     const Fallback none{nullptr, nullptr, 0};
-    if (pa.mode != 0 || pa.samples)
+    if (pa.face_routine == 1)
+        hipLaunchKernelGGL(k_clip_pivot, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash,
+                           hints, range_of(lo, hi, list, count, (unsigned long long)(hi - lo)), n_seed_cells, rows,
+                           out, cand, cand_cap, ctr, pa);
+    else if (pa.mode != 0 || pa.samples)
         hipLaunchKernelGGL(k_clip_prop<double>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax,
                            cell_hash, hints, range_of(lo, hi, list, count, (unsigned long long)(hi - lo)),
                            n_seed_cells, rows, out, cand, cand_cap, ctr, 0.0, 0.0, none, pa);
