@@ -98,9 +98,11 @@ typedef struct {
                              proposed for. */
     int32_t chain_groups; /* affine-chain tile: 0 = the context's table (am_tune_chain); 1, 2
                              or 4 column groups of 16 (4, 8 or 16 cells per workgroup; more
-                             cells share each streamed weight fragment); 3 = four cells with
-                             the previous layer's rows (at most 128 units) also kept in LDS
-                             for the next layer's B operand; 5 = four cells whose K loop runs
+                             cells share each streamed weight fragment); 3 = four cells
+                             reading the previous layer's rows from LDS as the B operand
+                             (layers of at most 128 units stay there; for nets up to 512
+                             units wide each layer is staged there, masked, from global
+                             memory); 5 = four cells whose K loop runs
                              only over the source units active in any of them (sources of at
                              most 1024 units; rows then differ from the dense sum in the last
                              bits) */

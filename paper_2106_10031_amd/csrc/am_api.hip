@@ -39,6 +39,8 @@ void launch_fused(const DevNet &, const uint64_t *, const int *, const int *, co
                   hipStream_t);
 size_t fused_lds_bytes(const DevNet &);
 hipError_t prepare_fused(size_t);
+size_t chain_res_lds_bytes(const DevNet &);
+hipError_t prepare_chain_res(size_t);
 void launch_rows_unpad(const DevNet &, long long, const void *, bool, double *, hipStream_t);
 void launch_insert(const DevNet &, const Candidates &, const CellArrays &, unsigned long long *, unsigned long long,
                    Counters *, unsigned long long, long long, hipStream_t);
@@ -620,6 +622,10 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     // the fused kernel keeps the rows of four cells in LDS next to 4 x 1.75 KiB of clip scratch
     const size_t fb = fused_lds_bytes(dn);
     ctx->fused_ok = fb + 8192 <= ctx->lds_limit && prepare_fused(fb) == hipSuccess;
+    {
+        const size_t rb = chain_res_lds_bytes(ctx->dn);
+        if (rb > 0 && prepare_chain_res(rb) != hipSuccess) return fail(ctx, AM_E_HIP, "chain LDS attribute failed");
+    }
     (void)hipGetLastError();
     ctx->loaded = true;
     return AM_OK;

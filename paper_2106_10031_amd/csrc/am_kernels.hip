@@ -191,6 +191,130 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes
     }
 }
 
+// ---- staged chain: four cells per workgroup; before each layer the rows of
+// the previous hidden layer (written by the workgroup to global memory) are
+// copied once, masked by the cells' codes and zero padded to the K-steps,
+// into one LDS buffer (widest hidden layer x 16 doubles, at most kResMax
+// units), so the four waves read their B operand there instead of each
+// fetching it through L1.  Shortcut sources are read from global memory as
+// in the dense tile.  Ends with a barrier.
+constexpr int kResMax = 512;
+
+template <int KC>
+__device__ void chain_tile_res(const DevNet &net, const uint64_t *__restrict__ codes,
+                               const int *__restrict__ cell_shape, const int *list, long long c0, int ncell,
+                               double *zb, long long rs, long long cs, uint64_t *code_lds, int *shape_lds,
+                               double *zr) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    constexpr int nwaves = 4;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const int q = col & 3;
+    const int cl = col >> 2;
+    stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds, 4);
+    const bool cell_ok = cl < ncell;
+    const long long bias_base = (long long)shape_lds[cl] * net.bias_stride;
+    const uint64_t *code = code_lds + cl * net.W;
+    double *zc = zb + cl * cs + q;
+
+    for (int l = 1; l < net.n_layers; ++l) {
+        const int nl = net.width[l];
+        const int mtiles = (nl + 15) >> 4;
+        const int jp = l - 1;
+        const int njp = net.width[jp];
+        const int ldp = (njp + 3) & ~3;
+        if (jp >= 1) {
+            // stage the previous layer: element (k, cell, q) at zr[k * 16 + 4 cell + q]
+            const int uoff = net.unit_off[jp];
+            const long long roff = (long long)net.row_off[jp] * rs;
+            for (int t = threadIdx.x; t < 16 * ldp; t += blockDim.x) {
+                const int c = t / (4 * ldp);
+                const int r = t - c * 4 * ldp;
+                const int k = r >> 2, qq = r & 3;
+                double v = 0.0;
+                if (c < ncell && k < njp && code_bit(code_lds + c * net.W, uoff + k))
+                    v = zb[c * cs + roff + (long long)k * rs + qq];
+                zr[k * 16 + 4 * c + qq] = v;
+            }
+            __syncthreads();
+        }
+        for (int mt0 = wave; mt0 < mtiles; mt0 += 2 * nwaves) {
+            const int mt1 = mt0 + nwaves;
+            const bool two = mt1 < mtiles;
+            v4d acc0 = v4d{0.0, 0.0, 0.0, 0.0}, acc1 = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < net.n_blocks; ++b) {
+                if (net.blk_dst[b] != l) continue;
+                const int j = net.blk_src[b];
+                const int ks_n = net.blk_ld[b] >> 2;
+                const int nj = net.width[j];
+                const double *fr0 = net.wfrag + net.blk_frag_off[b] + (long long)mt0 * ks_n * 64 + lane;
+                const double *fr1 = fr0 + (long long)(mt1 - mt0) * ks_n * 64;
+                if (j == 0) {
+                    const double bv = (kq < 3 && kq == q) ? 1.0 : 0.0;
+                    const double a0 = fr0[0], a1 = two ? fr1[0] : 0.0;
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0, 0, 0, 0);
+                    if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1, 0, 0, 0);
+                    continue;
+                }
+                if (j == jp) {
+                    // staged: masked and padded, no bounds or code tests
+                    const double *zin = zr + kq * 16 + col;
+                    for (int ks0 = 0; ks0 < ks_n; ks0 += KC) {
+                        double a0[KC], a1[KC], bv[KC];
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) {
+                            const int ks = ks0 + u;
+                            const bool kv = ks < ks_n;
+                            a0[u] = kv ? fr0[ks * 64] : 0.0;
+                            a1[u] = (kv && two) ? fr1[ks * 64] : 0.0;
+                            bv[u] = kv ? zin[ks * 64] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) {
+                            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc0, 0, 0, 0);
+                            if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc1, 0, 0, 0);
+                        }
+                    }
+                    continue;
+                }
+                const int uoff = net.unit_off[j];
+                const long long roff = (long long)net.row_off[j] * rs;
+                for (int ks0 = 0; ks0 < ks_n; ks0 += KC) {
+                    double a0[KC], a1[KC], bv[KC];
+#pragma unroll
+                    for (int u = 0; u < KC; ++u) {
+                        const int ks = ks0 + u;
+                        const bool kv = ks < ks_n;
+                        const int k = ks * 4 + kq;
+                        a0[u] = kv ? fr0[ks * 64] : 0.0;
+                        a1[u] = (kv && two) ? fr1[ks * 64] : 0.0;
+                        bv[u] = (kv && k < nj && cell_ok && code_bit(code, uoff + k)) ? zc[roff + k * rs] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < KC; ++u) {
+                        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], bv[u], acc0, 0, 0, 0);
+                        if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], bv[u], acc1, 0, 0, 0);
+                    }
+                }
+            }
+            if (cell_ok) {
+                const double *bias = net.bias + bias_base + net.bias_off[l];
+                double *z0 = zc + (long long)net.row_off[l] * rs;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r
+                    const int i0 = mt0 * 16 + kq + 4 * r;
+                    if (i0 < nl) z0[i0 * rs] = acc0[r] + (q == 3 ? bias[i0] : 0.0);
+                    const int i1 = mt1 * 16 + kq + 4 * r;
+                    if (two && i1 < nl) z0[i1 * rs] = acc1[r] + (q == 3 ? bias[i1] : 0.0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---- gathered chain: a tile's four cells share the MFMA columns, so a unit
 // that is off in all four contributes only zeros.  For source layers of at
 // most kListMax units the tile first lists the units active in any of its
@@ -1528,6 +1652,23 @@ __global__ __launch_bounds__(256) void k_chain_f64_lds(DevNet net, const uint64_
                       (long long)net.R * 4, code_lds, shape_lds, zl);
 }
 
+// Dense FP64 chain, four cells per workgroup, the previous hidden layer
+// staged in LDS (dynamic: widest hidden layer x 16 doubles).
+template <int KC>
+__global__ __launch_bounds__(256) void k_chain_f64_res(DevNet net, const uint64_t *__restrict__ codes,
+                                                       const int *__restrict__ cell_shape, CellRange rg,
+                                                       double *__restrict__ rows) {
+    __shared__ uint64_t code_lds[4 * kMaxWords];
+    __shared__ int shape_lds[4];
+    extern __shared__ double zr[];
+    const long long p0 = 4LL * blockIdx.x;
+    const long long n = rg.count();
+    if (p0 >= n) return;
+    const int ncell = (int)min(4LL, n - p0);
+    chain_tile_res<KC>(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, rows + p0 * (long long)net.R * 4,
+                       4, (long long)net.R * 4, code_lds, shape_lds, zr);
+}
+
 // Gathered FP64 chain, four cells per workgroup.
 template <int KC>
 __global__ __launch_bounds__(256) void k_chain_f64_gather(DevNet net, const uint64_t *__restrict__ codes,
@@ -1679,6 +1820,22 @@ __global__ void k_rows_unpad(DevNet net, long long n, const RowT *__restrict__ r
 
 size_t fused_lds_bytes(const DevNet &net) { return sizeof(double) * 16 * (size_t)net.R; }
 
+// Rows the staged chain holds in LDS: the widest hidden layer padded to
+// whole K-steps, or 0 when that exceeds kResMax.
+static int res_rows(const DevNet &net) {
+    int w = 0;
+    for (int l = 1; l < net.n_layers - 1; ++l) w = max(w, net.width[l]);
+    w = (w + 3) & ~3;
+    return w <= kResMax ? w : 0;
+}
+
+size_t chain_res_lds_bytes(const DevNet &net) { return (size_t)res_rows(net) * 16 * sizeof(double); }
+
+hipError_t prepare_chain_res(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_chain_f64_res<kKChunk>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
 hipError_t prepare_fused(size_t bytes) {
     return hipFuncSetAttribute((const void *)k_march_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)bytes);
@@ -1699,8 +1856,9 @@ static CellRange range_of(long long lo, long long hi, const int *list, const uns
 // Positions [0, hi - lo) of cells lo..hi-1, or (list != NULL) the first
 // *count entries of list, launched for up to hi - lo positions.
 // g: tile variant: 1, 2 or 4 column groups per workgroup (4 g cells); 3: four
-// cells with the previous layer's rows in LDS; 5: four cells with the K loop
-// over the units active in any of them.
+// cells with the previous layer's rows in LDS (kept there for layers of at
+// most 128 units, staged from global memory per layer for wider ones up to
+// 512); 5: four cells with the K loop over the units active in any of them.
 void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
                   const int *list, const unsigned long long *count, double *rows, int g, hipStream_t st) {
     if (hi <= lo) return;
@@ -1709,6 +1867,9 @@ void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shap
     if (g == 5)
         hipLaunchKernelGGL((k_chain_f64_gather<kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net,
                            codes, cell_shape, rg, rows);
+    else if (g == 3 && res_rows(net) > kLdsRows)
+        hipLaunchKernelGGL((k_chain_f64_res<kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256),
+                           chain_res_lds_bytes(net), st, net, codes, cell_shape, rg, rows);
     else if (g == 3)
         hipLaunchKernelGGL((k_chain_f64_lds<kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net, codes,
                            cell_shape, rg, rows);
@@ -1832,7 +1993,10 @@ void launch_step_end(Counters *ctr, hipStream_t st) { hipLaunchKernelGGL(k_step_
 void launch_chain_dev(const DevNet &net, const uint64_t *codes, const int *cell_shape, Counters *ctr, long long chunk,
                       double *rows, int g, hipStream_t st) {
     const CellRange rg = range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo);
-    if (g == 3)
+    if (g == 3 && res_rows(net) > kLdsRows)
+        hipLaunchKernelGGL((k_chain_f64_res<kKChunk>), dim3((unsigned)((chunk + 3) / 4)), dim3(256),
+                           chain_res_lds_bytes(net), st, net, codes, cell_shape, rg, rows);
+    else if (g == 3)
         hipLaunchKernelGGL((k_chain_f64_lds<kKChunk>), dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, net,
                            codes, cell_shape, rg, rows);
     else if (g >= 4)
