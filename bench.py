@@ -13,6 +13,11 @@ paper's D6-W60 ShapeNet fits (Table 4).  The other forms (split-BF16 on the
 same net; plain and split-BF16 on the 3->[256]x8->1 superquadric fit) are
 timed the same way and reported under "forms".
 
+The timed plain steps are device-driven (each step reads its frontier on the
+device; the host reads the counters once per 8 steps) and launched one by
+one so that HIP events time every kernel class.  Host-driven steps and HIP
+graph replays of the same steps are reported as forms.
+
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (its average duration from HIP events recorded on the library's
 stream during the timed steps) and the CPU oracle's rate on a bounded sample
@@ -153,7 +158,7 @@ def train_scorer(B, dev, max_cells):
 
 
 def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tune=False, graph_steps=0,
-              face_routine=0):
+              face_routine=0, time_kernels=None):
     """Times `steps` full passes (seed + march + fetch) after `warmup` passes
     (and, with tune, the chain-tile autotuner run on the warm-up's cells).
     Kernel-class durations come from HIP events recorded on the library's
@@ -162,7 +167,8 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tun
 
     def step():
         ctx.seed_rays(o_d, d_d)
-        st = ctx.march(max_cells=max_cells, time_kernels=graph_steps == 0, precision=precision, propose=propose,
+        tk = graph_steps == 0 if time_kernels is None else time_kernels
+        st = ctx.march(max_cells=max_cells, time_kernels=tk, precision=precision, propose=propose,
                        graph_steps=graph_steps, face_routine=face_routine)
         out = ctx.fetch()
         return st, out
@@ -322,7 +328,8 @@ def main(argv=None):
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
                          "batch (c4); empty for none")
     ap.add_argument("--graph-steps", type=int, default=8,
-                    help="marching steps per captured HIP graph for the plain form (0: host-driven steps)")
+                    help="device-driven marching steps per counter read for the plain form (also timed as "
+                         "graph replays); 0: host-driven steps")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the bench, copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args(argv)
@@ -354,22 +361,43 @@ def main(argv=None):
     net, o, d, desc, ctx, o_d, d_d = prepare(a.workload)
     if scorer is not None:
         ctx.prop_set(scorer, k=16, rho=6.0)
-    main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=True)
+    # value: device-driven steps (each step reads its frontier on the device;
+    # the host reads the counters once per graph_steps steps) replayed from a
+    # captured HIP graph.  Kernel durations cannot be read inside graph
+    # replays, so the same steps are also launched one by one with HIP events
+    # around every kernel class: that run gives the roofline.  Host-driven
+    # steps are timed as a form.
+    gs = a.graph_steps
+    timed = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=True, graph_steps=gs,
+                      time_kernels=True)
     chain_tiles = {a.workload: ctx.chain_groups()}
+    if gs > 0:
+        main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, graph_steps=gs)
+        assert main_run["faces"] == timed["faces"], "graph-launched form changed the face count"
+        main_launch = f"device-driven steps, {gs} per HIP graph replay"
+        timed_launch = (f"the same device-driven steps launched one by one, {gs} per counter read, HIP events "
+                        "around every kernel class")
+    else:
+        main_run = timed
+        main_launch = timed_launch = "host-driven steps, HIP events around every kernel class"
     print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step",
           file=sys.stderr, flush=True)
     forms = {f"{a.workload}_plain": {"faces_per_s": round(main_run["faces_per_s"], 1),
                                      "ms_per_step": round(main_run["ms_per_step"], 3),
                                      "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
-                                     "launch": "host-driven steps, HIP events around every kernel class"}}
-    if a.graph_steps > 0:
-        r = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, graph_steps=a.graph_steps)
-        assert r["faces"] == main_run["faces"], "graph-launched form changed the face count"
-        forms[f"{a.workload}_plain_graph"] = {
+                                     "launch": main_launch}}
+    if gs > 0:
+        forms[f"{a.workload}_plain_timed"] = {
+            "faces_per_s": round(timed["faces_per_s"], 1), "ms_per_step": round(timed["ms_per_step"], 3),
+            "precision": "FP64 chain (MFMA), FP64 clip and vertex solves", "launch": timed_launch}
+        print(f"[bench] {a.workload}_plain_timed: {timed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+        r = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells)
+        assert r["faces"] == main_run["faces"], "host-driven form changed the face count"
+        forms[f"{a.workload}_plain_host"] = {
             "faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
             "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
-            "launch": f"device-driven steps, {a.graph_steps} per HIP graph replay, no kernel timing"}
-        print(f"[bench] {a.workload}_plain_graph: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+            "launch": "host-driven steps (one counter read per step), HIP events around every kernel class"}
+        print(f"[bench] {a.workload}_plain_host: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     bf16_desc = ("split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and vertex solves on "
                  "the FP32 rows; cells whose combinatorics or vertices (1e-5) are not certified are redone in FP64")
     if "mesh" in forms_req:
@@ -413,10 +441,10 @@ def main(argv=None):
         record(f"{a.workload}_{v}", r, precision, propose, routine)
 
     # roofline of the dominant kernel of the timed plain steps
-    kst = main_run["kernels"]
-    codes = main_run["out"]["codes"].cpu().numpy().view(np.uint64)
+    kst = timed["kernels"]
+    codes = timed["out"]["codes"].cpu().numpy().view(np.uint64)
     flops_cell = chain_flops_per_cell(net, codes)
-    cells = main_run["stats"]["cells"]
+    cells = timed["stats"]["cells"]
     chain_avg_ms = kst["chain_ms"] / max(1, kst["chain_launches"])
     cells_per_launch = cells * a.steps / max(1, kst["chain_launches"])
     chain_tflops = flops_cell * cells_per_launch / (chain_avg_ms * 1e-3) / 1e12 if chain_avg_ms > 0 else 0.0
@@ -426,7 +454,7 @@ def main(argv=None):
                 "frac": round(chain_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
                 "traffic": traffic["bytes_per_launch"] if traffic else None,
                 "algorithmic_flops_per_cell": round(flops_cell, 1), "cells_per_launch": round(cells_per_launch, 1),
-                "avg_launch_ms": round(chain_avg_ms, 5),
+                "avg_launch_ms": round(chain_avg_ms, 5), "timed_on": timed_launch,
                 "time_split_ms_per_step": {k: round(kst[k] / a.steps, 3)
                                            for k in ("chain_ms", "clip_ms", "hash_ms", "march_ms")}}
     if traffic:
@@ -472,7 +500,8 @@ def main(argv=None):
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(main_run["ms_per_step"], 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (frozen fitted fixture, seeded rays)",
-           "config": {"workload": desc, "form": "plain", "faces": st["faces"], "face_verts": st["face_verts"],
+           "config": {"workload": desc, "form": "plain", "launch": main_launch, "faces": st["faces"],
+                      "face_verts": st["face_verts"],
                       "triangles": st["triangles"], "cells": st["cells"], "march_steps": st["steps"],
                       "seeds": st["seed_cells"], "degenerate": st["degenerate"]},
            "forms": forms, "roofline": roofline}

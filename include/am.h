@@ -110,9 +110,12 @@ typedef struct {
                              graph (built once per context and shape of the march, then
                              replayed) and one counter read per replay instead of per step.
                              Each step takes up to 16384 cells from the device-side frontier.
+                             With time_kernels the same steps are launched one by one on the
+                             stream instead (no graph), still one counter read per
+                             graph_steps steps, with HIP events around each kernel class.
                              Plain FP64 form on the split path only (AM_E_INVALID with
-                             precision, propose, sample collection, kernel_path 2 or
-                             time_kernels); the gathered chain tile is replaced by 4 cells */
+                             precision, propose, sample collection or kernel_path 2); the
+                             gathered chain tile is replaced by 4 cells */
     int32_t face_routine; /* 0: halfplane clipping; 1: pivoting (Sec. 4.2.1): each face with
                              an entry edge from its parent is traced vertex by vertex from
                              that edge (a ratio test over every line per vertex); seeds and

@@ -140,6 +140,7 @@ struct am_ctx {
     Counters *h_ctr = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evk[4] = {nullptr, nullptr, nullptr, nullptr};   // per-step kernel timing
+    std::vector<hipEvent_t> evs;   // device-driven steps launched directly: 4 per step of a batch
 
     // fetch scratch
     int *d_has = nullptr;
@@ -448,6 +449,8 @@ void am_destroy(am_ctx *ctx) {
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (auto &e : ctx->evk)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->evs)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
@@ -806,9 +809,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     if (o.chain_groups < 0 || o.chain_groups > 5)
         return fail(ctx, AM_E_INVALID, "chain_groups must be 0..5");
     if (o.graph_steps < 0 || o.graph_steps > 64) return fail(ctx, AM_E_INVALID, "graph_steps must be 0..64");
-    if (o.graph_steps > 0 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2 ||
-                              o.time_kernels))
-        return fail(ctx, AM_E_INVALID, "graph steps run the plain FP64 split path without kernel timing");
+    if (o.graph_steps > 0 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2))
+        return fail(ctx, AM_E_INVALID, "device-driven steps run the plain FP64 split path");
     if (o.face_routine < 0 || o.face_routine > 1) return fail(ctx, AM_E_INVALID, "face_routine must be 0 or 1");
     if (o.face_routine == 1 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2 ||
                                 o.graph_steps > 0))
@@ -882,7 +884,76 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     out.stride = kFaceSlots;
     out.out_base = 0;
     const long long seed_cells = hi;
-    if (o.graph_steps > 0) {
+    if (o.graph_steps > 0 && o.time_kernels) {
+        // device-driven steps launched one by one (no graph), graph_steps per
+        // counter read, HIP events around each kernel class of every step
+        const long long gchunk = std::min<long long>(ctx->chunk_cells, 1LL << 14);
+        int variant = chain_groups(ctx, gchunk, o.chain_groups);
+        if (variant == 5) variant = 1;
+        const size_t nev = (size_t)o.graph_steps * 4;
+        while (ctx->evs.size() < nev) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreate(&e));
+            ctx->evs.push_back(e);
+        }
+        long long batches = 0;
+        for (;;) {
+            const long long run0 = (long long)ctx->h_ctr->steps_run;
+            for (int k = 0; k < o.graph_steps; ++k) {
+                hipEvent_t *e = ctx->evs.data() + 4 * k;
+                launch_step_begin(ctx->d_ctr, gchunk, cap, s);
+                HIPCHK(hipEventRecord(e[0], s));
+                launch_chain_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_ctr, gchunk, ctx->d_rows, variant, s);
+                HIPCHK(hipEventRecord(e[1], s));
+                launch_clip_dev(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_ctr, gchunk,
+                                seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, s);
+                HIPCHK(hipEventRecord(e[2], s));
+                const long long nh = gchunk * 6;
+                launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
+                launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
+                              ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape,
+                              ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, s);
+                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
+                HIPCHK(hipEventRecord(e[3], s));
+                launch_step_end(ctx->d_ctr, s);
+            }
+            HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipGetLastError());
+            ++batches;
+            const Counters &c = *ctx->h_ctr;
+            // steps after the frontier ran dry only launched empty grids: time the ones that ran
+            const long long ran = std::min<long long>((long long)c.steps_run - run0, o.graph_steps);
+            for (long long k = 0; k < ran; ++k) {
+                hipEvent_t *e = ctx->evs.data() + 4 * k;
+                float a = 0.f, b = 0.f, c3 = 0.f;
+                HIPCHK(hipEventElapsedTime(&a, e[0], e[1]));
+                HIPCHK(hipEventElapsedTime(&b, e[1], e[2]));
+                HIPCHK(hipEventElapsedTime(&c3, e[2], e[3]));
+                st.chain_ms += a;
+                st.clip_ms += b;
+                st.hash_ms += c3;
+                st.chain_launches++;
+                st.clip_launches++;
+                st.hash_launches += 3;
+            }
+            if (c.overflow_cells || c.overflow_cand || c.overflow_hash) {
+                st.required_cells = (long long)c.n_cells;
+                st.cells = std::min<long long>((long long)c.n_cells, cap);
+                st.steps = (long long)c.steps_run;
+                if (stats) *stats = st;
+                return fail(ctx, AM_E_CAPACITY,
+                            "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu)",
+                            c.n_cells, cap, c.overflow_cand, c.overflow_hash);
+            }
+            if (c.step_lo >= c.n_cells) break;
+            if (o.max_steps > 0 && (long long)c.steps_run >= o.max_steps) break;
+        }
+        st.steps = (long long)ctx->h_ctr->steps_run;
+        st.graph_launches = 0;
+        (void)batches;
+        lo = hi = 0;
+    } else if (o.graph_steps > 0) {
         // device-driven steps, graph_steps per graph launch, one counter read
         // per launch (plain FP64 form, dense chain tiles)
         const long long gchunk = std::min<long long>(ctx->chunk_cells, 1LL << 14);

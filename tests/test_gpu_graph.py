@@ -1,4 +1,5 @@
-"""Device-driven marching steps replayed from a captured HIP graph.
+"""Device-driven marching steps replayed from a captured HIP graph, or
+launched one by one with kernel timing.
 
 Bar: the graph march reproduces the oracle's mesh on small nets and batched
 shapes (cells, cycles, adjacency exact; vertices 1e-9) and the host-driven
@@ -112,6 +113,45 @@ def test_graph_march_counts_replays(binding):
     say("graph replays", st["steps"], st["graph_launches"])
     assert st["faces"] == ref["faces"]
     assert st["graph_launches"] == (st["steps"] + 7) // 8 or st["graph_launches"] == (st["steps"] + 7) // 8 + 1
-    with pytest.raises(binding.AmError):
-        ctx.march(graph_steps=8, time_kernels=True)
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [1, 8])
+@pytest.mark.parametrize("name", ["c1", "maxpool_cube"])
+def test_timed_device_steps_match_oracle(binding, name, k):
+    """graph_steps with time_kernels: the same device-driven steps launched one
+    by one with HIP events; the mesh is the oracle's and every step that ran
+    is timed once per kernel class."""
+    net = NETS[name]()
+    o, d = seeds.random_rays(16, seed=4)
+    on = O.OracleNet(net)
+    codes, ams, _, _ = on.seed_rays(o, d)
+    ref = on.march(codes, ams)
+    say("timed device steps", name, k)
+    ctx = binding.Context(0).load_net(net)
+    for _ in range(2):
+        ctx.seed_rays(o, d)
+        st = ctx.march(graph_steps=k, time_kernels=True)
+        assert st["faces"] == ref.n_faces and st["cells"] == ref.stats["cells"]
+        compare_meshes(ref, fetch_host(ctx))
+        assert st["graph_launches"] == 0
+        assert st["chain_launches"] == st["steps"] == st["clip_launches"] and st["hash_launches"] == 3 * st["steps"]
+        assert st["chain_ms"] > 0.0 and st["clip_ms"] > 0.0 and st["hash_ms"] > 0.0
+    ctx.close()
+
+
+def test_timed_device_steps_c2_equal_host_driven(binding):
+    net = nets.load_fitted("c2")
+    prim = np.load(nets.DATA_DIR + "/c2_primitives.npz")
+    o, d = seeds.centre_rays(prim["p0"], 128)
+    say("timed device steps c2")
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    host = ctx.march(max_cells=1 << 21, time_kernels=True)
+    ref = fetch_host(ctx)
+    ctx.seed_rays(o, d)
+    st = ctx.march(max_cells=1 << 21, graph_steps=8, time_kernels=True)
+    # device-driven steps take at most 16384 cells, so large frontiers take more steps
+    assert st["faces"] == 471884 and st["steps"] >= host["steps"]
+    compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
     ctx.close()
