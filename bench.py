@@ -157,6 +157,18 @@ def train_scorer(B, dev, max_cells):
                     "steps": 150, "scorer": "8 features (padded 32) -> 128 -> 128 -> 1, FP16 weights on MFMA"}
 
 
+def chain_kernel_name(net, groups, graph_steps):
+    """The chain kernel the timed steps launch: device-driven steps take the
+    variant of the 2^14-cell bucket (the gathered tile becomes the 4-cell
+    one); host-driven steps mix buckets."""
+    if graph_steps <= 0:
+        return "k_chain_f64 (tile variants by launch size)"
+    v = groups[2]
+    wide = max(net.widths[1:-1]) > 128
+    return {1: "k_chain_f64<1, 8>", 2: "k_chain_f64<2, 4>", 3: "k_chain_f64_res<8>" if wide else "k_chain_f64_lds<8>",
+            4: "k_chain_f64<4, 4>", 5: "k_chain_f64<1, 8>"}[v]
+
+
 def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tune=False, graph_steps=0,
               face_routine=0, time_kernels=None):
     """Times `steps` full passes (seed + march + fetch) after `warmup` passes
@@ -330,6 +342,11 @@ def main(argv=None):
     ap.add_argument("--graph-steps", type=int, default=8,
                     help="device-driven marching steps per counter read for the plain form (also timed as "
                          "graph replays); 0: host-driven steps")
+    ap.add_argument("--chain-groups", default="",
+                    help="fixed chain tile variants per launch-size bucket, e.g. 1,3,3,3 (default: autotune)")
+    ap.add_argument("--legs", default="timed,graph,host",
+                    help="legs of the plain form: timed (device-driven, HIP events; gives the roofline), graph "
+                         "(the same steps as graph replays; gives value), host (host-driven steps)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the bench, copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args(argv)
@@ -368,10 +385,14 @@ def main(argv=None):
     # around every kernel class: that run gives the roofline.  Host-driven
     # steps are timed as a form.
     gs = a.graph_steps
-    timed = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=True, graph_steps=gs,
-                      time_kernels=True)
+    legs = set(x for x in a.legs.split(",") if x)
+    fixed_groups = [int(x) for x in a.chain_groups.split(",")] if a.chain_groups else None
+    if fixed_groups:
+        ctx.set_chain_groups(fixed_groups)
+    timed = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=fixed_groups is None,
+                      graph_steps=gs, time_kernels=True)
     chain_tiles = {a.workload: ctx.chain_groups()}
-    if gs > 0:
+    if gs > 0 and "graph" in legs:
         main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, graph_steps=gs)
         assert main_run["faces"] == timed["faces"], "graph-launched form changed the face count"
         main_launch = f"device-driven steps, {gs} per HIP graph replay"
@@ -386,11 +407,12 @@ def main(argv=None):
                                      "ms_per_step": round(main_run["ms_per_step"], 3),
                                      "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
                                      "launch": main_launch}}
-    if gs > 0:
+    if gs > 0 and "graph" in legs:
         forms[f"{a.workload}_plain_timed"] = {
             "faces_per_s": round(timed["faces_per_s"], 1), "ms_per_step": round(timed["ms_per_step"], 3),
             "precision": "FP64 chain (MFMA), FP64 clip and vertex solves", "launch": timed_launch}
         print(f"[bench] {a.workload}_plain_timed: {timed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    if gs > 0 and "host" in legs:
         r = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells)
         assert r["faces"] == main_run["faces"], "host-driven form changed the face count"
         forms[f"{a.workload}_plain_host"] = {
@@ -449,7 +471,8 @@ def main(argv=None):
     cells_per_launch = cells * a.steps / max(1, kst["chain_launches"])
     chain_tflops = flops_cell * cells_per_launch / (chain_avg_ms * 1e-3) / 1e12 if chain_avg_ms > 0 else 0.0
     traffic = measured_traffic()
-    roofline = {"kernel": "k_chain_f64", "bound": "mfma", "achieved": round(chain_tflops, 4),
+    roofline = {"kernel": chain_kernel_name(net, chain_tiles[a.workload], gs), "bound": "mfma",
+                "achieved": round(chain_tflops, 4),
                 "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(chain_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
                 "traffic": traffic["bytes_per_launch"] if traffic else None,
