@@ -91,14 +91,17 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of k_chain_f64 from the committed counter runs, or
-    None when the kernel sources changed since they were taken."""
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the chain kernel from the committed counter runs
+    (profile_summary.py traffic), or None when they were taken on another
+    kernel or the kernel sources changed since."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    if t.get("kernel", "").replace("am::", "") != kernel:
         return None
     return t
 
@@ -470,8 +473,9 @@ def main(argv=None):
     chain_avg_ms = kst["chain_ms"] / max(1, kst["chain_launches"])
     cells_per_launch = cells * a.steps / max(1, kst["chain_launches"])
     chain_tflops = flops_cell * cells_per_launch / (chain_avg_ms * 1e-3) / 1e12 if chain_avg_ms > 0 else 0.0
-    traffic = measured_traffic()
-    roofline = {"kernel": chain_kernel_name(net, chain_tiles[a.workload], gs), "bound": "mfma",
+    kname = chain_kernel_name(net, chain_tiles[a.workload], gs)
+    traffic = measured_traffic(kname)
+    roofline = {"kernel": kname, "bound": "mfma",
                 "achieved": round(chain_tflops, 4),
                 "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(chain_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
