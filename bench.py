@@ -395,15 +395,18 @@ def main(argv=None):
     timed = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=fixed_groups is None,
                       graph_steps=gs, time_kernels=True)
     chain_tiles = {a.workload: ctx.chain_groups()}
+    if gs > 0:
+        timed_launch = (f"device-driven steps launched one by one, {gs} per counter read, HIP events around "
+                        "every kernel class")
+    else:
+        timed_launch = "host-driven steps, HIP events around every kernel class"
     if gs > 0 and "graph" in legs:
         main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, graph_steps=gs)
         assert main_run["faces"] == timed["faces"], "graph-launched form changed the face count"
         main_launch = f"device-driven steps, {gs} per HIP graph replay"
-        timed_launch = (f"the same device-driven steps launched one by one, {gs} per counter read, HIP events "
-                        "around every kernel class")
     else:
         main_run = timed
-        main_launch = timed_launch = "host-driven steps, HIP events around every kernel class"
+        main_launch = timed_launch
     print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step",
           file=sys.stderr, flush=True)
     forms = {f"{a.workload}_plain": {"faces_per_s": round(main_run["faces_per_s"], 1),

@@ -5,6 +5,10 @@
         Markdown table of a --kernel-trace --stats run (calls, total and
         average duration per kernel).
 
+    python profile_summary.py counters <fetch.csv> <write.csv> --calib-mib M
+        Markdown table of HBM bytes per launch for every kernel of two --pmc
+        runs (FETCH_SIZE, then WRITE_SIZE), scaled as below.
+
     python profile_summary.py traffic <fetch.csv> <write.csv> --kernel NAME
             --workload TEXT --calib-mib M --algorithmic-bytes B --out FILE
         HBM bytes per launch of one kernel from two --pmc runs (FETCH_SIZE,
@@ -62,6 +66,27 @@ def calib_scale(per, mib: int) -> float:
     return mib * 1024.0 / avg
 
 
+def counters_table(fetch: str, write: str, mib: int, top: int) -> str:
+    f = load_counter(fetch)
+    w = load_counter(write)
+    fs, ws = calib_scale(f, mib), calib_scale(w, mib)
+    rows = []
+    for k, fv in f.items():
+        if k == "__amd_rocclr_copyBuffer":
+            continue
+        wv = [v for v, _ in w.get(k, [])]
+        fk = sum(v for v, _ in fv) / len(fv)
+        wk = sum(wv) / len(wv) if wv else 0.0
+        rows.append((k, len(fv), fk, wk, (fk * fs + wk * ws) * 1024.0 / 1e6))
+    rows.sort(key=lambda r: -r[4] * r[1])
+    out = [f"FETCH_SIZE scale {fs:.3f}, WRITE_SIZE scale {ws:.3f} (from the {mib} MiB copies)", "",
+           "| kernel | launches | FETCH_SIZE KiB/launch (raw) | WRITE_SIZE KiB/launch | HBM MB/launch (scaled) |",
+           "|---|---:|---:|---:|---:|"]
+    for k, n, fk, wk, mb in rows[:top]:
+        out.append(f"| `{k}` | {n} | {fk:.1f} | {wk:.1f} | {mb:.1f} |")
+    return "\n".join(out)
+
+
 def traffic(a) -> dict:
     f = load_counter(a.fetch)
     w = load_counter(a.write)
@@ -92,6 +117,11 @@ def main(argv=None) -> int:
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=20)
+    c = sub.add_parser("counters")
+    c.add_argument("fetch")
+    c.add_argument("write")
+    c.add_argument("--calib-mib", type=int, required=True)
+    c.add_argument("--top", type=int, default=16)
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
@@ -103,6 +133,9 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats(a.csv, a.top))
+        return 0
+    if a.cmd == "counters":
+        print(counters_table(a.fetch, a.write, a.calib_mib, a.top))
         return 0
     res = traffic(a)
     with open(a.out, "w") as fh:
