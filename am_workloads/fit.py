@@ -1,9 +1,10 @@
 """Fit ReLU MLP fixtures to analytic signed distance targets (input generation).
 
 The fitted nets stand in for the paper's per-shape SDF fits (the ShapeNet fits
-behind Tables 1-4 are not available).  Fitting is plain PyTorch on the CPU and
-has nothing to do with the meshing method; the resulting weights are frozen
-files under ``am_workloads/data`` whose SHA-256 is recorded in ``FIXTURES.sha256``.
+behind Tables 1-4 are not available).  Fitting is plain PyTorch (on the CPU by
+default, or on a GPU with --device; the wider fits were made that way) and has
+nothing to do with the meshing method; the resulting weights are frozen files
+under ``am_workloads/data`` whose SHA-256 is recorded in ``FIXTURES.sha256``.
 
     python -m am_workloads.fit c2        # 3->[90]x6->1, 8 spheres, seed 1
     python -m am_workloads.fit c3 --device cuda --out /tmp/fits   # 3->[256]x8->1, superquadrics
