@@ -896,7 +896,6 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             HIPCHK(hipEventCreate(&e));
             ctx->evs.push_back(e);
         }
-        long long batches = 0;
         for (;;) {
             const long long run0 = (long long)ctx->h_ctr->steps_run;
             for (int k = 0; k < o.graph_steps; ++k) {
@@ -920,7 +919,6 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             HIPCHK(hipGetLastError());
-            ++batches;
             const Counters &c = *ctx->h_ctr;
             // steps after the frontier ran dry only launched empty grids: time the ones that ran
             const long long ran = std::min<long long>((long long)c.steps_run - run0, o.graph_steps);
@@ -950,8 +948,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             if (o.max_steps > 0 && (long long)c.steps_run >= o.max_steps) break;
         }
         st.steps = (long long)ctx->h_ctr->steps_run;
+        st.max_frontier = (long long)ctx->h_ctr->max_frontier;
         st.graph_launches = 0;
-        (void)batches;
         lo = hi = 0;
     } else if (o.graph_steps > 0) {
         // device-driven steps, graph_steps per graph launch, one counter read
@@ -1017,6 +1015,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             if (o.max_steps > 0 && (long long)c.steps_run >= o.max_steps) break;
         }
         st.steps = (long long)ctx->h_ctr->steps_run;
+        st.max_frontier = (long long)ctx->h_ctr->max_frontier;
         st.graph_launches = launches;
         lo = hi = 0;
     }

@@ -147,7 +147,7 @@ struct Counters {
     unsigned long long steps_run;
     unsigned long long pivot_cells;      // pivoting form: faces traced by the walk
     unsigned long long pivot_fallback;   // ... and cells clipped instead
-    unsigned long long pad;
+    unsigned long long max_frontier;     // device-driven steps: largest frontier seen
 };
 
 // ---------------------------------------------------------------- helpers

@@ -1970,6 +1970,7 @@ __global__ void k_step_begin(Counters *c, unsigned long long chunk, unsigned lon
     const bool bad = c->overflow_cells || c->overflow_cand || c->overflow_hash;
     const unsigned long long lo = c->step_lo;
     unsigned long long n = (!bad && cells > lo) ? cells - lo : 0ull;
+    if (n > c->max_frontier) c->max_frontier = n;
     if (n > chunk) n = chunk;
     c->step_n = n;
     c->n_cand = 0ull;

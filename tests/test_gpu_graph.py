@@ -153,5 +153,6 @@ def test_timed_device_steps_c2_equal_host_driven(binding):
     st = ctx.march(max_cells=1 << 21, graph_steps=8, time_kernels=True)
     # device-driven steps take at most 16384 cells, so large frontiers take more steps
     assert st["faces"] == 471884 and st["steps"] >= host["steps"]
+    assert 0 < st["max_frontier"] and 0 < host["max_frontier"]
     compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
     ctx.close()
