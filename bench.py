@@ -446,7 +446,7 @@ def main(argv=None):
             st = r["stats"]
             e["precision"] = "FP64 chain (MFMA), FP64 pivoting walk"
             e["face_routine"] = ("pivoting (Sec. 4.2.1): each face traced from its entry edge, one ratio test "
-                                 "over every line per vertex; seeds clipped")
+                                 "over every line per vertex; seeds and cells without a usable entry edge clipped")
             e["walked_cells"] = st["pivot_cells"]
             e["clipped_cells"] = st["pivot_fallback"]
             e["clip_ms_per_step"] = round(r["kernels"]["clip_ms"] / r["steps"], 3)

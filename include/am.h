@@ -118,9 +118,9 @@ typedef struct {
                              gathered chain tile is replaced by 4 cells */
     int32_t face_routine; /* 0: halfplane clipping; 1: pivoting (Sec. 4.2.1): each face with
                              an entry edge from its parent is traced vertex by vertex from
-                             that edge (a ratio test over every line per vertex); seeds and
-                             cells entered across a box or comparison edge are clipped.  The
-                             faces are the same.  Plain FP64 form on the split path only
+                             that edge (a ratio test over every line per vertex); seeds,
+                             cells whose entry edge ends on a box plane or is degenerate, and
+                             walks that do not close are clipped.  The faces are the same.  Plain FP64 form on the split path only
                              (AM_E_INVALID with precision, propose, sample collection,
                              kernel_path 2 or graph_steps) */
     int32_t reserved;

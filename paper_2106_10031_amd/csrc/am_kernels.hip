@@ -1318,8 +1318,9 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         P.m = 4;
         bool walked = false;
         if constexpr (Pivot) {
-            // pivoting form: trace the face from the entry edge; cells
-            // without one (seeds, box or comparison entries) are clipped
+            // pivoting form: trace the face from the entry edge; seeds,
+            // entry edges ending on a box plane or degenerate, and walks
+            // that do not close are clipped
             EntryEdge E0;
             if (entry_edge(net, hints, cell, code, am, rb, rs, u, v, p0, E0)) {
                 const double aFd[4] = {fx, fy, fz, fw};
