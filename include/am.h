@@ -136,7 +136,7 @@ typedef struct {
     int64_t triangles;        /* sum of (m - 2): fan triangulation count */
     int64_t cells;            /* distinct cells discovered (incl. empty) */
     int64_t steps;            /* marching steps (frontier generations) */
-    int64_t max_frontier;     /* largest frontier */
+    int64_t max_frontier;     /* largest frontier (cells discovered, not yet processed) */
     int64_t seeds_in;         /* seed cells before deduplication */
     int64_t seed_cells;       /* distinct seed cells */
     int64_t seed_empty;       /* seed cells whose face is empty */
@@ -161,7 +161,8 @@ typedef struct {
     int64_t prop_cuts;        /* lines that cut in their every-line passes */
     int64_t graph_launches;   /* graph_steps > 0: graph replays */
     int64_t pivot_cells;      /* face_routine 1: faces traced by pivoting */
-    int64_t pivot_fallback;   /* face_routine 1: cells clipped instead (no usable entry edge) */
+    int64_t pivot_fallback;   /* face_routine 1: cells clipped instead (seeds, no usable entry
+                                 edge, or a walk that did not close) */
 } am_march_stats;
 
 /* Creates a context on `device` that enqueues its work on `hip_stream`
@@ -177,7 +178,7 @@ const char *am_last_error(const am_ctx *ctx);
 
 /* Loads a network (Sec. 2.2, 5.1, 5.2); see am_net_desc.  Rejects widths
  * < 1, width[0] != 3, non-feed-forward or duplicate blocks, layers with no
- * input block, N > 4096 and NaN/Inf parameters with AM_E_INVALID.  Resets
+ * input block, N > 8192 and NaN/Inf parameters with AM_E_INVALID.  Resets
  * any seeds and results. */
 am_status am_load_net(am_ctx *ctx, const am_net_desc *net);
 
