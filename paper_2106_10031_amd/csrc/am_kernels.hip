@@ -589,12 +589,15 @@ __device__ void chain_tile_bf16(const DevNet &net, const uint64_t *__restrict__ 
     }
 }
 
+// Hidden lines the precision check can list per cell (more: the cell is redone in FP64).
+constexpr int kNearMax = 256;
+
 struct PolyScratch {
     double a[kMaxPoly];
     double b[kMaxPoly];
     double r[kMaxPoly];
     int e[kMaxPoly];
-    int near[kWave];   // hidden lines the precision check must revisit
+    int near[kNearMax];   // hidden lines the precision check must revisit
 };
 
 struct Poly {
@@ -1393,7 +1396,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
                 // are the only hidden lines the precision check revisits
                 const uint64_t nm = ballot(valid && close);
                 const int at = n_near + __popcll(nm & ((1ull << lane) - 1ull));
-                if (valid && close && at < kWave) S.near[at] = g;
+                if (valid && close && at < kNearMax) S.near[at] = g;
                 n_near += __popcll(nm);
             }
             uint64_t mask = ballot(valid && cuts);
@@ -1518,7 +1521,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
             est = kSplitRowEps * vsens_a * (vsens_b * xm + vsens_r) / fmax(1.0, xm);
             shaky = !(est <= vertex_tol);
         }
-        const bool redo = m == 0 || flags != 0 || n_near > kWave || ballot(shaky) != 0 ||
+        const bool redo = m == 0 || flags != 0 || n_near > kNearMax || ballot(shaky) != 0 ||
                           margin_ambiguous(net, code, am, rb, rs, m, e_out, x[0], x[1], x[2], est, margin, S.near,
                                            n_near);
         if (redo) {
