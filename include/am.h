@@ -276,6 +276,16 @@ am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, 
 am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                    uint64_t *codes, int32_t *argmax, int32_t *shape_id);
 
+/* As am_fetch (same buffers and layout), with the faces in canonical order:
+ * sorted by shape id, then by code words (unsigned, word 0 first), then by
+ * argmax; nbr holds indices in that order.  Every face's cycle starts at its
+ * smallest edge id either way, so the output is independent of discovery
+ * order and equals the CPU reference's mesh array for array.  A stable radix
+ * sort per key word; device scratch of about 48 bytes per face is kept by
+ * the context.  Enqueued. */
+am_status am_fetch_sorted(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
+                          uint64_t *codes, int32_t *argmax, int32_t *shape_id);
+
 /* ---- Welded mesh: the output Z = {V, {P}} of Sec. 3, a shared vertex
  * array plus polygons that index it.  A march emits each face with its own
  * copy of its vertices; across a shared edge (edge i of face f, edge j of

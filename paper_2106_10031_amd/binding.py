@@ -24,7 +24,7 @@ EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_b
            "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch",
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
            "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups",
-           "am_seed_points_st", "am_weld", "am_triangles"]
+           "am_seed_points_st", "am_weld", "am_triangles", "am_fetch_sorted"]
 
 
 class AmError(RuntimeError):
@@ -92,6 +92,7 @@ def lib(path: str = LIB_PATH):
     L.am_march.argtypes = [vp, C.POINTER(MarchOpts), C.POINTER(MarchStats)]
     L.am_get_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.am_fetch_sorted.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.am_prop_param_count.argtypes = []
     L.am_prop_set.argtypes = [vp, vp, i64, i32, C.c_float]
     L.am_prop_collect.argtypes = [vp, vp, vp, i64, C.c_float]
@@ -342,8 +343,9 @@ class Context:
         self._check(self.L.am_get_counts(self.h, C.byref(f), C.byref(v), C.byref(c)))
         return f.value, v.value, c.value
 
-    def fetch(self):
-        """The mesh as device tensors (faces in discovery order)."""
+    def fetch(self, sorted=False):
+        """The mesh as device tensors (faces in discovery order, or with
+        sorted=True in canonical order: shape, code words, argmax)."""
         t = self.torch
         F, V, _ = self.counts()
         dev = self.device
@@ -351,8 +353,9 @@ class Context:
                    verts=t.empty((V, 3), dtype=t.float64, device=dev), nbr=t.empty(V, dtype=t.int64, device=dev),
                    codes=t.empty((F, self.W), dtype=t.int64, device=dev), argmax=t.empty(F, dtype=t.int32, device=dev),
                    shape=t.empty(F, dtype=t.int32, device=dev))
-        self._check(self.L.am_fetch(self.h, _p(out["offsets"]), _p(out["ids"]), _p(out["verts"]), _p(out["nbr"]),
-                                    _p(out["codes"]), _p(out["argmax"]), _p(out["shape"])))
+        fn = self.L.am_fetch_sorted if sorted else self.L.am_fetch
+        self._check(fn(self.h, _p(out["offsets"]), _p(out["ids"]), _p(out["verts"]), _p(out["nbr"]),
+                       _p(out["codes"]), _p(out["argmax"]), _p(out["shape"])))
         return out
 
 

@@ -72,6 +72,12 @@ hipError_t launch_fetch(const DevNet &, long long, const int *, const int *, con
                         void *, size_t, long long, long long *, int *, double *, long long *, uint64_t *, int *,
                         int *, hipStream_t);
 hipError_t weld_tmp_bytes(long long, size_t *);
+hipError_t sorted_fetch_tmp_bytes(long long, size_t *);
+hipError_t launch_fetch_sorted(const DevNet &, long long, const int *, const int *, const double *, const int *,
+                               const uint64_t *, const int *, const int *, int, int *, int *, long long *,
+                               long long *, void *, size_t, long long, int *, int *, int *, int *, uint64_t *,
+                               uint64_t *, long long *, long long *, void *, size_t, long long *, int *, double *,
+                               long long *, uint64_t *, int *, int *, hipStream_t);
 hipError_t launch_weld(long long, long long, const long long *, const int *, const long long *, const int *,
                        const double *, int, long long, long long *, int *, int *, void *, size_t,
                        unsigned long long *, long long *, double *, hipStream_t);
@@ -179,6 +185,14 @@ struct am_ctx {
     size_t weld_tmp = 0;
     long long weld_n = 0;
     unsigned long long *d_weld_unpaired = nullptr;
+
+    // canonical-order fetch scratch (per face)
+    long long sf_cap = 0;
+    int *d_sf_cell = nullptr, *d_sf_pa = nullptr, *d_sf_pb = nullptr, *d_sf_rank = nullptr;
+    uint64_t *d_sf_ka = nullptr, *d_sf_kb = nullptr;
+    long long *d_sf_mc = nullptr, *d_sf_vo = nullptr;
+    char *d_sf_tmp = nullptr;
+    size_t sf_tmp = 0;
 
     // last result
     bool have_result = false;
@@ -443,6 +457,15 @@ void am_destroy(am_ctx *ctx) {
     dfree(ctx->d_weld_vid);
     dfree(ctx->d_weld_tmp);
     dfree(ctx->d_weld_unpaired);
+    dfree(ctx->d_sf_cell);
+    dfree(ctx->d_sf_pa);
+    dfree(ctx->d_sf_pb);
+    dfree(ctx->d_sf_rank);
+    dfree(ctx->d_sf_ka);
+    dfree(ctx->d_sf_kb);
+    dfree(ctx->d_sf_mc);
+    dfree(ctx->d_sf_vo);
+    dfree(ctx->d_sf_tmp);
     if (ctx->h_prop_loss) (void)hipHostFree(ctx->h_prop_loss);
     dfree(ctx->d_ctr);
     if (ctx->h_ctr) (void)hipHostFree(ctx->h_ctr);
@@ -1165,6 +1188,39 @@ am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, i
                         ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
                         ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
                         (long long *)nbr, codes, argmax, shape_id, ctx->stream));
+    return AM_OK;
+}
+
+am_status am_fetch_sorted(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
+                          uint64_t *codes, int32_t *argmax, int32_t *shape_id) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->have_result) return fail(ctx, AM_E_STATE, "no march result");
+    TRY(set_device(ctx));
+    TRY(ensure_scan(ctx, std::max<long long>(ctx->res_cells, 1)));
+    const long long F = ctx->res_faces;
+    if (F >= (1LL << 31)) return fail(ctx, AM_E_INVALID, "too many faces to sort");
+    if (F > ctx->sf_cap || !ctx->d_sf_cell) {
+        const long long n = std::max<long long>(F, 1);
+        TRY(dalloc(ctx, ctx->d_sf_cell, n));
+        TRY(dalloc(ctx, ctx->d_sf_pa, n));
+        TRY(dalloc(ctx, ctx->d_sf_pb, n));
+        TRY(dalloc(ctx, ctx->d_sf_rank, n));
+        TRY(dalloc(ctx, ctx->d_sf_ka, n));
+        TRY(dalloc(ctx, ctx->d_sf_kb, n));
+        TRY(dalloc(ctx, ctx->d_sf_mc, n));
+        TRY(dalloc(ctx, ctx->d_sf_vo, n));
+        size_t b = 0;
+        HIPCHK(sorted_fetch_tmp_bytes(n, &b));
+        TRY(dalloc(ctx, ctx->d_sf_tmp, b));
+        ctx->sf_tmp = b;
+        ctx->sf_cap = n;
+    }
+    HIPCHK(launch_fetch_sorted(ctx->dn, ctx->res_cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr,
+                               ctx->d_codes, ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx,
+                               ctx->d_mcount, ctx->d_voff, ctx->d_scan, ctx->scan_bytes, F, ctx->d_sf_cell,
+                               ctx->d_sf_pa, ctx->d_sf_pb, ctx->d_sf_rank, ctx->d_sf_ka, ctx->d_sf_kb, ctx->d_sf_mc,
+                               ctx->d_sf_vo, ctx->d_sf_tmp, ctx->sf_tmp, (long long *)offsets, ids, verts,
+                               (long long *)nbr, codes, argmax, shape_id, ctx->stream));
     return AM_OK;
 }
 

@@ -535,6 +535,81 @@ __global__ void k_fetch_tail(long long *o_off, long long F, const long long *vof
     if (threadIdx.x == 0 && blockIdx.x == 0 && o_off) o_off[F] = n > 0 ? voff[n - 1] + face_m[n - 1] : 0;
 }
 
+// ---- canonical face order: faces sorted by shape id, then code words
+// (unsigned, word 0 first), then argmax; neighbour indices follow the order.
+// Least-significant-key-first passes of a stable radix sort over a face
+// permutation.
+
+__global__ void k_face_cells(const int *face_m, const int *fidx, long long n, int *face_cell) {
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x)
+        if (face_m[c] > 0) face_cell[fidx[c]] = (int)c;
+}
+
+__global__ void k_iota_int(int *v, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        v[i] = (int)i;
+}
+
+// which >= 0: code word `which`; -1: argmax; -2: shape id.
+__global__ void k_sort_key(const int *perm, const int *face_cell, const uint64_t *codes, const int *argmax,
+                           const int *shape, int W, int which, long long F, uint64_t *keys) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < F;
+         p += (long long)gridDim.x * blockDim.x) {
+        const long long c = face_cell[perm[p]];
+        uint64_t k;
+        if (which >= 0) k = codes[c * W + which];
+        else if (which == -1) k = (uint64_t)(uint32_t)argmax[c];
+        else k = (uint64_t)(uint32_t)(shape ? shape[c] : 0);
+        keys[p] = k;
+    }
+}
+
+__global__ void k_sorted_counts(const int *perm, const int *face_cell, const int *face_m, long long F, int *rank,
+                                long long *mcount) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < F;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int f = perm[p];
+        rank[f] = (int)p;
+        mcount[p] = face_m[face_cell[f]];
+    }
+}
+
+__global__ void k_fetch_sorted(const DevNet net, long long F, const int *perm, const int *face_cell,
+                               const int *rank, const long long *voff, const int *face_m, const int *fidx,
+                               const int *ids, const double *verts, const int *nbr, const uint64_t *codes,
+                               const int *argmax, const int *shape, int stride, long long *o_off, int *o_ids,
+                               double *o_verts, long long *o_nbr, uint64_t *o_codes, int *o_am, int *o_shape) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < F;
+         p += (long long)gridDim.x * blockDim.x) {
+        const long long c = face_cell[perm[p]];
+        const int m = face_m[c];
+        const long long o = voff[p];
+        if (o_off) o_off[p] = o;
+        if (o_codes)
+            for (int w = 0; w < net.W; ++w) o_codes[p * net.W + w] = codes[c * net.W + w];
+        if (o_am) o_am[p] = argmax[c];
+        if (o_shape) o_shape[p] = shape[c];
+        for (int i = 0; i < m; ++i) {
+            const long long s = c * stride + i;
+            if (o_ids) o_ids[o + i] = ids[s];
+            if (o_verts) {
+                o_verts[(o + i) * 3 + 0] = verts[s * 3 + 0];
+                o_verts[(o + i) * 3 + 1] = verts[s * 3 + 1];
+                o_verts[(o + i) * 3 + 2] = verts[s * 3 + 2];
+            }
+            if (o_nbr) {
+                const int g = nbr[s];
+                o_nbr[o + i] = g < 0 ? -1 : (face_m[g] > 0 ? (long long)rank[fidx[g]] : -2);
+            }
+        }
+    }
+}
+
+__global__ void k_sorted_tail(long long *o_off, long long F, const long long *voff, const long long *mcount) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && o_off) o_off[F] = F > 0 ? voff[F - 1] + mcount[F - 1] : 0;
+}
+
 // ---------------------------------------------------------------- launchers
 
 static unsigned grid_for(long long n, int block = 256, long long cap = 2048) {
@@ -652,6 +727,65 @@ hipError_t launch_fetch(const DevNet &net, long long n, const int *face_m, const
     hipLaunchKernelGGL(k_fetch, dim3(grid_for(n)), dim3(256), 0, st, net, n, face_m, fidx, voff, ids, verts, nbr,
                        codes, argmax, shape, stride, o_off, o_ids, o_verts, o_nbr, o_codes, o_am, o_shape);
     hipLaunchKernelGGL(k_fetch_tail, dim3(1), dim3(64), 0, st, o_off, F, voff, face_m, n);
+    return hipGetLastError();
+}
+
+// Scratch of the canonical fetch for F faces: sort temporary bytes (the scan
+// temporary of launch_fetch is reused for the sorted counts).
+hipError_t sorted_fetch_tmp_bytes(long long F, size_t *bytes) {
+    size_t a = 0, b = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                                      (const int *)nullptr, (int *)nullptr, (int)F, 0, 64);
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, b, (long long *)nullptr, (long long *)nullptr, (int)F);
+    *bytes = a > b ? a : b;
+    return e;
+}
+
+// As launch_fetch, faces in canonical order.  face_cell, perm_a, perm_b, rank
+// [F] ints, keys_a, keys_b [F] u64, mcs, voffs [F] i64 scratch; tmp holds
+// sorted_fetch_tmp_bytes(F) (and scan_tmp_bytes(n) for the cell scan).
+hipError_t launch_fetch_sorted(const DevNet &net, long long n, const int *face_m, const int *ids,
+                               const double *verts, const int *nbr, const uint64_t *codes, const int *argmax,
+                               const int *shape, int stride, int *has, int *fidx, long long *mcount,
+                               long long *voff, void *scan_tmp, size_t scan_bytes, long long F, int *face_cell,
+                               int *perm_a, int *perm_b, int *rank, uint64_t *keys_a, uint64_t *keys_b,
+                               long long *mcs, long long *voffs, void *tmp, size_t tmp_bytes, long long *o_off,
+                               int *o_ids, double *o_verts, long long *o_nbr, uint64_t *o_codes, int *o_am,
+                               int *o_shape, hipStream_t st) {
+    if (n <= 0 || F <= 0) {
+        if (o_off) return hipMemsetAsync(o_off, 0, sizeof(long long), st);
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_face_flags, dim3(grid_for(n)), dim3(256), 0, st, face_m, n, has, mcount);
+    size_t tb = scan_bytes;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(scan_tmp, tb, has, fidx, (int)n, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_face_cells, dim3(grid_for(n)), dim3(256), 0, st, face_m, fidx, n, face_cell);
+    hipLaunchKernelGGL(k_iota_int, dim3(grid_for(F)), dim3(256), 0, st, perm_a, F);
+    // least significant key first: argmax, code words W-1 .. 0, shape
+    for (int pass = 0; pass < net.W + 2; ++pass) {
+        const int which = pass == 0 ? -1 : (pass <= net.W ? net.W - pass : -2);
+        if (which == -2 && net.S <= 1) break;
+        if (which == -1 && net.M <= 1) continue;
+        hipLaunchKernelGGL(k_sort_key, dim3(grid_for(F)), dim3(256), 0, st, perm_a, face_cell, codes, argmax, shape,
+                           net.W, which, F, keys_a);
+        tb = tmp_bytes;
+        e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys_a, keys_b, perm_a, perm_b, (int)F, 0,
+                                               which >= 0 ? 64 : 32, st);
+        if (e != hipSuccess) return e;
+        int *t = perm_a;
+        perm_a = perm_b;
+        perm_b = t;
+    }
+    hipLaunchKernelGGL(k_sorted_counts, dim3(grid_for(F)), dim3(256), 0, st, perm_a, face_cell, face_m, F, rank, mcs);
+    tb = tmp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, mcs, voffs, (int)F, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fetch_sorted, dim3(grid_for(F)), dim3(256), 0, st, net, F, perm_a, face_cell, rank, voffs,
+                       face_m, fidx, ids, verts, nbr, codes, argmax, shape, stride, o_off, o_ids, o_verts, o_nbr,
+                       o_codes, o_am, o_shape);
+    hipLaunchKernelGGL(k_sorted_tail, dim3(1), dim3(64), 0, st, o_off, F, voffs, mcs);
     return hipGetLastError();
 }
 

@@ -275,3 +275,80 @@ def test_c2_full_march_equals_oracle(binding, c2_case, c2_ref, path):
     got = fetch_host(ctx)
     assert st["faces"] == ref.n_faces and st["cells"] == ref.stats["cells"]
     compare_meshes(ref, got)
+
+
+# ------------------------------------------------------- canonical fetch
+
+def _fetch_sorted_host(ctx):
+    from paper_2106_10031_amd.binding import mesh_to_host
+    from gpu_common import HostMesh
+    h = mesh_to_host(ctx.fetch(sorted=True))
+    return HostMesh(h["codes"], h["argmax"], h["offsets"], h["ids"], h["verts"], h["nbr"]), h["shape"]
+
+
+def _assert_arrays_equal_oracle(ref, got, vtol=1e-9):
+    assert np.array_equal(got.offsets, ref.offsets)
+    assert np.array_equal(got.codes, ref.codes) and np.array_equal(got.argmax, ref.argmax)
+    assert np.array_equal(got.ids, ref.ids)
+    assert np.array_equal(got.nbr, ref.nbr)
+    scale = np.maximum(1.0, np.abs(ref.verts).max(axis=1))
+    assert (np.abs(got.verts - ref.verts).max(axis=1) / scale).max() <= vtol
+
+
+@pytest.mark.parametrize("name", list(SMALL_NETS))
+def test_fetch_sorted_equals_oracle_arrays(binding, name):
+    """am_fetch_sorted gives the oracle's canonical mesh array for array."""
+    net = SMALL_NETS[name]()
+    o, d = seeds.random_rays(16, seed=4)
+    on, ref = _oracle_mesh(net, o, d)
+    say("fetch sorted", name, ref.n_faces)
+    ctx = _ctx(binding, net)
+    ctx.seed_rays(o, d)
+    ctx.march()
+    got, _ = _fetch_sorted_host(ctx)
+    _assert_arrays_equal_oracle(ref, got)
+
+
+def test_fetch_sorted_c2_equals_oracle_arrays(binding, c2_case, c2_ref):
+    net, o, d = c2_case
+    say("fetch sorted c2", c2_ref.n_faces)
+    ctx = _ctx(binding, net)
+    ctx.seed_rays(o, d)
+    ctx.march(max_cells=1 << 21)
+    got, _ = _fetch_sorted_host(ctx)
+    _assert_arrays_equal_oracle(c2_ref, got)
+
+
+def test_fetch_sorted_batched_orders_by_shape(binding):
+    sb = nets.latent_sphere_batch([16, 16, 16], reinject=3, latent_dim=8, n_shapes=6, seed=3)
+    o, d, sh = [], [], []
+    for s in range(sb.n_shapes):
+        a, b = seeds.random_rays(12, seed=100 + s)
+        o.append(a); d.append(b); sh.append(np.full(12, s, np.int32))
+    o, d, sh = np.concatenate(o), np.concatenate(d), np.concatenate(sh)
+    say("fetch sorted batched")
+    ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+    ctx.seed_rays(o, d, shape_id=sh)
+    ctx.march()
+    from paper_2106_10031_amd.binding import mesh_to_host
+    plain = mesh_to_host(ctx.fetch())
+    got, shape = _fetch_sorted_host(ctx)
+    keys = [(int(shape[f]),) + tuple(int(w) for w in got.codes[f]) + (int(got.argmax[f]),)
+            for f in range(got.n_faces)]
+    assert all(a < b for a, b in zip(keys, keys[1:]))
+    # the host's own ordering of the discovery-order fetch, neighbours remapped
+    codes = plain["codes"]
+    order = np.lexsort([plain["argmax"]] + [codes[:, w] for w in range(codes.shape[1] - 1, -1, -1)]
+                       + [plain["shape"]])
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    off = plain["offsets"]
+    ms = np.diff(off)[order]
+    idx = np.concatenate([np.arange(off[f], off[f + 1]) for f in order])
+    nb = plain["nbr"][idx]
+    nb = np.where(nb >= 0, inv[np.maximum(nb, 0)], nb)
+    assert np.array_equal(np.diff(got.offsets), ms)
+    assert np.array_equal(got.ids, plain["ids"][idx]) and np.array_equal(got.verts, plain["verts"][idx])
+    assert np.array_equal(got.nbr, nb)
+    assert np.array_equal(shape, plain["shape"][order])
+    ctx.close()
