@@ -244,6 +244,15 @@ am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const
 am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
                         int64_t n);
 
+/* Seeds from points (the start of Algorithm 1 is a point on the surface):
+ * the cell of each point pts[i] (DEVICE [n][3] f64; shape_id DEVICE [n] i32
+ * or NULL) by a forward pass (Eqns (NeuronState)-(MLPState)) is a seed.  A
+ * point off the surface gives a cell whose face may be empty; it then adds
+ * nothing (am_march returns AM_E_SEED only if every seed face is empty).  A
+ * shape id out of range drops the point.  Replaces any previous seeds.
+ * Enqueued. */
+am_status am_seed_points(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n);
+
 /* Sphere-tracing seeds (Sec. 4.3.1, Eqn (SphereTracing)), for SDF networks:
  * from each start point pts[i] (DEVICE [n][3] f64; shape_id DEVICE [n] i32 or
  * NULL), repeats x <- x - F(x) g / |g|^2 with g the gradient of F in the cell

@@ -24,7 +24,8 @@ EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_b
            "am_chain", "am_faces", "am_seed_rays", "am_seed_cells", "am_march", "am_get_counts", "am_fetch",
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
            "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups",
-           "am_seed_points_st", "am_weld", "am_triangles", "am_fetch_sorted"]
+           "am_seed_points_st", "am_weld", "am_triangles", "am_fetch_sorted",
+           "am_seed_points"]
 
 
 class AmError(RuntimeError):
@@ -93,6 +94,7 @@ def lib(path: str = LIB_PATH):
     L.am_get_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.am_fetch_sorted.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.am_seed_points.argtypes = [vp, vp, vp, i64]
     L.am_prop_param_count.argtypes = []
     L.am_prop_set.argtypes = [vp, vp, i64, i32, C.c_float]
     L.am_prop_collect.argtypes = [vp, vp, vp, i64, C.c_float]
@@ -244,6 +246,14 @@ class Context:
         sh = self._shape(shape_id)
         self._seed_keep = (codes, am, sh)   # the copy is enqueued on the stream
         self._check(self.L.am_seed_cells(self.h, _p(codes), _p(am), _p(sh), codes.shape[0]))
+
+    def seed_points(self, pts, shape_id=None):
+        """Seeds from the cells of points (forward pass on the device)."""
+        t = self.torch
+        P = self._dev(pts, t.float64).reshape(-1, 3)
+        sh = self._shape(shape_id)
+        self._seed_keep = (P, sh)           # the kernel reads them on the stream
+        self._check(self.L.am_seed_points(self.h, _p(P), _p(sh), P.shape[0]))
 
     def seed_points_st(self, pts, max_iter=64, shape_id=None):
         """Sphere-tracing seeds from start points; returns (status, iters, x) device tensors."""

@@ -806,6 +806,24 @@ am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argma
     return AM_OK;
 }
 
+am_status am_seed_points(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n <= 0 || !pts) return fail(ctx, AM_E_INVALID, "need at least one seed point");
+    TRY(set_device(ctx));
+    TRY(ensure_seed_cap(ctx, n));
+    launch_codes(ctx->dn, pts, shape_id, n, ctx->d_seed_codes, ctx->d_seed_am, nullptr, ctx->stream);
+    HIPCHK(hipGetLastError());
+    if (shape_id)
+        HIPCHK(hipMemcpyAsync(ctx->d_seed_shape, shape_id, sizeof(int) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    else
+        HIPCHK(hipMemsetAsync(ctx->d_seed_shape, 0, sizeof(int) * n, ctx->stream));
+    ctx->n_seeds = n;
+    ctx->seeds_have_status = false;
+    ctx->have_result = false;
+    return AM_OK;
+}
+
 am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats) {
     if (!ctx) return AM_E_INVALID;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");

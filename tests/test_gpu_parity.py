@@ -352,3 +352,25 @@ def test_fetch_sorted_batched_orders_by_shape(binding):
     assert np.array_equal(got.nbr, nb)
     assert np.array_equal(shape, plain["shape"][order])
     ctx.close()
+
+
+def test_seed_points_march_matches_oracle(binding):
+    """am_seed_points: seeds are the cells of the given points; surface points
+    from the oracle's own ray seeding give the oracle's mesh, and an
+    off-surface point adds no face."""
+    net = nets.c1_net()
+    o, d = seeds.random_rays(16, seed=4)
+    on = O.OracleNet(net)
+    codes, ams, pts, sts = on.seed_rays(o, d)
+    ref = on.march(codes, ams)
+    say("seed points c1", len(pts))
+    ctx = _ctx(binding, net)
+    far = np.array([[0.0, 0.0, 0.0]])            # F(0) < 0: inside, its cell has no face
+    ctx.seed_points(np.vstack([pts[sts == 0], far]))
+    st = ctx.march()
+    assert st["faces"] == ref.n_faces
+    compare_meshes(ref, fetch_host(ctx))
+    ctx.seed_points(far)
+    with pytest.raises(binding.AmError) as e:
+        ctx.march()
+    assert "AM_E_SEED" in str(e.value)
