@@ -49,7 +49,6 @@ void launch_commit(const DevNet &, const Candidates &, uint64_t *, int *, int *,
                    unsigned long long, long long, hipStream_t);
 hipError_t sort_tmp_bytes(long long, size_t *);
 void launch_step_begin(Counters *, long long, long long, hipStream_t);
-void launch_step_end(Counters *, hipStream_t);
 void launch_chain_dev(const DevNet &, const uint64_t *, const int *, Counters *, long long, double *, int,
                       hipStream_t);
 void launch_clip_dev(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, Counters *,
@@ -57,7 +56,8 @@ void launch_clip_dev(const DevNet &, const uint64_t *, const int *, const uint64
                      hipStream_t);
 hipError_t launch_sort_cells(const unsigned *, long long, long long, unsigned *, int *, int *, void *, size_t,
                              hipStream_t);
-void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t);
+void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t,
+                    long long = 0, long long = 0);
 void launch_codes(const DevNet &, const double *, const int *, long long, uint64_t *, int *, double *, hipStream_t);
 void launch_seed_rays(const DevNet &, const double *, const double *, const int *, long long, int, uint64_t *, int *,
                       int *, int *, hipStream_t);
@@ -937,11 +937,11 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             HIPCHK(hipEventCreate(&e));
             ctx->evs.push_back(e);
         }
+        launch_step_begin(ctx->d_ctr, gchunk, cap, s);   // later ranges: resolve ends each step
         for (;;) {
             const long long run0 = (long long)ctx->h_ctr->steps_run;
             for (int k = 0; k < o.graph_steps; ++k) {
                 hipEvent_t *e = ctx->evs.data() + 4 * k;
-                launch_step_begin(ctx->d_ctr, gchunk, cap, s);
                 HIPCHK(hipEventRecord(e[0], s));
                 launch_chain_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_ctr, gchunk, ctx->d_rows, variant, s);
                 HIPCHK(hipEventRecord(e[1], s));
@@ -953,9 +953,8 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
                 launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
                               ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape,
                               ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, s);
-                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
+                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s, gchunk, cap);
                 HIPCHK(hipEventRecord(e[3], s));
-                launch_step_end(ctx->d_ctr, s);
             }
             HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -1013,7 +1012,6 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < o.graph_steps; ++k) {
-                launch_step_begin(ctx->d_ctr, gchunk, cap, cs);
                 launch_chain_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_ctr, gchunk, ctx->d_rows, variant, cs);
                 launch_clip_dev(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_ctr, gchunk,
                                 seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, cs);
@@ -1022,8 +1020,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
                 launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
                               ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape,
                               ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, cs);
-                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, cs);
-                launch_step_end(ctx->d_ctr, cs);
+                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, cs, gchunk, cap);
             }
             const hipError_t ce = hipStreamEndCapture(cs, &g);
             if (ce != hipSuccess) return fail(ctx, AM_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
@@ -1036,6 +1033,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             ctx->graph_key = key;
         }
         long long launches = 0;
+        launch_step_begin(ctx->d_ctr, gchunk, cap, s);   // later ranges: resolve ends each step
         for (;;) {
             HIPCHK(hipGraphLaunch(ctx->graph_exec, s));
             HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));

@@ -136,6 +136,9 @@ __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uin
                                                 const int *seed_shape, unsigned long long *slots, Counters *ctr,
                                                 unsigned long long cand_cap, unsigned long long cap_cells) {
     const unsigned long long n = min(ctr->n_cand, cand_cap);
+    // resolve reads this copy, so that a device-driven step can clear n_cand
+    // for the next step while resolve runs
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->n_cand_prev = ctr->n_cand;
     const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
     // every lane of the wave runs the same number of iterations (wave_reserve)
     const unsigned long long n_round = (n + 63) & ~63ull;
@@ -178,9 +181,30 @@ __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uin
 
 // ----------------------------------------------------------------- resolve
 
+// With advance set (device-driven steps), one thread also ends the step and
+// takes the next step's range (up to chunk cells of the frontier, none after
+// an overflow) and clears the candidate count: nothing else in this kernel
+// reads the step fields or n_cand.
+__device__ void next_step_range(Counters *c, unsigned long long chunk, unsigned long long cap_cells) {
+    const unsigned long long cells = c->n_cells < cap_cells ? c->n_cells : cap_cells;
+    const bool bad = c->overflow_cells || c->overflow_cand || c->overflow_hash;
+    const unsigned long long lo = c->step_lo;
+    unsigned long long n = (!bad && cells > lo) ? cells - lo : 0ull;
+    if (n > c->max_frontier) c->max_frontier = n;
+    if (n > chunk) n = chunk;
+    c->step_n = n;
+    c->n_cand = 0ull;
+}
+
 __global__ __launch_bounds__(256) void k_resolve(Candidates cand, int *face_nbr, int stride, Counters *ctr,
-                                                 unsigned long long cand_cap) {
-    const unsigned long long n = min(ctr->n_cand, cand_cap);
+                                                 unsigned long long cand_cap, unsigned long long chunk,
+                                                 unsigned long long cap_cells, int advance) {
+    const unsigned long long n = min(ctr->n_cand_prev, cand_cap);
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
+        ctr->step_lo += ctr->step_n;
+        if (ctr->step_n) ctr->steps_run += 1ull;
+        next_step_range(ctr, chunk, cap_cells);
+    }
     for (unsigned long long t = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; t < n;
          t += (unsigned long long)gridDim.x * blockDim.x) {
         const int p = cand.parent[t];
@@ -653,9 +677,10 @@ hipError_t launch_sort_cells(const unsigned *cell_key, long long lo, long long n
 }
 
 void launch_resolve(const Candidates &cand, int *face_nbr, int stride, Counters *ctr, unsigned long long cand_cap,
-                    long long n_hint, hipStream_t st) {
-    hipLaunchKernelGGL(k_resolve, dim3(grid_for(n_hint)), dim3(256), 0, st, cand, face_nbr, stride, ctr,
-                       cand_cap);
+                    long long n_hint, hipStream_t st, long long chunk, long long cap_cells) {
+    hipLaunchKernelGGL(k_resolve, dim3(grid_for(n_hint)), dim3(256), 0, st, cand, face_nbr, stride, ctr, cand_cap,
+                       (unsigned long long)(chunk > 0 ? chunk : 0), (unsigned long long)(cap_cells > 0 ? cap_cells : 0),
+                       chunk > 0 ? 1 : 0);
 }
 
 size_t forward_lds_bytes(const DevNet &net, int code_bufs) {

@@ -148,6 +148,7 @@ struct Counters {
     unsigned long long pivot_cells;      // pivoting form: faces traced by the walk
     unsigned long long pivot_fallback;   // ... and cells clipped instead
     unsigned long long max_frontier;     // device-driven steps: largest frontier seen
+    unsigned long long n_cand_prev;      // the step's candidate count, copied by commit for resolve
 };
 
 // ---------------------------------------------------------------- helpers

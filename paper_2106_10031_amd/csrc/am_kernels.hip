@@ -1968,6 +1968,8 @@ void launch_prop_score(const PropNet &P, const float *X, long long n, float *z, 
 
 // Opens a step: up to `chunk` cells from step_lo (none after an overflow),
 // and clears the candidate count.
+// First range of a device-driven march (later ones are taken by the resolve
+// kernel that ends each step).
 __global__ void k_step_begin(Counters *c, unsigned long long chunk, unsigned long long cap_cells) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const unsigned long long cells = c->n_cells < cap_cells ? c->n_cells : cap_cells;
@@ -1980,18 +1982,10 @@ __global__ void k_step_begin(Counters *c, unsigned long long chunk, unsigned lon
     c->n_cand = 0ull;
 }
 
-__global__ void k_step_end(Counters *c) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    c->step_lo += c->step_n;
-    if (c->step_n) c->steps_run += 1ull;
-}
-
 void launch_step_begin(Counters *ctr, long long chunk, long long cap_cells, hipStream_t st) {
     hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, st, ctr, (unsigned long long)chunk,
                        (unsigned long long)cap_cells);
 }
-
-void launch_step_end(Counters *ctr, hipStream_t st) { hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, ctr); }
 
 // Chain (dense variants 1, 2, 3, 4) and clip of the device-driven step; grids
 // cover `chunk` cells, workgroups past the step's count exit at once.
