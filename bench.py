@@ -160,6 +160,29 @@ def train_scorer(B, dev, max_cells):
                     "steps": 150, "scorer": "8 features (padded 32) -> 128 -> 128 -> 1, FP16 weights on MFMA"}
 
 
+def cell_set_digest(out) -> str:
+    """Order-independent 64-bit digest of a march's cell set (code words,
+    argmax, shape id of every face), computed on the device: each face's
+    words are mixed with fixed odd multipliers and the mixed values summed
+    modulo 2^64.  Equal digests mean equal cell sets with overwhelming
+    probability, whatever the discovery order."""
+    import torch
+    codes = out["codes"]
+    F, W = codes.shape
+    if F == 0:
+        return "0" * 16
+    g = torch.Generator(device="cpu").manual_seed(20210618)
+    mult = torch.randint(1, 2 ** 62, (W + 2,), generator=g, dtype=torch.int64) * 2 + 1
+    mult = mult.to(codes.device)
+    h = (codes * mult[:W]).sum(dim=1)
+    h = h + out["argmax"].to(torch.int64) * mult[W] + out["shape"].to(torch.int64) * mult[W + 1]
+    h = h ^ (h >> 29)
+    h = h * int(mult[0].item())
+    h = h ^ (h >> 32)
+    total = int(h.sum().item()) & (2 ** 64 - 1)
+    return f"{total:016x}"
+
+
 def chain_kernel_name(net, groups, graph_steps):
     """The chain kernel the timed steps launch: device-driven steps take the
     variant of the 2^14-cell bucket (the gathered tile becomes the 4-cell
@@ -409,10 +432,11 @@ def main(argv=None):
         main_launch = timed_launch
     print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step",
           file=sys.stderr, flush=True)
+    plain_digest = cell_set_digest(main_run["out"])
     forms = {f"{a.workload}_plain": {"faces_per_s": round(main_run["faces_per_s"], 1),
                                      "ms_per_step": round(main_run["ms_per_step"], 3),
                                      "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
-                                     "launch": main_launch}}
+                                     "launch": main_launch, "cell_set_digest": plain_digest}}
     if gs > 0 and "graph" in legs:
         forms[f"{a.workload}_plain_timed"] = {
             "faces_per_s": round(timed["faces_per_s"], 1), "ms_per_step": round(timed["ms_per_step"], 3),
@@ -439,9 +463,13 @@ def main(argv=None):
     prop_desc = {0: None, 1: "top-16 lines by the trained scorer clipped before the every-line pass",
                  2: "top-16 lines by distance to the entry edge clipped before the every-line pass"}
 
-    def record(key, r, precision, propose, routine=0):
+    def record(key, r, precision, propose, routine=0, ref_digest=None):
         e = {"faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
              "faces": r["faces"], "precision": bf16_desc if precision else "FP64 chain (MFMA), FP64 clip"}
+        d = cell_set_digest(r["out"])
+        e["cell_set_digest"] = d
+        if ref_digest is not None:
+            e["exact_cell_set_match"] = d == ref_digest
         if routine:
             st = r["stats"]
             e["precision"] = "FP64 chain (MFMA), FP64 pivoting walk"
@@ -466,7 +494,7 @@ def main(argv=None):
         r = time_form(ctx, o_d, d_d, precision, a.steps, a.warmup, a.max_cells, propose=propose,
                       face_routine=routine)
         assert r["faces"] == main_run["faces"], f"{v} form changed the face count"
-        record(f"{a.workload}_{v}", r, precision, propose, routine)
+        record(f"{a.workload}_{v}", r, precision, propose, routine, ref_digest=plain_digest)
 
     # roofline of the dominant kernel of the timed plain steps
     kst = timed["kernels"]
@@ -503,6 +531,7 @@ def main(argv=None):
             ctx3.prop_set(scorer, k=16, rho=6.0)
         steps3 = max(1, min(a.steps, 3 if name == "c3" else 1))
         base = None
+        base_digest = None
         for i, (v, (precision, propose, routine)) in enumerate(todo):
             r = time_form(ctx3, o3, d3, precision, steps3, 1 if name == "c3" else 0,
                           a.max_cells if name == "c3" else max(a.max_cells, 1 << 26), propose=propose,
@@ -511,7 +540,9 @@ def main(argv=None):
             if base is None:
                 base = r["faces"]
             assert r["faces"] == base, f"{name} {v} form changed the face count"
-            record(f"{name}_{v}", r, precision, propose, routine)
+            record(f"{name}_{v}", r, precision, propose, routine, ref_digest=base_digest)
+            if base_digest is None:
+                base_digest = forms[f"{name}_{v}"]["cell_set_digest"]
         ctx3.close()
     if "ensemble" in forms_req:
         forms["ensemble_4x_d4w32"] = ensemble_form(B, dev, a.steps)
@@ -534,7 +565,9 @@ def main(argv=None):
                       "face_verts": st["face_verts"],
                       "triangles": st["triangles"], "cells": st["cells"], "march_steps": st["steps"],
                       "seeds": st["seed_cells"], "degenerate": st["degenerate"]},
-           "forms": forms, "roofline": roofline}
+           "forms": forms, "roofline": roofline,
+           "exact_cell_set_match": all(v.get("exact_cell_set_match", True) for v in forms.values()
+                                       if isinstance(v, dict))}
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(net, o, d, a.cpu_budget)
     if a.calib_copy_mib > 0:
