@@ -331,6 +331,30 @@ am_status am_weld(am_ctx *ctx, int64_t faces, const int64_t *offsets, const int3
 am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets,
                        const int64_t *corner_vertex, int64_t *tri, int64_t tri_rows);
 
+/* ---- Quadric edge-collapse simplification of a welded triangle mesh (the
+ * post-processing of Sec. 4.4, with Garland and Heckbert's quadric error
+ * metric; it gives up the exactness of the march).  Each vertex carries the
+ * area-weighted quadric of its triangles' planes; an edge collapses to the
+ * point minimising the summed quadric (or the best of its ends and midpoint).
+ * Rounds in parallel: every vertex keeps its cheapest edge, an edge cheapest
+ * at both ends claims the vertices of all triangles around it, and an edge
+ * holding all its claims collapses if its ends share exactly two neighbours
+ * and no surviving triangle turns by more than about 78 degrees.  Rounds stop
+ * at target_tris live triangles (the last round's collapses are rationed),
+ * when nothing collapses, or after max_rounds (0: 256).
+ *
+ * DEVICE in: vxyz [n_verts][3] f64, tri [n_tris][3] i64 (vertex ids; the
+ * welded mesh and its fan triangles, consistently oriented), boundary
+ * [n_verts] u8 or NULL (flagged vertices never move).  DEVICE out (capacity
+ * n_verts and n_tris rows): v_out, tri_out, compacted, vertex ids into v_out.
+ * HOST out: n_verts_out, n_tris_out, rounds_out, n_bad (input triangles with
+ * an id out of range or a repeated vertex, dropped).  Allocates its scratch
+ * (about 160 B per vertex and 40 B per triangle) for the call; synchronises. */
+am_status am_simplify(am_ctx *ctx, int64_t n_verts, const double *vxyz, int64_t n_tris, const int64_t *tri,
+                      const uint8_t *boundary, int64_t target_tris, int32_t max_rounds, double *v_out,
+                      int64_t *tri_out, int64_t *n_verts_out, int64_t *n_tris_out, int32_t *rounds_out,
+                      int64_t *n_bad);
+
 /* ---- Affine-chain tile autotuner.  The chain kernel has five tile
  * variants (opts.chain_groups): 4, 8 or 16 cells per workgroup (1, 2 or 4
  * column groups of the 16-column FP64 MFMA tile; more cells share each

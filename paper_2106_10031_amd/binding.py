@@ -25,7 +25,7 @@ EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_b
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
            "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups",
            "am_seed_points_st", "am_weld", "am_triangles", "am_fetch_sorted",
-           "am_seed_points"]
+           "am_seed_points", "am_simplify"]
 
 
 class AmError(RuntimeError):
@@ -95,6 +95,8 @@ def lib(path: str = LIB_PATH):
     L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.am_fetch_sorted.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.am_seed_points.argtypes = [vp, vp, vp, i64]
+    L.am_simplify.argtypes = [vp, i64, vp, i64, vp, vp, i64, i32, vp, vp, C.POINTER(i64), C.POINTER(i64),
+                              C.POINTER(i32), C.POINTER(i64)]
     L.am_prop_param_count.argtypes = []
     L.am_prop_set.argtypes = [vp, vp, i64, i32, C.c_float]
     L.am_prop_collect.argtypes = [vp, vp, vp, i64, C.c_float]
@@ -395,6 +397,21 @@ class Context:
         tri = t.empty((max(T, 1), 3), dtype=t.int64, device=self.device)
         self._check(self.L.am_triangles(self.h, F, _p(offsets), _p(corner_vertex), _p(tri), T))
         return tri[:T]
+
+
+    def simplify(self, vxyz, tri, target_tris, max_rounds=0, boundary=None):
+        """Quadric edge-collapse simplification of a welded triangle mesh
+        (device tensors); returns (vertices, triangles, rounds, dropped)."""
+        t = self.torch
+        V, T = vxyz.shape[0], tri.shape[0]
+        assert vxyz.dtype == t.float64 and tri.dtype == t.int64 and vxyz.is_contiguous() and tri.is_contiguous()
+        v_out = t.empty((V, 3), dtype=t.float64, device=self.device)
+        t_out = t.empty((T, 3), dtype=t.int64, device=self.device)
+        nv, nt, r, bad = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
+        self._check(self.L.am_simplify(self.h, V, _p(vxyz), T, _p(tri), _p(boundary), int(target_tris),
+                                       int(max_rounds), _p(v_out), _p(t_out), C.byref(nv), C.byref(nt), C.byref(r),
+                                       C.byref(bad)))
+        return v_out[:nv.value], t_out[:nt.value], r.value, bad.value
 
 
 def mesh_to_host(out):

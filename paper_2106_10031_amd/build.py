@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libam.so")
-SOURCES = ["am_kernels.hip", "am_frontier.hip", "am_learn.hip", "am_weld.hip", "am_api.hip"]
+SOURCES = ["am_kernels.hip", "am_frontier.hip", "am_learn.hip", "am_weld.hip", "am_qecd.hip", "am_api.hip"]
 ARCH = "gfx950"
 
 

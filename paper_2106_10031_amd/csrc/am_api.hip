@@ -73,6 +73,9 @@ hipError_t launch_fetch(const DevNet &, long long, const int *, const int *, con
                         int *, hipStream_t);
 hipError_t weld_tmp_bytes(long long, size_t *);
 hipError_t sorted_fetch_tmp_bytes(long long, size_t *);
+size_t qecd_scratch_bytes(long long, long long);
+hipError_t run_qecd(const double *, long long, const long long *, long long, const unsigned char *, long long, int,
+                    void *, double *, long long *, long long *, long long *, int *, long long *, hipStream_t);
 hipError_t launch_fetch_sorted(const DevNet &, long long, const int *, const int *, const double *, const int *,
                                const uint64_t *, const int *, const int *, int, int *, int *, long long *,
                                long long *, void *, size_t, long long, int *, int *, int *, int *, uint64_t *,
@@ -1237,6 +1240,37 @@ am_status am_fetch_sorted(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *v
                                ctx->d_sf_pa, ctx->d_sf_pb, ctx->d_sf_rank, ctx->d_sf_ka, ctx->d_sf_kb, ctx->d_sf_mc,
                                ctx->d_sf_vo, ctx->d_sf_tmp, ctx->sf_tmp, (long long *)offsets, ids, verts,
                                (long long *)nbr, codes, argmax, shape_id, ctx->stream));
+    return AM_OK;
+}
+
+// ---- quadric edge-collapse simplification
+
+am_status am_simplify(am_ctx *ctx, int64_t n_verts, const double *vxyz, int64_t n_tris, const int64_t *tri,
+                      const uint8_t *boundary, int64_t target_tris, int32_t max_rounds, double *v_out,
+                      int64_t *tri_out, int64_t *n_verts_out, int64_t *n_tris_out, int32_t *rounds_out,
+                      int64_t *n_bad) {
+    if (!ctx) return AM_E_INVALID;
+    if (n_verts <= 0 || n_tris <= 0 || !vxyz || !tri || !v_out || !tri_out)
+        return fail(ctx, AM_E_INVALID, "need vertices, triangles and output buffers");
+    if (n_verts >= (1LL << 31) || 3 * n_tris >= (1LL << 31))
+        return fail(ctx, AM_E_INVALID, "at most 2^31 - 1 vertices and (2^31 - 1) / 3 triangles");
+    if (target_tris < 0) return fail(ctx, AM_E_INVALID, "negative target");
+    if (max_rounds <= 0) max_rounds = 256;
+    if (max_rounds > 4096) return fail(ctx, AM_E_INVALID, "max_rounds must be at most 4096");
+    TRY(set_device(ctx));
+    char *scratch = nullptr;
+    TRY(dalloc(ctx, scratch, qecd_scratch_bytes(n_verts, n_tris)));
+    long long Vo = 0, To = 0, bad = 0;
+    int rounds = 0;
+    const hipError_t e = run_qecd(vxyz, n_verts, (const long long *)tri, n_tris, boundary, target_tris, max_rounds,
+                                  scratch, v_out, (long long *)tri_out, &Vo, &To, &rounds, &bad, ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
+    dfree(scratch);
+    if (e != hipSuccess) return fail(ctx, AM_E_HIP, "simplification failed: %s", hipGetErrorString(e));
+    if (n_verts_out) *n_verts_out = Vo;
+    if (n_tris_out) *n_tris_out = To;
+    if (rounds_out) *rounds_out = rounds;
+    if (n_bad) *n_bad = bad;
     return AM_OK;
 }
 

@@ -1,0 +1,111 @@
+"""Quadric edge-collapse simplification (am_simplify; Sec. 4.4) of the
+welded triangle mesh of a march.
+
+The result depends on collapse order, so it is checked against what does not:
+  * the cube net's mesh (48 triangles, 26 vertices: face centres and edge
+    midpoints lie on one or two planes, corners on three) simplifies at zero
+    cost to 12 triangles on the 8 corners, with area 6 and volume 1 exactly;
+  * on C1 and C2 at 10 %: the triangle count reaches the target, the mesh
+    stays closed and consistently oriented (each undirected edge in exactly
+    two triangles, once each way), the Euler characteristic is unchanged,
+    every vertex stays near the zero set (|F| from the CPU reference's
+    forward pass) and the enclosed volume changes by under 1 %.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from am_workloads import nets, seeds
+from gpu_common import say
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_10031_amd import binding as B
+    return B
+
+
+def _welded_tris(ctx):
+    dev = ctx.fetch()
+    cv, vx, unp = ctx.weld(dev)
+    assert unp == 0
+    tri = ctx.triangles(dev["offsets"], cv)
+    return vx.contiguous(), tri.contiguous()
+
+
+def _area_volume(V, T):
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    cr = np.cross(b - a, c - a)
+    return 0.5 * np.linalg.norm(cr, axis=1).sum(), np.einsum("ij,ij->i", a, cr).sum() / 6.0
+
+
+def _check_closed(T, n_verts):
+    e = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    key = e[:, 0] * n_verts + e[:, 1]
+    assert len(np.unique(key)) == len(key), "a directed edge appears twice"
+    rev = e[:, 1] * n_verts + e[:, 0]
+    assert np.all(np.isin(rev, key)), "an edge has no opposite half"
+    return len(key) // 2
+
+
+def test_cube_simplifies_to_its_corners(binding):
+    net = nets.cube_net()
+    ctx = binding.Context(0).load_net(net)
+    o, d = seeds.random_rays(16, seed=4)
+    ctx.seed_rays(o, d)
+    ctx.march()
+    vx, tri = _welded_tris(ctx)
+    say("simplify cube", vx.shape[0], tri.shape[0])
+    v2, t2, rounds, bad = ctx.simplify(vx, tri, 12)
+    V = v2.cpu().numpy()
+    T = t2.cpu().numpy()
+    assert bad == 0 and len(T) == 12 and len(V) == 8, (len(T), len(V), rounds)
+    assert np.all(np.abs(np.abs(V) - 0.5) <= 1e-12)
+    A, Vol = _area_volume(V, T)
+    assert abs(A - 6.0) < 1e-12 and abs(Vol - 1.0) < 1e-12
+    _check_closed(T, len(V))
+
+
+def _case(name):
+    if name == "c1":
+        return nets.c1_net(), seeds.random_rays(16, seed=4), 2
+    net = nets.load_fitted("c2")
+    prim = np.load(os.path.join(nets.DATA_DIR, "c2_primitives.npz"))
+    return net, seeds.centre_rays(prim["p0"], 128), 4
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_simplify_to_ten_percent(binding, name):
+    net, (o, d), chi = _case(name)
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    ctx.march(max_cells=1 << 21)
+    vx, tri = _welded_tris(ctx)
+    T0 = tri.shape[0]
+    V0 = vx.cpu().numpy()
+    A0, Vol0 = _area_volume(V0, tri.cpu().numpy())
+    target = T0 // 10
+    say("simplify", name, T0, "->", target)
+    v2, t2, rounds, bad = ctx.simplify(vx, tri, target)
+    V = v2.cpu().numpy()
+    T = t2.cpu().numpy()
+    say("simplified", name, len(T), "triangles", len(V), "vertices", rounds, "rounds")
+    assert bad == 0
+    assert len(T) <= target + 2
+    E = _check_closed(T, len(V))
+    assert len(V) - E + len(T) == chi
+    A, Vol = _area_volume(V, T)
+    assert abs(Vol - Vol0) <= 0.01 * abs(Vol0)
+    on = O.OracleNet(net)
+    pick = np.random.default_rng(0).choice(len(V), size=min(2000, len(V)), replace=False)
+    F = np.array([on.forward(V[i])[0] for i in pick])
+    say("max |F| at simplified vertices", float(np.abs(F).max()))
+    assert np.abs(F).max() <= 0.02
