@@ -326,3 +326,126 @@ def fan_triangles(offsets, corner_vertex):
         for k in range(1, m - 1):
             out.append((cv[a0], cv[a0 + k], cv[a0 + k + 1]))
     return np.array(out, np.int64).reshape(-1, 3)
+
+
+# ----------------------------------------------- quadric edge collapse
+
+def qecd(verts, tris, target_tris: int, _mutate: int = 0):
+    """Sequential quadric edge-collapse decimation (Sec. 4.4; Garland and
+    Heckbert's metric, which the paper adopts), the reference for the GPU's
+    parallel rounds.  Vertex quadrics are area-weighted sums of their
+    triangles' plane quadrics; an edge collapses to the minimiser of the
+    summed quadric when that 3x3 system is well conditioned and the point
+    lies within two edge lengths of the midpoint, else to the best of its two
+    ends and midpoint.  The cheapest edge whose ends share exactly two
+    neighbours and two triangles, and whose collapse turns no surviving
+    triangle by more than the angle with cosine 0.2, collapses first (a lazy
+    heap).  Returns (verts [V'][3], tris [T'][3]) with unused vertices
+    dropped.  Plain numpy and Python loops: small meshes only.
+    ``_mutate`` plants a mistake for the checks of the checks (1: every edge
+    collapses to its midpoint).
+    """
+    import heapq
+
+    P = np.array(verts, np.float64).copy()
+    T = [list(map(int, t)) for t in tris]
+    nV = len(P)
+    Q = np.zeros((nV, 4, 4))
+    for a, b, c in T:
+        n = np.cross(P[b] - P[a], P[c] - P[a])
+        ln = np.linalg.norm(n)
+        if ln == 0.0:
+            continue
+        p = np.append(n / ln, -np.dot(n / ln, P[a]))
+        K = np.outer(p, p) * 0.5 * ln
+        for v in (a, b, c):
+            Q[v] += K
+    live = [True] * len(T)
+    adj = [set() for _ in range(nV)]
+    for t, (a, b, c) in enumerate(T):
+        for v in (a, b, c):
+            adj[v].add(t)
+
+    def placement(a, b):
+        q = Q[a] + Q[b]
+        if _mutate == 1:
+            v = 0.5 * (P[a] + P[b])
+            h = np.append(v, 1.0)
+            return max(h @ q @ h, 0.0), v
+        A, r = q[:3, :3], -q[:3, 3]
+        best, vb = None, None
+        det = np.linalg.det(A)
+        scale = abs(A[0, 0]) + abs(A[1, 1]) + abs(A[2, 2])
+        if scale > 0.0 and abs(det) > 1e-10 * scale ** 3:
+            v = np.linalg.solve(A, r)
+            if np.linalg.norm(v - 0.5 * (P[a] + P[b])) <= 2.0 * np.linalg.norm(P[b] - P[a]):
+                h = np.append(v, 1.0)
+                best, vb = max(h @ q @ h, 0.0), v
+        for v in (P[a], P[b], 0.5 * (P[a] + P[b])):
+            h = np.append(v, 1.0)
+            c = max(h @ q @ h, 0.0)
+            if best is None or c < best:
+                best, vb = c, v.copy()
+        return best, vb
+
+    def valid(a, b, v):
+        shared = [t for t in adj[a] if b in T[t]]
+        na = {w for t in adj[a] for w in T[t]} - {a, b}
+        nb = {w for t in adj[b] for w in T[t]} - {a, b}
+        if len(shared) != 2 or len(na & nb) != 2:
+            return False
+        for s in (a, b):
+            for t in adj[s]:
+                c = T[t]
+                if a in c and b in c:
+                    continue
+                n0 = np.cross(P[c[1]] - P[c[0]], P[c[2]] - P[c[0]])
+                q = [v if x in (a, b) else P[x] for x in c]
+                n1 = np.cross(q[1] - q[0], q[2] - q[0])
+                l0, l1 = np.linalg.norm(n0), np.linalg.norm(n1)
+                if not (l1 > 1e-12 * l0) or not (np.dot(n0, n1) > 0.2 * l0 * l1):
+                    return False
+        return True
+
+    heap = []
+    stamp = [0] * nV
+
+    def push_edges(v):
+        for t in adj[v]:
+            for w in T[t]:
+                if w != v:
+                    a, b = min(v, w), max(v, w)
+                    c, _ = placement(a, b)
+                    heapq.heappush(heap, (c, a, b, stamp[a], stamp[b]))
+
+    for v in range(nV):
+        push_edges(v)
+    n_live = sum(live)
+    while n_live > target_tris and heap:
+        c, a, b, sa, sb = heapq.heappop(heap)
+        if sa != stamp[a] or sb != stamp[b] or not adj[a] or not adj[b]:
+            continue
+        if not any(b in T[t] for t in adj[a]):
+            continue
+        c, v = placement(a, b)
+        if not valid(a, b, v):
+            continue
+        P[a] = v
+        Q[a] = Q[a] + Q[b]
+        for t in list(adj[b]):
+            if a in T[t]:
+                live[t] = False
+                n_live -= 1
+                for w in T[t]:
+                    adj[w].discard(t)
+            else:
+                T[t] = [a if x == b else x for x in T[t]]
+                adj[a].add(t)
+        adj[b] = set()
+        stamp[a] += 1
+        stamp[b] += 1
+        push_edges(a)
+    kept = [T[t] for t in range(len(T)) if live[t]]
+    used = sorted({v for t in kept for v in t})
+    remap = {v: i for i, v in enumerate(used)}
+    return P[used], np.array([[remap[v] for v in t] for t in kept], np.int64).reshape(-1, 3)

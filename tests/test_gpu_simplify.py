@@ -5,6 +5,8 @@ The result depends on collapse order, so it is checked against what does not:
   * the cube net's mesh (48 triangles, 26 vertices: face centres and edge
     midpoints lie on one or two planes, corners on three) simplifies at zero
     cost to 12 triangles on the 8 corners, with area 6 and volume 1 exactly;
+  * against the CPU reference's sequential collapse on a closed net: the
+    same counts and topology, vertex error and volume on a par;
   * on C1 and C2 at 10 %: the triangle count reaches the target, the mesh
     stays closed and consistently oriented (each undirected edge in exactly
     two triangles, once each way), the Euler characteristic is unchanged,
@@ -109,3 +111,38 @@ def test_simplify_to_ten_percent(binding, name):
     F = np.array([on.forward(V[i])[0] for i in pick])
     say("max |F| at simplified vertices", float(np.abs(F).max()))
     assert np.abs(F).max() <= 0.02
+
+
+def test_simplify_matches_the_sequential_reference(binding):
+    """Parallel rounds against the oracle's sequential collapse (cheapest
+    edge first) on the same closed net at 20 %: the same triangle count, and
+    vertex error, volume and topology on a par (the two orders differ, so
+    the meshes do)."""
+    net = nets.random_sphere_like([24, 24], seed=5, radius=0.4, scale=0.3)
+    rays = seeds.random_rays(16, seed=4)
+    on = O.OracleNet(net)
+    codes, ams, _, _ = on.seed_rays(*rays)
+    mesh = on.march(codes, ams)
+    cv, rvx, _ = O.weld(mesh, net.n_hidden)
+    rtri = O.fan_triangles(mesh.offsets, cv)
+    target = len(rtri) // 5
+    RV, RT = O.qecd(rvx, rtri, target)
+    say("simplify vs reference", len(rtri), "->", target)
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(*rays)
+    ctx.march()
+    vx, tri = _welded_tris(ctx)
+    assert tri.shape[0] == len(rtri)
+    v2, t2, rounds, bad = ctx.simplify(vx, tri, target)
+    V = v2.cpu().numpy()
+    T = t2.cpu().numpy()
+    assert len(T) == len(RT) and len(V) == len(RV)
+    E, RE = _check_closed(T, len(V)), _check_closed(RT, len(RV))
+    assert len(V) - E + len(T) == len(RV) - RE + len(RT)
+    _, vol = _area_volume(V, T)
+    _, rvol = _area_volume(RV, RT)
+    assert abs(vol - rvol) <= 0.005 * abs(rvol)
+    F = np.abs([on.forward(v)[0] for v in V]).max()
+    RF = np.abs([on.forward(v)[0] for v in RV]).max()
+    say("max |F|: GPU", F, "reference", RF)
+    assert F <= 2.0 * RF + 1e-6
