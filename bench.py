@@ -236,7 +236,8 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tun
 
 def mesh_form(ctx, mesh, reps=5):
     """The welded output Z = {V, {P}} (Sec. 3) of a fetched march: shared
-    vertices (am_weld) and fan triangles (am_triangles), timed together."""
+    vertices (am_weld) and fan triangles (am_triangles), timed together;
+    then their simplification (am_simplify), timed alone."""
     import torch
     for rep in range(reps + 1):
         if rep == 1:
@@ -247,9 +248,20 @@ def mesh_form(ctx, mesh, reps=5):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / reps
     F = mesh["offsets"].shape[0] - 1
-    return {"ms": round(ms, 3), "faces": int(F), "corners": int(cv.shape[0]), "vertices": int(vx.shape[0]),
-            "triangles": int(tri.shape[0]), "unpaired_edges": int(unp),
-            "faces_per_s": round(F / (ms * 1e-3), 1) if ms > 0 else None}
+    out = {"ms": round(ms, 3), "faces": int(F), "corners": int(cv.shape[0]), "vertices": int(vx.shape[0]),
+           "triangles": int(tri.shape[0]), "unpaired_edges": int(unp),
+           "faces_per_s": round(F / (ms * 1e-3), 1) if ms > 0 else None}
+    # quadric edge-collapse simplification (Sec. 4.4) of those triangles to 10 %
+    target = int(tri.shape[0]) // 10
+    for rep in range(3):
+        if rep == 1:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        v2, t2, rounds, bad = ctx.simplify(vx, tri, target)
+    torch.cuda.synchronize()
+    out["simplify"] = {"ms": round((time.perf_counter() - t0) * 1e3 / 2, 3), "target_triangles": target,
+                       "triangles": int(t2.shape[0]), "vertices": int(v2.shape[0]), "rounds": int(rounds)}
+    return out
 
 
 def seeding_forms(ctx, o, d, max_cells, reps=5):
