@@ -340,8 +340,11 @@ am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets,
  * at both ends claims the vertices of all triangles around it, and an edge
  * holding all its claims collapses if its ends share exactly two neighbours
  * and no surviving triangle turns by more than about 78 degrees.  Rounds stop
- * at target_tris live triangles (the last round's collapses are rationed),
- * when nothing collapses, or after max_rounds (0: 256).
+ * at target_tris live triangles (the last round's collapses are rationed, so
+ * the count ends at the target or one below it: a collapse removes two),
+ * when nothing collapses, or after max_rounds (0: 256; at most 4096).
+ * Errors: AM_E_INVALID for empty inputs, a NULL buffer, a negative target,
+ * 3 * n_verts or 3 * n_tris at or above 2^31, or max_rounds above 4096.
  *
  * DEVICE in: vxyz [n_verts][3] f64, tri [n_tris][3] i64 (vertex ids; the
  * welded mesh and its fan triangles, consistently oriented), boundary

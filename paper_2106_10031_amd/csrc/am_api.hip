@@ -1252,8 +1252,8 @@ am_status am_simplify(am_ctx *ctx, int64_t n_verts, const double *vxyz, int64_t 
     if (!ctx) return AM_E_INVALID;
     if (n_verts <= 0 || n_tris <= 0 || !vxyz || !tri || !v_out || !tri_out)
         return fail(ctx, AM_E_INVALID, "need vertices, triangles and output buffers");
-    if (n_verts >= (1LL << 31) || 3 * n_tris >= (1LL << 31))
-        return fail(ctx, AM_E_INVALID, "at most 2^31 - 1 vertices and (2^31 - 1) / 3 triangles");
+    if (3 * n_verts >= (1LL << 31) || 3 * n_tris >= (1LL << 31))   // 32-bit ids index 3-wide rows
+        return fail(ctx, AM_E_INVALID, "at most (2^31 - 1) / 3 vertices and as many triangles");
     if (target_tris < 0) return fail(ctx, AM_E_INVALID, "negative target");
     if (max_rounds <= 0) max_rounds = 256;
     if (max_rounds > 4096) return fail(ctx, AM_E_INVALID, "max_rounds must be at most 4096");

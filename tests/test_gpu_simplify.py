@@ -7,6 +7,8 @@ The result depends on collapse order, so it is checked against what does not:
     cost to 12 triangles on the 8 corners, with area 6 and volume 1 exactly;
   * against the CPU reference's sequential collapse on a closed net: the
     same counts and topology, vertex error and volume on a par;
+  * edge cases: bad input triangles, targets out of reach either way, frozen
+    vertices, and the argument checks;
   * on C1 and C2 at 10 %: the triangle count reaches the target, the mesh
     stays closed and consistently oriented (each undirected edge in exactly
     two triangles, once each way), the Euler characteristic is unchanged,
@@ -146,3 +148,51 @@ def test_simplify_matches_the_sequential_reference(binding):
     RF = np.abs([on.forward(v)[0] for v in RV]).max()
     say("max |F|: GPU", F, "reference", RF)
     assert F <= 2.0 * RF + 1e-6
+
+
+def test_simplify_edge_cases(binding):
+    """Bad input triangles are dropped and counted; a target at or above the
+    live count leaves the mesh as it is; a target nothing can reach stops
+    when no edge can collapse, with the mesh still closed; sizes beyond the
+    32-bit ids and other bad arguments are rejected before any launch."""
+    import ctypes as C
+    net = nets.cube_net()
+    ctx = binding.Context(0).load_net(net)
+    o, d = seeds.random_rays(16, seed=4)
+    ctx.seed_rays(o, d)
+    ctx.march()
+    vx, tri = _welded_tris(ctx)
+    nV, nT = vx.shape[0], tri.shape[0]
+    say("simplify edge cases", nV, nT)
+    junk = torch.tensor([[0, 0, 1], [0, 1, nV], [-1, 2, 3]], dtype=torch.int64, device="cuda")
+    tri_bad = torch.cat([tri, junk]).contiguous()
+    for target in (nT, 10 * nT):
+        v2, t2, rounds, bad = ctx.simplify(vx, tri_bad, target)
+        assert bad == 3 and rounds == 0
+        assert torch.equal(t2, tri) and torch.equal(v2, vx)
+    v2, t2, rounds, bad = ctx.simplify(vx, tri, 0)
+    V, T = v2.cpu().numpy(), t2.cpu().numpy()
+    assert bad == 0 and rounds >= 1 and 2 <= len(T) <= 12
+    E = _check_closed(T, len(V))
+    assert len(V) - E + len(T) == 2
+    # a boundary flag on every vertex freezes the mesh
+    frozen = torch.ones(nV, dtype=torch.uint8, device="cuda")
+    v2, t2, rounds, bad = ctx.simplify(vx, tri, 12, boundary=frozen)
+    assert torch.equal(t2, tri) and rounds == 1
+    # argument checks (no launch: the sizes are refused first)
+    P = lambda t: C.c_void_p(t.data_ptr())
+    vo = torch.empty_like(vx)
+    to = torch.empty_like(tri)
+    nv, nt, r, nb = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
+    L = ctx.L
+
+    def call(V, T, target, max_rounds):
+        return L.am_simplify(ctx.h, V, P(vx), T, P(tri), None, target, max_rounds, P(vo), P(to), C.byref(nv),
+                             C.byref(nt), C.byref(r), C.byref(nb))
+
+    assert call(1 << 30, nT, 12, 0) != 0
+    assert call(nV, 1 << 30, 12, 0) != 0
+    assert call(nV, 0, 12, 0) != 0
+    assert call(nV, nT, -1, 0) != 0
+    assert call(nV, nT, 12, 5000) != 0
+    assert call(nV, nT, 12, 0) == 0 and nt.value == 12
