@@ -361,6 +361,35 @@ def c4_forms(B, dev, steps, max_cells):
                              "faces": faces_single, "note": "one march per shape, same context, one pass"}}
 
 
+def chain_sweep(B, name, counts, groups, reps=10):
+    """The affine chain alone (am_chain) at several cell counts per launch.
+    Codes are random (each unit on with probability 1/2), not cells of the
+    surface: the dense chain does the same work for any code.  Times are
+    HIP events around each call, so they include the unpadding copy;
+    a kernel trace of the same run gives the chain kernel by itself."""
+    import torch
+    net = workload(name)[0]
+    ctx = B.Context(0).load_net(net)
+    if groups:
+        ctx.set_chain_groups(groups)
+    rng = np.random.default_rng(1)
+    out = []
+    for n in counts:
+        codes = torch.as_tensor(rng.integers(0, 2 ** 62, size=(n, ctx.W), dtype=np.int64), device="cuda")
+        ctx.chain(codes)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            ctx.chain(codes)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out.append({"cells": n, "ms_per_call": round(ms, 4), "ns_per_cell": round(ms * 1e6 / n, 2)})
+        print(f"[bench] chain sweep {name} {n} cells: {ms * 1e3:.1f} us per call", file=sys.stderr, flush=True)
+    return {"chain_sweep": name, "chain_groups": ctx.chain_groups(), "calls": out}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,6 +416,9 @@ def main(argv=None):
                          "(the same steps as graph replays; gives value), host (host-driven steps)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the bench, copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--chain-sweep", default="",
+                    help="instead of the bench: the workload's chain alone (am_chain) at these cell counts, "
+                         "e.g. 256,1024,3500,14000, ten launches each (for a kernel trace)")
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -398,6 +430,10 @@ def main(argv=None):
     from paper_2106_10031_amd import binding as B
 
     dev = torch.device("cuda", 0)
+    if a.chain_sweep:
+        print(json.dumps(chain_sweep(B, a.workload, [int(x) for x in a.chain_sweep.split(",")],
+                                     [int(x) for x in a.chain_groups.split(",")] if a.chain_groups else None)))
+        return 0
     forms_req = [f for f in a.forms.split(",") if f]
 
     def prepare(name):

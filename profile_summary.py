@@ -5,6 +5,11 @@
         Markdown table of a --kernel-trace --stats run (calls, total and
         average duration per kernel).
 
+    python profile_summary.py dispatches <kernel_trace.csv> --kernel NAME
+        Markdown table of one kernel's dispatches of a --kernel-trace run,
+        grouped by launch size (workgroups): count, median and fastest
+        duration.
+
     python profile_summary.py counters <fetch.csv> <write.csv> --calib-mib M
         Markdown table of HBM bytes per launch for every kernel of two --pmc
         runs (FETCH_SIZE, then WRITE_SIZE), scaled as below.
@@ -46,6 +51,22 @@ def stats(path: str, top: int) -> str:
     for r in rows[:top]:
         out.append(f"| `{short_name(r['Name'])}` | {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def dispatches(path: str, kernel: str) -> str:
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if short_name(r["Kernel_Name"]) != kernel:
+            continue
+        wg = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+        per[wg].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    if not per:
+        raise SystemExit(f"kernel {kernel} not in the trace")
+    out = ["| workgroups | dispatches | median (us) | fastest (us) |", "|---:|---:|---:|---:|"]
+    for wg in sorted(per):
+        v = sorted(per[wg])
+        out.append(f"| {wg} | {len(v)} | {v[len(v) // 2]:.1f} | {v[0]:.1f} |")
     return "\n".join(out)
 
 
@@ -117,6 +138,9 @@ def main(argv=None) -> int:
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=20)
+    dp = sub.add_parser("dispatches")
+    dp.add_argument("csv")
+    dp.add_argument("--kernel", required=True)
     c = sub.add_parser("counters")
     c.add_argument("fetch")
     c.add_argument("write")
@@ -133,6 +157,9 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats(a.csv, a.top))
+        return 0
+    if a.cmd == "dispatches":
+        print(dispatches(a.csv, a.kernel))
         return 0
     if a.cmd == "counters":
         print(counters_table(a.fetch, a.write, a.calib_mib, a.top))
