@@ -339,7 +339,9 @@ am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets,
  * Rounds in parallel: every vertex keeps its cheapest edge, an edge cheapest
  * at both ends claims the vertices of all triangles around it, and an edge
  * holding all its claims collapses if its ends share exactly two neighbours
- * and no surviving triangle turns by more than about 78 degrees.  Rounds stop
+ * and no surviving triangle turns by more than about 78 degrees; claims
+ * repeat three times a round among edges whose neighbourhoods no collapse
+ * of that round has touched.  Rounds stop
  * at target_tris live triangles (the last round's collapses are rationed, so
  * the count ends at the target or one below it: a collapse removes two),
  * when nothing collapses, or after max_rounds (0: 256; at most 4096).

@@ -13,7 +13,11 @@
 //      the triangles around a and b (atomic minimum of its key);
 //   4. an edge that holds all its claims owns that neighbourhood: it checks
 //      again that it is collapsible, takes a ticket from the round's budget,
-//      and collapses b into a at v.
+//      collapses b into a at v, and locks the neighbourhood;
+//   5. steps 3-4 repeat (kClaimPasses in all) among the candidates whose
+//      neighbourhoods hold no locked vertex: a vertex that is not locked has
+//      the same triangles, position and quadric as at the start of the round,
+//      so its adjacency and edge keys are still exact.
 // Neighbourhoods of committed collapses are disjoint, so their updates do not
 // race.  Vertices flagged as boundary never move.  Rounds repeat until the
 // live triangle count reaches the target, nothing collapses, or max_rounds.
@@ -153,6 +157,11 @@ __global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long lon
         p[i] = v;
 }
 
+__global__ void k_fill_uchar(unsigned char *p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 __global__ void k_fill_int(int *p, long long n, int v) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = v;
@@ -250,9 +259,12 @@ __device__ void for_ring(const int *tri, const int *adj_off, const int *adj, int
     }
 }
 
+constexpr int kClaimPasses = 3;
+
 __global__ void k_edge_claim(const int *tri, const unsigned char *tlive, long long T, const double *pos,
                              const double *Q, const unsigned char *boundary, const unsigned long long *vmin,
-                             const int *adj_off, const int *adj, unsigned long long *claim) {
+                             const int *adj_off, const int *adj, const unsigned char *lock,
+                             unsigned long long *claim) {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < T * 3;
          e += (long long)gridDim.x * blockDim.x) {
         const long long t = e / 3;
@@ -264,6 +276,11 @@ __global__ void k_edge_claim(const int *tri, const unsigned char *tlive, long lo
         double v[3];
         const unsigned long long key = edge_key(edge_cost(pos, Q, a, b, v), e);
         if (vmin[a] != key || vmin[b] != key) continue;
+        bool free = true;
+        auto unlocked = [&](int w) { free = free && !lock[w]; };
+        for_ring(tri, adj_off, adj, a, unlocked);
+        for_ring(tri, adj_off, adj, b, unlocked);
+        if (!free) continue;
         auto mark = [&](int w) { atomicMin(&claim[w], key); };
         for_ring(tri, adj_off, adj, a, mark);
         for_ring(tri, adj_off, adj, b, mark);
@@ -273,7 +290,7 @@ __global__ void k_edge_claim(const int *tri, const unsigned char *tlive, long lo
 __global__ void k_edge_collapse(int *tri, unsigned char *tlive, long long T, double *pos, double *Q,
                                 const unsigned char *boundary, const unsigned long long *vmin, const int *adj_off,
                                 const int *adj, const unsigned long long *claim, int *rep,
-                                unsigned long long *tickets, unsigned long long budget,
+                                unsigned char *lock, unsigned long long *tickets, unsigned long long budget,
                                 unsigned long long *removed) {
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < T * 3;
          e += (long long)gridDim.x * blockDim.x) {
@@ -287,12 +304,16 @@ __global__ void k_edge_collapse(int *tri, unsigned char *tlive, long long T, dou
         const unsigned long long key = edge_key(edge_cost(pos, Q, a, b, v), e);
         if (vmin[a] != key || vmin[b] != key) continue;
         bool own = true;
-        auto check = [&](int w) { own = own && claim[w] == key; };
+        auto check = [&](int w) { own = own && claim[w] == key && !lock[w]; };
         for_ring(tri, adj_off, adj, a, check);
         for_ring(tri, adj_off, adj, b, check);
         if (!own) continue;
         if (!edge_valid(tri, adj_off, adj, pos, a, b, v)) continue;
         if (atomicAdd(tickets, 1ull) >= budget) continue;
+        // lock the neighbourhood for the round's later passes
+        auto take = [&](int w) { lock[w] = 1; };
+        for_ring(tri, adj_off, adj, a, take);
+        for_ring(tri, adj_off, adj, b, take);
         // collapse b into a at v (the neighbourhood is this edge's alone)
         pos[a * 3] = v[0];
         pos[a * 3 + 1] = v[1];
@@ -373,14 +394,14 @@ size_t qecd_scratch_bytes(long long V, long long T) {
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, s2, (int *)nullptr, (int *)nullptr, (int)(T > V ? T : V));
     if (s2 > scan) scan = s2;
     const size_t v = (size_t)V + 1, t = (size_t)T;
-    // 18 carved arrays, each padded to 256 bytes; 160 B per vertex, 40 per triangle
-    return 256 * 32 + v * 160 + t * 40 + scan;
+    // 19 carved arrays, each padded to 256 bytes; 161 B per vertex, 40 per triangle
+    return 256 * 32 + v * 161 + t * 40 + scan;
 }
 
 struct QecdScratch {
     double *pos, *Q;
     int *rep, *tri, *cnt, *off, *cur, *adj, *tflag, *tidx, *used, *vidx;
-    unsigned char *tlive;
+    unsigned char *tlive, *lock;
     unsigned long long *vmin, *claim, *ctr;   // ctr: [0] tickets, [1] removed, [2] bad input
     void *scan;
     size_t scan_bytes;
@@ -407,6 +428,7 @@ static QecdScratch carve(void *base, long long V, long long T, size_t scan_bytes
     s.vidx = (int *)take(sizeof(int) * V);
     s.tri = (int *)take(sizeof(int) * 3 * T);
     s.tlive = (unsigned char *)take(T);
+    s.lock = (unsigned char *)take(V);
     s.adj = (int *)take(sizeof(int) * 3 * T);
     s.tflag = (int *)take(sizeof(int) * T);
     s.tidx = (int *)take(sizeof(int) * T);
@@ -453,15 +475,19 @@ hipError_t run_qecd(const double *vin, long long V, const long long *tri_in, lon
         hipLaunchKernelGGL(k_adj_fill, dim3(qblocks(T)), dim3(256), 0, st, s.tri, s.tlive, T, s.off, s.cur, s.adj);
         // costs, local minima, claims, collapses
         hipLaunchKernelGGL(k_fill_u64, dim3(qblocks(V)), dim3(256), 0, st, s.vmin, V, ~0ull);
-        hipLaunchKernelGGL(k_fill_u64, dim3(qblocks(V)), dim3(256), 0, st, s.claim, V, ~0ull);
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, s.ctr, 2, 0ull);
+        hipLaunchKernelGGL(k_fill_uchar, dim3(qblocks(V)), dim3(256), 0, st, s.lock, V);
         hipLaunchKernelGGL(k_edge_min, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos, s.Q,
                            boundary, s.off, s.adj, s.vmin);
-        hipLaunchKernelGGL(k_edge_claim, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos, s.Q,
-                           boundary, s.vmin, s.off, s.adj, s.claim);
         const unsigned long long budget = (unsigned long long)((live - target_tris + 1) / 2);
-        hipLaunchKernelGGL(k_edge_collapse, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos, s.Q,
-                           boundary, s.vmin, s.off, s.adj, s.claim, s.rep, s.ctr, budget, s.ctr + 1);
+        for (int pass = 0; pass < kClaimPasses; ++pass) {
+            hipLaunchKernelGGL(k_fill_u64, dim3(qblocks(V)), dim3(256), 0, st, s.claim, V, ~0ull);
+            hipLaunchKernelGGL(k_edge_claim, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos,
+                               s.Q, boundary, s.vmin, s.off, s.adj, s.lock, s.claim);
+            hipLaunchKernelGGL(k_edge_collapse, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos,
+                               s.Q, boundary, s.vmin, s.off, s.adj, s.claim, s.rep, s.lock, s.ctr, budget,
+                               s.ctr + 1);
+        }
         e = hipMemcpyAsync(h, s.ctr, sizeof(h), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(st);
