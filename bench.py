@@ -312,9 +312,11 @@ def ensemble_form(B, dev, steps):
                         "(untrained), 128 rays from the centres"}
 
 
-def c4_forms(B, dev, steps, max_cells):
+def c4_forms(B, dev, steps, max_cells, scorer=None):
     """The 64-shape decoder batch: one batched march (all shapes in one
-    frontier, chain tiles autotuned on it) against one march per shape."""
+    frontier, chain tiles autotuned on it) against one march per shape; with
+    a scorer, also the batched march with the split-BF16 chain and learned
+    proposals together, checked against the plain batched cell set."""
     import torch
     from am_workloads import nets, seeds
     sb = nets.c4_batch()
@@ -339,7 +341,40 @@ def c4_forms(B, dev, steps, max_cells):
         st = batched()
     torch.cuda.synchronize()
     t_b = (time.perf_counter() - t0) / steps
-    counts = np.bincount(ctx.fetch()["shape"].cpu().numpy(), minlength=S)
+    plain_out = ctx.fetch()
+    counts = np.bincount(plain_out["shape"].cpu().numpy(), minlength=S)
+    plain_digest = cell_set_digest(plain_out)
+    plain_verts = ctx.fetch(sorted=True)["verts"] if scorer is not None else None
+    combined = None
+    if scorer is not None:
+        ctx.prop_set(scorer, k=16, rho=6.0)
+
+        def batched_lb():
+            ctx.seed_rays(o, d, shape_id=sh)
+            # certified at 2e-6: the certificate's error constant was calibrated on narrower nets
+            return ctx.march(max_cells=max_cells, time_kernels=True, precision=1, propose=1, vertex_tol=2e-6)
+
+        batched_lb()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st_c = batched_lb()
+        torch.cuda.synchronize()
+        t_c = (time.perf_counter() - t0) / steps
+        assert st_c["faces"] == st["faces"], "learned + split-BF16 batched march changed the face count"
+        dg = cell_set_digest(ctx.fetch())
+        gv = ctx.fetch(sorted=True)["verts"]
+        verr = ((gv - plain_verts).abs().amax(dim=1) / plain_verts.abs().amax(dim=1).clamp(min=1.0)).max()
+        combined = {"faces_per_s": round(st_c["faces"] / t_c, 1), "ms_per_step": round(t_c * 1e3, 3),
+                    "faces": st_c["faces"], "cell_set_digest": dg, "exact_cell_set_match": dg == plain_digest,
+                    "vs_plain_batched": round(t_b / t_c, 4),
+                    "precision": "split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and "
+                                 "vertex solves; uncertified cells redone in FP64",
+                    "proposals": "top-16 lines by the trained scorer clipped before the every-line pass",
+                    "vertex_tol": 2e-6,
+                    "max_vertex_rel_err_vs_fp64": float(verr.item()),
+                    "escalated_cells": st_c["escalated"],
+                    "accept_rate": round(st_c["prop_accepted"] / max(1, st_c["prop_cells"]), 4)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     faces_single = 0
@@ -353,12 +388,15 @@ def c4_forms(B, dev, steps, max_cells):
     ctx.close()
     desc = ("64 shapes of one decoder [x; z] (3+256) -> [512]x8 -> 1 with [x; z] re-entering layer 4, "
             "0.01*MLP + |x|_1 - r_i, radii 0.008..0.35 geometric, 16 rays per shape")
-    return {"c4_batched": {"faces_per_s": round(st["faces"] / t_b, 1), "ms_per_step": round(t_b * 1e3, 3),
-                           "faces": st["faces"], "march_steps": st["steps"],
+    out = {"c4_batched": {"faces_per_s": round(st["faces"] / t_b, 1), "ms_per_step": round(t_b * 1e3, 3),
+                           "faces": st["faces"], "march_steps": st["steps"], "cell_set_digest": plain_digest,
                            "faces_per_shape_min_max": [int(counts.min()), int(counts.max())],
                            "chain_groups_tuned": groups, "workload": desc},
             "c4_per_shape": {"faces_per_s": round(faces_single / t_s, 1), "ms_per_step": round(t_s * 1e3, 3),
                              "faces": faces_single, "note": "one march per shape, same context, one pass"}}
+    if combined is not None:
+        out["c4_learned_bf16"] = combined
+    return out
 
 
 def chain_sweep(B, name, counts, groups, reps=10):
@@ -401,11 +439,12 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
                     default="seeding,mesh,pivot,bf16,distance,learned,learned_bf16,c3,c3_pivot,c3_bf16,c3_learned,"
-                            "c3_learned_bf16,ensemble,c4,c5,c5_learned",
+                            "c3_learned_bf16,ensemble,c4,c4_learned_bf16,c5,c5_learned",
                     help="other forms to time on the same net (seeding, mesh, pivot, bf16, distance, learned, "
                          "learned_bf16), on "
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
-                         "batch (c4); empty for none")
+                         "batch (c4; c4_learned_bf16: with the split-BF16 chain and learned proposals "
+                         "together); empty for none")
     ap.add_argument("--graph-steps", type=int, default=8,
                     help="device-driven marching steps per counter read for the plain form (also timed as "
                          "graph replays); 0: host-driven steps")
@@ -596,10 +635,13 @@ def main(argv=None):
         forms["ensemble_4x_d4w32"] = ensemble_form(B, dev, a.steps)
         print(f"[bench] ensemble: {forms['ensemble_4x_d4w32']['ms_per_step']:.2f} ms/step", file=sys.stderr,
               flush=True)
-    if "c4" in forms_req:
-        forms.update(c4_forms(B, dev, max(1, min(a.steps, 2)), a.max_cells))
+    if "c4" in forms_req or "c4_learned_bf16" in forms_req:
+        forms.update(c4_forms(B, dev, max(1, min(a.steps, 2)), a.max_cells,
+                              scorer if "c4_learned_bf16" in forms_req else None))
         print(f"[bench] c4: {forms['c4_batched']['ms_per_step']:.1f} ms batched, "
-              f"{forms['c4_per_shape']['ms_per_step']:.1f} ms per-shape", file=sys.stderr, flush=True)
+              f"{forms['c4_per_shape']['ms_per_step']:.1f} ms per-shape"
+              + (f", {forms['c4_learned_bf16']['ms_per_step']:.1f} ms learned + split-BF16"
+                 if "c4_learned_bf16" in forms else ""), file=sys.stderr, flush=True)
     if train_info:
         forms["scorer_training"] = train_info
     forms["chain_tiles_tuned"] = {k: v for k, v in chain_tiles.items()}

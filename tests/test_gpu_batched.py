@@ -120,3 +120,38 @@ def test_wide_decoder_batch_equals_single_shape_marches(binding):
         total += one.n_faces
     assert st["faces"] == total
     ctx.close()
+
+
+@pytest.mark.parametrize("propose", [2, 1], ids=["distance", "scorer"])
+def test_wide_decoder_batch_bf16_with_proposals_equals_plain(binding, propose):
+    """All three growth patterns at once on the decoder batch's first 12
+    shapes: one batched march with the split-BF16 chain and proposed clip
+    lines (ordered by distance, or by an untrained scorer: proposals are
+    always checked, so any scorer gives the exact face set) against the
+    plain FP64 batched march.  Cells, cycles and adjacency exact; vertices
+    within the precision form's 1e-5.  The certificate's error constant was
+    calibrated on narrower nets; with this decoder's fan-in (up to 771 over
+    nine layers) the default certificate (1e-5) let a vertex 2.5e-5 off
+    through, so the march certifies at vertex_tol = 2e-6."""
+    from gpu_common import compare_meshes_fast
+    from paper_2106_10031_amd.learn import init_params
+    sb = nets.c4_batch()
+    keep = 12
+    o1, d1 = seeds.centre_rays(np.zeros((1, 3)), 16)
+    o = np.tile(o1, (keep, 1)); d = np.tile(d1, (keep, 1))
+    sh = np.repeat(np.arange(keep, dtype=np.int32), len(o1))
+    say("c4 batch of", keep, "shapes, bf16 + proposals", propose)
+    ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
+    ctx.seed_rays(o, d, shape_id=sh)
+    st0 = ctx.march(max_cells=1 << 20)
+    ref = fetch_host(ctx)
+    if propose == 1:
+        ctx.prop_set(init_params(7).astype(np.float32), k=16, rho=6.0)
+    ctx.seed_rays(o, d, shape_id=sh)
+    st = ctx.march(max_cells=1 << 20, precision=1, propose=propose, vertex_tol=2e-6)
+    got = fetch_host(ctx)
+    assert st["faces"] == st0["faces"]
+    compare_meshes_fast(ref, got, vtol=1e-5)
+    assert st["prop_cells"] > 0
+    say("escalated", st["escalated"], "proposed", st["prop_cells"], "accepted", st["prop_accepted"])
+    ctx.close()
