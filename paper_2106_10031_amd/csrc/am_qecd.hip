@@ -21,6 +21,8 @@
 // Neighbourhoods of committed collapses are disjoint, so their updates do not
 // race.  Vertices flagged as boundary never move.  Rounds repeat until the
 // live triangle count reaches the target, nothing collapses, or max_rounds.
+// Whenever fewer than half the rows in use hold live triangles, the live ones
+// are compacted (in order) so that later rounds scan fewer rows.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -157,9 +159,9 @@ __global__ void k_fill_u64(unsigned long long *p, long long n, unsigned long lon
         p[i] = v;
 }
 
-__global__ void k_fill_uchar(unsigned char *p, long long n) {
+__global__ void k_fill_uchar(unsigned char *p, long long n, unsigned char v) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0;
+        p[i] = v;
 }
 
 __global__ void k_fill_int(int *p, long long n, int v) {
@@ -369,6 +371,18 @@ __global__ void k_compact(const int *tri, const unsigned char *tlive, long long 
     }
 }
 
+// Stable compaction of the live triangles: triangle t goes to row tidx[t].
+__global__ void k_tri_compact(const int *tri, const unsigned char *tlive, long long T, const int *tidx, int *tri2) {
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < T;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (!tlive[t]) continue;
+        const long long o = tidx[t];
+        tri2[o * 3] = tri[t * 3];
+        tri2[o * 3 + 1] = tri[t * 3 + 1];
+        tri2[o * 3 + 2] = tri[t * 3 + 2];
+    }
+}
+
 __global__ void k_tri_load(const long long *tri_in, long long T, long long V, int *tri, unsigned char *tlive,
                            unsigned long long *bad) {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < T;
@@ -394,13 +408,13 @@ size_t qecd_scratch_bytes(long long V, long long T) {
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, s2, (int *)nullptr, (int *)nullptr, (int)(T > V ? T : V));
     if (s2 > scan) scan = s2;
     const size_t v = (size_t)V + 1, t = (size_t)T;
-    // 19 carved arrays, each padded to 256 bytes; 161 B per vertex, 40 per triangle
-    return 256 * 32 + v * 161 + t * 40 + scan;
+    // 20 carved arrays, each padded to 256 bytes; 161 B per vertex, 52 per triangle
+    return 256 * 32 + v * 161 + t * 52 + scan;
 }
 
 struct QecdScratch {
     double *pos, *Q;
-    int *rep, *tri, *cnt, *off, *cur, *adj, *tflag, *tidx, *used, *vidx;
+    int *rep, *tri, *tri2, *cnt, *off, *cur, *adj, *tflag, *tidx, *used, *vidx;
     unsigned char *tlive, *lock;
     unsigned long long *vmin, *claim, *ctr;   // ctr: [0] tickets, [1] removed, [2] bad input
     void *scan;
@@ -427,6 +441,7 @@ static QecdScratch carve(void *base, long long V, long long T, size_t scan_bytes
     s.used = (int *)take(sizeof(int) * V);
     s.vidx = (int *)take(sizeof(int) * V);
     s.tri = (int *)take(sizeof(int) * 3 * T);
+    s.tri2 = (int *)take(sizeof(int) * 3 * T);
     s.tlive = (unsigned char *)take(T);
     s.lock = (unsigned char *)take(V);
     s.adj = (int *)take(sizeof(int) * 3 * T);
@@ -464,27 +479,52 @@ hipError_t run_qecd(const double *vin, long long V, const long long *tri_in, lon
     long long live = T - (long long)h[2];
     *bad_out = (long long)h[2];
     int rounds = 0;
+    long long Tc = T;   // rows of tri / tlive in use
     while (live > target_tris && rounds < max_rounds) {
+        if (live < Tc / 2) {
+            // drop dead triangles (stable), so that later rounds scan fewer rows
+            hipLaunchKernelGGL(k_tri_flags, dim3(qblocks(Tc)), dim3(256), 0, st, s.tlive, Tc, s.tflag);
+            size_t cb = s.scan_bytes;
+            e = hipcub::DeviceScan::ExclusiveSum(s.scan, cb, s.tflag, s.tidx, (int)Tc, st);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_tri_compact, dim3(qblocks(Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.tidx,
+                               s.tri2);
+            int last[2] = {0, 0};
+            e = hipMemcpyAsync(&last[0], s.tidx + Tc - 1, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return e;
+            e = hipMemcpyAsync(&last[1], s.tflag + Tc - 1, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return e;
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return e;
+            const long long n = (long long)last[0] + last[1];
+            if (n > 0) {
+                e = hipMemcpyAsync(s.tri, s.tri2, sizeof(int) * 3 * (size_t)n, hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(k_fill_uchar, dim3(qblocks(n)), dim3(256), 0, st, s.tlive, n, (unsigned char)1);
+            Tc = n;
+            live = n;
+        }
         // adjacency of the live triangles
         hipLaunchKernelGGL(k_fill_int, dim3(qblocks(V + 1)), dim3(256), 0, st, s.cnt, V + 1, 0);
         hipLaunchKernelGGL(k_fill_int, dim3(qblocks(V)), dim3(256), 0, st, s.cur, V, 0);
-        hipLaunchKernelGGL(k_adj_count, dim3(qblocks(T)), dim3(256), 0, st, s.tri, s.tlive, T, s.cnt);
+        hipLaunchKernelGGL(k_adj_count, dim3(qblocks(Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.cnt);
         size_t tb = s.scan_bytes;
         e = hipcub::DeviceScan::ExclusiveSum(s.scan, tb, s.cnt, s.off, (int)(V + 1), st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_adj_fill, dim3(qblocks(T)), dim3(256), 0, st, s.tri, s.tlive, T, s.off, s.cur, s.adj);
+        hipLaunchKernelGGL(k_adj_fill, dim3(qblocks(Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.off, s.cur, s.adj);
         // costs, local minima, claims, collapses
         hipLaunchKernelGGL(k_fill_u64, dim3(qblocks(V)), dim3(256), 0, st, s.vmin, V, ~0ull);
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, s.ctr, 2, 0ull);
-        hipLaunchKernelGGL(k_fill_uchar, dim3(qblocks(V)), dim3(256), 0, st, s.lock, V);
-        hipLaunchKernelGGL(k_edge_min, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos, s.Q,
+        hipLaunchKernelGGL(k_fill_uchar, dim3(qblocks(V)), dim3(256), 0, st, s.lock, V, (unsigned char)0);
+        hipLaunchKernelGGL(k_edge_min, dim3(qblocks(3 * Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos, s.Q,
                            boundary, s.off, s.adj, s.vmin);
         const unsigned long long budget = (unsigned long long)((live - target_tris + 1) / 2);
         for (int pass = 0; pass < kClaimPasses; ++pass) {
             hipLaunchKernelGGL(k_fill_u64, dim3(qblocks(V)), dim3(256), 0, st, s.claim, V, ~0ull);
-            hipLaunchKernelGGL(k_edge_claim, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos,
+            hipLaunchKernelGGL(k_edge_claim, dim3(qblocks(3 * Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos,
                                s.Q, boundary, s.vmin, s.off, s.adj, s.lock, s.claim);
-            hipLaunchKernelGGL(k_edge_collapse, dim3(qblocks(3 * T)), dim3(256), 0, st, s.tri, s.tlive, T, s.pos,
+            hipLaunchKernelGGL(k_edge_collapse, dim3(qblocks(3 * Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos,
                                s.Q, boundary, s.vmin, s.off, s.adj, s.claim, s.rep, s.lock, s.ctr, budget,
                                s.ctr + 1);
         }
@@ -498,26 +538,28 @@ hipError_t run_qecd(const double *vin, long long V, const long long *tri_in, lon
     }
     // compaction
     hipLaunchKernelGGL(k_fill_int, dim3(qblocks(V)), dim3(256), 0, st, s.used, V, 0);
-    hipLaunchKernelGGL(k_vert_used, dim3(qblocks(T)), dim3(256), 0, st, s.tri, s.tlive, T, s.used);
+    hipLaunchKernelGGL(k_vert_used, dim3(qblocks(Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.used);
     size_t tb = s.scan_bytes;
     e = hipcub::DeviceScan::ExclusiveSum(s.scan, tb, s.used, s.vidx, (int)V, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tri_flags, dim3(qblocks(T)), dim3(256), 0, st, s.tlive, T, s.tflag);
+    hipLaunchKernelGGL(k_tri_flags, dim3(qblocks(Tc)), dim3(256), 0, st, s.tlive, Tc, s.tflag);
     tb = s.scan_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(s.scan, tb, s.tflag, s.tidx, (int)T, st);
+    e = hipcub::DeviceScan::ExclusiveSum(s.scan, tb, s.tflag, s.tidx, (int)Tc, st);
     if (e != hipSuccess) return e;
-    long long VT = V > T ? V : T;
-    hipLaunchKernelGGL(k_compact, dim3(qblocks(VT)), dim3(256), 0, st, s.tri, s.tlive, T, s.tidx, s.used, s.vidx, V,
+    long long VT = V > Tc ? V : Tc;
+    hipLaunchKernelGGL(k_compact, dim3(qblocks(VT)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.tidx, s.used, s.vidx, V,
                        s.pos, tri_out, v_out);
     int tail[4] = {0, 0, 0, 0};
     e = hipMemcpyAsync(&tail[0], s.vidx + V - 1, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(&tail[1], s.used + V - 1, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(&tail[2], s.tidx + T - 1, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(&tail[3], s.tflag + T - 1, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
+    if (Tc > 0) {
+        e = hipMemcpyAsync(&tail[2], s.tidx + Tc - 1, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(&tail[3], s.tflag + Tc - 1, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return e;
+    }
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
     *V_out = (long long)tail[0] + tail[1];
