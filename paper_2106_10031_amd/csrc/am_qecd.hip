@@ -275,9 +275,12 @@ __global__ void k_edge_claim(const int *tri, const unsigned char *tlive, long lo
         const int a = tri[t * 3 + k], b = tri[t * 3 + (k + 1) % 3];
         if (a >= b) continue;
         if (boundary && (boundary[a] || boundary[b])) continue;
+        // a candidate's key (edge id in the low word) is the minimum at both ends
+        const unsigned long long va = vmin[a];
+        if ((unsigned)va != (unsigned)e || vmin[b] != va) continue;
         double v[3];
         const unsigned long long key = edge_key(edge_cost(pos, Q, a, b, v), e);
-        if (vmin[a] != key || vmin[b] != key) continue;
+        if (va != key) continue;
         bool free = true;
         auto unlocked = [&](int w) { free = free && !lock[w]; };
         for_ring(tri, adj_off, adj, a, unlocked);
@@ -302,9 +305,12 @@ __global__ void k_edge_collapse(int *tri, unsigned char *tlive, long long T, dou
         const int a = tri[t * 3 + k], b = tri[t * 3 + (k + 1) % 3];
         if (a >= b) continue;
         if (boundary && (boundary[a] || boundary[b])) continue;
+        // a candidate's key (edge id in the low word) is the minimum at both ends
+        const unsigned long long va = vmin[a];
+        if ((unsigned)va != (unsigned)e || vmin[b] != va) continue;
         double v[3];
         const unsigned long long key = edge_key(edge_cost(pos, Q, a, b, v), e);
-        if (vmin[a] != key || vmin[b] != key) continue;
+        if (va != key) continue;
         bool own = true;
         auto check = [&](int w) { own = own && claim[w] == key && !lock[w]; };
         for_ring(tri, adj_off, adj, a, check);
