@@ -354,7 +354,7 @@ am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets,
  * n_verts and n_tris rows): v_out, tri_out, compacted, vertex ids into v_out.
  * HOST out: n_verts_out, n_tris_out, rounds_out, n_bad (input triangles with
  * an id out of range or a repeated vertex, dropped).  Allocates its scratch
- * (about 160 B per vertex and 52 B per triangle) for the call; synchronises. */
+ * (about 165 B per vertex and 52 B per triangle) for the call; synchronises. */
 am_status am_simplify(am_ctx *ctx, int64_t n_verts, const double *vxyz, int64_t n_tris, const int64_t *tri,
                       const uint8_t *boundary, int64_t target_tris, int32_t max_rounds, double *v_out,
                       int64_t *tri_out, int64_t *n_verts_out, int64_t *n_tris_out, int32_t *rounds_out,

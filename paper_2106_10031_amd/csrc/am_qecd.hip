@@ -9,8 +9,9 @@
 //   1. vertex -> triangle adjacency of the live triangles (count, scan, fill);
 //   2. every collapsible edge (link condition, no flipped triangle) posts its
 //      cost key (cost bits, edge id) to both endpoints with an atomic minimum;
-//   3. an edge that is the minimum at both endpoints claims every vertex of
-//      the triangles around a and b (atomic minimum of its key);
+//   3. an edge that is the minimum at both endpoints (listed once, by its
+//      first end) claims every vertex of the triangles around a and b
+//      (atomic minimum of its key);
 //   4. an edge that holds all its claims owns that neighbourhood: it checks
 //      again that it is collapsible, takes a ticket from the round's budget,
 //      collapses b into a at v, and locks the neighbourhood;
@@ -243,6 +244,9 @@ __global__ void k_edge_min(const int *tri, const unsigned char *tlive, long long
         if (boundary && (boundary[a] || boundary[b])) continue;
         double v[3];
         const unsigned long long key = edge_key(edge_cost(pos, Q, a, b, v), e);
+        // minima only fall and keys are unique: a key above both current minima
+        // can never be the minimum at either end, so it needs no validity check
+        if (key > vmin[a] && key > vmin[b]) continue;
         // only collapsible edges compete, so an invalid cheapest edge cannot block a vertex
         if (!edge_valid(tri, adj_off, adj, pos, a, b, v)) continue;
         atomicMin(&vmin[a], key);
@@ -263,12 +267,34 @@ __device__ void for_ring(const int *tri, const int *adj_off, const int *adj, int
 
 constexpr int kClaimPasses = 3;
 
+// Candidates of the round: the edge e named by vertex a's minimum, when a is
+// the edge's first end and the edge is the minimum at its other end too.
+// Each vertex adds at most one edge, so the list holds at most V entries.
+__global__ void k_cand_list(const unsigned long long *vmin, long long V, const int *tri, long long T, int *cand,
+                            unsigned long long *n_cand) {
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V;
+         v += (long long)gridDim.x * blockDim.x) {
+        const unsigned long long key = vmin[v];
+        if (key == ~0ull) continue;
+        const long long e = (long long)(unsigned)key;
+        if (e >= 3 * T) continue;
+        const long long t = e / 3;
+        const int k = (int)(e - t * 3);
+        const int a = tri[t * 3 + k], b = tri[t * 3 + (k + 1) % 3];
+        if (a != v || vmin[b] != key) continue;
+        cand[atomicAdd(n_cand, 1ull)] = (int)e;
+    }
+}
+
 __global__ void k_edge_claim(const int *tri, const unsigned char *tlive, long long T, const double *pos,
                              const double *Q, const unsigned char *boundary, const unsigned long long *vmin,
-                             const int *adj_off, const int *adj, const unsigned char *lock,
-                             unsigned long long *claim) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < T * 3;
-         e += (long long)gridDim.x * blockDim.x) {
+                             const int *adj_off, const int *adj, const unsigned char *lock, const int *cand,
+                             const unsigned long long *n_cand, unsigned long long *claim) {
+    const long long nc = (long long)*n_cand;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nc;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long e = cand[i];
+        if (e >= 3 * T) continue;
         const long long t = e / 3;
         const int k = (int)(e - t * 3);
         if (!tlive[t]) continue;
@@ -295,10 +321,14 @@ __global__ void k_edge_claim(const int *tri, const unsigned char *tlive, long lo
 __global__ void k_edge_collapse(int *tri, unsigned char *tlive, long long T, double *pos, double *Q,
                                 const unsigned char *boundary, const unsigned long long *vmin, const int *adj_off,
                                 const int *adj, const unsigned long long *claim, int *rep,
-                                unsigned char *lock, unsigned long long *tickets, unsigned long long budget,
+                                unsigned char *lock, const int *cand, const unsigned long long *n_cand,
+                                unsigned long long *tickets, unsigned long long budget,
                                 unsigned long long *removed) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < T * 3;
-         e += (long long)gridDim.x * blockDim.x) {
+    const long long nc = (long long)*n_cand;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nc;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long e = cand[i];
+        if (e >= 3 * T) continue;
         const long long t = e / 3;
         const int k = (int)(e - t * 3);
         if (!tlive[t]) continue;
@@ -414,15 +444,15 @@ size_t qecd_scratch_bytes(long long V, long long T) {
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, s2, (int *)nullptr, (int *)nullptr, (int)(T > V ? T : V));
     if (s2 > scan) scan = s2;
     const size_t v = (size_t)V + 1, t = (size_t)T;
-    // 20 carved arrays, each padded to 256 bytes; 161 B per vertex, 52 per triangle
-    return 256 * 32 + v * 161 + t * 52 + scan;
+    // 21 carved arrays, each padded to 256 bytes; 165 B per vertex, 52 per triangle
+    return 256 * 32 + v * 165 + t * 52 + scan;
 }
 
 struct QecdScratch {
     double *pos, *Q;
-    int *rep, *tri, *tri2, *cnt, *off, *cur, *adj, *tflag, *tidx, *used, *vidx;
+    int *rep, *tri, *tri2, *cand, *cnt, *off, *cur, *adj, *tflag, *tidx, *used, *vidx;
     unsigned char *tlive, *lock;
-    unsigned long long *vmin, *claim, *ctr;   // ctr: [0] tickets, [1] removed, [2] bad input
+    unsigned long long *vmin, *claim, *ctr;   // ctr: [0] tickets, [1] removed, [2] bad input, [3] candidates
     void *scan;
     size_t scan_bytes;
 };
@@ -439,6 +469,7 @@ static QecdScratch carve(void *base, long long V, long long T, size_t scan_bytes
     s.pos = (double *)take(sizeof(double) * 3 * V);
     s.Q = (double *)take(sizeof(double) * 10 * V);
     s.rep = (int *)take(sizeof(int) * V);
+    s.cand = (int *)take(sizeof(int) * V);
     s.vmin = (unsigned long long *)take(8 * V);
     s.claim = (unsigned long long *)take(8 * V);
     s.cnt = (int *)take(sizeof(int) * (V + 1));
@@ -525,14 +556,17 @@ hipError_t run_qecd(const double *vin, long long V, const long long *tri_in, lon
         hipLaunchKernelGGL(k_fill_uchar, dim3(qblocks(V)), dim3(256), 0, st, s.lock, V, (unsigned char)0);
         hipLaunchKernelGGL(k_edge_min, dim3(qblocks(3 * Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos, s.Q,
                            boundary, s.off, s.adj, s.vmin);
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, s.ctr + 3, 1, 0ull);
+        hipLaunchKernelGGL(k_cand_list, dim3(qblocks(V)), dim3(256), 0, st, s.vmin, V, s.tri, Tc, s.cand,
+                           s.ctr + 3);
         const unsigned long long budget = (unsigned long long)((live - target_tris + 1) / 2);
         for (int pass = 0; pass < kClaimPasses; ++pass) {
             hipLaunchKernelGGL(k_fill_u64, dim3(qblocks(V)), dim3(256), 0, st, s.claim, V, ~0ull);
-            hipLaunchKernelGGL(k_edge_claim, dim3(qblocks(3 * Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos,
-                               s.Q, boundary, s.vmin, s.off, s.adj, s.lock, s.claim);
-            hipLaunchKernelGGL(k_edge_collapse, dim3(qblocks(3 * Tc)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos,
-                               s.Q, boundary, s.vmin, s.off, s.adj, s.claim, s.rep, s.lock, s.ctr, budget,
-                               s.ctr + 1);
+            hipLaunchKernelGGL(k_edge_claim, dim3(qblocks(V)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos, s.Q,
+                               boundary, s.vmin, s.off, s.adj, s.lock, s.cand, s.ctr + 3, s.claim);
+            hipLaunchKernelGGL(k_edge_collapse, dim3(qblocks(V)), dim3(256), 0, st, s.tri, s.tlive, Tc, s.pos,
+                               s.Q, boundary, s.vmin, s.off, s.adj, s.claim, s.rep, s.lock, s.cand, s.ctr + 3,
+                               s.ctr, budget, s.ctr + 1);
         }
         e = hipMemcpyAsync(h, s.ctr, sizeof(h), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return e;
