@@ -37,7 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def short_name(name: str) -> str:
-    n = name.split("(")[0]
+    n = name.replace("(anonymous namespace)::", "").split("(")[0]
     if n.startswith("void "):
         n = n[5:]
     if "rocprim" in n:
