@@ -278,7 +278,19 @@ uint64_t splitmix64(uint64_t &s) {
     return z ^ (z >> 31);
 }
 
+// The captured steps hold device addresses and a copy of the net by value:
+// every buffer or net change must drop them before anything is freed.
+void drop_graph(am_ctx *c) {
+    if (c->graph_exec) {
+        if (c->cap_stream) (void)hipStreamSynchronize(c->cap_stream);
+        (void)hipGraphExecDestroy(c->graph_exec);
+    }
+    c->graph_exec = nullptr;
+    c->graph_key.clear();
+}
+
 void free_march(am_ctx *c) {
+    drop_graph(c);
     dfree(c->d_codes);
     dfree(c->d_am);
     dfree(c->d_shape);
@@ -322,6 +334,7 @@ void free_march(am_ctx *c) {
 }
 
 void free_net(am_ctx *c) {
+    drop_graph(c);
     dfree(c->d_weights);
     dfree(c->d_wfrag);
     dfree(c->d_wcol);
@@ -446,8 +459,9 @@ void am_destroy(am_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    drop_graph(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    ctx->cap_stream = nullptr;
     free_march(ctx);
     free_net(ctx);
     dfree(ctx->d_prop_w);

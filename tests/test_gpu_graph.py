@@ -156,3 +156,30 @@ def test_timed_device_steps_c2_equal_host_driven(binding):
     assert 0 < st["max_frontier"] and 0 < host["max_frontier"]
     compare_meshes_fast(ref, fetch_host(ctx), vtol=0.0)
     ctx.close()
+
+
+def test_graph_march_after_reloading_the_net(binding):
+    """A context that replayed captured steps for one net and then loads
+    another (same or different sizes) must not replay the old graph: its
+    nodes hold the freed buffers and the old net by value.  Every march is
+    compared with a fresh context's march of the same net."""
+    net_a = NETS["c1"]()
+    net_b = NETS["sphere_like_2x24"]()
+    net_c = nets.random_sphere_like([24, 24], seed=9, radius=0.5, scale=0.4)
+    o, d = seeds.random_rays(16, seed=4)
+    refs = {}
+    for name, net in (("a", net_a), ("b", net_b), ("c", net_c)):
+        fresh = binding.Context(0).load_net(net)
+        fresh.seed_rays(o, d)
+        fresh.march(graph_steps=4)
+        refs[name] = fetch_host(fresh)
+        fresh.close()
+    say("graph march after reload")
+    ctx = binding.Context(0)
+    for name, net in (("a", net_a), ("b", net_b), ("c", net_c), ("a", net_a)):
+        ctx.load_net(net)
+        ctx.seed_rays(o, d)
+        st = ctx.march(graph_steps=4)
+        assert st["faces"] == refs[name].n_faces
+        compare_meshes_fast(refs[name], fetch_host(ctx), vtol=0.0)
+    ctx.close()
