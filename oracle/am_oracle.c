@@ -47,6 +47,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define TAU (1.0 / 1099511627776.0) /* 2^-40 */
 
@@ -373,6 +376,10 @@ int orc_face_from_rows(const orc_net *net, const uint64_t *code, int32_t argmax,
         double ax = P[i].a - P[0].a, ay = P[i].b - P[0].b;
         double bx = P[i + 1].a - P[0].a, by = P[i + 1].b - P[0].b;
         A2 += ax * by - bx * ay;
+    }
+    if (ORC_MUTATE == 15) { /* the absolute shoelace about the frame origin */
+        A2 = 0.0;
+        for (int i = 0; i < m; i++) A2 += P[i].a * P[(i + 1) % m].b - P[(i + 1) % m].a * P[i].b;
     }
     *area = 0.5 * A2;
     if (!(A2 > 0.0)) { *flags |= ORC_FACE_EMPTY; return 0; }
@@ -881,6 +888,135 @@ orc_result *orc_march(const orc_net *net, const uint64_t *seed_codes, const int3
     free(rows);
     free(ncode);
     return R;
+}
+
+/* The same march, with the faces of each batch of active cells computed in
+ * parallel.  Algorithm 1 pops the active cells one at a time; the face of a
+ * cell depends only on its code, and every cell of the batch [lo, hi) is
+ * already in the list when the batch starts, so solving the batch first and
+ * then appending faces and neighbours in cell order (as the one-at-a-time
+ * loop does) gives the same cell ids, faces and adjacency.  Built without
+ * OpenMP the pragmas are ignored and it runs on one thread.  batch <= 0 means
+ * 16384 cells. */
+orc_result *orc_march_batched(const orc_net *net, const uint64_t *seed_codes, const int32_t *seed_argmax,
+                              int64_t n_seeds, int64_t max_cells, int64_t batch) {
+    if (batch <= 0) batch = 16384;
+    orc_result *R = (orc_result *)calloc(1, sizeof(orc_result));
+    R->W = orc_code_words(net);
+    R->N = n_hidden(net);
+    R->M = n_heads(net);
+    R->cap_cells = 1024;
+    R->codes = (uint64_t *)malloc(sizeof(uint64_t) * R->cap_cells * R->W);
+    R->argmax = (int32_t *)malloc(sizeof(int32_t) * R->cap_cells);
+    R->m = (int32_t *)malloc(sizeof(int32_t) * R->cap_cells);
+    R->fflags = (int32_t *)malloc(sizeof(int32_t) * R->cap_cells);
+    R->voff = (int64_t *)malloc(sizeof(int64_t) * R->cap_cells);
+    R->cap_v = 4096;
+    R->ids = (int32_t *)malloc(sizeof(int32_t) * R->cap_v);
+    R->verts = (double *)malloc(sizeof(double) * 3 * R->cap_v);
+    R->nbr = (int64_t *)malloc(sizeof(int64_t) * R->cap_v);
+    R->hcap = 4096;
+    R->htab = (int64_t *)malloc(sizeof(int64_t) * R->hcap);
+    for (int64_t k = 0; k < R->hcap; k++) R->htab[k] = -1;
+    R->n_seeds_in = n_seeds;
+    for (int64_t s = 0; s < n_seeds; s++) {
+        int fresh;
+        find_or_add(R, seed_codes + s * R->W, seed_argmax[s], &fresh);
+        if (!fresh) R->n_seed_dup++;
+    }
+    int64_t n_seed_cells = R->n_cells;
+    int32_t *bm = (int32_t *)malloc(sizeof(int32_t) * batch);
+    int32_t *bfl = (int32_t *)malloc(sizeof(int32_t) * batch);
+    int32_t *bids = (int32_t *)malloc(sizeof(int32_t) * batch * ORC_MAX_M);
+    double *bverts = (double *)malloc(sizeof(double) * 3 * batch * ORC_MAX_M);
+    uint64_t *ncode = (uint64_t *)malloc(8 * R->W);
+    int64_t lo = 0;
+    while (lo < R->n_cells) {
+        int64_t hi = R->n_cells;
+        if (hi - lo > batch) hi = lo + batch;
+        if (max_cells > 0 && hi > max_cells) hi = max_cells;
+        if (lo >= hi) break;
+        /* faces of the batch: read-only access to R->codes (nothing is
+         * inserted until the batch is solved) */
+#pragma omp parallel
+        {
+            double *rows = (double *)malloc(sizeof(double) * 4 * (R->N + R->M));
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t c = lo; c < hi; c++) {
+                double area;
+                int64_t b = c - lo;
+                orc_chain(net, R->codes + c * R->W, rows);
+                bm[b] = orc_face_from_rows(net, R->codes + c * R->W, R->argmax[c], rows, ORC_MAX_M,
+                                           bids + b * ORC_MAX_M, bverts + 3 * b * ORC_MAX_M, &area, &bfl[b]);
+            }
+            free(rows);
+        }
+        /* append faces and neighbours in cell order */
+        for (int64_t c = lo; c < hi; c++) {
+            int64_t b = c - lo;
+            int m = bm[b];
+            R->fflags[c] = bfl[b];
+            if (m == 0) {
+                if (c < n_seed_cells) R->n_seed_empty++;
+                else R->n_degenerate++;
+                continue;
+            }
+            if (bfl[b]) R->n_degenerate++;
+            while (R->n_v + m > R->cap_v) {
+                R->cap_v *= 2;
+                R->ids = (int32_t *)realloc(R->ids, sizeof(int32_t) * R->cap_v);
+                R->verts = (double *)realloc(R->verts, sizeof(double) * 3 * R->cap_v);
+                R->nbr = (int64_t *)realloc(R->nbr, sizeof(int64_t) * R->cap_v);
+            }
+            int64_t off = R->n_v;
+            R->voff[c] = off;
+            R->m[c] = m;
+            R->n_v += m;
+            for (int i = 0; i < m; i++) {
+                int id = bids[b * ORC_MAX_M + i];
+                R->ids[off + i] = id;
+                memcpy(R->verts + 3 * (off + i), bverts + 3 * (b * ORC_MAX_M + i), sizeof(double) * 3);
+                if (id < 0) { R->nbr[off + i] = -1; continue; }
+                memcpy(ncode, R->codes + c * R->W, 8 * R->W);
+                int32_t nam = R->argmax[c];
+                if (id < R->N) ncode[id >> 6] ^= (uint64_t)1 << (id & 63);
+                else nam = id - R->N;
+                int fresh;
+                R->nbr[off + i] = find_or_add(R, ncode, nam, &fresh);
+            }
+        }
+        lo = hi;
+    }
+    free(bm); free(bfl); free(bids); free(bverts); free(ncode);
+    return R;
+}
+
+/* Faces of n given cells (orc_face for each), in parallel when built with
+ * OpenMP.  ids [n][max_m], verts [n][max_m][3], m [n], flags [n]. */
+void orc_faces_batched(const orc_net *net, const uint64_t *codes, const int32_t *argmax, int64_t n, int max_m,
+                       int32_t *m, int32_t *ids, double *verts, int32_t *flags) {
+    int W = orc_code_words(net), NM = n_hidden(net) + n_heads(net);
+#pragma omp parallel
+    {
+        double *rows = (double *)malloc(sizeof(double) * 4 * NM);
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t i = 0; i < n; i++) {
+            double area;
+            orc_chain(net, codes + i * W, rows);
+            m[i] = orc_face_from_rows(net, codes + i * W, argmax ? argmax[i] : 0, rows, max_m,
+                                      ids + i * max_m, verts + 3 * i * max_m, &area, &flags[i]);
+        }
+        free(rows);
+    }
+}
+
+/* Threads the batched routines use (1 when built without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void orc_result_free(orc_result *R) {

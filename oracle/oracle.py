@@ -25,9 +25,29 @@ def build(force: bool = True, out: str = LIB_PATH, mutate: int = 0) -> str:
     """
     if force or not os.path.exists(out):
         tmp = out + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wno-unused-function"]
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
         if mutate:
             cmd.append(f"-DORC_MUTATE={int(mutate)}")
+        subprocess.check_call(cmd + [SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+OMP_LIB_PATH = os.path.join(HERE, "liborc_omp.so")
+
+
+def build_omp(force: bool = True, out: str = OMP_LIB_PATH) -> str:
+    """The same source built with OpenMP (-O3) for the batched routines.
+
+    Contraction and reassociation stay off (no -march, -ffp-contract=off), so
+    every face is computed with the same IEEE operations as in the -O2 build
+    and the two give identical meshes (checked by a test); only the batch
+    driver runs on several threads.
+    """
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall",
+               "-Wno-unused-function"]
         subprocess.check_call(cmd + [SRC, "-o", tmp, "-lm"])
         os.replace(tmp, out)
     return out
@@ -48,9 +68,12 @@ def lib(path: str = LIB_PATH):
     L = _libs.get(path)
     if L is None:
         if not os.path.exists(path):
-            if path != LIB_PATH:
+            if path == LIB_PATH:
+                build()
+            elif path == OMP_LIB_PATH:
+                build_omp()
+            else:
                 raise FileNotFoundError(path)
-            build()
         L = C.CDLL(path)
         P = C.POINTER
         L.orc_code_words.argtypes = [P(_Net)]
@@ -75,6 +98,13 @@ def lib(path: str = LIB_PATH):
         L.orc_seed_st.restype = C.c_int
         L.orc_march.argtypes = [P(_Net), P(C.c_uint64), P(C.c_int32), C.c_int64, C.c_int64]
         L.orc_march.restype = C.c_void_p
+        L.orc_march_batched.argtypes = [P(_Net), P(C.c_uint64), P(C.c_int32), C.c_int64, C.c_int64, C.c_int64]
+        L.orc_march_batched.restype = C.c_void_p
+        L.orc_faces_batched.argtypes = [P(_Net), P(C.c_uint64), P(C.c_int32), C.c_int64, C.c_int,
+                                        P(C.c_int32), P(C.c_int32), P(C.c_double), P(C.c_int32)]
+        L.orc_faces_batched.restype = None
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = C.c_int
         L.orc_result_free.argtypes = [C.c_void_p]
         L.orc_result_counts.argtypes = [C.c_void_p, P(C.c_int64)]
         L.orc_result_fetch.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_double),
@@ -197,15 +227,42 @@ class OracleNet:
         return (np.asarray(codes, np.uint64).reshape(-1, W), np.asarray(ams, np.int32),
                 np.asarray(pts, np.float64).reshape(-1, 3), np.asarray(sts, np.int32))
 
-    def march(self, seed_codes, seed_argmax=None, max_cells=0):
+    def threads(self):
+        """Threads of the batched routines in the loaded build."""
+        return int(self._L.orc_threads())
+
+    def faces_batched(self, codes, argmax=None, max_m=128):
+        """orc_face of every given cell (parallel in the OpenMP build):
+        (m [n], ids [n, max_m], verts [n, max_m, 3], flags [n])."""
+        codes = np.ascontiguousarray(np.asarray(codes, np.uint64).reshape(-1, self.W))
+        n = codes.shape[0]
+        am = None if argmax is None else np.ascontiguousarray(argmax, np.int32)
+        m = np.zeros(n, np.int32)
+        ids = np.zeros((n, max_m), np.int32)
+        verts = np.zeros((n, max_m, 3))
+        flags = np.zeros(n, np.int32)
+        self._L.orc_faces_batched(C.byref(self.s), _ptr(codes, C.c_uint64),
+                                  None if am is None else _ptr(am, C.c_int32), n, int(max_m),
+                                  _ptr(m, C.c_int32), _ptr(ids, C.c_int32), _ptr(verts, C.c_double),
+                                  _ptr(flags, C.c_int32))
+        return m, ids, verts, flags
+
+    def march(self, seed_codes, seed_argmax=None, max_cells=0, batch=None):
+        """Algorithm 1 from the seed cells (FIFO).  batch: None = one cell at
+        a time (orc_march); an int = orc_march_batched with that batch size
+        (the same mesh; parallel in the OpenMP build)."""
         seed_codes = np.ascontiguousarray(np.asarray(seed_codes, np.uint64).reshape(-1, self.W))
         S = seed_codes.shape[0]
         if seed_argmax is None:
             seed_argmax = np.zeros(S, np.int32)
         seed_argmax = np.ascontiguousarray(seed_argmax, np.int32)
         L = self._L
-        R = L.orc_march(C.byref(self.s), _ptr(seed_codes, C.c_uint64), _ptr(seed_argmax, C.c_int32),
-                        S, int(max_cells))
+        if batch is None:
+            R = L.orc_march(C.byref(self.s), _ptr(seed_codes, C.c_uint64), _ptr(seed_argmax, C.c_int32),
+                            S, int(max_cells))
+        else:
+            R = L.orc_march_batched(C.byref(self.s), _ptr(seed_codes, C.c_uint64), _ptr(seed_argmax, C.c_int32),
+                                    S, int(max_cells), int(batch))
         if not R:
             raise MemoryError("oracle march failed")
         try:
