@@ -178,6 +178,24 @@ def maxpool_cube_net() -> Net:
 # Seeded random nets.
 # ---------------------------------------------------------------------------
 
+def sliver_net(h: float = 2.0 ** -28) -> Net:
+    """F = z - 1/2 cut by six hidden planes that leave the hidden units
+    without effect on F (zero output weights), so every face lies in the plane
+    z = 1/2 and the faces tile the square [-1,1]^2 x {1/2} (total area 4).
+
+    Units: x > 3/4, y > 3/4, x + y > 3/2 + h, x > -3/4, y > -3/4,
+    -x - y > 3/2.  With h = 2^-28 the first three bound a right triangle with
+    legs h at (3/4, 3/4): a face of area h^2/2 = 2^-57 about 1 away from the
+    plane's foot point (0, 0, 1/2).  The last three meet in one point
+    (-3/4, -3/4): the cell with units 3, 4 and 5 on touches the plane there
+    and has a face of zero area.  Every weight and bias is dyadic.
+    """
+    W1 = np.array([[1, 0, 0], [0, 1, 0], [1, 1, 0], [1, 0, 0], [0, 1, 0], [-1, -1, 0]], np.float64)
+    b1 = np.array([-0.75, -0.75, -1.5 - h, 0.75, 0.75, -1.5])
+    return Net([3, 6, 1], [(1, 0, W1), (2, 0, np.array([[0.0, 0.0, 1.0]])), (2, 1, np.zeros((1, 6)))],
+               [b1, np.array([-0.5])])
+
+
 def he_mlp(hidden: Sequence[int], seed: int, bias_std: float = 0.01,
            n_in: int = 3, n_out: int = 1) -> Tuple[list, list]:
     """Plain MLP parameters with W ~ N(0, 2/fan_in), b ~ N(0, bias_std^2).

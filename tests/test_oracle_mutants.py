@@ -6,7 +6,8 @@ missing ReLU mask, dropped shortcut blocks, a reversed max-pool comparison, a
 wrong edge pair in the vertex solve, the wrong tie rule, a wrong neighbour
 flip, a transposed weight block, ON vertices treated as outside, two
 sphere-tracing seeding mistakes (no gradient normalisation, wrong head) and
-two pivoting mistakes (no positive-length-edge rule, no orientation fix).  The
+two pivoting mistakes (no positive-length-edge rule, no orientation fix) and
+the area taken by the absolute shoelace instead of from the first vertex.  The
 test runs a battery of the pins (closed-form nets, brute force, Lemma 1,
 closedness) against every mutant and asserts that at least one pin fails.
 """
@@ -37,6 +38,7 @@ MUTANTS = {
     12: "sphere-tracing gradient taken from head 0, not the argmax head",
     13: "pivoting accepts a plane without a positive-length edge on it",
     14: "pivoting keeps the walk's orientation",
+    15: "face area by the absolute shoelace about the frame origin",
 }
 
 
@@ -71,6 +73,19 @@ def _pin_exact(lib_path, net, F, V, area, vol):
     assert chi == 2 and v == V
     A, Vol = MC.area_volume(mesh)
     assert abs(A - area) < 1e-12 and abs(Vol - vol) < 1e-12
+
+
+def _pin_sliver(lib_path):
+    """The sliver net: 14 faces tiling the square (area 4), one of area 2^-57."""
+    net = nets.sliver_net()
+    on = O.OracleNet(net, lib_path)
+    code, am, _ = on.code(np.array([0.0, 0.0, 0.5]))
+    mesh = on.march(code[None], np.array([am]))
+    assert mesh.n_faces == 14
+    A, _ = MC.area_volume(mesh)
+    assert abs(A - 4.0) < 1e-12
+    _, _, area, _ = on.face(np.array([0b011011], np.uint64))
+    assert area == 2.0 ** -57
 
 
 def _pin_brute(lib_path, net):
@@ -134,6 +149,7 @@ def _battery(lib_path):
         ("pivot_cube", lambda: PV.pin_exact(lib_path, nets.cube_net)),
         ("pivot_octahedron_split", lambda: PV.pin_exact(lib_path, nets.octahedron_split_net)),
         ("pivot_brute", lambda: PV.pin_brute(lib_path, _net_mlp_square())),
+        ("sliver", lambda: _pin_sliver(lib_path)),
     ]
     failed = []
     for name, fn in pins:

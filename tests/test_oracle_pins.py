@@ -306,3 +306,32 @@ def test_seed_without_sign_change_is_rejected():
     on = O.OracleNet(nets.cube_net())
     st, x, code, am = on.seed_ray(np.array([0.0, 0.0, 0.0]), np.array([0.2, 0.1, 0.0]))
     assert st == 1
+
+
+def test_sliver_face_and_zero_area_touch():
+    """Which cells count (a face counts iff it has positive area): the sliver
+    net's triangle of area 2^-57, about 1 away from the plane's foot point, is
+    a face; the cell whose three planes meet in one point of the zero plane
+    has a face of zero area and is not one.  Brute force over all 64 codes
+    (naive pairs, its own area rule) agrees, and the 14 faces tile the square
+    of area 4."""
+    net = nets.sliver_net()
+    h = 2.0 ** -28
+    _compare_with_brute(net)
+    on = O.OracleNet(net)
+    ids, vs, area, flags = on.face(np.array([0b011011], np.uint64))
+    assert area == 2.0 ** -57 and flags == 0
+    assert list(ids) == [0, 1, 2]
+    want = np.array([[0.75, 0.75 + h, 0.5], [0.75, 0.75, 0.5], [0.75 + h, 0.75, 0.5]])
+    for w in want:        # the three corners, in some rotation of the cycle
+        assert np.min(np.max(np.abs(vs - w), axis=1)) <= 1e-15
+    ids, vs, area, flags = on.face(np.array([0b111000], np.uint64))
+    assert len(ids) == 0 and flags & 1
+    bits = np.array([0, 0, 0, 1, 1, 1], np.float64)
+    rows = brute.chains(net, bits[None])[0]
+    assert brute.face_by_pairs(rows, bits, 0, net.n_hidden, net.n_heads) is None
+    code, am, _ = on.code(np.array([0.0, 0.0, 0.5]))
+    mesh = on.march(code[None], np.array([am]))
+    assert mesh.n_faces == 14
+    A, _ = MC.area_volume(mesh)
+    assert abs(A - 4.0) < 1e-12
