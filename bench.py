@@ -106,8 +106,29 @@ def measured_traffic(kernel: str):
     return t
 
 
+def host_cpu():
+    """Model name and logical CPU counts of the host (from /proc/cpuinfo)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(net, o, d, budget_s: float):
-    """The oracle (single thread, as it stands) on a BFS prefix of the workload."""
+    """The oracle as it stands on the host cores: the single-threaded build on
+    a BFS prefix of the workload, and the batched march (the same per-cell
+    routines, each batch of active cells spread over OpenMP threads) on as
+    much of the march as fits the budget."""
     from oracle import oracle as O
     on = O.OracleNet(net)
     t0 = time.perf_counter()
@@ -117,16 +138,31 @@ def cpu_baseline(net, o, d, budget_s: float):
     probe = on.march(codes, ams, max_cells=20000)
     per_cell = (time.perf_counter() - t1) / max(1, probe.stats["cells"])
     # later cells cost more than the first ones (larger tables), hence the 0.4
-    cells = int(max(20000, min(2_000_000, 0.4 * budget_s / max(per_cell, 1e-7))))
+    half = 0.5 * budget_s
+    cells = int(max(20000, min(2_000_000, 0.4 * half / max(per_cell, 1e-7))))
     t2 = time.perf_counter()
     mesh = on.march(codes, ams, max_cells=cells)
     t_march = time.perf_counter() - t2
     faces = mesh.n_faces
-    rate = faces / (t_seed + t_march)
-    return {"value": round(rate, 1), "unit": "faces/s", "cores": 1, "kind": "oracle",
-            "sample": f"dichotomy seeding of {len(o)} rays ({t_seed:.2f} s) + FIFO march of the first "
-                      f"{min(cells, mesh.stats['cells'])} cells ({faces} faces, {t_march:.2f} s) of the same "
-                      f"workload, single-threaded C oracle, FP64"}
+    rate1 = faces / (t_seed + t_march)
+    single = {"value": round(rate1, 1), "unit": "faces/s", "cores": 1,
+              "sample": f"dichotomy seeding of {len(o)} rays ({t_seed:.2f} s) + FIFO march of the first "
+                        f"{min(cells, mesh.stats['cells'])} cells ({faces} faces, {t_march:.2f} s), "
+                        f"single-threaded C oracle (gcc -O2), FP64"}
+    om = O.OracleNet(net, lib_path=O.OMP_LIB_PATH)
+    threads = om.threads()
+    cells_p = int(max(20000, min(50_000_000, 0.4 * half * threads / max(per_cell, 1e-7))))
+    t3 = time.perf_counter()
+    mesh_p = om.march(codes, ams, max_cells=cells_p, batch=16384)
+    t_par = time.perf_counter() - t3
+    full = mesh_p.stats["cells"] < cells_p
+    rate_p = mesh_p.n_faces / (t_seed + t_par)
+    return {"value": round(rate_p, 1), "unit": "faces/s", "cores": threads, "kind": "oracle",
+            "sample": f"dichotomy seeding of {len(o)} rays ({t_seed:.2f} s, one thread) + "
+                      + ("the whole march" if full else f"FIFO march of the first {cells_p} cells")
+                      + f" ({mesh_p.n_faces} faces, {t_par:.2f} s) with faces of each batch of 16384 active cells "
+                        f"on {threads} OpenMP threads (gcc -O3, no contraction), C oracle, FP64",
+            "single_thread": single, "host": host_cpu()}
 
 
 def train_scorer(B, dev, max_cells):
@@ -181,6 +217,59 @@ def cell_set_digest(out) -> str:
     h = h ^ (h >> 32)
     total = int(h.sum().item()) & (2 ** 64 - 1)
     return f"{total:016x}"
+
+
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_check(ctx, name: str):
+    """The context's last mesh against the oracle's record of the workload
+    (tests/golden/<name>.json, written by the CPU oracle alone): faces and
+    corners, and SHA-256 digests of the canonical cell set (codes, argmax),
+    cycles (polygon sizes, edge ids) and adjacency (neighbour face per edge),
+    all exact; sampled vertices within 1e-9 relative.  Outside the timed
+    region.  None when there is no record."""
+    import hashlib
+    path = os.path.join(GOLDEN_DIR, f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    smp = np.load(os.path.join(GOLDEN_DIR, f"{name}_verts.npz"))
+    out = ctx.fetch(sorted=True)
+    off = out["offsets"].cpu().numpy()
+    codes = out["codes"].cpu().numpy().view(np.uint64)
+    am = out["argmax"].cpu().numpy()
+    ids = out["ids"].cpu().numpy()
+    nbr = out["nbr"].cpu().numpy()
+    h1 = hashlib.sha256(np.ascontiguousarray(codes, "<u8").tobytes())
+    h1.update(np.ascontiguousarray(am, "<i4").tobytes())
+    h2 = hashlib.sha256(np.diff(off).astype("<i8").tobytes())
+    h2.update(np.ascontiguousarray(ids, "<i4").tobytes())
+    h3 = hashlib.sha256(np.ascontiguousarray(nbr, "<i8").tobytes())
+    got = {"cell_set": h1.hexdigest(), "cycles": h2.hexdigest(), "adjacency": h3.hexdigest()}
+    F = len(off) - 1
+    match = (F == rec["faces"] and int(off[-1]) == rec["face_verts"]
+             and all(got[k] == rec["sha256"][k] for k in got))
+    verr = None
+    if F == rec["faces"]:
+        fs = smp["faces"]
+        lo, hi = off[fs], off[fs + 1]
+        idx = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+        if len(idx) == len(smp["verts"]):
+            v = out["verts"][torch_index(idx, out["verts"].device)].cpu().numpy()
+            ref = smp["verts"]
+            verr = float((np.abs(v - ref).max(axis=1) / np.maximum(1.0, np.abs(ref).max(axis=1))).max())
+        else:
+            match = False
+    match = match and verr is not None and verr <= 1e-9
+    return {"golden_match": bool(match), "record": os.path.relpath(path, ROOT), "faces": F,
+            "digests_equal": {k: got[k] == rec["sha256"][k] for k in got},
+            "sampled_faces": int(len(smp["faces"])), "max_sampled_vertex_rel_err": verr}
+
+
+def torch_index(idx, device):
+    import torch
+    return torch.as_tensor(idx, dtype=torch.int64, device=device)
 
 
 def chain_kernel_name(net, groups, graph_steps):
@@ -520,6 +609,8 @@ def main(argv=None):
     print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step",
           file=sys.stderr, flush=True)
     plain_digest = cell_set_digest(main_run["out"])
+    golden = {a.workload: golden_check(ctx, a.workload)}   # the last march is the timed configuration
+    print(f"[bench] golden {a.workload}: {golden[a.workload]}", file=sys.stderr, flush=True)
     forms = {f"{a.workload}_plain": {"faces_per_s": round(main_run["faces_per_s"], 1),
                                      "ms_per_step": round(main_run["ms_per_step"], 3),
                                      "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
@@ -630,6 +721,8 @@ def main(argv=None):
             record(f"{name}_{v}", r, precision, propose, routine, ref_digest=base_digest)
             if base_digest is None:
                 base_digest = forms[f"{name}_{v}"]["cell_set_digest"]
+                golden[name] = golden_check(ctx3, name)
+                print(f"[bench] golden {name}: {golden[name]}", file=sys.stderr, flush=True)
         ctx3.close()
     if "ensemble" in forms_req:
         forms["ensemble_4x_d4w32"] = ensemble_form(B, dev, a.steps)
@@ -656,6 +749,10 @@ def main(argv=None):
                       "triangles": st["triangles"], "cells": st["cells"], "march_steps": st["steps"],
                       "seeds": st["seed_cells"], "degenerate": st["degenerate"]},
            "forms": forms, "roofline": roofline,
+           "golden": {k: g for k, g in golden.items() if g is not None},
+           "golden_match": bool(golden.get(a.workload)) and all(g["golden_match"] for g in golden.values()
+                                                                 if g is not None),
+           "golden_unrecorded": sorted(k for k, g in golden.items() if g is None),
            "exact_cell_set_match": all(v.get("exact_cell_set_match", True) for v in forms.values()
                                        if isinstance(v, dict))}
     if not a.no_cpu_baseline:

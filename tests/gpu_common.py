@@ -1,5 +1,6 @@
 """Helpers for the GPU parity tests (device mesh -> host, mesh comparison)."""
 import dataclasses
+import os
 import sys
 
 import numpy as np
@@ -97,6 +98,59 @@ def compare_meshes_fast(ref, got, vtol=1e-9):
     assert np.array_equal(rn, gn), "adjacency differs"
     scale = np.maximum(1.0, np.repeat(np.abs(rv).reshape(-1, 3).max(axis=1), 1))
     err = np.abs(gv - rv).max(axis=1) / np.maximum(1.0, np.abs(rv).max(axis=1))
+    worst = float(err.max()) if len(err) else 0.0
+    assert worst <= vtol, worst
+    return worst
+
+
+# ---------------------------------------------------------------- golden records
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """The oracle's record of a workload (tests/golden/<name>.json and its
+    vertex sample), or None when it has not been written."""
+    import json
+    p = os.path.join(GOLDEN_DIR, f"{name}.json")
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    rec["sample"] = dict(np.load(os.path.join(GOLDEN_DIR, f"{name}_verts.npz")))
+    return rec
+
+
+def mesh_digests(codes, argmax, offsets, ids, nbr):
+    """SHA-256 of the canonical arrays: codes then argmax; polygon sizes then
+    edge ids; neighbour face per edge (little-endian, as the records hold)."""
+    import hashlib
+    m = np.diff(np.asarray(offsets, np.int64)).astype("<i8")
+    a = hashlib.sha256(np.ascontiguousarray(codes, "<u8").tobytes())
+    a.update(np.ascontiguousarray(argmax, "<i4").tobytes())
+    b = hashlib.sha256(m.tobytes())
+    b.update(np.ascontiguousarray(ids, "<i4").tobytes())
+    c = hashlib.sha256(np.ascontiguousarray(nbr, "<i8").tobytes())
+    return {"cell_set": a.hexdigest(), "cycles": b.hexdigest(), "adjacency": c.hexdigest()}
+
+
+def check_golden(ctx, rec, vtol=1e-9):
+    """The context's last mesh, fetched in canonical order, against an oracle
+    record: counts and the three digests exact, sampled vertices within vtol
+    relative.  Returns the worst sampled vertex error."""
+    from paper_2106_10031_amd.binding import mesh_to_host
+    h = mesh_to_host(ctx.fetch(sorted=True))
+    F = len(h["offsets"]) - 1
+    assert F == rec["faces"], (F, rec["faces"])
+    assert int(h["offsets"][-1]) == rec["face_verts"], (int(h["offsets"][-1]), rec["face_verts"])
+    assert np.all(h["shape"] == 0)
+    dg = mesh_digests(h["codes"], h["argmax"], h["offsets"], h["ids"], h["nbr"])
+    for k in ("cell_set", "cycles", "adjacency"):
+        assert dg[k] == rec["sha256"][k], f"{rec['workload']}: {k} digest differs from the oracle's"
+    s = rec["sample"]
+    off = h["offsets"]
+    got = np.concatenate([h["verts"][off[f]:off[f + 1]] for f in s["faces"]])
+    assert np.array_equal(np.diff(off)[s["faces"]], s["m"])
+    ref = s["verts"]
+    err = np.abs(got - ref).max(axis=1) / np.maximum(1.0, np.abs(ref).max(axis=1))
     worst = float(err.max()) if len(err) else 0.0
     assert worst <= vtol, worst
     return worst
