@@ -225,6 +225,21 @@ am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, 
 am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
                    int64_t n, int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags);
 
+/* am_faces without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, layout and results as am_faces (bit for bit).
+ * The chain rows go through a fixed 32 MiB device scratch array that the
+ * library holds on every GPU it runs on until the process ends; its address is
+ * looked up when a context is created on the device.  n cells are processed
+ * in batches of floor(32 MiB / (32 R)) cells (R = padded rows per cell, about
+ * N + M), one batch after another on the context's stream.  The call itself
+ * allocates nothing; a network whose single cell needs more than 32 MiB of
+ * rows is rejected with AM_E_INVALID.  Every context on one GPU shares that
+ * GPU's scratch: calls on different streams that overlap in time race (their
+ * results are then undefined); calls on one stream do not.  Enqueued. */
+am_status am_faces_noalloc(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
+                           int64_t n, int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags);
+
 /* Seeds by dichotomy along rays o + t d, t in [0,1] (Sec. 4.3.2): bisect
  * until both bracket ends share one code (at most max_iter halvings, <= 0
  * means 200), then take the linear root inside that cell; the seed cell is

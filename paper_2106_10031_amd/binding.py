@@ -25,7 +25,7 @@ EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_b
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
            "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups",
            "am_seed_points_st", "am_weld", "am_triangles", "am_fetch_sorted",
-           "am_seed_points", "am_simplify"]
+           "am_seed_points", "am_simplify", "am_faces_noalloc"]
 
 
 class AmError(RuntimeError):
@@ -88,6 +88,7 @@ def lib(path: str = LIB_PATH):
     L.am_codes.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.am_chain.argtypes = [vp, vp, vp, i64, i32, vp]
     L.am_faces.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
+    L.am_faces_noalloc.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
     L.am_seed_rays.argtypes = [vp, vp, vp, vp, i64, i32, vp]
     L.am_seed_cells.argtypes = [vp, vp, vp, vp, i64]
     L.am_march.argtypes = [vp, C.POINTER(MarchOpts), C.POINTER(MarchStats)]
@@ -229,6 +230,16 @@ class Context:
         self._check(self.L.am_faces(self.h, _p(codes), _p(am), _p(sh), n, int(max_m), _p(m), _p(ids), _p(verts),
                                     _p(flags)))
         return m, ids, verts, flags
+
+    def faces_into(self, codes, argmax, shape_id, m, ids, verts, flags, noalloc=True):
+        """am_faces_noalloc (or am_faces) into caller-allocated outputs:
+        codes [n][W] i64, argmax [n] i32 or None, shape_id [n] i32 or None,
+        m [n] i32, ids [n][max_m] i32, verts [n][max_m][3] f64, flags [n] i32
+        or None (all device tensors, contiguous)."""
+        n = codes.shape[0]
+        fn = self.L.am_faces_noalloc if noalloc else self.L.am_faces
+        self._check(fn(self.h, _p(codes), _p(argmax), _p(shape_id), n, int(ids.shape[1]), _p(m), _p(ids),
+                       _p(verts), _p(flags)))
 
     # --------------------------------------------------------------- march
     def seed_rays(self, orig, dirs, max_iter=200, shape_id=None):

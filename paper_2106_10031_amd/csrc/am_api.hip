@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -89,6 +90,38 @@ void launch_triangles(long long, long long, const long long *, const long long *
 }  // namespace am
 
 using namespace am;
+
+// ---- scratch of am_faces_noalloc: the FP64 chain rows of one batch of cells.
+// One copy per GPU, part of the loaded code object (it lives until the process
+// ends).  Host code must not use the array's name as a device address: each
+// device's address comes from hipGetSymbolAddress, taken once per device when
+// a context is created on it, and only that pointer is passed to kernels.
+static constexpr size_t kNoAllocScratchBytes = 32ull << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on `device` (the current device); looked up once.
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = (double *)ptr;
+    return hipSuccess;
+}
+
+double *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+}  // namespace
 
 struct am_ctx {
     int device = 0;
@@ -445,6 +478,10 @@ am_status am_create(am_ctx **out, int device, void *hip_stream) {
         delete ctx;
         return AM_E_HIP;
     }
+    if (noalloc_scratch_init(device) != hipSuccess) {
+        am_destroy(ctx);
+        return AM_E_HIP;
+    }
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
     ctx->lds_limit = (size_t)lds;
@@ -742,6 +779,41 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, co
         out.out_base = 0;
         Candidates none{};
         launch_clip(ctx->dn, codes, argmax, nullptr, nullptr, lo, hi, nullptr, nullptr, 0, ctx->d_rows, out, none, 0,
+                    nullptr, PropArgs{}, ctx->stream);
+    }
+    HIPCHK(hipGetLastError());
+    return AM_OK;
+}
+
+am_status am_faces_noalloc(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
+                           int64_t n, int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
+    if (n < 0 || max_m < 3 || max_m > kMaxPoly || (n > 0 && (!codes || !m || !ids || !verts)))
+        return fail(ctx, AM_E_INVALID, "bad arguments (max_m must be 3..%d)", kMaxPoly);
+    const size_t per_cell = sizeof(double) * 4 * (size_t)ctx->dn.R;
+    const long long batch = (long long)(kNoAllocScratchBytes / per_cell);
+    if (batch < 1)
+        return fail(ctx, AM_E_INVALID,
+                    "am_faces_noalloc: the rows of one cell need %zu bytes, more than its %zu-byte scratch",
+                    per_cell, kNoAllocScratchBytes);
+    TRY(set_device(ctx));
+    double *rows = noalloc_scratch(ctx->device);
+    if (!rows) return fail(ctx, AM_E_STATE, "am_faces_noalloc: no scratch address for device %d", ctx->device);
+    for (long long lo = 0; lo < n; lo += batch) {
+        const long long hi = std::min<long long>(n, lo + batch);
+        launch_chain(ctx->dn, codes, shape_id, lo, hi, nullptr, nullptr, rows, chain_groups(ctx, hi - lo, 0),
+                     ctx->stream);
+        ClipOut out{};
+        out.m = m;
+        out.ids = ids;
+        out.verts = verts;
+        out.nbr = nullptr;
+        out.flags = flags;
+        out.stride = max_m;
+        out.out_base = 0;
+        Candidates none{};
+        launch_clip(ctx->dn, codes, argmax, nullptr, nullptr, lo, hi, nullptr, nullptr, 0, rows, out, none, 0,
                     nullptr, PropArgs{}, ctx->stream);
     }
     HIPCHK(hipGetLastError());
