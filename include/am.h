@@ -34,14 +34,16 @@
  *
  * Memory: every pointer argument is either a host pointer or a device pointer
  * as stated per call.  The context owns its device scratch (allocated on
- * am_load_net / am_march and freed by am_destroy) and enqueues all work on
- * the HIP stream given to am_create.  No call throws or aborts across the
- * ABI; failures return a status and am_last_error() describes them.  A
+ * am_load_net / am_march from the allocator given to am_create, and freed by
+ * am_destroy) and enqueues all work on the HIP stream given to am_create.
+ * No call throws or aborts across the ABI; failures return a status and
+ * am_last_error() describes them.  A
  * context must not be used from two threads at once.
  */
 #ifndef AM_H
 #define AM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -61,16 +63,26 @@ typedef enum {
 
 typedef struct am_ctx am_ctx;
 
+/* Element type of the weights and biases of an am_net_desc. */
+enum { AM_F64 = 0, AM_F32 = 1 };
+
+/* Where am_fetch writes: caller DEVICE buffers (enqueued) or HOST memory
+ * (the call synchronises). */
+enum { AM_DEVICE = 0, AM_HOST = 1 };
+
 /* Network description.  All pointers are HOST pointers, borrowed for the
- * call only (the weights are copied to the device, widened to FP64). */
+ * call only (the weights are copied to the device, widened exactly to FP64). */
 typedef struct {
     int32_t n_layers;             /* L + 2 (input, hidden layers, head layer) */
     const int32_t *width;         /* [n_layers]; width[0] must be 3 */
     int32_t n_blocks;
     const int32_t *blk_dst;       /* [n_blocks], 1 <= dst < n_layers */
     const int32_t *blk_src;       /* [n_blocks], 0 <= src < dst */
-    const double *const *blk_w;   /* [n_blocks] row-major width[dst] x width[src] */
-    const double *const *bias;    /* [n_layers]; bias[l] has width[l] entries, bias[0] unused */
+    const void *const *blk_w;     /* [n_blocks] row-major width[dst] x width[src], of type dtype */
+    const void *const *bias;      /* [n_layers]; bias[l] has width[l] entries of type dtype, bias[0] unused */
+    int32_t n_heads;              /* M >= 1 heads joined by a max (Sec. 5.2); 0 = width[n_layers-1],
+                                     else it must equal width[n_layers-1] */
+    int32_t dtype;                /* AM_F64 (0) or AM_F32 (1): element type of blk_w and bias */
 } am_net_desc;
 
 typedef struct {
@@ -86,8 +98,13 @@ typedef struct {
                              a face is kept only if every vertex's estimated relative error
                              is at most `vertex_tol` and no other constraint comes within
                              `margin` + that estimate of a vertex (and no edge is that
-                             short), else its cell is redone by the FP64 chain and clip, so
-                             cells, cycles and adjacency equal the FP64 result */
+                             short), else its cell is redone by the FP64 chain and clip.
+                             The estimate is the vertex's first-order sensitivity to its
+                             rows times a row error measured for each loaded net on the
+                             first march's seed cells (stats.split_row_eps).  This is an
+                             empirical certificate, not a bound: cells, cycles and
+                             adjacency equal the FP64 result unless an unmeasured error
+                             exceeds 8x the largest measured one */
     int32_t propose;      /* learned form (not in the paper, which sorts planes by distance
                              in its pivoting routine, Sec. 4.2.1): before the every-line clip,
                              clip the best k hidden lines near the edge the cell was entered
@@ -105,7 +122,15 @@ typedef struct {
                              memory); 5 = four cells whose K loop runs
                              only over the source units active in any of them (sources of at
                              most 1024 units; rows then differ from the dense sum in the last
-                             bits) */
+                             bits); 6, 7 = 4 or 8 cells whose previous layer is written,
+                             masked, by the producing MFMA tiles into LDS as the next B
+                             operand, with weight fragments streamed one batch of K-steps
+                             ahead (as FP32 when every weight is an FP32 number), one 16-row
+                             output tile per wave (two if the widest layer is over 256); 8 =
+                             as 6 with two output tiles per wave.  6..8 need layers of at
+                             most 512 units and their LDS (widest hidden layer x 16 x 4 or 8
+                             cells doubles); otherwise they run as 1.  Variants 1..4 and 6..8
+                             sum in the same order (equal rows) */
     int32_t graph_steps;  /* > 0 (<= 64): device-driven steps, this many captured in one HIP
                              graph (built once per context and shape of the march, then
                              replayed) and one counter read per replay instead of per step.
@@ -113,21 +138,27 @@ typedef struct {
                              With time_kernels the same steps are launched one by one on the
                              stream instead (no graph), still one counter read per
                              graph_steps steps, with HIP events around each kernel class.
-                             Plain FP64 form on the split path only (AM_E_INVALID with
-                             precision, propose, sample collection or kernel_path 2); the
-                             gathered chain tile is replaced by 4 cells */
+                             Every form of the split path (FP64 or split-BF16 with its FP64
+                             redo, with or without proposals, one shape or a batch);
+                             AM_E_INVALID with sample collection, kernel_path 2 or pivoting.
+                             The gathered chain tile (5) is replaced by 1 */
     int32_t face_routine; /* 0: halfplane clipping; 1: pivoting (Sec. 4.2.1): each face with
                              an entry edge from its parent is traced vertex by vertex from
                              that edge (a ratio test over every line per vertex); seeds,
                              cells whose entry edge ends on a box plane or is degenerate, and
-                             walks that do not close are clipped.  The faces are the same.  Plain FP64 form on the split path only
-                             (AM_E_INVALID with precision, propose, sample collection,
-                             kernel_path 2 or graph_steps) */
-    int32_t reserved;
-    double margin;        /* relative sign-test margin of precision 1 (0: 4e-6) */
+                             walks that do not close are clipped.  The faces are the same.
+                             Plain FP64 form on the split path only (AM_E_INVALID with
+                             precision, propose, sample collection, kernel_path 2 or
+                             graph_steps) */
+    int32_t async;        /* 1: enqueue the march on a worker thread and return at once;
+                             am_wait blocks until it ends and returns its status and stats.
+                             Until then every other call on the context returns AM_E_STATE
+                             (am_busy tells whether it still runs) */
+    double margin;        /* relative sign-test margin of precision 1 (0: the measured one,
+                             stats.split_margin) */
     double vertex_tol;    /* precision 1: a cell is also redone in FP64 when a vertex's
-                             estimated relative error (1.2e-6 x its first-order sensitivity
-                             to the rows) exceeds this (0: 1e-5) */
+                             estimated relative error (stats.split_row_eps x its first-order
+                             sensitivity to the rows) exceeds this (0: 1e-5) */
 } am_march_opts;
 
 typedef struct {
@@ -163,11 +194,32 @@ typedef struct {
     int64_t pivot_cells;      /* face_routine 1: faces traced by pivoting */
     int64_t pivot_fallback;   /* face_routine 1: cells clipped instead (seeds, no usable entry
                                  edge, or a walk that did not close) */
+    /* precision 1: the certificate's constants for the loaded net, measured on
+       the first march's seed cells (at most 2048) against the FP64 chain and clip */
+    double split_row_eps;     /* relative row error per unit of vertex sensitivity (8 x measured) */
+    double split_margin;      /* sign-test margin used (opts.margin, else 8 x the measured one) */
+    int64_t calib_vertices;   /* vertices those were measured on */
 } am_march_stats;
 
+/* Device memory supplier.  alloc returns `bytes` of device memory on
+ * `device` for work on `stream` (a hipStream_t), or NULL on failure (the call
+ * that needed it then returns AM_E_OOM); release returns a block alloc gave.
+ * A caching allocator (PyTorch's) may hand a released block to the next
+ * alloc on the same stream at once: the library enqueues all its work on
+ * that stream.  `user` is passed back unchanged. */
+typedef struct {
+    void *(*alloc)(void *user, size_t bytes, int device, void *stream);
+    void (*release)(void *user, void *ptr, int device, void *stream);
+    void *user;
+} am_allocator;
+
 /* Creates a context on `device` that enqueues its work on `hip_stream`
- * (a hipStream_t; NULL = the default stream). */
-am_status am_create(am_ctx **out, int device, void *hip_stream);
+ * (a hipStream_t; NULL = the default stream).  Every device buffer the
+ * context owns comes from `alloc` (copied; NULL = hipMalloc / hipFree),
+ * except pinned host memory for its counters and the fixed scratch of
+ * am_faces_noalloc.  AM_E_INVALID if alloc gives only one of its two
+ * functions. */
+am_status am_create(am_ctx **out, int device, void *hip_stream, const am_allocator *alloc);
 
 /* Frees the context and every device buffer it owns.  NULL is a no-op. */
 void am_destroy(am_ctx *ctx);
@@ -240,7 +292,8 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, co
 am_status am_faces_noalloc(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
                            int64_t n, int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags);
 
-/* Seeds by dichotomy along rays o + t d, t in [0,1] (Sec. 4.3.2): bisect
+/* Seeds by dichotomy along rays o + t d, t in [0, t_max] (Sec. 4.3.2; t_max
+ * <= 0 means 1): bisect
  * until both bracket ends share one code (at most max_iter halvings, <= 0
  * means 200), then take the linear root inside that cell; the seed cell is
  * the code and argmax at the root.  DEVICE pointers: orig [R][3], dir [R][3]
@@ -250,7 +303,7 @@ am_status am_faces_noalloc(am_ctx *ctx, const uint64_t *codes, const int32_t *ar
  * Replaces any previous seeds; the seed cells are kept in the context for
  * am_march.  Enqueued. */
 am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const int32_t *shape_id,
-                       int64_t n_rays, int32_t max_iter, int32_t *status_out);
+                       int64_t n_rays, double t_max, int32_t max_iter, int32_t *status_out);
 
 /* Seeds given directly as cells.  DEVICE pointers: codes [n][W] u64,
  * argmax [n] i32 and shape_id [n] i32 (NULL = all 0).  Seeds with an argmax
@@ -283,31 +336,43 @@ am_status am_seed_points_st(am_ctx *ctx, const double *pts, const int32_t *shape
                             int32_t *status_out, int32_t *iters_out, double *x_out);
 
 /* Marches from the current seeds (Algorithm 1, all active cells at once)
- * until the active set is empty.  Blocks until done.  opts may be NULL.
- * Returns AM_E_CAPACITY (stats->required_cells set) when max_cells is too
- * small; AM_E_SEED when every seed face is empty. */
+ * until the active set is empty.  Blocks until done unless opts->async (then
+ * use am_wait; stats is not written).  opts may be NULL.  Returns
+ * AM_E_CAPACITY (stats->required_cells set) when max_cells is too small;
+ * AM_E_SEED when every seed face is empty. */
 am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats);
 
-/* Sizes of the last march's result. */
-am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, int64_t *cells);
+/* Waits for the asynchronous march started by am_march (opts->async = 1):
+ * returns that march's status and fills stats (may be NULL).  AM_E_STATE if
+ * none was started since the last wait. */
+am_status am_wait(am_ctx *ctx, am_march_stats *stats);
 
-/* Copies the last march's mesh into caller-owned DEVICE buffers, faces in
- * discovery order:  offsets [F+1] i64 (CSR into the per-edge arrays),
- * ids [V] i32 edge constraint ids, verts [V][3] f64 (vertex i starts edge i),
- * nbr [V] i64 face index across edge i (-1 box edge, -2 neighbour cell has
- * no face), codes [F][W] u64, argmax [F] i32, shape_id [F] i32.  Any pointer
- * may be NULL to skip that output.  Enqueued. */
-am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
+/* *busy = 1 while an asynchronous march runs on the context, else 0. */
+am_status am_busy(const am_ctx *ctx, int32_t *busy);
+
+/* Sizes of the last march's result: faces, polygon corners, fan triangles
+ * (corners - 2 faces), cells discovered.  Any pointer may be NULL. */
+am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, int64_t *tris, int64_t *cells);
+
+/* Copies the last march's mesh into caller-owned buffers, faces in discovery
+ * order:  offsets [F+1] i64 (CSR into the per-edge arrays), ids [V] i32 edge
+ * constraint ids, verts [V][3] f64 (vertex i starts edge i), nbr [V] i64 face
+ * index across edge i (-1 box edge, -2 neighbour cell has no face), codes
+ * [F][W] u64, argmax [F] i32, shape_id [F] i32; F, V from am_get_counts.
+ * where = AM_DEVICE: DEVICE buffers, enqueued.  where = AM_HOST: HOST memory;
+ * the arrays are staged in device memory the context keeps, copied, and the
+ * call synchronises.  Any pointer may be NULL to skip that output. */
+am_status am_fetch(am_ctx *ctx, int32_t where, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                    uint64_t *codes, int32_t *argmax, int32_t *shape_id);
 
-/* As am_fetch (same buffers and layout), with the faces in canonical order:
+/* As am_fetch (same `where`, buffers and layout), with the faces in canonical order:
  * sorted by shape id, then by code words (unsigned, word 0 first), then by
  * argmax; nbr holds indices in that order.  Every face's cycle starts at its
  * smallest edge id either way, so the output is independent of discovery
  * order and equals the CPU reference's mesh array for array.  A stable radix
  * sort per key word; device scratch of about 48 bytes per face is kept by
  * the context.  Enqueued. */
-am_status am_fetch_sorted(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
+am_status am_fetch_sorted(am_ctx *ctx, int32_t where, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                           uint64_t *codes, int32_t *argmax, int32_t *shape_id);
 
 /* ---- Welded mesh: the output Z = {V, {P}} of Sec. 3, a shared vertex
@@ -375,23 +440,24 @@ am_status am_simplify(am_ctx *ctx, int64_t n_verts, const double *vxyz, int64_t 
                       int64_t *tri_out, int64_t *n_verts_out, int64_t *n_tris_out, int32_t *rounds_out,
                       int64_t *n_bad);
 
-/* ---- Affine-chain tile autotuner.  The chain kernel has five tile
+/* ---- Affine-chain tile autotuner.  The chain kernel has eight tile
  * variants (opts.chain_groups): 4, 8 or 16 cells per workgroup (1, 2 or 4
  * column groups of the 16-column FP64 MFMA tile; more cells share each
  * streamed weight fragment, fewer fill the chip at small frontiers); 3: four
  * cells reading the previous layer from LDS; 5: four cells whose K loop
- * skips the units that are off in all of them.  The context keeps one
- * variant per launch-size bucket (fewer than 2^11 cells, 2^13, 2^15, more);
- * all start at 1. */
+ * skips the units that are off in all of them; 6, 7, 8: the staged-B chain
+ * (see am_march_opts.chain_groups).  The context keeps one variant per
+ * launch-size bucket (fewer than 2^11 cells, 2^13, 2^15, more); all start
+ * at 1. */
 
 /* Times the chain kernel on the first 2^10, 2^12, 2^14 and 2^16 cells of the
  * last march (fewer if it has fewer) for each variant, `reps` launches each,
  * and keeps the fastest per bucket.  ms_out (HOST, may be NULL) receives the
- * 4 x 5 average launch times (bucket-major; variants 1, 2, 3, 4, 5).
- * AM_E_STATE without a finished march. */
+ * 4 x 8 average launch times (bucket-major; variants 1..8; -1 for a variant
+ * that cannot run on the loaded net).  AM_E_STATE without a finished march. */
 am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out);
 
-/* Sets / reads the 4 per-bucket variants (each 1..5; HOST arrays). */
+/* Sets / reads the 4 per-bucket variants (each 1..8; HOST arrays). */
 am_status am_set_chain_groups(am_ctx *ctx, const int32_t *groups);
 am_status am_get_chain_groups(const am_ctx *ctx, int32_t *groups);
 

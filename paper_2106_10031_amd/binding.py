@@ -25,7 +25,11 @@ EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_b
            "am_prop_param_count", "am_prop_set", "am_prop_collect", "am_prop_collected", "am_prop_grad",
            "am_prop_adam", "am_prop_score", "am_tune_chain", "am_set_chain_groups", "am_get_chain_groups",
            "am_seed_points_st", "am_weld", "am_triangles", "am_fetch_sorted",
-           "am_seed_points", "am_simplify", "am_faces_noalloc"]
+           "am_seed_points", "am_simplify", "am_faces_noalloc", "am_wait", "am_busy"]
+
+
+# chain tile variants (am_march_opts.chain_groups, am_tune_chain)
+CHAIN_VARIANTS = 8
 
 
 class AmError(RuntimeError):
@@ -34,17 +38,22 @@ class AmError(RuntimeError):
         self.status = status
 
 
+AM_F64, AM_F32 = 0, 1          # am_net_desc.dtype
+AM_DEVICE, AM_HOST = 0, 1      # am_fetch's `where`
+
+
 class NetDesc(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("width", C.POINTER(C.c_int32)), ("n_blocks", C.c_int32),
                 ("blk_dst", C.POINTER(C.c_int32)), ("blk_src", C.POINTER(C.c_int32)),
-                ("blk_w", C.POINTER(C.POINTER(C.c_double))), ("bias", C.POINTER(C.POINTER(C.c_double)))]
+                ("blk_w", C.POINTER(C.c_void_p)), ("bias", C.POINTER(C.c_void_p)),
+                ("n_heads", C.c_int32), ("dtype", C.c_int32)]
 
 
 class MarchOpts(C.Structure):
     _fields_ = [("max_cells", C.c_int64), ("max_steps", C.c_int32), ("strict", C.c_int32),
                 ("time_kernels", C.c_int32), ("kernel_path", C.c_int32), ("precision", C.c_int32),
                 ("propose", C.c_int32), ("chain_groups", C.c_int32), ("graph_steps", C.c_int32),
-                ("face_routine", C.c_int32), ("reserved", C.c_int32),
+                ("face_routine", C.c_int32), ("async_", C.c_int32),
                 ("margin", C.c_double),
                 ("vertex_tol", C.c_double)]
 
@@ -59,11 +68,38 @@ class MarchStats(C.Structure):
                 ("hash_launches", C.c_int64), ("fused", C.c_int32), ("pad", C.c_int32),
                 ("escalated", C.c_int64), ("prop_cells", C.c_int64), ("prop_accepted", C.c_int64),
                 ("prop_cuts", C.c_int64), ("graph_launches", C.c_int64), ("pivot_cells", C.c_int64),
-                ("pivot_fallback", C.c_int64)]
+                ("pivot_fallback", C.c_int64), ("split_row_eps", C.c_double), ("split_margin", C.c_double),
+                ("calib_vertices", C.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("reserved", "pad")}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", C.c_void_p)]
+
+
+def _torch_alloc(user, nbytes, device, stream):
+    """am_allocator.alloc backed by PyTorch's caching allocator."""
+    import torch
+    try:
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes), int(device), _STREAMS.get(stream or 0)))
+    except Exception:   # out of memory: the library reports AM_E_OOM
+        return None
+
+
+def _torch_release(user, ptr, device, stream):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_TORCH_ALLOC = Allocator(ALLOC_FN(_torch_alloc), RELEASE_FN(_torch_release), None)
+_STREAMS = {}          # hipStream_t -> the torch stream it belongs to
+_LIVE = None           # contexts still open (closed at exit, while torch is alive)
 
 _lib = None
 
@@ -77,7 +113,7 @@ def lib(path: str = LIB_PATH):
         raise RuntimeError(f"{path} is missing: build it with python paper_2106_10031_amd/build.py")
     L = C.CDLL(path)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
-    L.am_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.am_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.POINTER(Allocator)]
     L.am_destroy.argtypes = [vp]
     L.am_destroy.restype = None
     L.am_last_error.argtypes = [vp]
@@ -89,12 +125,14 @@ def lib(path: str = LIB_PATH):
     L.am_chain.argtypes = [vp, vp, vp, i64, i32, vp]
     L.am_faces.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
     L.am_faces_noalloc.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
-    L.am_seed_rays.argtypes = [vp, vp, vp, vp, i64, i32, vp]
+    L.am_seed_rays.argtypes = [vp, vp, vp, vp, i64, C.c_double, i32, vp]
     L.am_seed_cells.argtypes = [vp, vp, vp, vp, i64]
     L.am_march.argtypes = [vp, C.POINTER(MarchOpts), C.POINTER(MarchStats)]
-    L.am_get_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
-    L.am_fetch.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
-    L.am_fetch_sorted.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.am_wait.argtypes = [vp, C.POINTER(MarchStats)]
+    L.am_busy.argtypes = [vp, C.POINTER(i32)]
+    L.am_get_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.am_fetch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.am_fetch_sorted.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.am_seed_points.argtypes = [vp, vp, vp, i64]
     L.am_simplify.argtypes = [vp, i64, vp, i64, vp, vp, i64, i32, vp, vp, C.POINTER(i64), C.POINTER(i64),
                               C.POINTER(i32), C.POINTER(i64)]
@@ -128,7 +166,12 @@ def _p(t):
 class Context:
     """One am_ctx bound to a device and a torch stream."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, allocator: str = "torch"):
+        """allocator: "torch" (device memory from PyTorch's caching allocator,
+        the default) or None (the library's own hipMalloc)."""
+        global _LIVE
+        import atexit
+        import weakref
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -137,11 +180,20 @@ class Context:
         self.stream = stream
         self.L = lib()
         h = C.c_void_p()
-        st = self.L.am_create(C.byref(h), int(device), C.c_void_p(stream.cuda_stream))
+        if allocator not in ("torch", None):
+            raise ValueError("allocator must be 'torch' or None")
+        if allocator == "torch":
+            _STREAMS[stream.cuda_stream or 0] = stream
+        alloc = C.byref(_TORCH_ALLOC) if allocator == "torch" else None
+        st = self.L.am_create(C.byref(h), int(device), C.c_void_p(stream.cuda_stream), alloc)
         if st != AM_OK:
             raise AmError(st, "am_create failed")
         self.h = h
         self.N = self.M = self.W = self.S = None
+        if _LIVE is None:
+            _LIVE = weakref.WeakSet()
+            atexit.register(lambda: [c.close() for c in list(_LIVE)])
+        _LIVE.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -159,23 +211,25 @@ class Context:
             raise AmError(st, self.L.am_last_error(self.h).decode())
 
     # ------------------------------------------------------------------ net
-    def load_net(self, net, shape_bias=None):
+    def load_net(self, net, shape_bias=None, dtype=AM_F64):
         """Loads a network given as (widths, blocks [(dst, src, W)], bias [per layer >= 1]).
 
         With ``shape_bias`` ([S, sum of widths of layers >= 1]), loads S shapes
         that share the weights and use row s as their biases (am_load_batch).
+        dtype AM_F32 hands the library FP32 arrays (each value rounded to
+        FP32 first; exact for nets stored in FP32).
         """
         widths = np.asarray(net.widths, np.int32)
         dst = np.asarray([d for d, _, _ in net.blocks], np.int32)
         src = np.asarray([s for _, s, _ in net.blocks], np.int32)
-        ws = [np.ascontiguousarray(W, np.float64) for _, _, W in net.blocks]
-        bs = [np.zeros(3)] + [np.ascontiguousarray(b, np.float64) for b in net.bias]
-        DP = C.POINTER(C.c_double)
-        wp = (DP * len(ws))(*[w.ctypes.data_as(DP) for w in ws])
-        bp = (DP * len(bs))(*[b.ctypes.data_as(DP) for b in bs])
+        npt = np.float32 if dtype == AM_F32 else np.float64
+        ws = [np.ascontiguousarray(W, npt) for _, _, W in net.blocks]
+        bs = [np.zeros(3, npt)] + [np.ascontiguousarray(b, npt) for b in net.bias]
+        wp = (C.c_void_p * len(ws))(*[w.ctypes.data for w in ws])
+        bp = (C.c_void_p * len(bs))(*[b.ctypes.data for b in bs])
         desc = NetDesc(len(widths), widths.ctypes.data_as(C.POINTER(C.c_int32)), len(ws),
                        dst.ctypes.data_as(C.POINTER(C.c_int32)), src.ctypes.data_as(C.POINTER(C.c_int32)),
-                       wp, bp)
+                       wp, bp, int(widths[-1]), int(dtype))
         if shape_bias is None:
             self._check(self.L.am_load_net(self.h, C.byref(desc)))
         else:
@@ -242,14 +296,15 @@ class Context:
                        _p(verts), _p(flags)))
 
     # --------------------------------------------------------------- march
-    def seed_rays(self, orig, dirs, max_iter=200, shape_id=None):
+    def seed_rays(self, orig, dirs, max_iter=200, shape_id=None, t_max=1.0):
         t = self.torch
         o = self._dev(orig, t.float64).reshape(-1, 3)
         d = self._dev(dirs, t.float64).reshape(-1, 3)
         sh = self._shape(shape_id)
         status = t.empty(o.shape[0], dtype=t.int32, device=self.device)
         self._seed_keep = (o, d, sh)        # the kernel reads them on the stream
-        self._check(self.L.am_seed_rays(self.h, _p(o), _p(d), _p(sh), o.shape[0], int(max_iter), _p(status)))
+        self._check(self.L.am_seed_rays(self.h, _p(o), _p(d), _p(sh), o.shape[0], float(t_max), int(max_iter),
+                                        _p(status)))
         return status
 
     def seed_cells(self, codes, argmax=None, shape_id=None):
@@ -282,10 +337,13 @@ class Context:
         return status, iters, x
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
-              margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0, graph_steps=0, face_routine=0):
+              margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0, graph_steps=0, face_routine=0,
+              wait=True):
+        """am_march; with wait=False it returns None at once (asynchronous
+        march) and wait() gives its stats."""
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
                          int(kernel_path), int(precision), int(propose), int(chain_groups), int(graph_steps),
-                         int(face_routine))
+                         int(face_routine), 0 if wait else 1)
         opts.margin = float(margin)
         opts.vertex_tol = float(vertex_tol)
         stats = MarchStats()
@@ -294,16 +352,32 @@ class Context:
             err = AmError(st, self.L.am_last_error(self.h).decode())
             err.stats = stats.as_dict()
             raise err
+        return stats.as_dict() if wait else None
+
+    def wait(self):
+        """am_wait: the stats of the asynchronous march (raises on its error)."""
+        stats = MarchStats()
+        st = self.L.am_wait(self.h, C.byref(stats))
+        if st != AM_OK:
+            err = AmError(st, self.L.am_last_error(self.h).decode())
+            err.stats = stats.as_dict()
+            raise err
         return stats.as_dict()
+
+    def busy(self):
+        b = C.c_int32()
+        self._check(self.L.am_busy(self.h, C.byref(b)))
+        return bool(b.value)
 
     # ------------------------------------------------------------ chain tiles
     def tune_chain(self, reps=5):
         """Times the chain tiles on the last march's cells and keeps the
-        fastest per launch size; returns (variants[4], ms[4][5])."""
+        fastest per launch size; returns (variants[4], ms[4][CHAIN_VARIANTS])
+        (-1 for a variant that cannot run on the loaded net)."""
         import numpy as np
-        ms = np.zeros(20, dtype=np.float32)
+        ms = np.zeros(4 * CHAIN_VARIANTS, dtype=np.float32)
         self._check(self.L.am_tune_chain(self.h, int(reps), ms.ctypes.data_as(C.c_void_p)))
-        return self.chain_groups(), ms.reshape(4, 5)
+        return self.chain_groups(), ms.reshape(4, CHAIN_VARIANTS)
 
     def chain_groups(self):
         import numpy as np
@@ -362,23 +436,32 @@ class Context:
         return z
 
     def counts(self):
-        f, v, c = C.c_int64(), C.c_int64(), C.c_int64()
-        self._check(self.L.am_get_counts(self.h, C.byref(f), C.byref(v), C.byref(c)))
-        return f.value, v.value, c.value
+        """(faces, corners, triangles, cells) of the last march."""
+        f, v, tr, c = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.L.am_get_counts(self.h, C.byref(f), C.byref(v), C.byref(tr), C.byref(c)))
+        return f.value, v.value, tr.value, c.value
 
-    def fetch(self, sorted=False):
-        """The mesh as device tensors (faces in discovery order, or with
-        sorted=True in canonical order: shape, code words, argmax)."""
+    def fetch(self, sorted=False, where=AM_DEVICE):
+        """The mesh (faces in discovery order, or with sorted=True in
+        canonical order: shape, code words, argmax) as device tensors, or with
+        where=AM_HOST as numpy arrays filled by the library's host copy."""
         t = self.torch
-        F, V, _ = self.counts()
-        dev = self.device
-        out = dict(offsets=t.empty(F + 1, dtype=t.int64, device=dev), ids=t.empty(V, dtype=t.int32, device=dev),
-                   verts=t.empty((V, 3), dtype=t.float64, device=dev), nbr=t.empty(V, dtype=t.int64, device=dev),
-                   codes=t.empty((F, self.W), dtype=t.int64, device=dev), argmax=t.empty(F, dtype=t.int32, device=dev),
-                   shape=t.empty(F, dtype=t.int32, device=dev))
+        F, V, _, _ = self.counts()
+        if where == AM_HOST:
+            out = dict(offsets=np.empty(F + 1, np.int64), ids=np.empty(V, np.int32), verts=np.empty((V, 3)),
+                       nbr=np.empty(V, np.int64), codes=np.empty((F, self.W), np.int64), argmax=np.empty(F, np.int32),
+                       shape=np.empty(F, np.int32))
+            ptr = {k: C.c_void_p(v.ctypes.data) for k, v in out.items()}
+        else:
+            dev = self.device
+            out = dict(offsets=t.empty(F + 1, dtype=t.int64, device=dev), ids=t.empty(V, dtype=t.int32, device=dev),
+                       verts=t.empty((V, 3), dtype=t.float64, device=dev), nbr=t.empty(V, dtype=t.int64, device=dev),
+                       codes=t.empty((F, self.W), dtype=t.int64, device=dev),
+                       argmax=t.empty(F, dtype=t.int32, device=dev), shape=t.empty(F, dtype=t.int32, device=dev))
+            ptr = {k: _p(v) for k, v in out.items()}
         fn = self.L.am_fetch_sorted if sorted else self.L.am_fetch
-        self._check(fn(self.h, _p(out["offsets"]), _p(out["ids"]), _p(out["verts"]), _p(out["nbr"]),
-                       _p(out["codes"]), _p(out["argmax"]), _p(out["shape"])))
+        self._check(fn(self.h, int(where), ptr["offsets"], ptr["ids"], ptr["verts"], ptr["nbr"], ptr["codes"],
+                       ptr["argmax"], ptr["shape"]))
         return out
 
 

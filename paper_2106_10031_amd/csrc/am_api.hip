@@ -12,8 +12,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/am.h"
@@ -25,7 +27,9 @@ void launch_clip(const DevNet &, const uint64_t *, const int *, const uint64_t *
                  const Candidates &, unsigned long long, Counters *, const PropArgs &, hipStream_t);
 void launch_clip_f32(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, long long,
                      long long, long long, const float *, const ClipOut &, const Candidates &, unsigned long long,
-                     Counters *, double, double, int *, unsigned long long *, const PropArgs &, hipStream_t);
+                     Counters *, double, double, double, int *, unsigned long long *, const PropArgs &, hipStream_t);
+void launch_calib_split(const DevNet &, const uint64_t *, const int *, long long, const double *, const float *,
+                        const int *, const int *, const double *, int, unsigned long long *, hipStream_t);
 void launch_prop_score(const PropNet &, const float *, long long, float *, hipStream_t);
 long long prop_param_count();
 int prop_grad_blocks();
@@ -42,6 +46,7 @@ size_t fused_lds_bytes(const DevNet &);
 hipError_t prepare_fused(size_t);
 size_t chain_res_lds_bytes(const DevNet &);
 hipError_t prepare_chain_res(size_t);
+int prepare_chain_lb(const DevNet &, size_t);
 void launch_rows_unpad(const DevNet &, long long, const void *, bool, double *, hipStream_t);
 void launch_insert(const DevNet &, const Candidates &, const CellArrays &, unsigned long long *, unsigned long long,
                    Counters *, unsigned long long, long long, hipStream_t);
@@ -54,13 +59,16 @@ void launch_chain_dev(const DevNet &, const uint64_t *, const int *, Counters *,
                       hipStream_t);
 void launch_clip_dev(const DevNet &, const uint64_t *, const int *, const uint64_t *, const int *, Counters *,
                      long long, long long, const double *, const ClipOut &, const Candidates &, unsigned long long,
-                     hipStream_t);
+                     const PropArgs &, hipStream_t);
+void launch_split_step_dev(const DevNet &, const uint64_t *, const int *, const int *, const uint64_t *, const int *,
+                           Counters *, long long, long long, double *, const ClipOut &, const Candidates &,
+                           unsigned long long, double, double, double, int *, int, const PropArgs &, hipStream_t);
 hipError_t launch_sort_cells(const unsigned *, long long, long long, unsigned *, int *, int *, void *, size_t,
                              hipStream_t);
 void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t,
                     long long = 0, long long = 0);
 void launch_codes(const DevNet &, const double *, const int *, long long, uint64_t *, int *, double *, hipStream_t);
-void launch_seed_rays(const DevNet &, const double *, const double *, const int *, long long, int, uint64_t *, int *,
+void launch_seed_rays(const DevNet &, const double *, const double *, const int *, long long, double, int, uint64_t *, int *,
                       int *, int *, hipStream_t);
 void launch_seed_st(const DevNet &, const double *, const int *, long long, int, uint64_t *, int *, int *, int *,
                     int *, double *, hipStream_t);
@@ -127,12 +135,14 @@ struct am_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    am_allocator alloc{};        // all zero: hipMalloc / hipFree
 
     // network
     bool loaded = false;
     DevNet dn{};
     double *d_weights = nullptr;
     double *d_wfrag = nullptr;
+    float *d_wfrag32 = nullptr;   // the fragments as FP32 when every weight is an FP32 number
     double *d_wcol = nullptr;
     uint16_t *d_wfrag16 = nullptr;
     int *d_fb_list = nullptr;                 // cells the split-BF16 pass hands to FP64
@@ -205,6 +215,7 @@ struct am_ctx {
     // learned form: scorer weights (FP16 matrices, FP32 vectors), counters,
     // collection buffers (caller-owned) and training scratch
     bool prop_loaded = false;
+    long long prop_version = 0;
     PropArgs prop{};
     char *d_prop_w = nullptr;
     unsigned long long *d_prop_stats = nullptr;
@@ -230,6 +241,28 @@ struct am_ctx {
     char *d_sf_tmp = nullptr;
     size_t sf_tmp = 0;
 
+    // staging of an AM_HOST fetch (grown when a call needs more)
+    char *d_hstage = nullptr;
+    size_t hstage_bytes = 0;
+
+    // asynchronous march: the worker thread, its result
+    std::thread worker;
+    std::atomic<bool> busy{false};
+    am_status async_status = AM_OK;
+    am_march_stats async_stats{};
+
+    // split-BF16 certificate of the loaded net, measured on a march's first
+    // cells (calibrate_split): relative row error per unit of vertex
+    // sensitivity, sign-test margin, vertices measured
+    bool calib_ok = false;
+    double calib_eps = 0.0, calib_margin = 0.0;
+    long long calib_vertices = 0;
+    unsigned long long *d_calib = nullptr;
+
+    // simplification scratch (grown when a call needs more)
+    char *d_qecd = nullptr;
+    size_t qecd_bytes = 0;
+
     // last result
     bool have_result = false;
     long long res_cells = 0, res_faces = 0, res_fverts = 0;
@@ -238,6 +271,7 @@ struct am_ctx {
 namespace {
 
 constexpr long long kChainBucket[3] = {1LL << 11, 1LL << 13, 1LL << 15};
+constexpr int kChainVariants = 8;
 
 int chain_groups(const am_ctx *ctx, long long n, int forced) {
     if (forced > 0) return forced;
@@ -263,21 +297,32 @@ am_status fail(am_ctx *c, am_status s, const char *fmt, ...) {
             return fail(ctx, AM_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
     } while (0)
 
+// Device memory of the context: the caller's allocator when one was given to
+// am_create, else hipMalloc / hipFree.
 template <class T>
-void dfree(T *&p) {
-    if (p) (void)hipFree((void *)p);
+void dfree(am_ctx *c, T *&p) {
+    if (p) {
+        if (c->alloc.release) c->alloc.release(c->alloc.user, (void *)p, c->device, (void *)c->stream);
+        else (void)hipFree((void *)p);
+    }
     p = nullptr;
 }
 
 template <class T>
 am_status dalloc(am_ctx *ctx, T *&p, size_t count) {
-    dfree(p);
+    dfree(ctx, p);
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)&p, sizeof(T) * count);
+    const size_t bytes = sizeof(T) * count;
+    if (ctx->alloc.alloc) {
+        p = (T *)ctx->alloc.alloc(ctx->alloc.user, bytes, ctx->device, (void *)ctx->stream);
+        if (!p) return fail(ctx, AM_E_OOM, "the caller's allocator returned no memory for %zu bytes", bytes);
+        return AM_OK;
+    }
+    hipError_t e = hipMalloc((void **)&p, bytes);
     if (e != hipSuccess) {
         p = nullptr;
         (void)hipGetLastError();
-        return fail(ctx, AM_E_OOM, "hipMalloc of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
+        return fail(ctx, AM_E_OOM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     }
     return AM_OK;
 }
@@ -324,40 +369,40 @@ void drop_graph(am_ctx *c) {
 
 void free_march(am_ctx *c) {
     drop_graph(c);
-    dfree(c->d_codes);
-    dfree(c->d_am);
-    dfree(c->d_shape);
-    dfree(c->d_hash);
-    dfree(c->d_hints);
-    dfree(c->d_fm);
-    dfree(c->d_fids);
-    dfree(c->d_fverts);
-    dfree(c->d_fnbr);
-    dfree(c->d_fflags);
-    dfree(c->d_slots);
-    dfree(c->cand.parent);
-    dfree(c->cand.slot);
-    dfree(c->cand.unit);
-    dfree(c->cand.hash);
-    dfree(c->cand.kind);
-    dfree(c->cand.ref);
-    dfree(c->cand.cell);
-    dfree(c->cand.hint_prev);
-    dfree(c->cand.hint_next);
-    dfree(c->cand.key);
-    dfree(c->d_cell_key);
-    dfree(c->d_key_sorted);
-    dfree(c->d_order);
-    dfree(c->d_ids);
-    dfree(c->d_sort_tmp);
-    dfree(c->d_rows);
-    dfree(c->d_fb_list);
-    dfree(c->d_fb_count);
-    dfree(c->d_has);
-    dfree(c->d_fidx);
-    dfree(c->d_mcount);
-    dfree(c->d_voff);
-    dfree(c->d_scan);
+    dfree(c, c->d_codes);
+    dfree(c, c->d_am);
+    dfree(c, c->d_shape);
+    dfree(c, c->d_hash);
+    dfree(c, c->d_hints);
+    dfree(c, c->d_fm);
+    dfree(c, c->d_fids);
+    dfree(c, c->d_fverts);
+    dfree(c, c->d_fnbr);
+    dfree(c, c->d_fflags);
+    dfree(c, c->d_slots);
+    dfree(c, c->cand.parent);
+    dfree(c, c->cand.slot);
+    dfree(c, c->cand.unit);
+    dfree(c, c->cand.hash);
+    dfree(c, c->cand.kind);
+    dfree(c, c->cand.ref);
+    dfree(c, c->cand.cell);
+    dfree(c, c->cand.hint_prev);
+    dfree(c, c->cand.hint_next);
+    dfree(c, c->cand.key);
+    dfree(c, c->d_cell_key);
+    dfree(c, c->d_key_sorted);
+    dfree(c, c->d_order);
+    dfree(c, c->d_ids);
+    dfree(c, c->d_sort_tmp);
+    dfree(c, c->d_rows);
+    dfree(c, c->d_fb_list);
+    dfree(c, c->d_fb_count);
+    dfree(c, c->d_has);
+    dfree(c, c->d_fidx);
+    dfree(c, c->d_mcount);
+    dfree(c, c->d_voff);
+    dfree(c, c->d_scan);
     c->cap_cells = 0;
     c->hcap = 0;
     c->cand_cap = 0;
@@ -368,17 +413,18 @@ void free_march(am_ctx *c) {
 
 void free_net(am_ctx *c) {
     drop_graph(c);
-    dfree(c->d_weights);
-    dfree(c->d_wfrag);
-    dfree(c->d_wcol);
-    dfree(c->d_wfrag16);
-    dfree(c->d_bias);
-    dfree(c->d_row_of_unit);
-    dfree(c->d_zobrist);
-    dfree(c->d_seed_codes);
-    dfree(c->d_seed_am);
-    dfree(c->d_seed_status);
-    dfree(c->d_seed_shape);
+    dfree(c, c->d_weights);
+    dfree(c, c->d_wfrag);
+    dfree(c, c->d_wfrag32);
+    dfree(c, c->d_wcol);
+    dfree(c, c->d_wfrag16);
+    dfree(c, c->d_bias);
+    dfree(c, c->d_row_of_unit);
+    dfree(c, c->d_zobrist);
+    dfree(c, c->d_seed_codes);
+    dfree(c, c->d_seed_am);
+    dfree(c, c->d_seed_status);
+    dfree(c, c->d_seed_shape);
     c->n_seeds = c->seed_cap = 0;
     c->loaded = false;
 }
@@ -461,21 +507,23 @@ am_status ensure_scan(am_ctx *ctx, long long n) {
 
 extern "C" {
 
-am_status am_create(am_ctx **out, int device, void *hip_stream) {
+am_status am_create(am_ctx **out, int device, void *hip_stream, const am_allocator *alloc) {
     if (!out) return AM_E_INVALID;
     *out = nullptr;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return AM_E_HIP;
     if (device < 0 || device >= count) return AM_E_INVALID;
+    if (alloc && (!alloc->alloc) != (!alloc->release)) return AM_E_INVALID;   // both or neither
     am_ctx *ctx = new am_ctx();
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    if (alloc) ctx->alloc = *alloc;
     if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void **)&ctx->h_ctr, sizeof(Counters)) != hipSuccess ||
-        hipMalloc((void **)&ctx->d_ctr, sizeof(Counters)) != hipSuccess ||
+        dalloc(ctx, ctx->d_ctr, 1) != AM_OK ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
         hipEventCreate(&ctx->evk[0]) != hipSuccess || hipEventCreate(&ctx->evk[1]) != hipSuccess ||
         hipEventCreate(&ctx->evk[2]) != hipSuccess || hipEventCreate(&ctx->evk[3]) != hipSuccess) {
-        delete ctx;
+        am_destroy(ctx);
         return AM_E_HIP;
     }
     if (noalloc_scratch_init(device) != hipSuccess) {
@@ -493,6 +541,7 @@ am_status am_create(am_ctx **out, int device, void *hip_stream) {
 
 void am_destroy(am_ctx *ctx) {
     if (!ctx) return;
+    if (ctx->worker.joinable()) ctx->worker.join();
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
@@ -501,27 +550,30 @@ void am_destroy(am_ctx *ctx) {
     ctx->cap_stream = nullptr;
     free_march(ctx);
     free_net(ctx);
-    dfree(ctx->d_prop_w);
-    dfree(ctx->d_prop_stats);
-    dfree(ctx->d_prop_nsamp);
-    dfree(ctx->d_prop_scratch);
-    dfree(ctx->d_prop_loss);
-    dfree(ctx->d_weld_parent);
-    dfree(ctx->d_weld_root);
-    dfree(ctx->d_weld_vid);
-    dfree(ctx->d_weld_tmp);
-    dfree(ctx->d_weld_unpaired);
-    dfree(ctx->d_sf_cell);
-    dfree(ctx->d_sf_pa);
-    dfree(ctx->d_sf_pb);
-    dfree(ctx->d_sf_rank);
-    dfree(ctx->d_sf_ka);
-    dfree(ctx->d_sf_kb);
-    dfree(ctx->d_sf_mc);
-    dfree(ctx->d_sf_vo);
-    dfree(ctx->d_sf_tmp);
+    dfree(ctx, ctx->d_prop_w);
+    dfree(ctx, ctx->d_prop_stats);
+    dfree(ctx, ctx->d_prop_nsamp);
+    dfree(ctx, ctx->d_prop_scratch);
+    dfree(ctx, ctx->d_prop_loss);
+    dfree(ctx, ctx->d_weld_parent);
+    dfree(ctx, ctx->d_weld_root);
+    dfree(ctx, ctx->d_weld_vid);
+    dfree(ctx, ctx->d_weld_tmp);
+    dfree(ctx, ctx->d_weld_unpaired);
+    dfree(ctx, ctx->d_sf_cell);
+    dfree(ctx, ctx->d_sf_pa);
+    dfree(ctx, ctx->d_sf_pb);
+    dfree(ctx, ctx->d_sf_rank);
+    dfree(ctx, ctx->d_sf_ka);
+    dfree(ctx, ctx->d_sf_kb);
+    dfree(ctx, ctx->d_sf_mc);
+    dfree(ctx, ctx->d_sf_vo);
+    dfree(ctx, ctx->d_sf_tmp);
+    dfree(ctx, ctx->d_qecd);
+    dfree(ctx, ctx->d_hstage);
+    dfree(ctx, ctx->d_calib);
     if (ctx->h_prop_loss) (void)hipHostFree(ctx->h_prop_loss);
-    dfree(ctx->d_ctr);
+    dfree(ctx, ctx->d_ctr);
     if (ctx->h_ctr) (void)hipHostFree(ctx->h_ctr);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -532,7 +584,11 @@ void am_destroy(am_ctx *ctx) {
     delete ctx;
 }
 
-const char *am_last_error(const am_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *am_last_error(const am_ctx *ctx) {
+    if (!ctx) return "null context";
+    if (ctx->busy) return "an asynchronous march is running on this context (am_wait)";
+    return ctx->err.c_str();
+}
 
 static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, const double *shape_bias);
 
@@ -540,12 +596,14 @@ am_status am_load_net(am_ctx *ctx, const am_net_desc *nd) { return load_impl(ctx
 
 am_status am_load_batch(am_ctx *ctx, const am_net_desc *nd, int32_t n_shapes, const double *shape_bias) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (n_shapes < 1 || !shape_bias) return fail(ctx, AM_E_INVALID, "need n_shapes >= 1 and a bias table");
     return load_impl(ctx, nd, n_shapes, shape_bias);
 }
 
 static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, const double *shape_bias) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!nd || !nd->width || nd->n_layers < 2 || nd->n_layers > kMaxLayers || nd->n_blocks < 1 ||
         nd->n_blocks > kMaxBlocks || !nd->blk_dst || !nd->blk_src || !nd->blk_w || !nd->bias)
         return fail(ctx, AM_E_INVALID, "bad network descriptor (layers 2..%d, blocks 1..%d)", kMaxLayers,
@@ -553,6 +611,15 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     TRY(set_device(ctx));
     const int L2 = nd->n_layers;
     if (nd->width[0] != 3) return fail(ctx, AM_E_INVALID, "width[0] must be 3");
+    if (nd->dtype != AM_F64 && nd->dtype != AM_F32) return fail(ctx, AM_E_INVALID, "dtype must be AM_F64 or AM_F32");
+    if (nd->n_heads != 0 && nd->n_heads != nd->width[L2 - 1])
+        return fail(ctx, AM_E_INVALID, "n_heads %d differs from the head layer's width %d", nd->n_heads,
+                    nd->width[L2 - 1]);
+    const bool f32src = nd->dtype == AM_F32;
+    // element i of a source array, widened exactly to FP64
+    auto src_at = [f32src](const void *a, size_t i) {
+        return f32src ? (double)((const float *)a)[i] : ((const double *)a)[i];
+    };
     for (int l = 1; l < L2; ++l)
         if (nd->width[l] < 1) return fail(ctx, AM_E_INVALID, "width[%d] < 1", l);
     long long N = 0;
@@ -607,10 +674,10 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
         dn.blk_off[b] = (long long)hw.size();
         hw.resize(hw.size() + (size_t)rows * ld, 0.0);
         double *dst = hw.data() + dn.blk_off[b];
-        const double *src = nd->blk_w[b];
+        const void *src = nd->blk_w[b];
         for (int i = 0; i < nd_; ++i)
             for (int k = 0; k < ns; ++k) {
-                const double w = src[(size_t)i * ns + k];
+                const double w = src_at(src, (size_t)i * ns + k);
                 if (!std::isfinite(w)) return fail(ctx, AM_E_INVALID, "block %d has a non-finite weight", b);
                 dst[(size_t)i * ld + k] = w;
             }
@@ -644,14 +711,14 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
         dn.blk_ld32[b] = ld32;
         dn.blk_frag16_off[b] = (long long)(h16.size() / 8);
         if (sr == 0) continue;
-        const double *src = nd->blk_w[b];
+        const void *src = nd->blk_w[b];
         for (int mt = 0; mt < rows16 / 16; ++mt)
             for (int ks = 0; ks < ld32 / 32; ++ks)
                 for (int t = 0; t < 3; ++t)
                     for (int l = 0; l < 64; ++l)
                         for (int u = 0; u < 8; ++u) {
                             const int i = mt * 16 + l % 16, k = ks * 32 + 8 * (l / 16) + u;
-                            double w = (i < nd_ && k < ns) ? src[(size_t)i * ns + k] : 0.0;
+                            double w = (i < nd_ && k < ns) ? src_at(src, (size_t)i * ns + k) : 0.0;
                             uint16_t term = 0;
                             for (int tt = 0; tt <= t; ++tt) {   // w = h + m + l, each the rounded remainder
                                 term = bf16_bits((float)w);
@@ -664,7 +731,7 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     for (int sh = 0; sh < n_shapes; ++sh)
         for (int l = 1; l < L2; ++l)
             for (int k = 0; k < nd->width[l]; ++k) {
-                const double v = shape_bias ? shape_bias[(size_t)sh * boff + dn.bias_off[l] + k] : nd->bias[l][k];
+                const double v = shape_bias ? shape_bias[(size_t)sh * boff + dn.bias_off[l] + k] : src_at(nd->bias[l], k);
                 if (!std::isfinite(v)) return fail(ctx, AM_E_INVALID, "bias of shape %d layer %d is not finite", sh, l);
                 hb[(size_t)sh * boff + dn.bias_off[l] + k] = v;
             }
@@ -677,6 +744,23 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     uint64_t sm = 0x5eed0fa11c0de5ull;
     for (auto &z : zob) z = splitmix64(sm);
 
+    // FP32 copy of the fragments when it is exact (fitted nets are stored in FP32)
+    bool all_f32 = true;
+    for (double w : hf)
+        if ((double)(float)w != w) {
+            all_f32 = false;
+            break;
+        }
+    if (all_f32) {
+        std::vector<float> hf32(hf.begin(), hf.end());
+        TRY(dalloc(ctx, ctx->d_wfrag32, hf32.size()));
+        HIPCHK(hipMemcpy(ctx->d_wfrag32, hf32.data(), sizeof(float) * hf32.size(), hipMemcpyHostToDevice));
+    }
+    {
+        int wmax = 0;
+        for (int l = 1; l < L2 - 1; ++l) wmax = std::max(wmax, nd->width[l]);
+        dn.lb_kpad = (wmax + 31) & ~31;
+    }
     TRY(dalloc(ctx, ctx->d_weights, hw.size()));
     TRY(dalloc(ctx, ctx->d_wfrag, hf.size()));
     TRY(dalloc(ctx, ctx->d_wcol, hc.size()));
@@ -693,11 +777,15 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     HIPCHK(hipMemcpy(ctx->d_zobrist, zob.data(), sizeof(uint64_t) * zob.size(), hipMemcpyHostToDevice));
     dn.weights = ctx->d_weights;
     dn.wfrag = ctx->d_wfrag;
+    dn.wfrag32 = ctx->d_wfrag32;
     dn.wcol = ctx->d_wcol;
     dn.wfrag16 = ctx->d_wfrag16;
     dn.bias = ctx->d_bias;
     dn.row_of_unit = ctx->d_row_of_unit;
     dn.zobrist = ctx->d_zobrist;
+    ctx->calib_ok = false;   // the split-BF16 certificate is measured per net
+    dn.lb_ok = prepare_chain_lb(dn, ctx->lds_limit);
+    (void)hipGetLastError();
     ctx->dn = dn;
     // the fused kernel keeps the rows of four cells in LDS next to 4 x 1.75 KiB of clip scratch
     const size_t fb = fused_lds_bytes(dn);
@@ -724,6 +812,7 @@ am_status am_net_dims(const am_ctx *ctx, int32_t *n_hidden, int32_t *n_heads, in
 am_status am_codes(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n, uint64_t *codes,
                    int32_t *argmax, double *F) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n < 0 || (n > 0 && !pts)) return fail(ctx, AM_E_INVALID, "bad points");
     TRY(set_device(ctx));
@@ -735,6 +824,7 @@ am_status am_codes(am_ctx *ctx, const double *pts, const int32_t *shape_id, int6
 am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, int64_t n, int32_t precision,
                    double *rows) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n < 0 || (n > 0 && (!codes || !rows)) || precision < 0 || precision > 1)
         return fail(ctx, AM_E_INVALID, "bad arguments");
@@ -760,6 +850,7 @@ am_status am_chain(am_ctx *ctx, const uint64_t *codes, const int32_t *shape_id, 
 am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id, int64_t n,
                    int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n < 0 || max_m < 3 || max_m > kMaxPoly || (n > 0 && (!codes || !m || !ids || !verts)))
         return fail(ctx, AM_E_INVALID, "bad arguments (max_m must be 3..%d)", kMaxPoly);
@@ -788,6 +879,7 @@ am_status am_faces(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, co
 am_status am_faces_noalloc(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
                            int64_t n, int32_t max_m, int32_t *m, int32_t *ids, double *verts, int32_t *flags) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n < 0 || max_m < 3 || max_m > kMaxPoly || (n > 0 && (!codes || !m || !ids || !verts)))
         return fail(ctx, AM_E_INVALID, "bad arguments (max_m must be 3..%d)", kMaxPoly);
@@ -831,13 +923,16 @@ static am_status ensure_seed_cap(am_ctx *ctx, long long n) {
 }
 
 am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const int32_t *shape_id, int64_t n_rays,
-                       int32_t max_iter, int32_t *status_out) {
+                       double t_max, int32_t max_iter, int32_t *status_out) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n_rays <= 0 || !orig || !dir) return fail(ctx, AM_E_INVALID, "need at least one ray");
     TRY(set_device(ctx));
     TRY(ensure_seed_cap(ctx, n_rays));
-    launch_seed_rays(ctx->dn, orig, dir, shape_id, n_rays, max_iter > 0 ? max_iter : 200, ctx->d_seed_codes,
+    if (!std::isfinite(t_max)) return fail(ctx, AM_E_INVALID, "t_max must be finite");
+    launch_seed_rays(ctx->dn, orig, dir, shape_id, n_rays, t_max > 0.0 ? t_max : 1.0, max_iter > 0 ? max_iter : 200,
+                     ctx->d_seed_codes,
                      ctx->d_seed_am, ctx->d_seed_shape, ctx->d_seed_status, ctx->stream);
     if (status_out)
         HIPCHK(hipMemcpyAsync(status_out, ctx->d_seed_status, sizeof(int) * n_rays, hipMemcpyDeviceToDevice,
@@ -852,6 +947,7 @@ am_status am_seed_rays(am_ctx *ctx, const double *orig, const double *dir, const
 am_status am_seed_points_st(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n, int32_t max_iter,
                             int32_t *status_out, int32_t *iters_out, double *x_out) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n <= 0 || !pts) return fail(ctx, AM_E_INVALID, "need at least one start point");
     if (max_iter < 0 || max_iter > 100000) return fail(ctx, AM_E_INVALID, "max_iter must be 0..100000");
@@ -875,6 +971,7 @@ am_status am_seed_points_st(am_ctx *ctx, const double *pts, const int32_t *shape
 am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argmax, const int32_t *shape_id,
                         int64_t n) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n <= 0 || !codes) return fail(ctx, AM_E_INVALID, "need at least one seed cell");
     TRY(set_device(ctx));
@@ -897,6 +994,7 @@ am_status am_seed_cells(am_ctx *ctx, const uint64_t *codes, const int32_t *argma
 
 am_status am_seed_points(am_ctx *ctx, const double *pts, const int32_t *shape_id, int64_t n) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (n <= 0 || !pts) return fail(ctx, AM_E_INVALID, "need at least one seed point");
     TRY(set_device(ctx));
@@ -913,8 +1011,92 @@ am_status am_seed_points(am_ctx *ctx, const double *pts, const int32_t *shape_id
     return AM_OK;
 }
 
+static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats);
+
 am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
+    if (ctx->worker.joinable()) ctx->worker.join();   // an asynchronous march nobody waited for
+    if (opts && opts->async) {
+        const am_march_opts o = *opts;
+        ctx->busy = true;
+        ctx->worker = std::thread([ctx, o]() {
+            am_march_stats st{};
+            const am_status r = march_impl(ctx, &o, &st);
+            ctx->async_stats = st;
+            ctx->async_status = r;
+            ctx->busy = false;
+        });
+        return AM_OK;
+    }
+    return march_impl(ctx, opts, stats);
+}
+
+am_status am_wait(am_ctx *ctx, am_march_stats *stats) {
+    if (!ctx) return AM_E_INVALID;
+    if (!ctx->worker.joinable()) {
+        if (stats) *stats = am_march_stats{};
+        return fail(ctx, AM_E_STATE, "no asynchronous march to wait for");
+    }
+    ctx->worker.join();
+    if (stats) *stats = ctx->async_stats;
+    return ctx->async_status;
+}
+
+am_status am_busy(const am_ctx *ctx, int32_t *busy) {
+    if (!ctx || !busy) return AM_E_INVALID;
+    *busy = ctx->busy ? 1 : 0;
+    return AM_OK;
+}
+
+// Measures the split-BF16 certificate's constants for the loaded net on the
+// first n (<= chunk / 2) cells of the march: their FP64 rows and faces (at the
+// start of the rows and face buffers, which the march overwrites) against
+// their FP32 rows (k_calib_split).  row_eps = 8 x the largest ratio of vertex
+// error to first-order sensitivity, margin = 8 x the largest sign-test error
+// of a row at a vertex relative to |c|_1 (1 + |v|_inf); with fewer than 512
+// vertices measured, at least 5e-6 and 1.6e-5.
+static am_status calibrate_split(am_ctx *ctx, long long n) {
+    const DevNet &net = ctx->dn;
+    hipStream_t s = ctx->stream;
+    if (!ctx->d_calib) TRY(dalloc(ctx, ctx->d_calib, 3));
+    double *r64 = ctx->d_rows;
+    float *r32 = (float *)(ctx->d_rows + (size_t)n * net.R * 4);
+    launch_chain(net, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, r64, 1, s);
+    ClipOut out{};
+    out.m = ctx->d_fm;
+    out.ids = ctx->d_fids;
+    out.verts = ctx->d_fverts;
+    out.nbr = nullptr;
+    out.flags = ctx->d_fflags;
+    out.stride = kFaceSlots;
+    out.out_base = 0;
+    const Candidates none{};
+    launch_clip(net, ctx->d_codes, ctx->d_am, nullptr, nullptr, 0, n, nullptr, nullptr, 0, r64, out, none, 0, nullptr,
+                PropArgs{}, s);
+    launch_chain_bf16(net, ctx->d_codes, ctx->d_shape, 0, n, r32, s);
+    HIPCHK(hipMemsetAsync(ctx->d_calib, 0, 3 * sizeof(unsigned long long), s));
+    launch_calib_split(net, ctx->d_codes, ctx->d_am, n, r64, r32, ctx->d_fm, ctx->d_fids, ctx->d_fverts, kFaceSlots,
+                       ctx->d_calib, s);
+    unsigned long long h[3] = {0, 0, 0};
+    HIPCHK(hipMemcpyAsync(h, ctx->d_calib, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    double ratio = 0.0, marg = 0.0;
+    memcpy(&ratio, &h[0], sizeof ratio);
+    memcpy(&marg, &h[1], sizeof marg);
+    ctx->calib_vertices = (long long)h[2];
+    ctx->calib_eps = std::max(1e-7, 8.0 * ratio);
+    ctx->calib_margin = std::max(1e-7, 8.0 * marg);
+    if (ctx->calib_vertices < 512) {
+        ctx->calib_eps = std::max(ctx->calib_eps, 5e-6);
+        ctx->calib_margin = std::max(ctx->calib_margin, 1.6e-5);
+    }
+    ctx->calib_ok = true;
+    return AM_OK;
+}
+
+static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats) {
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (ctx->n_seeds <= 0) return fail(ctx, AM_E_STATE, "no seeds");
     TRY(set_device(ctx));
@@ -936,11 +1118,11 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
                     fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
     if (o.propose < 0 || o.propose > 3) return fail(ctx, AM_E_INVALID, "propose must be 0..3");
-    if (o.chain_groups < 0 || o.chain_groups > 5)
-        return fail(ctx, AM_E_INVALID, "chain_groups must be 0..5");
+    if (o.chain_groups < 0 || o.chain_groups > kChainVariants)
+        return fail(ctx, AM_E_INVALID, "chain_groups must be 0..%d", kChainVariants);
     if (o.graph_steps < 0 || o.graph_steps > 64) return fail(ctx, AM_E_INVALID, "graph_steps must be 0..64");
-    if (o.graph_steps > 0 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2))
-        return fail(ctx, AM_E_INVALID, "device-driven steps run the plain FP64 split path");
+    if (o.graph_steps > 0 && (ctx->prop.samples || o.kernel_path == 2))
+        return fail(ctx, AM_E_INVALID, "device-driven steps run the split path without sample collection");
     if (o.face_routine < 0 || o.face_routine > 1) return fail(ctx, AM_E_INVALID, "face_routine must be 0 or 1");
     if (o.face_routine == 1 && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.kernel_path == 2 ||
                                 o.graph_steps > 0))
@@ -962,11 +1144,6 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     } else {
         pa.stats = nullptr;
     }
-    // default margin: the largest sign-test error of the split-BF16 rows at an
-    // exact vertex, relative to |c|_1 (1 + |v|_inf), was 1.3e-6 over 4,000
-    // vertices of the 6x90 sphere-union fit; each vertex adds its own error
-    // estimate to this margin
-    const double margin = o.margin > 0.0 ? o.margin : 4e-6;
     const double vtol = o.vertex_tol > 0.0 ? o.vertex_tol : 1e-5;
     am_march_stats st{};
     st.fused = fused ? 1 : 0;
@@ -1005,6 +1182,17 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         return fail(ctx, AM_E_SEED, "no ray produced a seed");
     }
 
+    // the split-BF16 certificate of this net: measured once, on up to 2048
+    // seed cells, before their faces are computed for the march
+    if (o.precision == 1 && !ctx->calib_ok) TRY(calibrate_split(ctx, std::min<long long>(hi, 2048)));
+    // sign-test margin: the caller's, else the measured one; each vertex adds
+    // its own error estimate to it
+    const double margin = o.margin > 0.0 ? o.margin : ctx->calib_margin;
+    if (o.precision == 1) {
+        st.split_row_eps = ctx->calib_eps;
+        st.split_margin = margin;
+        st.calib_vertices = ctx->calib_vertices;
+    }
     ClipOut out{};
     out.m = ctx->d_fm;
     out.ids = ctx->d_fids;
@@ -1014,12 +1202,40 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     out.stride = kFaceSlots;
     out.out_base = 0;
     const long long seed_cells = hi;
+    // one device-driven step (graph_steps > 0): chain and clip of the range the
+    // counters hold (split-BF16 with its FP64 redo, or FP64), then the hash
+    // kernels; resolve takes the next range.  Events e[0..3], when given, mark
+    // the chain, clip and hash phases.
+    const long long gchunk = std::min<long long>(ctx->chunk_cells, 1LL << 14);
+    int variant = chain_groups(ctx, gchunk, o.chain_groups);
+    if (variant == 5) variant = 1;   // the gathered tile needs a sorted step
+    auto dev_step = [&](hipStream_t q, hipEvent_t *e) -> hipError_t {
+        hipError_t r = hipSuccess;
+        if (e) r = hipEventRecord(e[0], q);
+        if (o.precision == 1) {
+            launch_split_step_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_ctr,
+                                  gchunk, seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, margin, vtol,
+                                  ctx->calib_eps, ctx->d_fb_list, variant, pa, q);
+            if (e && r == hipSuccess) r = hipEventRecord(e[1], q);   // the split step is timed as chain
+        } else {
+            launch_chain_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_ctr, gchunk, ctx->d_rows, variant, q);
+            if (e && r == hipSuccess) r = hipEventRecord(e[1], q);
+            launch_clip_dev(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_ctr, gchunk, seed_cells,
+                            ctx->d_rows, out, ctx->cand, ctx->cand_cap, pa, q);
+        }
+        if (e && r == hipSuccess) r = hipEventRecord(e[2], q);
+        const long long nh = gchunk * 6;
+        launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, nh, q);
+        launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
+                      ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape, ctx->d_slots,
+                      ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, q);
+        launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, q, gchunk, cap);
+        if (e && r == hipSuccess) r = hipEventRecord(e[3], q);
+        return r;
+    };
     if (o.graph_steps > 0 && o.time_kernels) {
         // device-driven steps launched one by one (no graph), graph_steps per
         // counter read, HIP events around each kernel class of every step
-        const long long gchunk = std::min<long long>(ctx->chunk_cells, 1LL << 14);
-        int variant = chain_groups(ctx, gchunk, o.chain_groups);
-        if (variant == 5) variant = 1;
         const size_t nev = (size_t)o.graph_steps * 4;
         while (ctx->evs.size() < nev) {
             hipEvent_t e = nullptr;
@@ -1031,19 +1247,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             const long long run0 = (long long)ctx->h_ctr->steps_run;
             for (int k = 0; k < o.graph_steps; ++k) {
                 hipEvent_t *e = ctx->evs.data() + 4 * k;
-                HIPCHK(hipEventRecord(e[0], s));
-                launch_chain_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_ctr, gchunk, ctx->d_rows, variant, s);
-                HIPCHK(hipEventRecord(e[1], s));
-                launch_clip_dev(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_ctr, gchunk,
-                                seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, s);
-                HIPCHK(hipEventRecord(e[2], s));
-                const long long nh = gchunk * 6;
-                launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, nh, s);
-                launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
-                              ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape,
-                              ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, s);
-                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s, gchunk, cap);
-                HIPCHK(hipEventRecord(e[3], s));
+                HIPCHK(dev_step(s, e));
             }
             HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -1082,15 +1286,19 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
         lo = hi = 0;
     } else if (o.graph_steps > 0) {
         // device-driven steps, graph_steps per graph launch, one counter read
-        // per launch (plain FP64 form, dense chain tiles)
-        const long long gchunk = std::min<long long>(ctx->chunk_cells, 1LL << 14);
-        int variant = chain_groups(ctx, gchunk, o.chain_groups);
-        if (variant == 5) variant = 1;
+        // per launch
+        auto bits = [](double x) {
+            long long b;
+            memcpy(&b, &x, sizeof b);
+            return b;
+        };
         const std::vector<long long> key = {(long long)o.graph_steps, gchunk, variant, (long long)ctx->d_codes,
                                             (long long)ctx->d_rows, (long long)ctx->cand.parent,
                                             (long long)ctx->d_slots, (long long)hmask, (long long)ctx->d_fm,
                                             (long long)net.wfrag, (long long)net.bias, cap, seed_cells,
-                                            (long long)ctx->cand_cap};
+                                            (long long)ctx->cand_cap, (long long)o.precision, (long long)o.propose,
+                                            bits(margin), bits(vtol), bits(ctx->calib_eps),
+                                            (long long)ctx->d_fb_list, (long long)pa.stats, ctx->prop_version};
         if (!ctx->graph_exec || ctx->graph_key != key) {
             if (ctx->graph_exec) {
                 HIPCHK(hipGraphExecDestroy(ctx->graph_exec));
@@ -1100,17 +1308,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             hipStream_t cs = ctx->cap_stream;
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < o.graph_steps; ++k) {
-                launch_chain_dev(net, ctx->d_codes, ctx->d_shape, ctx->d_ctr, gchunk, ctx->d_rows, variant, cs);
-                launch_clip_dev(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_ctr, gchunk,
-                                seed_cells, ctx->d_rows, out, ctx->cand, ctx->cand_cap, cs);
-                const long long nh = gchunk * 6;
-                launch_insert(net, ctx->cand, ca, ctx->d_slots, hmask, ctx->d_ctr, ctx->cand_cap, nh, cs);
-                launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
-                              ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape,
-                              ctx->d_slots, ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, cs);
-                launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, cs, gchunk, cap);
-            }
+            for (int k = 0; k < o.graph_steps; ++k) (void)dev_step(cs, nullptr);
             const hipError_t ce = hipStreamEndCapture(cs, &g);
             if (ce != hipSuccess) return fail(ctx, AM_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
             const hipError_t ie = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
@@ -1165,7 +1363,7 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
             if (tk) HIPCHK(hipEventRecord(ctx->evk[1], s));
             launch_clip_f32(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, lo, lo + n, seed_cells,
                             (const float *)ctx->d_rows, out, ctx->cand, ctx->cand_cap, ctx->d_ctr, margin, vtol,
-                            ctx->d_fb_list, ctx->d_fb_count, pa, s);
+                            ctx->calib_eps, ctx->d_fb_list, ctx->d_fb_count, pa, s);
             launch_chain(net, ctx->d_codes, ctx->d_shape, 0, n, ctx->d_fb_list, ctx->d_fb_count, ctx->d_rows,
                          chain_groups(ctx, n, o.chain_groups), s);
             launch_clip(net, ctx->d_codes, ctx->d_am, ctx->d_hash, ctx->d_hints, 0, n, ctx->d_fb_list,
@@ -1275,33 +1473,91 @@ am_status am_march(am_ctx *ctx, const am_march_opts *opts, am_march_stats *stats
     return AM_OK;
 }
 
-am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, int64_t *cells) {
-    if (!ctx || !ctx->have_result) return AM_E_STATE;
+am_status am_get_counts(const am_ctx *ctx, int64_t *faces, int64_t *face_verts, int64_t *tris, int64_t *cells) {
+    if (!ctx || ctx->busy || !ctx->have_result) return AM_E_STATE;
     if (faces) *faces = ctx->res_faces;
     if (face_verts) *face_verts = ctx->res_fverts;
+    if (tris) *tris = ctx->res_fverts - 2 * ctx->res_faces;
     if (cells) *cells = ctx->res_cells;
     return AM_OK;
 }
 
-am_status am_fetch(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr, uint64_t *codes,
-                   int32_t *argmax, int32_t *shape_id) {
+// Output arrays of a fetch, in caller memory (host or device).
+struct FetchOut {
+    int64_t *offsets;
+    int32_t *ids;
+    double *verts;
+    int64_t *nbr;
+    uint64_t *codes;
+    int32_t *argmax;
+    int32_t *shape_id;
+};
+
+static am_status fetch_device(am_ctx *ctx, bool sorted, const FetchOut &o);
+
+// AM_HOST: the device fetch into a staging buffer kept by the context, then
+// one copy per requested array into the caller's host memory.
+static am_status fetch_any(am_ctx *ctx, int32_t where, bool sorted, const FetchOut &o) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
+    if (ctx->busy) return AM_E_STATE;
+    if (where != AM_DEVICE && where != AM_HOST) return fail(ctx, AM_E_INVALID, "where must be AM_DEVICE or AM_HOST");
     if (!ctx->have_result) return fail(ctx, AM_E_STATE, "no march result");
+    if (where == AM_DEVICE) return fetch_device(ctx, sorted, o);
     TRY(set_device(ctx));
-    TRY(ensure_scan(ctx, std::max<long long>(ctx->res_cells, 1)));
-    HIPCHK(launch_fetch(ctx->dn, ctx->res_cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
-                        ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
-                        ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
-                        (long long *)nbr, codes, argmax, shape_id, ctx->stream));
+    const long long F = ctx->res_faces, V = ctx->res_fverts, Wd = ctx->dn.W;
+    const size_t sz[7] = {sizeof(int64_t) * (size_t)(F + 1), sizeof(int32_t) * (size_t)V, sizeof(double) * 3 * (size_t)V,
+                          sizeof(int64_t) * (size_t)V,     sizeof(uint64_t) * (size_t)(F * Wd),
+                          sizeof(int32_t) * (size_t)F,     sizeof(int32_t) * (size_t)F};
+    void *host[7] = {o.offsets, o.ids, o.verts, o.nbr, o.codes, o.argmax, o.shape_id};
+    size_t off[7], total = 0;
+    for (int k = 0; k < 7; ++k) {
+        off[k] = total;
+        if (host[k]) total += (sz[k] + 255) & ~(size_t)255;
+    }
+    if (total > ctx->hstage_bytes || !ctx->d_hstage) {
+        TRY(dalloc(ctx, ctx->d_hstage, total));
+        ctx->hstage_bytes = total;
+    }
+    char *b = ctx->d_hstage;
+    const FetchOut d{o.offsets ? (int64_t *)(b + off[0]) : nullptr, o.ids ? (int32_t *)(b + off[1]) : nullptr,
+                     o.verts ? (double *)(b + off[2]) : nullptr,   o.nbr ? (int64_t *)(b + off[3]) : nullptr,
+                     o.codes ? (uint64_t *)(b + off[4]) : nullptr, o.argmax ? (int32_t *)(b + off[5]) : nullptr,
+                     o.shape_id ? (int32_t *)(b + off[6]) : nullptr};
+    TRY(fetch_device(ctx, sorted, d));
+    for (int k = 0; k < 7; ++k)
+        if (host[k] && sz[k] > 0) HIPCHK(hipMemcpyAsync(host[k], b + off[k], sz[k], hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return AM_OK;
 }
 
-am_status am_fetch_sorted(am_ctx *ctx, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
+am_status am_fetch(am_ctx *ctx, int32_t where, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
+                   uint64_t *codes, int32_t *argmax, int32_t *shape_id) {
+    return fetch_any(ctx, where, false, FetchOut{offsets, ids, verts, nbr, codes, argmax, shape_id});
+}
+
+am_status am_fetch_sorted(am_ctx *ctx, int32_t where, int64_t *offsets, int32_t *ids, double *verts, int64_t *nbr,
                           uint64_t *codes, int32_t *argmax, int32_t *shape_id) {
-    if (!ctx) return AM_E_INVALID;
-    if (!ctx->have_result) return fail(ctx, AM_E_STATE, "no march result");
+    return fetch_any(ctx, where, true, FetchOut{offsets, ids, verts, nbr, codes, argmax, shape_id});
+}
+
+static am_status fetch_device(am_ctx *ctx, bool sorted, const FetchOut &o) {
+    int64_t *offsets = o.offsets;
+    int32_t *ids = o.ids;
+    double *verts = o.verts;
+    int64_t *nbr = o.nbr;
+    uint64_t *codes = o.codes;
+    int32_t *argmax = o.argmax;
+    int32_t *shape_id = o.shape_id;
     TRY(set_device(ctx));
     TRY(ensure_scan(ctx, std::max<long long>(ctx->res_cells, 1)));
+    if (!sorted) {
+        HIPCHK(launch_fetch(ctx->dn, ctx->res_cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
+                            ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
+                            ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
+                            (long long *)nbr, codes, argmax, shape_id, ctx->stream));
+        return AM_OK;
+    }
     const long long F = ctx->res_faces;
     if (F >= (1LL << 31)) return fail(ctx, AM_E_INVALID, "too many faces to sort");
     if (F > ctx->sf_cap || !ctx->d_sf_cell) {
@@ -1336,6 +1592,7 @@ am_status am_simplify(am_ctx *ctx, int64_t n_verts, const double *vxyz, int64_t 
                       int64_t *tri_out, int64_t *n_verts_out, int64_t *n_tris_out, int32_t *rounds_out,
                       int64_t *n_bad) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (n_verts <= 0 || n_tris <= 0 || !vxyz || !tri || !v_out || !tri_out)
         return fail(ctx, AM_E_INVALID, "need vertices, triangles and output buffers");
     if (3 * n_verts >= (1LL << 31) || 3 * n_tris >= (1LL << 31))   // 32-bit ids index 3-wide rows
@@ -1344,14 +1601,17 @@ am_status am_simplify(am_ctx *ctx, int64_t n_verts, const double *vxyz, int64_t 
     if (max_rounds <= 0) max_rounds = 256;
     if (max_rounds > 4096) return fail(ctx, AM_E_INVALID, "max_rounds must be at most 4096");
     TRY(set_device(ctx));
-    char *scratch = nullptr;
-    TRY(dalloc(ctx, scratch, qecd_scratch_bytes(n_verts, n_tris)));
+    const size_t qb = qecd_scratch_bytes(n_verts, n_tris);
+    if (qb > ctx->qecd_bytes || !ctx->d_qecd) {   // kept by the context, grown when needed
+        TRY(dalloc(ctx, ctx->d_qecd, qb));
+        ctx->qecd_bytes = qb;
+    }
+    char *scratch = ctx->d_qecd;
     long long Vo = 0, To = 0, bad = 0;
     int rounds = 0;
     const hipError_t e = run_qecd(vxyz, n_verts, (const long long *)tri, n_tris, boundary, target_tris, max_rounds,
                                   scratch, v_out, (long long *)tri_out, &Vo, &To, &rounds, &bad, ctx->stream);
     (void)hipStreamSynchronize(ctx->stream);
-    dfree(scratch);
     if (e != hipSuccess) return fail(ctx, AM_E_HIP, "simplification failed: %s", hipGetErrorString(e));
     if (n_verts_out) *n_verts_out = Vo;
     if (n_tris_out) *n_tris_out = To;
@@ -1366,6 +1626,7 @@ am_status am_weld(am_ctx *ctx, int64_t faces, const int64_t *offsets, const int3
                   const int32_t *argmax, const double *verts, int64_t corners, int64_t *corner_vertex,
                   double *vxyz, int64_t vxyz_rows, int64_t *n_vertices, int64_t *n_unpaired) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->loaded) return fail(ctx, AM_E_STATE, "no network loaded");
     if (faces < 0 || corners < 0 || vxyz_rows < 0) return fail(ctx, AM_E_INVALID, "negative size");
     if (corners >= (1LL << 31)) return fail(ctx, AM_E_INVALID, "at most 2^31 - 1 corners");
@@ -1418,6 +1679,7 @@ am_status am_weld(am_ctx *ctx, int64_t faces, const int64_t *offsets, const int3
 am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets, const int64_t *corner_vertex,
                        int64_t *tri, int64_t tri_rows) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (faces < 0 || tri_rows < 0) return fail(ctx, AM_E_INVALID, "negative size");
     if (faces > 0 && (!offsets || !corner_vertex || !tri))
         return fail(ctx, AM_E_INVALID, "offsets, corner_vertex and tri are required");
@@ -1439,8 +1701,8 @@ am_status am_triangles(am_ctx *ctx, int64_t faces, const int64_t *offsets, const
 am_status am_set_chain_groups(am_ctx *ctx, const int32_t *groups) {
     if (!ctx || !groups) return AM_E_INVALID;
     for (int b = 0; b < 4; ++b)
-        if (groups[b] < 1 || groups[b] > 5)
-            return fail(ctx, AM_E_INVALID, "chain tile variants are 1..5");
+        if (groups[b] < 1 || groups[b] > kChainVariants)
+            return fail(ctx, AM_E_INVALID, "chain tile variants are 1..%d", kChainVariants);
     for (int b = 0; b < 4; ++b) ctx->chain_g[b] = groups[b];
     return AM_OK;
 }
@@ -1453,30 +1715,36 @@ am_status am_get_chain_groups(const am_ctx *ctx, int32_t *groups) {
 
 am_status am_tune_chain(am_ctx *ctx, int32_t reps, float *ms_out) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->have_result || ctx->res_cells <= 0) return fail(ctx, AM_E_STATE, "tuning needs a finished march");
     if (reps < 1 || reps > 100) return fail(ctx, AM_E_INVALID, "reps must be 1..100");
     TRY(set_device(ctx));
-    const int gs[5] = {1, 2, 3, 4, 5};
+    const int nv = kChainVariants;
     const long long sizes[4] = {1LL << 10, 1LL << 12, 1LL << 14, 1LL << 16};
     hipStream_t s = ctx->stream;
     for (int b = 0; b < 4; ++b) {
         const long long n = std::min<long long>({sizes[b], ctx->res_cells, ctx->chunk_cells});
         float best = 0.f;
         int best_g = 1;
-        for (int gi = 0; gi < 5; ++gi) {
-            launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, gs[gi], s);
+        for (int gi = 0; gi < nv; ++gi) {
+            const int g = gi + 1;
+            if (g >= 6 && !((ctx->dn.lb_ok >> (g - 6)) & 1)) {   // cannot run on this net
+                if (ms_out) ms_out[b * nv + gi] = -1.f;
+                continue;
+            }
+            launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, g, s);
             HIPCHK(hipEventRecord(ctx->evk[0], s));
             for (int r = 0; r < reps; ++r)
-                launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, gs[gi], s);
+                launch_chain(ctx->dn, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, ctx->d_rows, g, s);
             HIPCHK(hipEventRecord(ctx->evk[1], s));
             HIPCHK(hipEventSynchronize(ctx->evk[1]));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, ctx->evk[0], ctx->evk[1]));
             ms /= (float)reps;
-            if (ms_out) ms_out[b * 5 + gi] = ms;
+            if (ms_out) ms_out[b * nv + gi] = ms;
             if (gi == 0 || ms < best) {
                 best = ms;
-                best_g = gs[gi];
+                best_g = g;
             }
         }
         ctx->chain_g[b] = best_g;
@@ -1491,6 +1759,7 @@ int64_t am_prop_param_count(void) { return prop_param_count(); }
 
 am_status am_prop_set(am_ctx *ctx, const float *params, int64_t n_params, int32_t k, float rho) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!params || n_params != prop_param_count())
         return fail(ctx, AM_E_INVALID, "the scorer has %lld parameters", prop_param_count());
     if (k < 1 || k > kPropK) return fail(ctx, AM_E_INVALID, "k must be 1..%d", kPropK);
@@ -1523,11 +1792,13 @@ am_status am_prop_set(am_ctx *ctx, const float *params, int64_t n_params, int32_
     ctx->prop.k = k;
     ctx->prop.rho = rho;
     ctx->prop_loaded = true;
+    ++ctx->prop_version;   // captured steps hold the scorer by value
     return AM_OK;
 }
 
 am_status am_prop_collect(am_ctx *ctx, float *samples, uint8_t *labels, int64_t cap, float rho) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     TRY(set_device(ctx));
     if (!samples || !labels || cap <= 0) {
         ctx->prop.samples = nullptr;
@@ -1562,6 +1833,7 @@ am_status am_prop_collected(am_ctx *ctx, int64_t *n) {
 am_status am_prop_grad(am_ctx *ctx, const float *X, const uint8_t *y, int64_t n, const float *params, float *grad,
                        double *loss) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (n <= 0 || !X || !y || !params || !grad) return fail(ctx, AM_E_INVALID, "bad arguments");
     TRY(set_device(ctx));
     const long long P = prop_param_count();
@@ -1583,6 +1855,7 @@ am_status am_prop_grad(am_ctx *ctx, const float *X, const uint8_t *y, int64_t n,
 
 am_status am_prop_adam(am_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step, float lr) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!params || !grad || !m || !v || step < 1 || !(lr > 0.f)) return fail(ctx, AM_E_INVALID, "bad arguments");
     TRY(set_device(ctx));
     launch_prop_adam(params, grad, m, v, step, lr, ctx->stream);
@@ -1592,6 +1865,7 @@ am_status am_prop_adam(am_ctx *ctx, float *params, const float *grad, float *m, 
 
 am_status am_prop_score(am_ctx *ctx, const float *X, int64_t n, float *z) {
     if (!ctx) return AM_E_INVALID;
+    if (ctx->busy) return AM_E_STATE;
     if (!ctx->prop_loaded) return fail(ctx, AM_E_STATE, "no proposal scorer loaded");
     if (n < 0 || (n > 0 && (!X || !z))) return fail(ctx, AM_E_INVALID, "bad arguments");
     TRY(set_device(ctx));

@@ -183,8 +183,8 @@ __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uin
 
 // With advance set (device-driven steps), one thread also ends the step and
 // takes the next step's range (up to chunk cells of the frontier, none after
-// an overflow) and clears the candidate count: nothing else in this kernel
-// reads the step fields or n_cand.
+// an overflow) and clears the candidate and fallback counts: nothing else in
+// this kernel reads the step fields, n_cand or fb_n.
 __device__ void next_step_range(Counters *c, unsigned long long chunk, unsigned long long cap_cells) {
     const unsigned long long cells = c->n_cells < cap_cells ? c->n_cells : cap_cells;
     const bool bad = c->overflow_cells || c->overflow_cand || c->overflow_hash;
@@ -194,6 +194,7 @@ __device__ void next_step_range(Counters *c, unsigned long long chunk, unsigned 
     if (n > chunk) n = chunk;
     c->step_n = n;
     c->n_cand = 0ull;
+    c->fb_n = 0ull;
 }
 
 __global__ __launch_bounds__(256) void k_resolve(Candidates cand, int *face_nbr, int stride, Counters *ctr,
@@ -287,10 +288,10 @@ __global__ __launch_bounds__(256) void k_codes(DevNet net, const double *pts, co
     }
 }
 
-// Dichotomy along o + t d, t in [0, 1]: keep a bracket with a sign change,
+// Dichotomy along o + t d, t in [0, t_max]: keep a bracket with a sign change,
 // halve it until both ends share one code, then take the linear root.
 __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *orig, const double *dir,
-                                                   const int *shape_id, long long n_rays, int max_iter,
+                                                   const int *shape_id, long long n_rays, double t_max, int max_iter,
                                                    uint64_t *seed_codes, int *seed_am, int *seed_shape,
                                                    int *status) {
     extern __shared__ double lds[];
@@ -310,12 +311,12 @@ __global__ __launch_bounds__(256) void k_seed_rays(DevNet net, const double *ori
         if (threadIdx.x == 0) seed_shape[r] = sh;
         double f_lo = wg_forward(net, sh, o, act, c_m, &a_lo);
         for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_lo[w] = c_m[w];
-        for (int i = 0; i < 3; ++i) x[i] = o[i] + d[i];
+        for (int i = 0; i < 3; ++i) x[i] = o[i] + t_max * d[i];
         double f_hi = wg_forward(net, sh, x, act, c_m, &a_hi);
         for (int w = threadIdx.x; w < net.W; w += blockDim.x) c_hi[w] = c_m[w];
         __syncthreads();
         int st = 0;
-        double t_lo = 0.0, t_hi = 1.0;
+        double t_lo = 0.0, t_hi = t_max;
         if (!sh_ok) {
             st = 3;   // shape id out of range
         } else if ((f_lo > 0.0) == (f_hi > 0.0)) {
@@ -695,11 +696,11 @@ void launch_codes(const DevNet &net, const double *pts, const int *shape_id, lon
 }
 
 void launch_seed_rays(const DevNet &net, const double *orig, const double *dir, const int *shape_id, long long n,
-                      int max_iter, uint64_t *seed_codes, int *seed_am, int *seed_shape, int *status,
+                      double t_max, int max_iter, uint64_t *seed_codes, int *seed_am, int *seed_shape, int *status,
                       hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_seed_rays, dim3(grid_for(n, 1, 8192)), dim3(256), forward_lds_bytes(net, 3), st, net,
-                       orig, dir, shape_id, n, max_iter, seed_codes, seed_am, seed_shape, status);
+                       orig, dir, shape_id, n, t_max, max_iter, seed_codes, seed_am, seed_shape, status);
 }
 
 void launch_seed_st(const DevNet &net, const double *pts, const int *shape_id, long long n, int max_iter,

@@ -54,6 +54,11 @@ struct DevNet {
     // wcol[blk_col_off + k * 16 ceil(n_dst / 16) + i] (gathered chain)
     const double *wcol;
     long long blk_col_off[kMaxBlocks];
+    // the FP64 fragments as FP32 values when every weight is exactly an FP32
+    // number (nullptr otherwise): half the bytes to stream, widened exactly
+    const float *wfrag32;
+    int lb_kpad;               // rows of the staged-B chain's LDS buffer (widest hidden layer, to 32)
+    int lb_ok;                 // bit v - 6 set: staged-B chain variant v (6, 7, 8) can run
     const double *bias;        // [S][bias_stride]: shape s, layer l at s * bias_stride + bias_off[l]
     const int *row_of_unit;    // [N + M] padded row of global unit g
     const uint64_t *zobrist;   // [N + M + S] keys of the cell fingerprint (units, heads, shapes)
@@ -149,6 +154,7 @@ struct Counters {
     unsigned long long pivot_fallback;   // ... and cells clipped instead
     unsigned long long max_frontier;     // device-driven steps: largest frontier seen
     unsigned long long n_cand_prev;      // the step's candidate count, copied by commit for resolve
+    unsigned long long fb_n;             // device-driven split-BF16 steps: cells handed to FP64
 };
 
 // ---------------------------------------------------------------- helpers

@@ -711,13 +711,11 @@ __device__ double inv_norm3(const double A[3][3]) {
     return fmax(r0, fmax(r1, r2)) / fabs(det);
 }
 
-// Relative error of the split-BF16 rows per unit of first-order vertex
-// sensitivity, a calibrated constant (not a bound): the largest ratio of vertex
-// error to |A^-1|_inf max_k (|A_k|_1 |x|_inf + |r_k|) / max(1, |x|_inf),
-// measured against FP64 rows with no vertex redone, was 3.6e-7 over all
-// 1,887,520 vertices of the 6x90 sphere-union fit and 8.4e-7 over all
-// 33,049,480 vertices of the 8x256 superquadric fit; 1.2e-6 is used.
-constexpr double kSplitRowEps = 1.2e-6;
+// The split-BF16 certificate scales each vertex's first-order sensitivity to
+// the rows, |A^-1|_inf max_k (|A_k|_1 |x|_inf + |r_k|) / max(1, |x|_inf), by a
+// relative row error eps measured for the loaded net (k_calib_split, on the
+// first cells of a march, against the FP64 chain and clip) and passed in
+// Fallback::row_eps.
 
 // Solves A x = r (3x3) by elimination with row pivoting; false if singular.
 __device__ bool solve3(double A[3][3], double r[3], double x[3]) {
@@ -757,6 +755,7 @@ struct Fallback {
     int *list;
     unsigned long long *count;
     unsigned long long cap;
+    double row_eps;    // relative error of the FP32 rows per unit of vertex sensitivity
 };
 
 // Precision check of a face computed from approximate rows: true when a
@@ -1518,7 +1517,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         double est = 0.0;
         if (lane < m) {
             const double xm = fmax(fabs(x[0]), fmax(fabs(x[1]), fabs(x[2])));
-            est = kSplitRowEps * vsens_a * (vsens_b * xm + vsens_r) / fmax(1.0, xm);
+            est = fb.row_eps * vsens_a * (vsens_b * xm + vsens_r) / fmax(1.0, xm);
             shaky = !(est <= vertex_tol);
         }
         const bool redo = m == 0 || flags != 0 || n_near > kNearMax || ballot(shaky) != 0 ||
@@ -1602,6 +1601,91 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
 }
 
 
+
+// ---- calibration of the split-BF16 certificate.  For cells whose faces the
+// FP64 chain and clip produced (m, ids, verts), each vertex is solved again
+// from the FP32 rows of its two edges and the face plane, as the split form
+// does, and compared with the FP64 vertex:
+//   ratio  = |x32 - x64|_inf / max(1, |x64|_inf) / sensitivity(FP32 rows),
+//   margin = max over hidden and head rows of |(c32 - c64) . [x64; 1]| /
+//            (|c64|_1 (1 + |x64|_inf)).
+// The largest of each over all vertices goes to out[0], out[1] (non-negative
+// doubles compared as integers by atomicMax); out[2] counts the vertices.
+// One wave per cell.
+__global__ __launch_bounds__(256) void k_calib_split(DevNet net, const uint64_t *__restrict__ codes,
+                                                     const int *__restrict__ argmax, long long n,
+                                                     const double *__restrict__ rows64,
+                                                     const float *__restrict__ rows32, const int *__restrict__ fm,
+                                                     const int *__restrict__ fids, const double *__restrict__ fverts,
+                                                     int stride, unsigned long long *out) {
+    const int lane = lane_id();
+    const long long cell = 4LL * blockIdx.x + (threadIdx.x >> 6);
+    if (cell >= n) return;
+    const int m = fm[cell];
+    if (m < 3 || m > stride) return;
+    const uint64_t *code = codes + cell * net.W;
+    const int am = argmax ? argmax[cell] : 0;
+    if (am < 0 || am >= net.M) return;
+    const double *r64 = rows64 + cell * (long long)net.R * 4;
+    const float *r32 = rows32 + cell * (long long)net.R * 4;
+    double ratio = 0.0, marg = 0.0;
+    double x64[3] = {0.0, 0.0, 0.0};
+    if (lane < m) {
+        const long long o = cell * stride + lane;
+        const int e = fids[o];
+        const int ep = fids[cell * stride + (lane == 0 ? m - 1 : lane - 1)];
+        for (int k = 0; k < 3; ++k) x64[k] = fverts[o * 3 + k];
+        double ca[4], cb[4];
+        constraint_row(net, ep, code, am, r32, 4, ca);
+        constraint_row(net, e, code, am, r32, 4, cb);
+        const float *aF = r32 + (long long)net.row_of_unit[net.N + am] * 4;
+        double A[3][3] = {{ca[0], ca[1], ca[2]}, {cb[0], cb[1], cb[2]}, {aF[0], aF[1], aF[2]}};
+        double rr[3] = {-ca[3], -cb[3], -(double)aF[3]};
+        const double an = inv_norm3(A);
+        const double s0 = fabs(A[0][0]) + fabs(A[0][1]) + fabs(A[0][2]);
+        const double s1 = fabs(A[1][0]) + fabs(A[1][1]) + fabs(A[1][2]);
+        const double s2 = fabs(A[2][0]) + fabs(A[2][1]) + fabs(A[2][2]);
+        const double rmax = fmax(fabs(rr[0]), fmax(fabs(rr[1]), fabs(rr[2])));
+        double x32[3];
+        if (solve3(A, rr, x32)) {
+            const double xm = fmax(fabs(x64[0]), fmax(fabs(x64[1]), fabs(x64[2])));
+            const double sens = an * (fmax(s0, fmax(s1, s2)) * xm + rmax) / fmax(1.0, xm);
+            const double err = fmax(fabs(x32[0] - x64[0]), fmax(fabs(x32[1] - x64[1]), fabs(x32[2] - x64[2])));
+            if (sens > 0.0 && sens < __builtin_inf()) ratio = err / fmax(1.0, xm) / sens;
+        }
+    }
+    // sign-test error of every hidden and head row at every vertex
+    for (int i = 0; i < m; ++i) {
+        const double xi = bcast(x64[0], i), yi = bcast(x64[1], i), zi = bcast(x64[2], i);
+        const double sc = 1.0 + fmax(fabs(xi), fmax(fabs(yi), fabs(zi)));
+        for (int g = lane; g < net.N + net.M; g += kWave) {
+            const long long row = (long long)net.row_of_unit[g] * 4;
+            const double *a = r64 + row;
+            const float *b = r32 + row;
+            const double d = ((double)b[0] - a[0]) * xi + ((double)b[1] - a[1]) * yi + ((double)b[2] - a[2]) * zi +
+                             ((double)b[3] - a[3]);
+            const double cn = fabs(a[0]) + fabs(a[1]) + fabs(a[2]) + fabs(a[3]);
+            if (cn > 0.0) marg = fmax(marg, fabs(d) / (cn * sc));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ratio = fmax(ratio, __shfl_xor(ratio, o, kWave));
+        marg = fmax(marg, __shfl_xor(marg, o, kWave));
+    }
+    if (lane == 0) {
+        if (ratio == ratio) atomicMax(&out[0], (unsigned long long)__double_as_longlong(ratio));
+        if (marg == marg) atomicMax(&out[1], (unsigned long long)__double_as_longlong(marg));
+        atomicAdd(&out[2], (unsigned long long)m);
+    }
+}
+
+void launch_calib_split(const DevNet &net, const uint64_t *codes, const int *argmax, long long n,
+                        const double *rows64, const float *rows32, const int *fm, const int *fids,
+                        const double *fverts, int stride, unsigned long long *out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_calib_split, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net, codes, argmax, n, rows64,
+                       rows32, fm, fids, fverts, stride, out);
+}
 
 // Positions 0..count-1 of a step: cell lo + p, or list[p] (count read on the
 // device from *list_count, at most cap).
@@ -1691,6 +1775,185 @@ __global__ __launch_bounds__(256) void k_chain_f64_gather(DevNet net, const uint
                           cnt_lds);
 }
 
+// ---- staged-B chain.  The producing layer writes its output, masked by the
+// cells' codes (diag(s_l)) and zero padded, into one LDS buffer that the next
+// layer reads as its B operand: the K loop has no code tests, no branches and
+// no global B loads.  Weight fragments (A) stream from L2 one batch of K-steps
+// ahead of the MFMAs that use them; when every weight is an FP32 number they
+// stream as FP32 (half the bytes) and are widened exactly in registers.
+// Wave w owns the 16-row output tiles w, w + nwaves, ... (at most MTW) for all
+// 4 G cells of the workgroup and keeps their accumulators until the layer's
+// barrier, so a single LDS buffer suffices.  Blocks from the input use
+// Z_0 = [I | 0]; a source other than the previous layer (a shortcut between
+// hidden layers) is read from the rows in global memory with code tests.
+constexpr int kLbKSteps = 8;    // A fragments loaded ahead, per output tile slot x MTW
+
+template <typename AT>
+__device__ __forceinline__ const AT *lb_frags(const DevNet &net);
+template <>
+__device__ __forceinline__ const double *lb_frags<double>(const DevNet &net) { return net.wfrag; }
+template <>
+__device__ __forceinline__ const float *lb_frags<float>(const DevNet &net) { return net.wfrag32; }
+
+template <int G, int MTW, typename AT>
+__global__ __launch_bounds__(MTW == 1 ? 1024 : 512) void k_chain_lb(DevNet net, const uint64_t *__restrict__ codes,
+                                                   const int *__restrict__ cell_shape, CellRange rg,
+                                                   double *__restrict__ rows) {
+    constexpr int NC = 4 * G;            // cells per workgroup
+    constexpr int NCOL = 16 * G;         // MFMA columns
+    constexpr int KC = kLbKSteps / MTW;  // K-steps per batch
+    extern __shared__ double bsh[];      // [net.lb_kpad][NCOL]: masked rows of the previous layer
+    __shared__ uint64_t code_lds[NC * kMaxWords];
+    __shared__ int shape_lds[NC];
+    const long long p0 = (long long)NC * blockIdx.x;
+    const long long n = rg.count();
+    if (p0 >= n) return;
+    const int ncell = (int)min((long long)NC, n - p0);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int col = lane & 15;    // MFMA column (B, D) / row within the tile (A)
+    const int kq = lane >> 4;     // k within the K-step (A, B) / row offset (D)
+    const int q = col & 3;        // homogeneous component of this column
+    const int cl = col >> 2;      // cell of this column within its group
+    stage_tile(net, codes, cell_shape, rg.list, rg.tile_base(p0), ncell, code_lds, shape_lds, NC);
+    for (int t = threadIdx.x; t < net.lb_kpad * NCOL; t += blockDim.x) bsh[t] = 0.0;
+    __syncthreads();
+    double *zb = rows + p0 * (long long)net.R * 4;
+    const long long cs = (long long)net.R * 4;
+    const AT *wf = lb_frags<AT>(net);
+
+    for (int l = 1; l < net.n_layers; ++l) {
+        const int nl = net.width[l];
+        const int mtiles = (nl + 15) >> 4;
+        int nmt = 0;   // output tiles of this wave in this layer
+#pragma unroll
+        for (int s = 0; s < MTW; ++s)
+            if (wave + s * nwaves < mtiles) nmt = s + 1;
+        v4d acc[MTW][G];
+#pragma unroll
+        for (int s = 0; s < MTW; ++s)
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[s][g] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < net.n_blocks; ++b) {
+            if (net.blk_dst[b] != l || nmt == 0) continue;
+            const int j = net.blk_src[b];
+            const int ks_n = net.blk_ld[b] >> 2;
+            const AT *fr[MTW];
+#pragma unroll
+            for (int s = 0; s < MTW; ++s)   // an idle slot reads the last tile (in bounds, unused)
+                fr[s] = wf + net.blk_frag_off[b] + (long long)min(wave + s * nwaves, mtiles - 1) * ks_n * 64 + lane;
+            if (j == 0) {
+                // Z_0 = [I | 0]: one K-step; row k of B is e_k for k < 3
+                const double bv = (kq < 3 && kq == q) ? 1.0 : 0.0;
+#pragma unroll
+                for (int s = 0; s < MTW; ++s) {
+                    if (s >= nmt) break;
+                    const double a = (double)fr[s][0];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[s][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[s][g], 0, 0, 0);
+                }
+                continue;
+            }
+            if (j == l - 1) {
+                // B from LDS; rows past the source's width read as zeros, so the
+                // clamped A loads of the last batch contribute nothing
+                AT ac[MTW][KC], an[MTW][KC];
+#pragma unroll
+                for (int s = 0; s < MTW; ++s)
+#pragma unroll
+                    for (int u = 0; u < KC; ++u) ac[s][u] = fr[s][min(u, ks_n - 1) * 64];
+                const double *bcol = bsh + kq * NCOL + col;
+                for (int ks0 = 0; ks0 < ks_n; ks0 += KC) {
+#pragma unroll
+                    for (int s = 0; s < MTW; ++s)
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) an[s][u] = fr[s][min(ks0 + KC + u, ks_n - 1) * 64];
+                    double bv[KC][G];
+#pragma unroll
+                    for (int u = 0; u < KC; ++u)
+#pragma unroll
+                        for (int g = 0; g < G; ++g) bv[u][g] = bcol[(ks0 + u) * 4 * NCOL + g * 16];
+#pragma unroll
+                    for (int u = 0; u < KC; ++u)
+#pragma unroll
+                        for (int s = 0; s < MTW; ++s) {
+                            if (s >= nmt) break;
+                            const double a = (double)ac[s][u];
+#pragma unroll
+                            for (int g = 0; g < G; ++g)
+                                acc[s][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[u][g], acc[s][g], 0, 0, 0);
+                        }
+#pragma unroll
+                    for (int s = 0; s < MTW; ++s)
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) ac[s][u] = an[s][u];
+                }
+                continue;
+            }
+            // a shortcut from an earlier hidden layer: its rows, written by this
+            // workgroup, from global memory, masked here
+            const int nj = net.width[j];
+            const int uoff = net.unit_off[j];
+            const long long roff = (long long)net.row_off[j] * 4;
+            for (int ks = 0; ks < ks_n; ++ks) {
+                const int k = ks * 4 + kq;
+                double bv[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int c = 4 * g + cl;
+                    bv[g] = (k < nj && c < ncell && code_bit(code_lds + c * net.W, uoff + k))
+                                ? zb[c * cs + roff + (long long)k * 4 + q] : 0.0;
+                }
+#pragma unroll
+                for (int s = 0; s < MTW; ++s) {
+                    if (s >= nmt) break;
+                    const double a = (double)fr[s][ks * 64];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[s][g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[g], acc[s][g], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();   // every wave is done with the previous layer's B
+        // rows (plus bias) to global memory; masked rows into the B buffer.
+        // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r.
+        const bool hidden = l < net.n_layers - 1;
+#pragma unroll
+        for (int s = 0; s < MTW; ++s) {
+            if (s >= nmt) break;
+            const int mt = wave + s * nwaves;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int c = 4 * g + cl;
+                const bool ok = c < ncell;
+                const double *bias = net.bias + (long long)shape_lds[c] * net.bias_stride + net.bias_off[l];
+                const uint64_t *code = code_lds + c * net.W;
+                double *z0 = zb + c * cs + (long long)net.row_off[l] * 4 + q;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = mt * 16 + kq + 4 * r;
+                    double v = acc[s][g][r];
+                    if (i < nl) {
+                        if (q == 3) v += bias[i];
+                        if (ok) z0[(long long)i * 4] = v;
+                    }
+                    if (hidden) {
+                        const bool on = ok && i < nl && code_bit(code, net.unit_off[l] + i);
+                        bsh[i * NCOL + g * 16 + col] = on ? v : 0.0;
+                    }
+                }
+            }
+        }
+        if (hidden) {
+            // rows the next layer's batches may read past this layer's tiles
+            const int r0 = mtiles * 16;
+            const int r1 = min(net.lb_kpad, (nl + 31) & ~31);
+            for (int t = threadIdx.x; t < (r1 - r0) * NCOL; t += blockDim.x) bsh[r0 * NCOL + t] = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
 // Split-BF16 chain: FP32 rows of position p go to rows[p][R][4].
 __global__ __launch_bounds__(256) void k_chain_bf16(DevNet net, const uint64_t *__restrict__ codes,
                                                     const int *__restrict__ cell_shape, CellRange rg,
@@ -1735,7 +1998,7 @@ __global__ __launch_bounds__(256) void k_clip_pivot(DevNet net, const uint64_t *
     const int wave = threadIdx.x >> 6;
     const long long p = 4LL * blockIdx.x + wave;
     if (p >= rg.count()) return;
-    const Fallback none{nullptr, nullptr, 0};
+    const Fallback none{nullptr, nullptr, 0, 0.0};
     clip_cell<double, false, true>(net, codes, argmax, cell_hash, hints, rg.cell(p), n_seed_cells,
                                    rows + p * (long long)net.R * 4, 4, scratch[wave], out, cand, cand_cap, ctr, 0.0,
                                    0.0, none, pa, nullptr);
@@ -1779,7 +2042,7 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
     const int ncell = (int)min(4LL, hi - c0);
     chain_tile<1, kKChunk>(net, codes, cell_shape, nullptr, c0, ncell, zl, 16, 4, code_lds, shape_lds);
     if (wave >= ncell) return;
-    const Fallback none{nullptr, nullptr, 0};
+    const Fallback none{nullptr, nullptr, 0, 0.0};
     const PropArgs off{};
     clip_cell<double, false>(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zl + wave * 4, 16,
                              scratch[wave], out, cand, cand_cap, ctr, 0.0, 0.0, none, off, nullptr);
@@ -1857,17 +2120,95 @@ static CellRange range_of(long long lo, long long hi, const int *list, const uns
     return r;
 }
 
+// Staged-B chain shapes: variant 6 = four cells per workgroup, 7 = eight, 8 =
+// four cells with two output tiles per wave; one tile per wave otherwise.
+// Tiles per wave double while the widest layer would need more waves than a
+// workgroup of that kind holds (16 with one tile per wave, else 8), up to 4.
+struct LbShape {
+    int G, MTW, nwaves;
+    bool f32;
+    size_t lds;
+};
+
+static bool lb_shape(const DevNet &net, int variant, LbShape &o) {
+    if (variant < 6 || variant > 8 || net.lb_kpad <= 0) return false;
+    int mt_max = 0;
+    for (int l = 1; l < net.n_layers; ++l) mt_max = max(mt_max, (net.width[l] + 15) / 16);
+    o.G = variant == 7 ? 2 : 1;
+    o.MTW = variant == 8 ? 2 : 1;
+    while (o.MTW <= 4 && (mt_max + o.MTW - 1) / o.MTW > (o.MTW == 1 ? 16 : 8)) o.MTW *= 2;
+    o.nwaves = (mt_max + o.MTW - 1) / o.MTW;
+    o.f32 = net.wfrag32 != nullptr;
+    o.lds = (size_t)net.lb_kpad * 16 * o.G * sizeof(double);
+    return o.MTW <= 4;
+}
+
+template <int G, int MTW, typename AT>
+static void launch_lb_t(const DevNet &net, const uint64_t *codes, const int *cell_shape, const CellRange &rg,
+                        long long n, double *rows, const LbShape &o, hipStream_t st) {
+    hipLaunchKernelGGL((k_chain_lb<G, MTW, AT>), dim3((unsigned)((n + 4 * G - 1) / (4 * G))), dim3(64 * o.nwaves),
+                       o.lds, st, net, codes, cell_shape, rg, rows);
+}
+
+template <int G, int MTW, typename AT>
+static hipError_t prepare_lb_t(size_t bytes) {
+    return hipFuncSetAttribute((const void *)k_chain_lb<G, MTW, AT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+// Sets the LDS limits of the staged-B chain for `net` and returns the mask
+// of variants (bit v - 6) that fit in lds_limit bytes per workgroup.
+int prepare_chain_lb(const DevNet &net, size_t lds_limit) {
+    int ok = 0;
+    for (int v = 6; v <= 8; ++v) {
+        LbShape o;
+        if (!lb_shape(net, v, o)) continue;
+        const size_t stat = sizeof(uint64_t) * 4 * o.G * kMaxWords + 64;
+        if (o.lds + stat > lds_limit) continue;
+        hipError_t e;
+#define AM_LB_PREP(G_, M_) (o.f32 ? prepare_lb_t<G_, M_, float>(o.lds) : prepare_lb_t<G_, M_, double>(o.lds))
+        if (o.G == 2)
+            e = o.MTW == 4 ? AM_LB_PREP(2, 4) : o.MTW == 2 ? AM_LB_PREP(2, 2) : AM_LB_PREP(2, 1);
+        else
+            e = o.MTW == 4 ? AM_LB_PREP(1, 4) : o.MTW == 2 ? AM_LB_PREP(1, 2) : AM_LB_PREP(1, 1);
+#undef AM_LB_PREP
+        if (e == hipSuccess) ok |= 1 << (v - 6);
+        else (void)hipGetLastError();
+    }
+    return ok;
+}
+
+// Launches staged-B variant `variant`; false if it cannot run on this net.
+static bool launch_lb(const DevNet &net, int variant, const uint64_t *codes, const int *cell_shape,
+                      const CellRange &rg, long long n, double *rows, hipStream_t st) {
+    LbShape o;
+    if (!((net.lb_ok >> (variant - 6)) & 1) || !lb_shape(net, variant, o)) return false;
+#define AM_LB_GO(G_, M_)                                                            \
+    (o.f32 ? launch_lb_t<G_, M_, float>(net, codes, cell_shape, rg, n, rows, o, st) \
+           : launch_lb_t<G_, M_, double>(net, codes, cell_shape, rg, n, rows, o, st))
+    if (o.G == 2)
+        o.MTW == 4 ? AM_LB_GO(2, 4) : o.MTW == 2 ? AM_LB_GO(2, 2) : AM_LB_GO(2, 1);
+    else
+        o.MTW == 4 ? AM_LB_GO(1, 4) : o.MTW == 2 ? AM_LB_GO(1, 2) : AM_LB_GO(1, 1);
+#undef AM_LB_GO
+    return true;
+}
+
 // Positions [0, hi - lo) of cells lo..hi-1, or (list != NULL) the first
 // *count entries of list, launched for up to hi - lo positions.
 // g: tile variant: 1, 2 or 4 column groups per workgroup (4 g cells); 3: four
 // cells with the previous layer's rows in LDS (kept there for layers of at
 // most 128 units, staged from global memory per layer for wider ones up to
-// 512); 5: four cells with the K loop over the units active in any of them.
+// 512); 5: four cells with the K loop over the units active in any of them;
+// 6, 7, 8: the staged-B chain (4, 8 cells; 4 cells with two tiles per wave),
+// or variant 1 where it cannot run.
 void launch_chain(const DevNet &net, const uint64_t *codes, const int *cell_shape, long long lo, long long hi,
                   const int *list, const unsigned long long *count, double *rows, int g, hipStream_t st) {
     if (hi <= lo) return;
     const CellRange rg = range_of(lo, hi, list, count, (unsigned long long)(hi - lo));
     const long long n = hi - lo;
+    if (g >= 6 && launch_lb(net, g, codes, cell_shape, rg, n, rows, st)) return;
+    if (g >= 6) g = 1;
     if (g == 5)
         hipLaunchKernelGGL((k_chain_f64_gather<kKChunk>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net,
                            codes, cell_shape, rg, rows);
@@ -1902,7 +2243,7 @@ void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, co
                  unsigned long long cand_cap, Counters *ctr, const PropArgs &pa, hipStream_t st) {
     if (hi <= lo) return;
     const long long blocks = (hi - lo + 3) / 4;
-    const Fallback none{nullptr, nullptr, 0};
+    const Fallback none{nullptr, nullptr, 0, 0.0};
     if (pa.face_routine == 1)
         hipLaunchKernelGGL(k_clip_pivot, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax, cell_hash,
                            hints, range_of(lo, hi, list, count, (unsigned long long)(hi - lo)), n_seed_cells, rows,
@@ -1920,11 +2261,11 @@ void launch_clip(const DevNet &net, const uint64_t *codes, const int *argmax, co
 void launch_clip_f32(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
                      const int *hints, long long lo, long long hi, long long n_seed_cells, const float *rows,
                      const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, Counters *ctr,
-                     double margin, double vertex_tol, int *fb_list, unsigned long long *fb_count,
+                     double margin, double vertex_tol, double row_eps, int *fb_list, unsigned long long *fb_count,
                      const PropArgs &pa, hipStream_t st) {
     if (hi <= lo) return;
     const long long blocks = (hi - lo + 3) / 4;
-    const Fallback fb{fb_list, fb_count, (unsigned long long)(hi - lo)};
+    const Fallback fb{fb_list, fb_count, (unsigned long long)(hi - lo), row_eps};
     if (pa.mode != 0 || pa.samples)
         hipLaunchKernelGGL(k_clip_prop<float>, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, argmax,
                            cell_hash, hints, range_of(lo, hi, nullptr, nullptr, 0), n_seed_cells, rows, out, cand,
@@ -1980,6 +2321,7 @@ __global__ void k_step_begin(Counters *c, unsigned long long chunk, unsigned lon
     if (n > chunk) n = chunk;
     c->step_n = n;
     c->n_cand = 0ull;
+    c->fb_n = 0ull;
 }
 
 void launch_step_begin(Counters *ctr, long long chunk, long long cap_cells, hipStream_t st) {
@@ -1992,6 +2334,8 @@ void launch_step_begin(Counters *ctr, long long chunk, long long cap_cells, hipS
 void launch_chain_dev(const DevNet &net, const uint64_t *codes, const int *cell_shape, Counters *ctr, long long chunk,
                       double *rows, int g, hipStream_t st) {
     const CellRange rg = range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo);
+    if (g >= 6 && launch_lb(net, g, codes, cell_shape, rg, chunk, rows, st)) return;
+    if (g >= 6) g = 1;
     if (g == 3 && res_rows(net) > kLdsRows)
         hipLaunchKernelGGL((k_chain_f64_res<kKChunk>), dim3((unsigned)((chunk + 3) / 4)), dim3(256),
                            chain_res_lds_bytes(net), st, net, codes, cell_shape, rg, rows);
@@ -2011,12 +2355,41 @@ void launch_chain_dev(const DevNet &net, const uint64_t *codes, const int *cell_
 
 void launch_clip_dev(const DevNet &net, const uint64_t *codes, const int *argmax, const uint64_t *cell_hash,
                      const int *hints, Counters *ctr, long long chunk, long long n_seed_cells, const double *rows,
-                     const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, hipStream_t st) {
-    const Fallback none{nullptr, nullptr, 0};
-    const PropArgs off{};
-    hipLaunchKernelGGL(k_clip<double>, dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, net, codes, argmax,
-                       cell_hash, hints, range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo), n_seed_cells, rows,
-                       out, cand, cand_cap, ctr, 0.0, 0.0, none, off);
+                     const ClipOut &out, const Candidates &cand, unsigned long long cand_cap, const PropArgs &pa,
+                     hipStream_t st) {
+    const Fallback none{nullptr, nullptr, 0, 0.0};
+    const CellRange rg = range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo);
+    if (pa.mode != 0)
+        hipLaunchKernelGGL(k_clip_prop<double>, dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, net, codes,
+                           argmax, cell_hash, hints, rg, n_seed_cells, rows, out, cand, cand_cap, ctr, 0.0, 0.0, none,
+                           pa);
+    else
+        hipLaunchKernelGGL(k_clip<double>, dim3((unsigned)((chunk + 3) / 4)), dim3(256), 0, st, net, codes, argmax,
+                           cell_hash, hints, rg, n_seed_cells, rows, out, cand, cand_cap, ctr, 0.0, 0.0, none, pa);
+}
+
+// Split-BF16 form of a device-driven step: the BF16 chain and the FP32-row
+// clip of the step's range; cells it cannot certify go to fb_list (count in
+// ctr->fb_n, cleared when the step's range is taken) and are redone by the
+// FP64 chain (variant g) and clip, all sized for `chunk` cells.
+void launch_split_step_dev(const DevNet &net, const uint64_t *codes, const int *cell_shape, const int *argmax,
+                           const uint64_t *cell_hash, const int *hints, Counters *ctr, long long chunk,
+                           long long n_seed_cells, double *rows, const ClipOut &out, const Candidates &cand,
+                           unsigned long long cand_cap, double margin, double vertex_tol, double row_eps,
+                           int *fb_list, int g, const PropArgs &pa, hipStream_t st) {
+    const CellRange rg = range_of(0, chunk, nullptr, nullptr, 0, &ctr->step_lo);
+    const unsigned blocks = (unsigned)((chunk + 3) / 4);
+    hipLaunchKernelGGL(k_chain_bf16, dim3(blocks), dim3(256), 0, st, net, codes, cell_shape, rg, (float *)rows);
+    const Fallback fb{fb_list, &ctr->fb_n, (unsigned long long)chunk, row_eps};
+    if (pa.mode != 0)
+        hipLaunchKernelGGL(k_clip_prop<float>, dim3(blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints, rg,
+                           n_seed_cells, (const float *)rows, out, cand, cand_cap, ctr, margin, vertex_tol, fb, pa);
+    else
+        hipLaunchKernelGGL(k_clip<float>, dim3(blocks), dim3(256), 0, st, net, codes, argmax, cell_hash, hints, rg,
+                           n_seed_cells, (const float *)rows, out, cand, cand_cap, ctr, margin, vertex_tol, fb, pa);
+    launch_chain(net, codes, cell_shape, 0, chunk, fb_list, &ctr->fb_n, rows, g == 5 ? 1 : g, st);
+    launch_clip(net, codes, argmax, cell_hash, hints, 0, chunk, fb_list, &ctr->fb_n, n_seed_cells, rows, out, cand,
+                cand_cap, ctr, pa, st);
 }
 
 }  // namespace am

@@ -52,10 +52,17 @@ CASES = [
     ("c2", dict(face_routine=1)),
     ("c2", dict(propose=2)),
     ("c2", dict(kernel_path=2)),
+    ("c2", dict(chain_groups=6)),
+    ("c2", dict(chain_groups=7)),
+    ("c2", dict(chain_groups=8)),
+    ("c2", dict(graph_steps=8, chain_groups=6)),
     ("c3", dict(chain_groups=1)),
     ("c3", dict(chain_groups=3)),
     ("c3", dict(chain_groups=5)),
     ("c3", dict(graph_steps=8)),
+    ("c3", dict(chain_groups=6)),
+    ("c3", dict(chain_groups=7)),
+    ("c3", dict(graph_steps=8, chain_groups=8)),
     ("c3", dict(face_routine=1)),
 ]
 
@@ -86,16 +93,24 @@ def test_fp64_forms_equal_the_oracle_record(binding, case):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
-def test_split_bf16_equals_the_oracle_record(binding, name):
+SPLIT_CASES = [("c2", {}), ("c3", {}), ("c2", dict(graph_steps=8)), ("c2", dict(graph_steps=8, propose=2)),
+               ("c3", dict(graph_steps=8, propose=2))]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[case_id(c) for c in SPLIT_CASES])
+def test_split_bf16_equals_the_oracle_record(binding, case):
+    """The split-BF16 form (host-driven, and device-driven steps replayed from
+    a captured graph, with distance-ordered proposals too) against the
+    oracle's record: cells, cycles and adjacency exact, vertices 1e-5."""
+    name, opts = case
     rec = golden(name)
     if rec is None:
         pytest.skip(f"no oracle record for {name}")
-    say("golden split-bf16", name)
+    say("golden split-bf16", case_id(case))
     ctx = binding.Context(0).load_net(net_of(name))
     o, d = rays(name)
     ctx.seed_rays(o, d)
-    st = ctx.march(max_cells=1 << 24 if name == "c3" else 1 << 21, precision=1)
+    st = ctx.march(max_cells=1 << 24 if name == "c3" else 1 << 21, precision=1, **opts)
     assert st["faces"] == rec["faces"]
     worst = check_golden(ctx, rec, vtol=1e-5)
     say("split-bf16 worst sampled vertex error", name, worst, "escalated", st["escalated"])

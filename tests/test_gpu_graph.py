@@ -96,8 +96,8 @@ def test_graph_march_capacity_then_retry(binding):
     ctx.seed_rays(o, d)
     st = ctx.march(max_cells=1 << 16, graph_steps=4)
     assert st["faces"] > 2000
-    with pytest.raises(binding.AmError):
-        ctx.march(graph_steps=4, precision=1)
+    with pytest.raises(binding.AmError):     # pivoting runs host-driven steps only
+        ctx.march(graph_steps=4, face_routine=1)
     ctx.close()
 
 
@@ -116,24 +116,26 @@ def test_graph_march_counts_replays(binding):
     ctx.close()
 
 
+@pytest.mark.parametrize("form", ["fp64", "split"])
 @pytest.mark.parametrize("k", [1, 8])
 @pytest.mark.parametrize("name", ["c1", "maxpool_cube"])
-def test_timed_device_steps_match_oracle(binding, name, k):
+def test_timed_device_steps_match_oracle(binding, name, k, form):
     """graph_steps with time_kernels: the same device-driven steps launched one
-    by one with HIP events; the mesh is the oracle's and every step that ran
-    is timed once per kernel class."""
+    by one with HIP events; the mesh is the oracle's (vertices 1e-5 for the
+    split-BF16 form) and every step that ran is timed once per kernel class."""
     net = NETS[name]()
     o, d = seeds.random_rays(16, seed=4)
     on = O.OracleNet(net)
     codes, ams, _, _ = on.seed_rays(o, d)
     ref = on.march(codes, ams)
-    say("timed device steps", name, k)
+    say("timed device steps", name, k, form)
     ctx = binding.Context(0).load_net(net)
+    prec = 1 if form == "split" else 0
     for _ in range(2):
         ctx.seed_rays(o, d)
-        st = ctx.march(graph_steps=k, time_kernels=True)
+        st = ctx.march(graph_steps=k, time_kernels=True, precision=prec, propose=2 * prec)
         assert st["faces"] == ref.n_faces and st["cells"] == ref.stats["cells"]
-        compare_meshes(ref, fetch_host(ctx))
+        compare_meshes(ref, fetch_host(ctx), vtol=1e-5 if prec else 1e-9)
         assert st["graph_launches"] == 0
         assert st["chain_launches"] == st["steps"] == st["clip_launches"] and st["hash_launches"] == 3 * st["steps"]
         assert st["chain_ms"] > 0.0 and st["clip_ms"] > 0.0 and st["hash_ms"] > 0.0
