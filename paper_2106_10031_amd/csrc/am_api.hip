@@ -44,6 +44,7 @@ void launch_fused(const DevNet &, const uint64_t *, const int *, const int *, co
                   hipStream_t);
 size_t fused_lds_bytes(const DevNet &);
 hipError_t prepare_fused(size_t);
+size_t fused_static_lds_bytes();
 size_t chain_res_lds_bytes(const DevNet &);
 hipError_t prepare_chain_res(size_t);
 int prepare_chain_lb(const DevNet &, size_t);
@@ -151,7 +152,6 @@ struct am_ctx {
     bool fused_ok = false;      // the fused kernel's rows fit in LDS
     bool prefer_fused = false;  // kernel_path 0 choice (the split path measured faster at width 90)
     double *d_bias = nullptr;
-    int *d_row_of_unit = nullptr;
     uint64_t *d_zobrist = nullptr;
 
     // seeds
@@ -419,7 +419,6 @@ void free_net(am_ctx *c) {
     dfree(c, c->d_wcol);
     dfree(c, c->d_wfrag16);
     dfree(c, c->d_bias);
-    dfree(c, c->d_row_of_unit);
     dfree(c, c->d_zobrist);
     dfree(c, c->d_seed_codes);
     dfree(c, c->d_seed_am);
@@ -656,7 +655,7 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
         dn.row_off[l] = row;
         dn.unit_off[l] = unit;
         dn.bias_off[l] = boff;
-        row += (nd->width[l] + 3) & ~3;
+        row += nd->width[l];   // rows are indexed by unit
         unit += nd->width[l];
         boff += nd->width[l];
     }
@@ -737,9 +736,6 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
             }
     dn.S = n_shapes;
     dn.bias_stride = boff;
-    std::vector<int> rou(N + M);
-    for (int l = 1; l < L2; ++l)
-        for (int k = 0; k < nd->width[l]; ++k) rou[dn.unit_off[l] + k] = dn.row_off[l] + k;
     std::vector<uint64_t> zob(N + M + n_shapes);
     uint64_t sm = 0x5eed0fa11c0de5ull;
     for (auto &z : zob) z = splitmix64(sm);
@@ -769,11 +765,9 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     HIPCHK(hipMemcpy(ctx->d_wfrag16, h16.data(), sizeof(uint16_t) * h16.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_wfrag, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice));
     TRY(dalloc(ctx, ctx->d_bias, hb.size()));
-    TRY(dalloc(ctx, ctx->d_row_of_unit, rou.size()));
     TRY(dalloc(ctx, ctx->d_zobrist, zob.size()));
     HIPCHK(hipMemcpy(ctx->d_weights, hw.data(), sizeof(double) * hw.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_bias, hb.data(), sizeof(double) * hb.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(ctx->d_row_of_unit, rou.data(), sizeof(int) * rou.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_zobrist, zob.data(), sizeof(uint64_t) * zob.size(), hipMemcpyHostToDevice));
     dn.weights = ctx->d_weights;
     dn.wfrag = ctx->d_wfrag;
@@ -781,7 +775,6 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     dn.wcol = ctx->d_wcol;
     dn.wfrag16 = ctx->d_wfrag16;
     dn.bias = ctx->d_bias;
-    dn.row_of_unit = ctx->d_row_of_unit;
     dn.zobrist = ctx->d_zobrist;
     ctx->calib_ok = false;   // the split-BF16 certificate is measured per net
     dn.lb_ok = prepare_chain_lb(dn, ctx->lds_limit);
@@ -789,7 +782,7 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     ctx->dn = dn;
     // the fused kernel keeps the rows of four cells in LDS next to 4 x 1.75 KiB of clip scratch
     const size_t fb = fused_lds_bytes(dn);
-    ctx->fused_ok = fb + 8192 <= ctx->lds_limit && prepare_fused(fb) == hipSuccess;
+    ctx->fused_ok = fb + fused_static_lds_bytes() <= ctx->lds_limit && prepare_fused(fb) == hipSuccess;
     {
         const size_t rb = chain_res_lds_bytes(ctx->dn);
         if (rb > 0 && prepare_chain_res(rb) != hipSuccess) return fail(ctx, AM_E_HIP, "chain LDS attribute failed");
@@ -1116,7 +1109,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         return fail(ctx, AM_E_INVALID, "the split-BF16 form runs on the split path");
     if (o.kernel_path == 2 && !ctx->fused_ok)
         return fail(ctx, AM_E_INVALID, "the fused kernel needs %zu bytes of LDS (limit %zu)",
-                    fused_lds_bytes(ctx->dn) + 8192, ctx->lds_limit);
+                    fused_lds_bytes(ctx->dn) + fused_static_lds_bytes(), ctx->lds_limit);
     if (o.propose < 0 || o.propose > 3) return fail(ctx, AM_E_INVALID, "propose must be 0..3");
     if (o.chain_groups < 0 || o.chain_groups > kChainVariants)
         return fail(ctx, AM_E_INVALID, "chain_groups must be 0..%d", kChainVariants);

@@ -22,17 +22,17 @@ constexpr double kTau = 9.094947017729282379150390625e-13;
 constexpr double kSquareHalf = 2.0;
 
 // Network as laid out in device memory.  Rows of the affine chain are kept
-// per cell in a padded layout: layer l (1..L+1) occupies rows
-// row_off[l] .. row_off[l] + width[l] - 1, with row_off a multiple of 4 so
-// that no 128-byte line straddles two layers.
+// per cell indexed by unit: layer l (1..L+1) occupies rows
+// row_off[l] .. row_off[l] + width[l] - 1 with row_off[l] = unit_off[l], so
+// row g holds hidden unit g and row N + i head i (R = N + M rows per cell).
 struct DevNet {
     int n_layers;              // L + 2
     int N, M, W;               // hidden units, heads, code words
     int S;                     // shapes sharing the weights (1 for a single net)
     int bias_stride;           // doubles per shape in `bias` (sum of widths of layers >= 1)
-    int R;                     // padded rows per cell
+    int R;                     // rows per cell (N + M)
     int width[kMaxLayers];
-    int row_off[kMaxLayers];   // padded row offset (layers >= 1)
+    int row_off[kMaxLayers];   // row offset of layer l (= unit_off[l])
     int unit_off[kMaxLayers];  // global unit offset (layer l >= 1; heads at N)
     int bias_off[kMaxLayers];  // offset of layer l's bias in `bias`
     int n_blocks;
@@ -60,7 +60,6 @@ struct DevNet {
     int lb_kpad;               // rows of the staged-B chain's LDS buffer (widest hidden layer, to 32)
     int lb_ok;                 // bit v - 6 set: staged-B chain variant v (6, 7, 8) can run
     const double *bias;        // [S][bias_stride]: shape s, layer l at s * bias_stride + bias_off[l]
-    const int *row_of_unit;    // [N + M] padded row of global unit g
     const uint64_t *zobrist;   // [N + M + S] keys of the cell fingerprint (units, heads, shapes)
 };
 

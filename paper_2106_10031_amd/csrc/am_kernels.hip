@@ -679,15 +679,15 @@ __device__ __forceinline__ void constraint_row(const DevNet &net, int id, const 
         c[ax] = (t & 1) ? -1.0 : 1.0;
         c[3] = -1.0;
     } else if (id < net.N) {
-        const RowT *z = rb + (long long)net.row_of_unit[id] * rs;
+        const RowT *z = rb + (long long)(id) * rs;
         const double sg = code_bit(code, id) ? -1.0 : 1.0;
         c[0] = sg * z[0];
         c[1] = sg * z[1];
         c[2] = sg * z[2];
         c[3] = sg * z[3];
     } else {
-        const RowT *zi = rb + (long long)net.row_of_unit[id] * rs;
-        const RowT *zj = rb + (long long)net.row_of_unit[net.N + am] * rs;
+        const RowT *zi = rb + (long long)(id) * rs;
+        const RowT *zj = rb + (long long)(net.N + am) * rs;
         c[0] = zi[0] - zj[0];
         c[1] = zi[1] - zj[1];
         c[2] = zi[2] - zj[2];
@@ -1019,7 +1019,7 @@ __device__ int propose_lines(const DevNet &net, const PropArgs &pa, PropScratch 
         float f[kPropF];
         double sd = 0.0;
         if (g < net.N && g != E.id[0] && g != E.id[1] && g != E.id[2]) {
-            const RowT *z = rb + (long long)net.row_of_unit[g] * rs;
+            const RowT *z = rb + (long long)(g) * rs;
             const int bit = code_bit(code, g);
             const double sg = bit ? -1.0 : 1.0;
             const double c0 = sg * z[0], c1 = sg * z[1], c2 = sg * z[2], c3 = sg * z[3];
@@ -1109,7 +1109,7 @@ __device__ __forceinline__ bool slot_line(const DevNet &net, int l, const uint64
                                           const double aF[4], double &cu, double &cv, double &cw, int &id) {
     double c[4];
     if (l < net.N) {
-        const RowT *z = rb + (long long)net.row_of_unit[l] * rs;
+        const RowT *z = rb + (long long)(l) * rs;
         const double sg = code_bit(code, l) ? -1.0 : 1.0;
         c[0] = sg * z[0];
         c[1] = sg * z[1];
@@ -1119,7 +1119,7 @@ __device__ __forceinline__ bool slot_line(const DevNet &net, int l, const uint64
     } else if (l < net.N + net.M) {
         const int hd = l - net.N;
         if (hd == am) return false;
-        const RowT *z = rb + (long long)net.row_of_unit[l] * rs;
+        const RowT *z = rb + (long long)(l) * rs;
         c[0] = z[0] - aF[0];
         c[1] = z[1] - aF[1];
         c[2] = z[2] - aF[2];
@@ -1283,7 +1283,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
     (void)ps;
 
     // ---- plane frame: n = a_F[0:3], foot point p0, orthonormal u, v with u x v = n/|n|
-    const RowT *aF = rb + (long long)net.row_of_unit[net.N + am] * rs;
+    const RowT *aF = rb + (long long)(net.N + am) * rs;
     const double fx = aF[0], fy = aF[1], fz = aF[2], fw = aF[3];
     const double nn = fx * fx + fy * fy + fz * fz;
     Poly P;
@@ -1338,15 +1338,25 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
         // share both planes).  Any order gives the same polygon; these first
         // leave most later lines with nothing to cut.
         if (hints) {
-            for (int h = 0; h < 3 && P.m > 0; ++h) {
-                const int id = hints[cell * 3 + h];
-                if (id < 0 || id >= net.N + net.M || id == net.N + am) continue;
-                double c[4];
-                constraint_row(net, id, code, am, rb, rs, c);
+            // all three rows are loaded before the first cut
+            int hid[3];
+            double hc[3][4];
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+                hid[h] = hints[cell * 3 + h];
+                if (hid[h] < 0 || hid[h] >= net.N + net.M || hid[h] == net.N + am) hid[h] = -1;
+            }
+#pragma unroll
+            for (int h = 0; h < 3; ++h)
+                if (hid[h] >= 0) constraint_row(net, hid[h], code, am, rb, rs, hc[h]);
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+                if (hid[h] < 0 || P.m <= 0) continue;
+                const double *c = hc[h];
                 const double hu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
                 const double hv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
                 const double hw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
-                sh_clip(P, hu, hv, hw, sqrt(hu * hu + hv * hv), id, S, flags);
+                sh_clip(P, hu, hv, hw, sqrt(hu * hu + hv * hv), hid[h], S, flags);
             }
         }
         // learned form: clip the proposed lines next; the pass below still
@@ -1375,7 +1385,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
             double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0, cn = 0.0;
             bool cuts = false, close = false;
             if (valid) {
-                const RowT *z = rb + (long long)net.row_of_unit[g] * rs;
+                const RowT *z = rb + (long long)(g) * rs;
                 const double sg = code_bit(code, g) ? -1.0 : 1.0;
                 const double c0 = sg * z[0], c1 = sg * z[1], c2 = sg * z[2], c3 = sg * z[3];
                 cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
@@ -1412,7 +1422,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
             const bool valid = hd < net.M && hd != am;
             double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0;
             if (valid) {
-                const RowT *zi = rb + (long long)net.row_of_unit[net.N + hd] * rs;
+                const RowT *zi = rb + (long long)(net.N + hd) * rs;
                 const double c0 = zi[0] - fx, c1 = zi[1] - fy, c2 = zi[2] - fz, c3 = zi[3] - fw;
                 cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
                 cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
@@ -1638,7 +1648,7 @@ __global__ __launch_bounds__(256) void k_calib_split(DevNet net, const uint64_t 
         double ca[4], cb[4];
         constraint_row(net, ep, code, am, r32, 4, ca);
         constraint_row(net, e, code, am, r32, 4, cb);
-        const float *aF = r32 + (long long)net.row_of_unit[net.N + am] * 4;
+        const float *aF = r32 + (long long)(net.N + am) * 4;
         double A[3][3] = {{ca[0], ca[1], ca[2]}, {cb[0], cb[1], cb[2]}, {aF[0], aF[1], aF[2]}};
         double rr[3] = {-ca[3], -cb[3], -(double)aF[3]};
         const double an = inv_norm3(A);
@@ -1659,7 +1669,7 @@ __global__ __launch_bounds__(256) void k_calib_split(DevNet net, const uint64_t 
         const double xi = bcast(x64[0], i), yi = bcast(x64[1], i), zi = bcast(x64[2], i);
         const double sc = 1.0 + fmax(fabs(xi), fmax(fabs(yi), fabs(zi)));
         for (int g = lane; g < net.N + net.M; g += kWave) {
-            const long long row = (long long)net.row_of_unit[g] * 4;
+            const long long row = (long long)(g) * 4;
             const double *a = r64 + row;
             const float *b = r32 + row;
             const double d = ((double)b[0] - a[0]) * xi + ((double)b[1] - a[1]) * yi + ((double)b[2] - a[2]) * zi +
@@ -2076,7 +2086,7 @@ __global__ void k_rows_unpad(DevNet net, long long n, const RowT *__restrict__ r
          t += (long long)gridDim.x * blockDim.x) {
         const long long c = t / G;
         const int g = (int)(t % G);
-        const RowT *src = rows + (c * net.R + net.row_of_unit[g]) * 4;
+        const RowT *src = rows + (c * net.R + (g)) * 4;
         double *dst = out + t * 4;
         dst[0] = src[0];
         dst[1] = src[1];
@@ -2086,6 +2096,9 @@ __global__ void k_rows_unpad(DevNet net, long long n, const RowT *__restrict__ r
 }
 
 size_t fused_lds_bytes(const DevNet &net) { return sizeof(double) * 16 * (size_t)net.R; }
+
+// Static LDS of the fused kernel: four waves' clip scratch and the tile's codes.
+size_t fused_static_lds_bytes() { return 4 * sizeof(PolyScratch) + 4 * kMaxWords * sizeof(uint64_t) + 64; }
 
 // Rows the staged chain holds in LDS: the widest hidden layer padded to
 // whole K-steps, or 0 when that exceeds kResMax.
