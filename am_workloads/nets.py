@@ -464,8 +464,82 @@ def latent_sphere_batch(hidden: Sequence[int], reinject: int, latent_dim: int, n
     return ShapeBatch(Net(widths, blocks, base), shape_bias)
 
 
-def c4_batch(n_shapes: int = 64, radius=(0.008, 0.35)) -> ShapeBatch:
-    """The batched workload: 64 shapes of one latent-conditioned decoder.
+def c4_batch(n_shapes: int = 64) -> ShapeBatch:
+    """The batched workload: 64 shapes of one trained latent-conditioned
+    decoder, each in its own domain box.
+
+    The decoder (frozen fixture am_workloads/data/c4.npz, written by
+    ``python -m am_workloads.fit c4``) is a [x; z] (3 + 256) -> [512] x 8 -> 1
+    ReLU MLP with [x; z] entering layer 1 and again layer 4 (fan-in
+    512 + 259), trained as an auto-decoder on 64 sphere unions (1-8 spheres
+    each, scaled by a log-uniform factor in [0.03, 0.6], ordered by it), one
+    latent per shape.  Each latent's terms fold into the biases of layers 1
+    and 4 (per-shape bias rows); x re-enters layer 4 as a linear shortcut from
+    the input (Sec. 5.1).
+
+    Shape s is marched in the box of half-size h_s centred on a point p_s of
+    its surface (c4_boxes.npz; h_s log-spaced from 1.2e-3 to 0.125).  The
+    network of shape s takes box coordinates y in [-1, 1]^3, x = p_s + h_s y:
+    since relu(t / h) = relu(t) / h for h > 0, every pre-activation of the
+    decoder at x equals h_s times that of a network with the decoder's
+    weights and biases (b + W_x p_s + W_z z_s) / h_s.  Weights stay shared, the
+    codes and the zero set are the decoder's, and faces come out in y.
+    """
+    z = np.load(os.path.join(DATA_DIR, "c4.npz"), allow_pickle=False)
+    box = np.load(os.path.join(DATA_DIR, "c4_boxes.npz"), allow_pickle=False)
+    Z = z["Z"].astype(np.float64)[:n_shapes]
+    reinject = int(z["reinject"])
+    n_w = len([k for k in z.files if k.startswith("W")])
+    Ws = [z[f"W{l}"].astype(np.float64) for l in range(n_w)]
+    bs = [z[f"b{l}"].astype(np.float64) for l in range(n_w)]
+    hidden = [W.shape[0] for W in Ws[:-1]]
+    L = len(hidden)
+    widths = [3] + hidden + [1]
+    blocks = [(1, 0, Ws[0][:, :3])]
+    zfold = {1: Ws[0][:, 3:]}
+    xfold = {1: Ws[0][:, :3]}
+    for l in range(1, L):
+        W = Ws[l]
+        if l + 1 == reinject:
+            h = hidden[l - 1]
+            blocks.append((l + 1, l, W[:, :h]))
+            blocks.append((l + 1, 0, W[:, h:h + 3]))
+            zfold[l + 1] = W[:, h + 3:]
+            xfold[l + 1] = W[:, h:h + 3]
+        else:
+            blocks.append((l + 1, l, W))
+    blocks.append((L + 1, L, Ws[-1]))
+    rows = []
+    for s in range(Z.shape[0]):
+        p, hs = box["centre"][s], float(box["half"][s])
+        bias = []
+        for l in range(1, L + 2):
+            b = bs[l - 1].copy()
+            if l in zfold:
+                b = b + zfold[l] @ Z[s] + xfold[l] @ p
+            bias.append(b / hs)
+        rows.append(np.concatenate(bias))
+    shape_bias = np.asarray(rows)
+    base = [shape_bias[0][o:o + w] for o, w in zip(np.cumsum([0] + widths[1:-1]), widths[1:])]
+    return ShapeBatch(Net(widths, blocks, base), shape_bias)
+
+
+def c4_seed_rays(n_shapes: int = 64):
+    """Seed rays of the batched workload, one per shape in its box
+    coordinates: the segment t e_x, t in [-a_s, a_s], through the surface
+    point at the box centre (its ends have opposite signs).  Returns origins,
+    directions (o + t d, t in [0, 1]) and shape ids."""
+    box = np.load(os.path.join(DATA_DIR, "c4_boxes.npz"), allow_pickle=False)
+    a = box["seed_a"][:n_shapes]
+    o = np.zeros((n_shapes, 3))
+    d = np.zeros((n_shapes, 3))
+    o[:, 0] = -a
+    d[:, 0] = 2.0 * a
+    return o, d, np.arange(n_shapes, dtype=np.int32)
+
+
+def c4_untrained_batch(n_shapes: int = 64, radius=(0.008, 0.35)) -> ShapeBatch:
+    """An untrained stand-in for the batched workload: 64 shapes of one latent-conditioned decoder.
 
     [x; z] (3 + 256) -> [512] x 8 -> 1 ReLU MLP with [x; z] entering layer 1
     and again layer 4 (fan-in 512 + 259), He-normal weights, biases

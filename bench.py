@@ -41,8 +41,8 @@ METRIC = "faces meshed/sec on 1 MI355X (plain vs learned+BF16 form); exact cell-
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-# measured HBM traffic of the dominant kernel, written from rocprofv3 --pmc runs
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_chain_f64_c2.json")
+# measured HBM traffic of kernels, written from rocprofv3 --pmc runs (profile_summary.py traffic)
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2106_10031_amd", "csrc", f)
                   for f in ("am_kernels.hip", "am_internal.h")]
 
@@ -84,6 +84,54 @@ def chain_flops_per_cell(net, codes: np.ndarray) -> float:
     return total
 
 
+def sample_codes(codes_dev, k: int = 20000, seed: int = 3) -> np.ndarray:
+    """A random sample of k face codes (all of them if fewer), as host uint64."""
+    import torch
+    F = codes_dev.shape[0]
+    if F <= k:
+        return codes_dev.cpu().numpy().view(np.uint64)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    idx = torch.randperm(F, generator=g)[:k].to(codes_dev.device)
+    return codes_dev[idx].cpu().numpy().view(np.uint64)
+
+
+def bf16_issued_flops_per_cell(net) -> float:
+    """MFMA FLOPs the split-BF16 chain issues per cell: six BF16 products per
+    block (l <- j), j >= 1, over 16-row output tiles and 32-wide K-steps, four
+    columns."""
+    r16 = lambda n: -(-n // 16) * 16
+    r32 = lambda n: -(-n // 32) * 32
+    return float(sum(6 * 2 * 4 * r16(net.widths[d]) * r32(net.widths[s]) for d, s, _ in net.blocks if s >= 1))
+
+
+def form_fractions(net, r, precision, codes_sample):
+    """Achieved rates of a form's chain kernel from its HIP-event times (host-
+    driven steps): algorithmic FLOPs (active inputs only, FP64-equivalent) per
+    second against the matrix peak of the chain's type (FP64 MFMA, or BF16
+    MFMA for the split form, where the issued BF16 FLOPs are given too), and
+    the rows it writes plus the codes it reads per second against HBM."""
+    k = r["kernels"]
+    if k["chain_launches"] <= 0 or k["chain_ms"] <= 0:
+        return None
+    cells = r["stats"]["cells"] * r["steps"]
+    t = k["chain_ms"] * 1e-3
+    alg = chain_flops_per_cell(net, codes_sample) * cells / t / 1e12
+    N, M = net.n_hidden, net.n_heads
+    W = max(1, -(-N // 64))
+    row_bytes = (N + M) * 4 * (4 if precision else 8) + W * 8
+    gbs = row_bytes * cells / t / 1e9
+    e = {"chain_ms_per_step": round(k["chain_ms"] / r["steps"], 3),
+         "chain_algorithmic_tflops": round(alg, 3),
+         "mfma_peak_tflops": PEAK_BF16_MFMA_TFLOPS if precision else PEAK_FP64_MFMA_TFLOPS,
+         "mfma_frac": round(alg / (PEAK_BF16_MFMA_TFLOPS if precision else PEAK_FP64_MFMA_TFLOPS), 6),
+         "chain_hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 5)}
+    if precision:
+        iss = bf16_issued_flops_per_cell(net) * cells / t / 1e12
+        e["chain_bf16_issued_tflops"] = round(iss, 2)
+        e["mfma_frac_issued"] = round(iss / PEAK_BF16_MFMA_TFLOPS, 5)
+    return e
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -92,18 +140,22 @@ def kernel_source_digest() -> str:
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of the chain kernel from the committed counter runs
-    (profile_summary.py traffic), or None when they were taken on another
-    kernel or the kernel sources changed since."""
-    try:
-        t = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_source_digest") != kernel_source_digest():
-        return None
-    if t.get("kernel", "").replace("am::", "") != kernel:
-        return None
-    return t
+    """HBM bytes per launch of a kernel on the 6x90 fit from the committed
+    counter runs (profiles/traffic_*.json, written by profile_summary.py
+    traffic), or None when none was taken on this kernel or the kernel
+    sources changed since."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(PROFILES, "traffic_*.json"))):
+        try:
+            t = json.load(open(path))
+        except (OSError, ValueError):
+            continue
+        if t.get("kernel", "").replace("am::", "") != kernel:
+            continue
+        if t.get("kernel_source_digest") != kernel_source_digest():
+            return None
+        return t
+    return None
 
 
 def host_cpu():
@@ -280,6 +332,13 @@ def chain_kernel_name(net, groups, graph_steps):
         return "k_chain_f64 (tile variants by launch size)"
     v = groups[2]
     wide = max(net.widths[1:-1]) > 128
+    if v >= 6:
+        mt = max((w + 15) // 16 for w in net.widths[1:])
+        mtw = 2 if v == 8 else 1
+        while mtw <= 4 and -(-mt // mtw) > (16 if mtw == 1 else 8):
+            mtw *= 2
+        f32 = all(np.array_equal(W.astype(np.float32).astype(np.float64), W) for _, _, W in net.blocks)
+        return f"k_chain_lb<{2 if v == 7 else 1}, {mtw}, {'float' if f32 else 'double'}>"
     return {1: "k_chain_f64<1, 8>", 2: "k_chain_f64<2, 4>", 3: "k_chain_f64_res<8>" if wide else "k_chain_f64_lds<8>",
             4: "k_chain_f64<4, 4>", 5: "k_chain_f64<1, 8>"}[v]
 
@@ -401,61 +460,61 @@ def ensemble_form(B, dev, steps):
                         "(untrained), 128 rays from the centres"}
 
 
-def c4_forms(B, dev, steps, max_cells, scorer=None):
+def c4_forms(B, dev, steps, max_cells, scorer=None, graph_steps=8):
     """The 64-shape decoder batch: one batched march (all shapes in one
-    frontier, chain tiles autotuned on it) against one march per shape; with
-    a scorer, also the batched march with the split-BF16 chain and learned
-    proposals together, checked against the plain batched cell set."""
+    frontier, chain tiles autotuned on it; device-driven steps replayed from
+    a captured graph) against one march per shape; with a scorer, also the
+    batched march with the split-BF16 chain and learned proposals together,
+    replayed the same way and checked against the plain batched cell set.
+    The chain's MFMA and HBM fractions of both come from one more march each
+    with host-driven steps and HIP events around every kernel class."""
     import torch
     from am_workloads import nets, seeds
     sb = nets.c4_batch()
-    o1, d1 = seeds.centre_rays(np.zeros((1, 3)), 16)
     S = sb.n_shapes
-    o = torch.as_tensor(np.tile(o1, (S, 1)), device=dev)
-    d = torch.as_tensor(np.tile(d1, (S, 1)), device=dev)
-    sh_np = np.repeat(np.arange(S, dtype=np.int32), len(o1))
+    o_np, d_np, sh_np = nets.c4_seed_rays(S)
+    o = torch.as_tensor(o_np, device=dev)
+    d = torch.as_tensor(d_np, device=dev)
     sh = torch.as_tensor(sh_np, device=dev)
     ctx = B.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
 
-    def batched():
+    def march(**kw):
         ctx.seed_rays(o, d, shape_id=sh)
-        return ctx.march(max_cells=max_cells, time_kernels=True)
+        return ctx.march(max_cells=max_cells, **kw)
 
-    st = batched()
+    def timed(reps, **kw):
+        march(**kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st_ = march(**kw)
+        torch.cuda.synchronize()
+        return st_, (time.perf_counter() - t0) / reps
+
+    march(time_kernels=True)
     groups, _ = ctx.tune_chain(reps=3)
-    batched()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        st = batched()
-    torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) / steps
+    st, t_b = timed(steps, graph_steps=graph_steps)
     plain_out = ctx.fetch()
     counts = np.bincount(plain_out["shape"].cpu().numpy(), minlength=S)
     plain_digest = cell_set_digest(plain_out)
+    codes_s = sample_codes(plain_out["codes"])
     plain_verts = ctx.fetch(sorted=True)["verts"] if scorer is not None else None
+    st_k = march(time_kernels=True)      # host-driven, HIP events: the chain's fractions
+    fr_plain = form_fractions(sb.net, {"kernels": st_k, "stats": st_k, "steps": 1}, 0, codes_s)
     combined = None
     if scorer is not None:
         ctx.prop_set(scorer, k=16, rho=6.0)
-
-        def batched_lb():
-            ctx.seed_rays(o, d, shape_id=sh)
-            return ctx.march(max_cells=max_cells, time_kernels=True, precision=1, propose=1)
-
-        batched_lb()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            st_c = batched_lb()
-        torch.cuda.synchronize()
-        t_c = (time.perf_counter() - t0) / steps
+        st_c, t_c = timed(steps, graph_steps=graph_steps, precision=1, propose=1)
         assert st_c["faces"] == st["faces"], "learned + split-BF16 batched march changed the face count"
         dg = cell_set_digest(ctx.fetch())
         gv = ctx.fetch(sorted=True)["verts"]
         verr = ((gv - plain_verts).abs().amax(dim=1) / plain_verts.abs().amax(dim=1).clamp(min=1.0)).max()
+        st_ck = march(time_kernels=True, precision=1, propose=1)
+        fr_c = form_fractions(sb.net, {"kernels": st_ck, "stats": st_ck, "steps": 1}, 1, codes_s)
         combined = {"faces_per_s": round(st_c["faces"] / t_c, 1), "ms_per_step": round(t_c * 1e3, 3),
                     "faces": st_c["faces"], "cell_set_digest": dg, "exact_cell_set_match": dg == plain_digest,
                     "vs_plain_batched": round(t_b / t_c, 4),
+                    "launch": f"device-driven steps, {graph_steps} per HIP graph replay",
                     "precision": "split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and "
                                  "vertex solves; uncertified cells redone in FP64",
                     "proposals": "top-16 lines by the trained scorer clipped before the every-line pass",
@@ -465,7 +524,8 @@ def c4_forms(B, dev, steps, max_cells, scorer=None):
                     "max_vertex_rel_err_vs_fp64": float(verr.item()),
                     "escalated_cells": st_c["escalated"],
                     "escalated_fraction": round(st_c["escalated"] / max(1, st_c["cells"]), 4),
-                    "accept_rate": round(st_c["prop_accepted"] / max(1, st_c["prop_cells"]), 4)}
+                    "accept_rate": round(st_c["prop_accepted"] / max(1, st_c["prop_cells"]), 4),
+                    "chain_roofline": fr_c}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     faces_single = 0
@@ -478,11 +538,13 @@ def c4_forms(B, dev, steps, max_cells, scorer=None):
     assert faces_single == st["faces"], "batched and per-shape marches differ"
     ctx.close()
     desc = ("64 shapes of one decoder [x; z] (3+256) -> [512]x8 -> 1 with [x; z] re-entering layer 4, "
-            "0.01*MLP + |x|_1 - r_i, radii 0.008..0.35 geometric, 16 rays per shape")
+            "trained as an auto-decoder on unions of 1-8 spheres at log-uniform scales 0.03..0.6; shape s "
+            "marched in a box of half-size 1.2e-3..0.125 (log-spaced) centred on its surface, one seed ray each")
     out = {"c4_batched": {"faces_per_s": round(st["faces"] / t_b, 1), "ms_per_step": round(t_b * 1e3, 3),
                            "faces": st["faces"], "march_steps": st["steps"], "cell_set_digest": plain_digest,
+                           "launch": f"device-driven steps, {graph_steps} per HIP graph replay",
                            "faces_per_shape_min_max": [int(counts.min()), int(counts.max())],
-                           "chain_groups_tuned": groups, "workload": desc},
+                           "chain_groups_tuned": groups, "workload": desc, "chain_roofline": fr_plain},
             "c4_per_shape": {"faces_per_s": round(faces_single / t_s, 1), "ms_per_step": round(t_s * 1e3, 3),
                              "faces": faces_single, "note": "one march per shape, same context, one pass"}}
     if combined is not None:
@@ -529,8 +591,8 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms",
-                    default="seeding,mesh,pivot,bf16,distance,learned,learned_bf16,c3,c3_pivot,c3_bf16,c3_learned,"
-                            "c3_learned_bf16,ensemble,c4,c4_learned_bf16,c5,c5_learned",
+                    default="seeding,mesh,pivot,bf16,distance,learned,learned_bf16,c3,c3_bf16,c3_learned_bf16,"
+                            "ensemble,c4,c4_learned_bf16,c5,c5_learned_bf16",
                     help="other forms to time on the same net (seeding, mesh, pivot, bf16, distance, learned, "
                          "learned_bf16), on "
                          "the 8x256 fit (c3, c3_bf16, c3_learned, c3_learned_bf16) and the 64-shape decoder "
@@ -643,9 +705,13 @@ def main(argv=None):
     prop_desc = {0: None, 1: "top-16 lines by the trained scorer clipped before the every-line pass",
                  2: "top-16 lines by distance to the entry edge clipped before the every-line pass"}
 
-    def record(key, r, precision, propose, routine=0, ref_digest=None):
+    def record(key, r, precision, propose, routine=0, ref_digest=None, net_=None):
         e = {"faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
              "faces": r["faces"], "precision": bf16_desc if precision else "FP64 chain (MFMA), FP64 clip"}
+        if net_ is not None and (propose == 0 or precision) and not routine:
+            fr = form_fractions(net_, r, precision, sample_codes(r["out"]["codes"]))
+            if fr:
+                e["chain_roofline"] = fr
         d = cell_set_digest(r["out"])
         e["cell_set_digest"] = d
         if ref_digest is not None:
@@ -678,31 +744,53 @@ def main(argv=None):
         r = time_form(ctx, o_d, d_d, precision, a.steps, a.warmup, a.max_cells, propose=propose,
                       face_routine=routine)
         assert r["faces"] == main_run["faces"], f"{v} form changed the face count"
-        record(f"{a.workload}_{v}", r, precision, propose, routine, ref_digest=plain_digest)
+        record(f"{a.workload}_{v}", r, precision, propose, routine, ref_digest=plain_digest, net_=net)
 
-    # roofline of the dominant kernel of the timed plain steps
+    # roofline of the dominant kernel of the timed plain steps: the chain
+    # (FP64 MFMA) or the clip (HBM: it reads every row the chain wrote)
     kst = timed["kernels"]
-    codes = timed["out"]["codes"].cpu().numpy().view(np.uint64)
+    codes = sample_codes(timed["out"]["codes"])
     flops_cell = chain_flops_per_cell(net, codes)
-    cells = timed["stats"]["cells"]
+    st_t = timed["stats"]
+    cells = st_t["cells"]
     chain_avg_ms = kst["chain_ms"] / max(1, kst["chain_launches"])
     cells_per_launch = cells * a.steps / max(1, kst["chain_launches"])
     chain_tflops = flops_cell * cells_per_launch / (chain_avg_ms * 1e-3) / 1e12 if chain_avg_ms > 0 else 0.0
     kname = chain_kernel_name(net, chain_tiles[a.workload], gs)
     traffic = measured_traffic(kname)
-    roofline = {"kernel": kname, "bound": "mfma",
-                "achieved": round(chain_tflops, 4),
-                "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(chain_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
-                "traffic": traffic["bytes_per_launch"] if traffic else None,
-                "algorithmic_flops_per_cell": round(flops_cell, 1), "cells_per_launch": round(cells_per_launch, 1),
-                "avg_launch_ms": round(chain_avg_ms, 5), "timed_on": timed_launch,
-                "time_split_ms_per_step": {k: round(kst[k] / a.steps, 3)
-                                           for k in ("chain_ms", "clip_ms", "hash_ms", "march_ms")}}
+    split = {k: round(kst[k] / a.steps, 3) for k in ("chain_ms", "clip_ms", "hash_ms", "march_ms")}
+    chain_entry = {"kernel": kname, "bound": "mfma",
+                   "achieved": round(chain_tflops, 4),
+                   "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(chain_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
+                   "traffic": traffic["bytes_per_launch"] if traffic else None,
+                   "algorithmic_flops_per_cell": round(flops_cell, 1), "cells_per_launch": round(cells_per_launch, 1),
+                   "avg_launch_ms": round(chain_avg_ms, 5), "timed_on": timed_launch,
+                   "time_split_ms_per_step": split}
     if traffic:
-        roofline["traffic_note"] = traffic.get("note", "")
+        chain_entry["traffic_note"] = traffic.get("note", "")
+    # clip: per cell it reads the cell's rows, code, argmax, hints and
+    # fingerprint and writes its face (ids, vertices, neighbour slots, size,
+    # flags) and one candidate per edge (parent, slot, unit, fingerprint,
+    # hints, key)
+    N, M = net.n_hidden, net.n_heads
+    W = max(1, -(-N // 64))
+    mbar = st_t["face_verts"] / max(1, st_t["faces"])
+    clip_bytes_cell = (N + M) * 32 + W * 8 + 4 + 12 + 8 + mbar * (4 + 24 + 4) + 8 + mbar * 32
+    clip_avg_ms = kst["clip_ms"] / max(1, kst["clip_launches"])
+    clip_gbs = clip_bytes_cell * cells_per_launch / (clip_avg_ms * 1e-3) / 1e9 if clip_avg_ms > 0 else 0.0
+    ctraffic = measured_traffic("k_clip<double>")
+    clip_entry = {"kernel": "k_clip<double>", "bound": "hbm", "achieved": round(clip_gbs, 2), "peak": PEAK_HBM_GBS,
+                  "unit": "GB/s", "frac": round(clip_gbs / PEAK_HBM_GBS, 6),
+                  "traffic": ctraffic["bytes_per_launch"] if ctraffic else None,
+                  "algorithmic_bytes_per_cell": round(clip_bytes_cell, 1), "cells_per_launch": round(cells_per_launch, 1),
+                  "avg_launch_ms": round(clip_avg_ms, 5), "timed_on": timed_launch, "time_split_ms_per_step": split}
+    if ctraffic:
+        clip_entry["traffic_note"] = ctraffic.get("note", "")
     if kst["clip_ms"] > kst["chain_ms"]:
-        roofline["dominant_by_time"] = "k_clip_f64"
+        roofline, roofline_other = clip_entry, chain_entry
+    else:
+        roofline, roofline_other = chain_entry, clip_entry
     ctx.close()
 
     for name in ("c3", "c5"):
@@ -724,7 +812,7 @@ def main(argv=None):
             if base is None:
                 base = r["faces"]
             assert r["faces"] == base, f"{name} {v} form changed the face count"
-            record(f"{name}_{v}", r, precision, propose, routine, ref_digest=base_digest)
+            record(f"{name}_{v}", r, precision, propose, routine, ref_digest=base_digest, net_=net3)
             if base_digest is None:
                 base_digest = forms[f"{name}_{v}"]["cell_set_digest"]
                 golden[name] = golden_check(ctx3, name)
@@ -754,7 +842,7 @@ def main(argv=None):
                       "face_verts": st["face_verts"],
                       "triangles": st["triangles"], "cells": st["cells"], "march_steps": st["steps"],
                       "seeds": st["seed_cells"], "degenerate": st["degenerate"]},
-           "forms": forms, "roofline": roofline,
+           "forms": forms, "roofline": roofline, "roofline_other_kernel": roofline_other,
            "golden": {k: g for k, g in golden.items() if g is not None},
            "golden_match": bool(golden.get(a.workload)) and all(g["golden_match"] for g in golden.values()
                                                                  if g is not None),

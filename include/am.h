@@ -58,7 +58,10 @@ typedef enum {
     AM_E_SEED = 4,       /* no seed produced a non-empty face */
     AM_E_DEGENERATE = 5, /* strict mode: a degenerate face was met */
     AM_E_HIP = 6,        /* a HIP runtime call failed */
-    AM_E_STATE = 7       /* call out of order (e.g. march before load) */
+    AM_E_STATE = 7,      /* call out of order (e.g. march before load) */
+    AM_E_STALL = 8       /* persistent march: a bounded device-side wait ran out (a cell's
+                            code never appeared, or no cell finished for about a second
+                            while one was in flight); the result is incomplete */
 } am_status;
 
 typedef struct am_ctx am_ctx;
@@ -86,12 +89,25 @@ typedef struct {
 } am_net_desc;
 
 typedef struct {
-    int64_t max_cells;    /* capacity of discovered cells (0: 1<<20) */
+    int64_t max_cells;    /* capacity of discovered cells (0: 1<<20); faces share room for 8
+                             corners per cell of this capacity (faces average about 4), and a
+                             march that needs more returns AM_E_CAPACITY */
     int32_t max_steps;    /* bound on marching steps (0: unbounded) */
     int32_t strict;       /* 1: return AM_E_DEGENERATE on a degenerate face */
     int32_t time_kernels; /* 1: time each kernel class with HIP events on the stream */
     int32_t kernel_path;  /* 0: the library's choice; 1: split (chain rows through HBM, then
-                             the clip); 2: fused chain+clip in LDS (AM_E_INVALID if too big) */
+                             the clip); 2: fused chain+clip in LDS (AM_E_INVALID if too big);
+                             3: persistent march, one launch for the whole march (the
+                             parallel marching of Sec. 4.2.2 without steps): as many
+                             workgroups as fit on the device take four discovered cells at a
+                             time from a device-side queue, compute their chain, clip them
+                             and insert their neighbours into the hash set at once, until no
+                             cell is left or in flight.  Plain FP64 form only (AM_E_INVALID
+                             with precision, propose, sample collection, pivoting,
+                             graph_steps or max_steps).  The cells, faces and adjacency are
+                             those of the stepped march; cell ids are assigned in the order
+                             cells are found, so only canonical fetches (am_fetch_sorted)
+                             are reproducible from run to run */
     int32_t precision;    /* 0: FP64 chain and clip.  1: split-BF16 chain on matrix cores
                              (each operand = three BF16 terms, six products, FP32
                              accumulation), clip and vertex solves in FP64 on the FP32 rows;

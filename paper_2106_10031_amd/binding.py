@@ -15,9 +15,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libam.so")
 
-AM_OK, AM_E_INVALID, AM_E_OOM, AM_E_CAPACITY, AM_E_SEED, AM_E_DEGENERATE, AM_E_HIP, AM_E_STATE = range(8)
+AM_OK, AM_E_INVALID, AM_E_OOM, AM_E_CAPACITY, AM_E_SEED, AM_E_DEGENERATE, AM_E_HIP, AM_E_STATE, AM_E_STALL = range(9)
 STATUS_NAMES = {0: "AM_OK", 1: "AM_E_INVALID", 2: "AM_E_OOM", 3: "AM_E_CAPACITY", 4: "AM_E_SEED",
-                5: "AM_E_DEGENERATE", 6: "AM_E_HIP", 7: "AM_E_STATE"}
+                5: "AM_E_DEGENERATE", 6: "AM_E_HIP", 7: "AM_E_STATE", 8: "AM_E_STALL"}
 
 # every symbol include/am.h declares
 EXPORTS = ["am_create", "am_destroy", "am_last_error", "am_load_net", "am_load_batch", "am_net_dims", "am_codes",

@@ -29,8 +29,12 @@ void launch_clip_f32(const DevNet &, const uint64_t *, const int *, const uint64
                      long long, long long, const float *, const ClipOut &, const Candidates &, unsigned long long,
                      Counters *, double, double, double, int *, unsigned long long *, const PropArgs &, hipStream_t);
 void launch_calib_split(const DevNet &, const uint64_t *, const int *, long long, const double *, const float *,
-                        const int *, const int *, const double *, int, unsigned long long *, hipStream_t);
+                        const int *, const int *, const double *, const long long *, unsigned long long *,
+                        hipStream_t);
 void launch_prop_score(const PropNet &, const float *, long long, float *, hipStream_t);
+hipError_t persist_grid(int *);
+void launch_persist(const DevNet &, uint64_t *, int *, int *, uint64_t *, int *, double *, int, long long,
+                    const ClipOut &, Counters *, const InlineInsert &, hipStream_t);
 long long prop_param_count();
 int prop_grad_blocks();
 void launch_prop_grad(const float *, const unsigned char *, long long, const float *, float *, float *, double *,
@@ -66,7 +70,7 @@ void launch_split_step_dev(const DevNet &, const uint64_t *, const int *, const 
                            unsigned long long, double, double, double, int *, int, const PropArgs &, hipStream_t);
 hipError_t launch_sort_cells(const unsigned *, long long, long long, unsigned *, int *, int *, void *, size_t,
                              hipStream_t);
-void launch_resolve(const Candidates &, int *, int, Counters *, unsigned long long, long long, hipStream_t,
+void launch_resolve(const Candidates &, int *, const long long *, Counters *, unsigned long long, long long, hipStream_t,
                     long long = 0, long long = 0);
 void launch_codes(const DevNet &, const double *, const int *, long long, uint64_t *, int *, double *, hipStream_t);
 void launch_seed_rays(const DevNet &, const double *, const double *, const int *, long long, double, int, uint64_t *, int *,
@@ -78,16 +82,16 @@ void launch_seed_cands(const DevNet &, const uint64_t *, const int *, const int 
                        const Candidates &, Counters *, unsigned long long, hipStream_t);
 hipError_t scan_tmp_bytes(long long, size_t *);
 hipError_t launch_fetch(const DevNet &, long long, const int *, const int *, const double *, const int *,
-                        const uint64_t *, const int *, const int *, int, int *, int *, long long *, long long *,
-                        void *, size_t, long long, long long *, int *, double *, long long *, uint64_t *, int *,
-                        int *, hipStream_t);
+                        const uint64_t *, const int *, const int *, const long long *, int *, int *, long long *,
+                        long long *, void *, size_t, long long, long long *, int *, double *, long long *,
+                        uint64_t *, int *, int *, hipStream_t);
 hipError_t weld_tmp_bytes(long long, size_t *);
 hipError_t sorted_fetch_tmp_bytes(long long, size_t *);
 size_t qecd_scratch_bytes(long long, long long);
 hipError_t run_qecd(const double *, long long, const long long *, long long, const unsigned char *, long long, int,
                     void *, double *, long long *, long long *, long long *, int *, long long *, hipStream_t);
 hipError_t launch_fetch_sorted(const DevNet &, long long, const int *, const int *, const double *, const int *,
-                               const uint64_t *, const int *, const int *, int, int *, int *, long long *,
+                               const uint64_t *, const int *, const int *, const long long *, int *, int *, long long *,
                                long long *, void *, size_t, long long, int *, int *, int *, int *, uint64_t *,
                                uint64_t *, long long *, long long *, void *, size_t, long long *, int *, double *,
                                long long *, uint64_t *, int *, int *, hipStream_t);
@@ -177,9 +181,11 @@ struct am_ctx {
     char *d_sort_tmp = nullptr;
     size_t sort_tmp = 0;
     int *d_fm = nullptr;
-    int *d_fids = nullptr;
-    double *d_fverts = nullptr;
-    int *d_fnbr = nullptr;
+    int *d_fids = nullptr;         // [slot_cap] face corners: edge ids
+    double *d_fverts = nullptr;    // [slot_cap][3] vertices
+    int *d_fnbr = nullptr;         // [slot_cap] neighbour cells
+    long long *d_foff = nullptr;   // [cap] first slot of each cell's face
+    unsigned long long slot_cap = 0;
     int *d_fflags = nullptr;
     unsigned long long hcap = 0;
     unsigned long long *d_slots = nullptr;
@@ -188,6 +194,14 @@ struct am_ctx {
     long long chunk_cells = 0;
     double *d_rows = nullptr;
     size_t rows_bytes = 0;
+    // persistent march: ready flags per cell, the epoch of the current march,
+    // and one rows buffer per resident workgroup
+    unsigned *d_ready = nullptr;
+    long long ready_cap = 0;
+    unsigned epoch = 0;
+    double *d_prows = nullptr;
+    size_t prows_bytes = 0;
+    int persist_blocks = 0;
     Counters *d_ctr = nullptr;
     Counters *h_ctr = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -369,6 +383,10 @@ void drop_graph(am_ctx *c) {
 
 void free_march(am_ctx *c) {
     drop_graph(c);
+    dfree(c, c->d_ready);
+    c->ready_cap = 0;
+    dfree(c, c->d_prows);
+    c->prows_bytes = 0;
     dfree(c, c->d_codes);
     dfree(c, c->d_am);
     dfree(c, c->d_shape);
@@ -378,6 +396,7 @@ void free_march(am_ctx *c) {
     dfree(c, c->d_fids);
     dfree(c, c->d_fverts);
     dfree(c, c->d_fnbr);
+    dfree(c, c->d_foff);
     dfree(c, c->d_fflags);
     dfree(c, c->d_slots);
     dfree(c, c->cand.parent);
@@ -444,9 +463,13 @@ am_status ensure_march(am_ctx *ctx, long long cells) {
     TRY(dalloc(ctx, ctx->d_hash, cells));
     TRY(dalloc(ctx, ctx->d_hints, (size_t)cells * 3));
     TRY(dalloc(ctx, ctx->d_fm, cells));
-    TRY(dalloc(ctx, ctx->d_fids, (size_t)cells * kFaceSlots));
-    TRY(dalloc(ctx, ctx->d_fverts, (size_t)cells * kFaceSlots * 3));
-    TRY(dalloc(ctx, ctx->d_fnbr, (size_t)cells * kFaceSlots));
+    // face corners: kSlotsPerCell per cell of the capacity on average
+    // (faces average about four corners), taken in order as faces are made
+    ctx->slot_cap = (unsigned long long)cells * kSlotsPerCell + kMaxPoly;
+    TRY(dalloc(ctx, ctx->d_fids, (size_t)ctx->slot_cap));
+    TRY(dalloc(ctx, ctx->d_fverts, (size_t)ctx->slot_cap * 3));
+    TRY(dalloc(ctx, ctx->d_fnbr, (size_t)ctx->slot_cap));
+    TRY(dalloc(ctx, ctx->d_foff, (size_t)cells));
     TRY(dalloc(ctx, ctx->d_fflags, cells));
     unsigned long long h = 1;
     while (h < 2ull * (unsigned long long)cells) h <<= 1;
@@ -1052,9 +1075,10 @@ am_status am_busy(const am_ctx *ctx, int32_t *busy) {
 static am_status calibrate_split(am_ctx *ctx, long long n) {
     const DevNet &net = ctx->dn;
     hipStream_t s = ctx->stream;
-    if (!ctx->d_calib) TRY(dalloc(ctx, ctx->d_calib, 3));
+    if (!ctx->d_calib) TRY(dalloc(ctx, ctx->d_calib, 4));
     double *r64 = ctx->d_rows;
     float *r32 = (float *)(ctx->d_rows + (size_t)n * net.R * 4);
+    HIPCHK(hipMemsetAsync(ctx->d_calib, 0, 4 * sizeof(unsigned long long), s));
     launch_chain(net, ctx->d_codes, ctx->d_shape, 0, n, nullptr, nullptr, r64, 1, s);
     ClipOut out{};
     out.m = ctx->d_fm;
@@ -1062,14 +1086,16 @@ static am_status calibrate_split(am_ctx *ctx, long long n) {
     out.verts = ctx->d_fverts;
     out.nbr = nullptr;
     out.flags = ctx->d_fflags;
-    out.stride = kFaceSlots;
+    out.stride = kMaxPoly;
     out.out_base = 0;
+    out.off = ctx->d_foff;
+    out.slot_n = ctx->d_calib + 3;   // its own slot counter: the march's starts at 0
+    out.slot_cap = ctx->slot_cap;
     const Candidates none{};
     launch_clip(net, ctx->d_codes, ctx->d_am, nullptr, nullptr, 0, n, nullptr, nullptr, 0, r64, out, none, 0, nullptr,
                 PropArgs{}, s);
     launch_chain_bf16(net, ctx->d_codes, ctx->d_shape, 0, n, r32, s);
-    HIPCHK(hipMemsetAsync(ctx->d_calib, 0, 3 * sizeof(unsigned long long), s));
-    launch_calib_split(net, ctx->d_codes, ctx->d_am, n, r64, r32, ctx->d_fm, ctx->d_fids, ctx->d_fverts, kFaceSlots,
+    launch_calib_split(net, ctx->d_codes, ctx->d_am, n, r64, r32, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_foff,
                        ctx->d_calib, s);
     unsigned long long h[3] = {0, 0, 0};
     HIPCHK(hipMemcpyAsync(h, ctx->d_calib, sizeof h, hipMemcpyDeviceToHost, s));
@@ -1103,7 +1129,12 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         ctx->cap_cells = 0;   // force a re-size with room for the seeds
         TRY(ensure_march(ctx, cap));
     }
-    if (o.kernel_path < 0 || o.kernel_path > 2) return fail(ctx, AM_E_INVALID, "kernel_path must be 0, 1 or 2");
+    if (o.kernel_path < 0 || o.kernel_path > 3) return fail(ctx, AM_E_INVALID, "kernel_path must be 0..3");
+    const bool persistent = o.kernel_path == 3;
+    if (persistent && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.face_routine != 0 ||
+                       o.graph_steps != 0 || o.max_steps != 0))
+        return fail(ctx, AM_E_INVALID, "the persistent march runs the plain FP64 form (no precision, proposals, "
+                                       "sample collection, pivoting, graph_steps or max_steps)");
     if (o.precision < 0 || o.precision > 1) return fail(ctx, AM_E_INVALID, "precision must be 0 or 1");
     if (o.precision == 1 && o.kernel_path == 2)
         return fail(ctx, AM_E_INVALID, "the split-BF16 form runs on the split path");
@@ -1124,7 +1155,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
     const bool collecting = ctx->prop.samples != nullptr;
     if ((o.propose != 0 || collecting) && o.kernel_path == 2)
         return fail(ctx, AM_E_INVALID, "proposals and sample collection run on the split path");
-    const bool fused = o.precision == 0 && o.propose == 0 && !collecting &&
+    const bool fused = !persistent && o.precision == 0 && o.propose == 0 && !collecting &&
                        (o.kernel_path == 2 || (o.kernel_path == 0 && ctx->prefer_fused && ctx->fused_ok));
     PropArgs pa = ctx->prop;
     pa.mode = o.propose;
@@ -1165,7 +1196,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
     st.seeds_in = (long long)ctx->h_ctr->n_cand;
     long long lo = 0, hi = (long long)ctx->h_ctr->n_cells;
     st.seed_cells = hi;
-    if (ctx->h_ctr->overflow_cells || ctx->h_ctr->overflow_cand || ctx->h_ctr->overflow_hash) {
+    if (ctx->h_ctr->overflowed()) {
         st.required_cells = hi;
         if (stats) *stats = st;
         return fail(ctx, AM_E_CAPACITY, "seed insertion overflowed the capacities");
@@ -1192,8 +1223,11 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
     out.verts = ctx->d_fverts;
     out.nbr = ctx->d_fnbr;
     out.flags = ctx->d_fflags;
-    out.stride = kFaceSlots;
+    out.stride = kMaxPoly;
     out.out_base = 0;
+    out.off = ctx->d_foff;
+    out.slot_n = &ctx->d_ctr->slot_n;
+    out.slot_cap = ctx->slot_cap;
     const long long seed_cells = hi;
     // one device-driven step (graph_steps > 0): chain and clip of the range the
     // counters hold (split-BF16 with its FP64 redo, or FP64), then the hash
@@ -1222,11 +1256,76 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         launch_commit(net, ctx->cand, ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_hash, ctx->d_hints,
                       ctx->d_cell_key, ctx->d_fm, ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape, ctx->d_slots,
                       ctx->d_ctr, ctx->cand_cap, (unsigned long long)cap, nh, q);
-        launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, q, gchunk, cap);
+        launch_resolve(ctx->cand, ctx->d_fnbr, ctx->d_foff, ctx->d_ctr, ctx->cand_cap, nh, q, gchunk, cap);
         if (e && r == hipSuccess) r = hipEventRecord(e[3], q);
         return r;
     };
-    if (o.graph_steps > 0 && o.time_kernels) {
+    if (persistent) {
+        // one launch: workgroups take cells from the device-side queue until
+        // none is left or in flight (k_march_persist)
+        if (ctx->persist_blocks <= 0) HIPCHK(persist_grid(&ctx->persist_blocks));
+        const size_t pb = (size_t)ctx->persist_blocks * 4 * (size_t)net.R * 4 * sizeof(double);
+        if (ctx->prows_bytes < pb) {
+            dfree(ctx, ctx->d_prows);
+            ctx->prows_bytes = 0;
+            TRY(dalloc(ctx, ctx->d_prows, pb / sizeof(double)));
+            ctx->prows_bytes = pb;
+        }
+        if (ctx->ready_cap < cap) {
+            dfree(ctx, ctx->d_ready);
+            ctx->ready_cap = 0;
+            TRY(dalloc(ctx, ctx->d_ready, (size_t)cap));
+            HIPCHK(hipMemsetAsync(ctx->d_ready, 0, sizeof(unsigned) * (size_t)cap, s));
+            ctx->ready_cap = cap;
+            ctx->epoch = 0;
+        }
+        if (++ctx->epoch == 0) {   // flags of 2^32 marches ago could match: clear them
+            HIPCHK(hipMemsetAsync(ctx->d_ready, 0, sizeof(unsigned) * (size_t)ctx->ready_cap, s));
+            ctx->epoch = 1;
+        }
+        InlineInsert ins{};
+        ins.codes = ctx->d_codes;
+        ins.argmax = ctx->d_am;
+        ins.shape = ctx->d_shape;
+        ins.cell_hash = ctx->d_hash;
+        ins.hints = ctx->d_hints;
+        ins.face_m = ctx->d_fm;
+        ins.slots = ctx->d_slots;
+        ins.hmask = hmask;
+        ins.ready = ctx->d_ready;
+        ins.epoch = ctx->epoch;
+        ins.cap_cells = (unsigned long long)cap;
+        ins.spin_limit = 1ull << 23;
+        if (o.time_kernels) HIPCHK(hipEventRecord(ctx->evk[0], s));
+        launch_persist(net, ctx->d_codes, ctx->d_shape, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_prows,
+                       ctx->persist_blocks, seed_cells, out, ctx->d_ctr, ins, s);
+        HIPCHK(hipGetLastError());
+        if (o.time_kernels) HIPCHK(hipEventRecord(ctx->evk[1], s));
+        HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipGetLastError());
+        if (o.time_kernels) {
+            float a = 0.f;
+            HIPCHK(hipEventElapsedTime(&a, ctx->evk[0], ctx->evk[1]));
+            st.chain_ms = a;
+            st.chain_launches = 1;
+        }
+        const Counters &c = *ctx->h_ctr;
+        st.steps = 1;
+        if (c.overflowed()) {
+            st.required_cells = (long long)c.n_cells;
+            st.cells = std::min<long long>((long long)c.n_cells, cap);
+            if (stats) *stats = st;
+            return fail(ctx, AM_E_CAPACITY,
+                        "capacity exceeded (cells %llu/%lld, hash overflow %llu, faces without room for their "
+                        "corners %llu)",
+                        c.n_cells, cap, c.overflow_hash, c.overflow_slots);
+        }
+        if (c.stalled || c.done_cells != c.n_cells)
+            return fail(ctx, AM_E_STALL, "persistent march stopped: %llu bounded waits ran out, %llu of %llu cells done",
+                        c.stalled, c.done_cells, c.n_cells);
+        lo = hi = 0;
+    } else if (o.graph_steps > 0 && o.time_kernels) {
         // device-driven steps launched one by one (no graph), graph_steps per
         // counter read, HIP events around each kernel class of every step
         const size_t nev = (size_t)o.graph_steps * 4;
@@ -1261,14 +1360,15 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
                 st.clip_launches++;
                 st.hash_launches += 3;
             }
-            if (c.overflow_cells || c.overflow_cand || c.overflow_hash) {
+            if (c.overflowed()) {
                 st.required_cells = (long long)c.n_cells;
                 st.cells = std::min<long long>((long long)c.n_cells, cap);
                 st.steps = (long long)c.steps_run;
                 if (stats) *stats = st;
                 return fail(ctx, AM_E_CAPACITY,
-                            "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu)",
-                            c.n_cells, cap, c.overflow_cand, c.overflow_hash);
+                            "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu, "
+                            "faces without room for their corners %llu)",
+                            c.n_cells, cap, c.overflow_cand, c.overflow_hash, c.overflow_slots);
             }
             if (c.step_lo >= c.n_cells) break;
             if (o.max_steps > 0 && (long long)c.steps_run >= o.max_steps) break;
@@ -1288,6 +1388,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         const std::vector<long long> key = {(long long)o.graph_steps, gchunk, variant, (long long)ctx->d_codes,
                                             (long long)ctx->d_rows, (long long)ctx->cand.parent,
                                             (long long)ctx->d_slots, (long long)hmask, (long long)ctx->d_fm,
+                                            (long long)ctx->d_foff, (long long)ctx->slot_cap,
                                             (long long)net.wfrag, (long long)net.bias, cap, seed_cells,
                                             (long long)ctx->cand_cap, (long long)o.precision, (long long)o.propose,
                                             bits(margin), bits(vtol), bits(ctx->calib_eps),
@@ -1321,14 +1422,15 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
             HIPCHK(hipGetLastError());
             ++launches;
             const Counters &c = *ctx->h_ctr;
-            if (c.overflow_cells || c.overflow_cand || c.overflow_hash) {
+            if (c.overflowed()) {
                 st.required_cells = (long long)c.n_cells;
                 st.cells = std::min<long long>((long long)c.n_cells, cap);
                 st.steps = (long long)c.steps_run;
                 if (stats) *stats = st;
                 return fail(ctx, AM_E_CAPACITY,
-                            "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu)",
-                            c.n_cells, cap, c.overflow_cand, c.overflow_hash);
+                            "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu, "
+                            "faces without room for their corners %llu)",
+                            c.n_cells, cap, c.overflow_cand, c.overflow_hash, c.overflow_slots);
             }
             if (c.step_lo >= c.n_cells) break;
             if (o.max_steps > 0 && (long long)c.steps_run >= o.max_steps) break;
@@ -1383,7 +1485,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
                   ctx->d_cell_key, ctx->d_fm,
                       ctx->d_seed_codes, ctx->d_seed_am, ctx->d_seed_shape, ctx->d_slots, ctx->d_ctr, ctx->cand_cap,
                       (unsigned long long)cap, nh, s);
-        launch_resolve(ctx->cand, ctx->d_fnbr, kFaceSlots, ctx->d_ctr, ctx->cand_cap, nh, s);
+        launch_resolve(ctx->cand, ctx->d_fnbr, ctx->d_foff, ctx->d_ctr, ctx->cand_cap, nh, s);
         if (tk) HIPCHK(hipEventRecord(ctx->evk[3], s));
         HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1402,13 +1504,14 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         }
         st.steps++;
         const Counters &c = *ctx->h_ctr;
-        if (c.overflow_cells || c.overflow_cand || c.overflow_hash) {
+        if (c.overflowed()) {
             st.required_cells = (long long)c.n_cells;
             st.cells = std::min<long long>((long long)c.n_cells, cap);
             if (stats) *stats = st;
             return fail(ctx, AM_E_CAPACITY,
-                        "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu)",
-                        c.n_cells, cap, c.overflow_cand, c.overflow_hash);
+                        "capacity exceeded (cells %llu/%lld, candidate overflow %llu, hash overflow %llu, "
+                        "faces without room for their corners %llu)",
+                        c.n_cells, cap, c.overflow_cand, c.overflow_hash, c.overflow_slots);
         }
         lo += n;
         hi = (long long)c.n_cells;
@@ -1440,7 +1543,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
     // faces and empty seeds: count through the fetch scan
     TRY(ensure_scan(ctx, std::max<long long>(st.cells, 1)));
     HIPCHK(launch_fetch(net, st.cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
-                        ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
+                        ctx->d_am, ctx->d_shape, ctx->d_foff, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
                         ctx->d_scan, ctx->scan_bytes, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                         nullptr, s));
     int last_idx = 0, last_has = 0;
@@ -1546,7 +1649,7 @@ static am_status fetch_device(am_ctx *ctx, bool sorted, const FetchOut &o) {
     TRY(ensure_scan(ctx, std::max<long long>(ctx->res_cells, 1)));
     if (!sorted) {
         HIPCHK(launch_fetch(ctx->dn, ctx->res_cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr, ctx->d_codes,
-                            ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
+                            ctx->d_am, ctx->d_shape, ctx->d_foff, ctx->d_has, ctx->d_fidx, ctx->d_mcount, ctx->d_voff,
                             ctx->d_scan, ctx->scan_bytes, ctx->res_faces, (long long *)offsets, ids, verts,
                             (long long *)nbr, codes, argmax, shape_id, ctx->stream));
         return AM_OK;
@@ -1570,7 +1673,7 @@ static am_status fetch_device(am_ctx *ctx, bool sorted, const FetchOut &o) {
         ctx->sf_cap = n;
     }
     HIPCHK(launch_fetch_sorted(ctx->dn, ctx->res_cells, ctx->d_fm, ctx->d_fids, ctx->d_fverts, ctx->d_fnbr,
-                               ctx->d_codes, ctx->d_am, ctx->d_shape, kFaceSlots, ctx->d_has, ctx->d_fidx,
+                               ctx->d_codes, ctx->d_am, ctx->d_shape, ctx->d_foff, ctx->d_has, ctx->d_fidx,
                                ctx->d_mcount, ctx->d_voff, ctx->d_scan, ctx->scan_bytes, F, ctx->d_sf_cell,
                                ctx->d_sf_pa, ctx->d_sf_pb, ctx->d_sf_rank, ctx->d_sf_ka, ctx->d_sf_kb, ctx->d_sf_mc,
                                ctx->d_sf_vo, ctx->d_sf_tmp, ctx->sf_tmp, (long long *)offsets, ids, verts,

@@ -22,12 +22,6 @@
 
 namespace am {
 
-constexpr uint64_t kPending = 1ull << 63;
-
-__device__ __forceinline__ uint32_t slot_tag(uint64_t h) {
-    return (uint32_t)((h >> 32) & 0x7fffffffu) | 0x40000000u;   // never zero
-}
-
 // Where the code of candidate t comes from: a parent cell with one flip, or
 // a seed code.
 struct CodeRef {
@@ -187,7 +181,7 @@ __global__ __launch_bounds__(256) void k_commit(DevNet net, Candidates cand, uin
 // this kernel reads the step fields, n_cand or fb_n.
 __device__ void next_step_range(Counters *c, unsigned long long chunk, unsigned long long cap_cells) {
     const unsigned long long cells = c->n_cells < cap_cells ? c->n_cells : cap_cells;
-    const bool bad = c->overflow_cells || c->overflow_cand || c->overflow_hash;
+    const bool bad = c->overflowed();
     const unsigned long long lo = c->step_lo;
     unsigned long long n = (!bad && cells > lo) ? cells - lo : 0ull;
     if (n > c->max_frontier) c->max_frontier = n;
@@ -197,7 +191,7 @@ __device__ void next_step_range(Counters *c, unsigned long long chunk, unsigned 
     c->fb_n = 0ull;
 }
 
-__global__ __launch_bounds__(256) void k_resolve(Candidates cand, int *face_nbr, int stride, Counters *ctr,
+__global__ __launch_bounds__(256) void k_resolve(Candidates cand, int *face_nbr, const long long *face_off, Counters *ctr,
                                                  unsigned long long cand_cap, unsigned long long chunk,
                                                  unsigned long long cap_cells, int advance) {
     const unsigned long long n = min(ctr->n_cand_prev, cand_cap);
@@ -215,7 +209,7 @@ __global__ __launch_bounds__(256) void k_resolve(Candidates cand, int *face_nbr,
         if (kind == kOwner) c = cand.cell[t];
         else if (kind == kFound) c = (int)cand.ref[t];
         else if (kind == kDup) c = cand.cell[cand.ref[t]];
-        face_nbr[(long long)p * stride + cand.slot[t]] = c;
+        face_nbr[face_off[p] + cand.slot[t]] = c;
     }
 }
 
@@ -526,7 +520,7 @@ __global__ void k_face_flags(const int *face_m, long long n, int *has, long long
 
 __global__ void k_fetch(const DevNet net, long long n, const int *face_m, const int *fidx, const long long *voff,
                         const int *ids, const double *verts, const int *nbr, const uint64_t *codes,
-                        const int *argmax, const int *shape, int stride, long long *o_off, int *o_ids,
+                        const int *argmax, const int *shape, const long long *foff, long long *o_off, int *o_ids,
                         double *o_verts, long long *o_nbr, uint64_t *o_codes, int *o_am, int *o_shape) {
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
@@ -540,7 +534,7 @@ __global__ void k_fetch(const DevNet net, long long n, const int *face_m, const 
         if (o_am) o_am[f] = argmax[c];
         if (o_shape) o_shape[f] = shape[c];
         for (int i = 0; i < m; ++i) {
-            const long long s = c * stride + i;
+            const long long s = foff[c] + i;
             if (o_ids) o_ids[o + i] = ids[s];
             if (o_verts) {
                 o_verts[(o + i) * 3 + 0] = verts[s * 3 + 0];
@@ -603,8 +597,9 @@ __global__ void k_sorted_counts(const int *perm, const int *face_cell, const int
 __global__ void k_fetch_sorted(const DevNet net, long long F, const int *perm, const int *face_cell,
                                const int *rank, const long long *voff, const int *face_m, const int *fidx,
                                const int *ids, const double *verts, const int *nbr, const uint64_t *codes,
-                               const int *argmax, const int *shape, int stride, long long *o_off, int *o_ids,
-                               double *o_verts, long long *o_nbr, uint64_t *o_codes, int *o_am, int *o_shape) {
+                               const int *argmax, const int *shape, const long long *foff, long long *o_off,
+                               int *o_ids, double *o_verts, long long *o_nbr, uint64_t *o_codes, int *o_am,
+                               int *o_shape) {
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < F;
          p += (long long)gridDim.x * blockDim.x) {
         const long long c = face_cell[perm[p]];
@@ -616,7 +611,7 @@ __global__ void k_fetch_sorted(const DevNet net, long long F, const int *perm, c
         if (o_am) o_am[p] = argmax[c];
         if (o_shape) o_shape[p] = shape[c];
         for (int i = 0; i < m; ++i) {
-            const long long s = c * stride + i;
+            const long long s = foff[c] + i;
             if (o_ids) o_ids[o + i] = ids[s];
             if (o_verts) {
                 o_verts[(o + i) * 3 + 0] = verts[s * 3 + 0];
@@ -677,9 +672,10 @@ hipError_t launch_sort_cells(const unsigned *cell_key, long long lo, long long n
     return hipcub::DeviceRadixSort::SortPairs(tmp, tb, cell_key + lo, keys_out, ids, order, (int)n, 0, 30, st);
 }
 
-void launch_resolve(const Candidates &cand, int *face_nbr, int stride, Counters *ctr, unsigned long long cand_cap,
+void launch_resolve(const Candidates &cand, int *face_nbr, const long long *face_off, Counters *ctr,
+                    unsigned long long cand_cap,
                     long long n_hint, hipStream_t st, long long chunk, long long cap_cells) {
-    hipLaunchKernelGGL(k_resolve, dim3(grid_for(n_hint)), dim3(256), 0, st, cand, face_nbr, stride, ctr, cand_cap,
+    hipLaunchKernelGGL(k_resolve, dim3(grid_for(n_hint)), dim3(256), 0, st, cand, face_nbr, face_off, ctr, cand_cap,
                        (unsigned long long)(chunk > 0 ? chunk : 0), (unsigned long long)(cap_cells > 0 ? cap_cells : 0),
                        chunk > 0 ? 1 : 0);
 }
@@ -735,7 +731,8 @@ hipError_t scan_tmp_bytes(long long n, size_t *bytes) {
 }
 
 hipError_t launch_fetch(const DevNet &net, long long n, const int *face_m, const int *ids, const double *verts,
-                        const int *nbr, const uint64_t *codes, const int *argmax, const int *shape, int stride,
+                        const int *nbr, const uint64_t *codes, const int *argmax, const int *shape,
+                        const long long *foff,
                         int *has, int *fidx, long long *mcount, long long *voff, void *tmp, size_t tmp_bytes,
                         long long F, long long *o_off, int *o_ids, double *o_verts, long long *o_nbr,
                         uint64_t *o_codes, int *o_am, int *o_shape, hipStream_t st) {
@@ -751,7 +748,7 @@ hipError_t launch_fetch(const DevNet &net, long long n, const int *face_m, const
     e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, mcount, voff, (int)n, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fetch, dim3(grid_for(n)), dim3(256), 0, st, net, n, face_m, fidx, voff, ids, verts, nbr,
-                       codes, argmax, shape, stride, o_off, o_ids, o_verts, o_nbr, o_codes, o_am, o_shape);
+                       codes, argmax, shape, foff, o_off, o_ids, o_verts, o_nbr, o_codes, o_am, o_shape);
     hipLaunchKernelGGL(k_fetch_tail, dim3(1), dim3(64), 0, st, o_off, F, voff, face_m, n);
     return hipGetLastError();
 }
@@ -773,7 +770,7 @@ hipError_t sorted_fetch_tmp_bytes(long long F, size_t *bytes) {
 // sorted_fetch_tmp_bytes(F) (and scan_tmp_bytes(n) for the cell scan).
 hipError_t launch_fetch_sorted(const DevNet &net, long long n, const int *face_m, const int *ids,
                                const double *verts, const int *nbr, const uint64_t *codes, const int *argmax,
-                               const int *shape, int stride, int *has, int *fidx, long long *mcount,
+                               const int *shape, const long long *foff, int *has, int *fidx, long long *mcount,
                                long long *voff, void *scan_tmp, size_t scan_bytes, long long F, int *face_cell,
                                int *perm_a, int *perm_b, int *rank, uint64_t *keys_a, uint64_t *keys_b,
                                long long *mcs, long long *voffs, void *tmp, size_t tmp_bytes, long long *o_off,
@@ -809,7 +806,7 @@ hipError_t launch_fetch_sorted(const DevNet &net, long long n, const int *face_m
     e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, mcs, voffs, (int)F, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fetch_sorted, dim3(grid_for(F)), dim3(256), 0, st, net, F, perm_a, face_cell, rank, voffs,
-                       face_m, fidx, ids, verts, nbr, codes, argmax, shape, stride, o_off, o_ids, o_verts, o_nbr,
+                       face_m, fidx, ids, verts, nbr, codes, argmax, shape, foff, o_off, o_ids, o_verts, o_nbr,
                        o_codes, o_am, o_shape);
     hipLaunchKernelGGL(k_sorted_tail, dim3(1), dim3(64), 0, st, o_off, F, voffs, mcs);
     return hipGetLastError();

@@ -13,7 +13,7 @@ constexpr int kMaxHidden = 8192;
 constexpr int kMaxHeads = 64;
 constexpr int kWave = 64;
 constexpr int kMaxPoly = 64;      // polygon vertices held by one wave (one per lane)
-constexpr int kFaceSlots = 64;    // stored vertices per cell in the face buffers
+constexpr int kSlotsPerCell = 8;  // face corners a march reserves per cell of its capacity (mean; faces hold up to 64)
 
 // On-line tolerance of the halfplane clip: 2^-40 relative (see am.h).
 constexpr double kTau = 9.094947017729282379150390625e-13;
@@ -121,15 +121,21 @@ struct CellArrays {
     const int *seed_shape;
 };
 
-// Where the clip kernel writes faces.
+// Where the clip kernel writes faces.  With off == NULL, face f (output
+// index cell - out_base) has `stride` slots at f * stride; otherwise each face
+// takes m consecutive slots from the shared counter *slot_n (at most slot_cap
+// in all) and off[f] records the first.
 struct ClipOut {
     int *m;               // [cells] vertex count, 0 = empty face
-    int *ids;             // [cells][stride]
-    double *verts;        // [cells][stride][3]
-    int *nbr;             // [cells][stride] neighbour cell (-1 box edge) or NULL
+    int *ids;             // [slots]
+    double *verts;        // [slots][3]
+    int *nbr;             // [slots] neighbour cell (-1 box edge) or NULL
     int *flags;           // [cells] or NULL
-    int stride;           // vertices stored per cell (<= kMaxPoly)
+    int stride;           // most vertices of a face (<= kMaxPoly); slots per face without off
     long long out_base;   // output index = cell - out_base
+    long long *off;       // [cells] first slot of each face, or NULL
+    unsigned long long *slot_n;   // slots taken so far (with off)
+    unsigned long long slot_cap;  // slots available (with off)
 };
 
 // Device-side counters of a march (one struct in device memory).
@@ -154,6 +160,46 @@ struct Counters {
     unsigned long long max_frontier;     // device-driven steps: largest frontier seen
     unsigned long long n_cand_prev;      // the step's candidate count, copied by commit for resolve
     unsigned long long fb_n;             // device-driven split-BF16 steps: cells handed to FP64
+    unsigned long long slot_n;           // face slots (corners) taken
+    unsigned long long overflow_slots;   // faces that found no room for their corners
+    // persistent march: next cell to take, cells finished, stop request, and
+    // bounded waits that ran out (a march with stalled > 0 has failed)
+    unsigned long long next_cell;
+    unsigned long long done_cells;
+    unsigned long long stop;
+    unsigned long long stalled;
+
+    __host__ __device__ bool overflowed() const {
+        return overflow_cells || overflow_cand || overflow_hash || overflow_slots;
+    }
+};
+
+// ---- device hash set of discovered cells (open addressing, 64-bit slots).
+// A committed slot holds tag(h) << 32 | cell id.  A slot being filled holds
+// kPending plus a reference to where the candidate's code comes from.
+constexpr uint64_t kPending = 1ull << 63;
+
+__device__ __forceinline__ uint32_t slot_tag(uint64_t h) {
+    return (uint32_t)((h >> 32) & 0x7fffffffu) | 0x40000000u;   // never zero
+}
+
+// What the persistent march needs to insert a face's neighbours into the
+// hash set as soon as the face is known (no candidate buffer): the cell
+// arrays it appends to, the set, the ready flags (ready[c] == epoch once cell
+// c's code and hints are written) and the bound on waits.
+struct InlineInsert {
+    uint64_t *codes;
+    int *argmax;
+    int *shape;
+    uint64_t *cell_hash;
+    int *hints;
+    int *face_m;
+    unsigned long long *slots;
+    unsigned long long hmask;
+    unsigned *ready;
+    unsigned epoch;
+    unsigned long long cap_cells;
+    unsigned long long spin_limit;   // polls of one wait before the march gives up
 };
 
 // ---------------------------------------------------------------- helpers

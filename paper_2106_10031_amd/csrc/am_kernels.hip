@@ -50,7 +50,7 @@ __device__ __forceinline__ long long tile_cell(const int *list, long long p0, in
 
 // Stages the codes and shape ids of a tile's ncell (<= nmax) cells in LDS
 // (ends with a barrier).
-__device__ void stage_tile(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ cell_shape,
+__device__ void stage_tile(const DevNet &net, const uint64_t *codes, const int *cell_shape,
                            const int *list, long long p0, int ncell, uint64_t *code_lds, int *shape_lds,
                            int nmax = 4) {
     for (int t = threadIdx.x; t < nmax * net.W; t += blockDim.x) {
@@ -78,8 +78,8 @@ __device__ void stage_tile(const DevNet &net, const uint64_t *__restrict__ codes
 constexpr int kLdsRows = 128;
 
 template <int G, int KC>
-__device__ void chain_tile(const DevNet &net, const uint64_t *__restrict__ codes,
-                           const int *__restrict__ cell_shape, const int *list, long long c0, int ncell, double *zb,
+__device__ void chain_tile(const DevNet &net, const uint64_t *codes,
+                           const int *cell_shape, const int *list, long long c0, int ncell, double *zb,
                            long long rs, long long cs, uint64_t *code_lds, int *shape_lds, double *zl = nullptr) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -1259,12 +1259,159 @@ __device__ bool pivot_poly(const DevNet &net, const uint64_t *code, int am, cons
     return false;
 }
 
+// ---- inline insertion (persistent march).  Lane i of a face with m
+// corners holds edge i (constraint e); its neighbour is the cell with unit e
+// flipped (hidden unit) or with head e - N as the argmax (a max-pool edge).
+// Three phases, so that no lane waits while it holds a claim:
+//   1. probe from the neighbour's fingerprint: an empty slot is claimed with
+//      CAS as kPending | 18-bit tag | e | this cell (the claim names its code:
+//      this cell's with e flipped); a committed slot with the same tag, or a
+//      claim with the same short tag, is compared on the full code;
+//   2. every claim becomes the next cell id: its code, argmax, shape,
+//      fingerprint and clip hints are written, then (release) the slot turns
+//      into tag | id and ready[id] into the epoch;
+//   3. a lane that met an equal claim of another wave waits (bounded) for it
+//      to be committed and takes its id.
+// Claims are committed in phase 2 without waiting on anything, so every wait
+// of phase 3 ends.  The neighbour ids go to the face's nbr slots.
+__device__ __forceinline__ uint64_t flip_word(const uint64_t *code, int flip, int w) {
+    uint64_t x = code[w];
+    if (flip >= 0 && (flip >> 6) == w) x ^= 1ull << (flip & 63);
+    return x;
+}
+
+__device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long long cell, const uint64_t *code,
+                                  int am, int m, int e_out, const ClipOut &out, long long obase, Counters *ctr) {
+    const int lane = lane_id();
+    const bool want = lane < m && e_out >= 0;
+    const int e_prev = shfl(e_out, lane == 0 ? m - 1 : lane - 1);
+    const int e_next = shfl(e_out, lane + 1 >= m ? 0 : lane + 1);
+    const uint64_t dm = ballot(lane < m && e_out < 0);
+    if (lane == 0 && dm) atomicAdd(&ctr->domain_edges, (unsigned long long)__popcll(dm));
+    const uint64_t h = I.cell_hash[cell];
+    const int shp = I.shape[cell];
+    uint64_t hn = 0;
+    int nam = am, flip = -1;
+    if (want) {
+        if (e_out < net.N) {
+            hn = h ^ net.zobrist[e_out];
+            flip = e_out;
+        } else {
+            hn = h ^ net.zobrist[net.N + am] ^ net.zobrist[e_out];
+            nam = e_out - net.N;
+        }
+    }
+    const unsigned long long tag = slot_tag(hn);
+    const unsigned long long ptag = (hn >> 46) & 0x3ffffull;
+    const unsigned long long mine = kPending | (ptag << 45) | ((unsigned long long)e_out << 31) |
+                                    (unsigned long long)cell;
+    unsigned long long pos = hn & I.hmask;
+    int state = want ? 0 : 3;   // 0 probing, 1 claimed, 2 equal claim met, 3 done
+    long long nid = -1;
+    // phase 1
+    for (unsigned long long probe = 0; state == 0; ++probe) {
+        if (probe > I.hmask) {
+            atomicAdd(&ctr->overflow_hash, 1ull);
+            __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            state = 3;
+            break;
+        }
+        // acquire: the code a slot names was written before the slot (a
+        // claim names a cell being processed, whose code came before its
+        // ready flag; a committed id's code comes before the commit)
+        unsigned long long sv = __hip_atomic_load(&I.slots[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (sv == 0) {
+            if (__hip_atomic_compare_exchange_strong(&I.slots[pos], &sv, mine, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                state = 1;
+                break;
+            }
+        }
+        int oc = -1, oflip = -1, oam = 0;
+        bool cmp = false;
+        if (sv & kPending) {
+            if (((sv >> 45) & 0x3ffffull) == ptag) {
+                // a claim: the code of cell (low 31 bits) with constraint e flipped
+                oc = (int)(sv & 0x7fffffffull);
+                const int oe = (int)((sv >> 31) & 0x3fffull);
+                oflip = oe < net.N ? oe : -1;
+                oam = oe < net.N ? I.argmax[oc] : oe - net.N;
+                cmp = true;
+            }
+        } else if (((sv >> 32) & 0x7fffffffull) == tag) {
+            oc = (int)(sv & 0xffffffffull);
+            if ((unsigned long long)oc < I.cap_cells) {
+                oam = I.argmax[oc];
+                cmp = true;
+            }
+        }
+        if (cmp && oam == nam && I.shape[oc] == shp) {
+            const uint64_t *ocode = I.codes + (long long)oc * net.W;
+            bool eq = true;
+            for (int w = 0; w < net.W && eq; ++w) eq = flip_word(ocode, oflip, w) == flip_word(code, flip, w);
+            if (eq) {
+                if (sv & kPending) {
+                    state = 2;
+                } else {
+                    nid = oc;
+                    state = 3;
+                }
+                break;
+            }
+        }
+        pos = (pos + 1) & I.hmask;
+    }
+    // phase 2
+    const bool own = state == 1;
+    unsigned long long base;
+    const unsigned long long id = wave_reserve(&ctr->n_cells, own, &base);
+    if (own) {
+        if (id >= I.cap_cells) {
+            atomicAdd(&ctr->overflow_cells, 1ull);
+            __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&I.slots[pos], (tag << 32) | 0xffffffffull, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            uint64_t *dst = I.codes + (long long)id * net.W;
+            for (int w = 0; w < net.W; ++w) dst[w] = flip_word(code, flip, w);
+            I.argmax[id] = nam;
+            I.shape[id] = shp;
+            I.cell_hash[id] = hn;
+            I.hints[id * 3 + 0] = e_out < net.N ? e_out : net.N + am;   // the crossed plane, in its ids
+            I.hints[id * 3 + 1] = e_prev;
+            I.hints[id * 3 + 2] = e_next;
+            I.face_m[id] = 0;
+            __hip_atomic_store(&I.slots[pos], (tag << 32) | id, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&I.ready[id], I.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            nid = (long long)id;
+        }
+    }
+    // phase 3
+    if (state == 2) {
+        unsigned long long sv = kPending;
+        for (unsigned long long k = 0; k < I.spin_limit; ++k) {
+            sv = __hip_atomic_load(&I.slots[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (!(sv & kPending)) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (sv & kPending) {
+            atomicAdd(&ctr->stalled, 1ull);
+            __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const unsigned long long oc = sv & 0xffffffffull;
+            nid = oc < I.cap_cells ? (long long)oc : -1;
+        }
+    }
+    if (want && out.nbr) out.nbr[obase + lane] = (int)nid;
+}
+
 template <typename RowT, bool Learn, bool Pivot = false>
-__device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes, const int *__restrict__ argmax,
-                          const uint64_t *__restrict__ cell_hash, const int *__restrict__ hints, long long cell,
+__device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *argmax,
+                          const uint64_t *cell_hash, const int *hints, long long cell,
                           long long n_seed_cells, const RowT *rb, long long rs, PolyScratch &S, const ClipOut &out,
                           const Candidates &cand, unsigned long long cand_cap, Counters *ctr, double margin,
-                          double vertex_tol, const Fallback &fb, const PropArgs &pa, PropScratch *ps) {
+                          double vertex_tol, const Fallback &fb, const PropArgs &pa, PropScratch *ps,
+                          const InlineInsert *ins = nullptr) {
     const int lane = lane_id();
     const uint64_t *code = codes + cell * net.W;
     const int am_in = argmax ? argmax[cell] : 0;
@@ -1543,8 +1690,22 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
             return;
         }
     }
+    long long obase = oi * out.stride;
+    if (out.off) {
+        // this face's corners take m consecutive slots of the shared buffer
+        unsigned long long b = 0;
+        if (lane == 0 && m > 0) b = atomicAdd(out.slot_n, (unsigned long long)m);
+        b = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b) |
+            ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32);
+        if (m > 0 && b + (unsigned long long)m > out.slot_cap) {
+            if (lane == 0 && ctr) atomicAdd(&ctr->overflow_slots, 1ull);
+            m = 0;
+        }
+        obase = (long long)b;
+        if (lane == 0) out.off[oi] = m > 0 ? obase : 0;
+    }
     if (m > 0 && lane < m) {
-        const long long o = oi * out.stride + lane;
+        const long long o = obase + lane;
         out.ids[o] = e_out;
         out.verts[o * 3 + 0] = x[0];
         out.verts[o * 3 + 1] = x[1];
@@ -1577,7 +1738,9 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *__restrict__ codes,
     }
 
     // ---- neighbour candidates: flip the unit (or the argmax) behind each edge
-    if (cand.parent && m > 0) {
+    if (ins && m > 0) {
+        insert_neighbours(net, *ins, cell, code, am, m, e_out, out, obase, ctr);
+    } else if (cand.parent && m > 0) {
         const bool want = lane < m && e_out >= 0;
         const int e_prev = shfl(e_out, lane == 0 ? m - 1 : lane - 1);
         const int e_next = shfl(e_out, lane + 1 >= m ? 0 : lane + 1);
@@ -1627,12 +1790,12 @@ __global__ __launch_bounds__(256) void k_calib_split(DevNet net, const uint64_t 
                                                      const double *__restrict__ rows64,
                                                      const float *__restrict__ rows32, const int *__restrict__ fm,
                                                      const int *__restrict__ fids, const double *__restrict__ fverts,
-                                                     int stride, unsigned long long *out) {
+                                                     const long long *__restrict__ foff, unsigned long long *out) {
     const int lane = lane_id();
     const long long cell = 4LL * blockIdx.x + (threadIdx.x >> 6);
     if (cell >= n) return;
     const int m = fm[cell];
-    if (m < 3 || m > stride) return;
+    if (m < 3 || m > kMaxPoly) return;
     const uint64_t *code = codes + cell * net.W;
     const int am = argmax ? argmax[cell] : 0;
     if (am < 0 || am >= net.M) return;
@@ -1641,9 +1804,9 @@ __global__ __launch_bounds__(256) void k_calib_split(DevNet net, const uint64_t 
     double ratio = 0.0, marg = 0.0;
     double x64[3] = {0.0, 0.0, 0.0};
     if (lane < m) {
-        const long long o = cell * stride + lane;
+        const long long o = foff[cell] + lane;
         const int e = fids[o];
-        const int ep = fids[cell * stride + (lane == 0 ? m - 1 : lane - 1)];
+        const int ep = fids[foff[cell] + (lane == 0 ? m - 1 : lane - 1)];
         for (int k = 0; k < 3; ++k) x64[k] = fverts[o * 3 + k];
         double ca[4], cb[4];
         constraint_row(net, ep, code, am, r32, 4, ca);
@@ -1691,10 +1854,10 @@ __global__ __launch_bounds__(256) void k_calib_split(DevNet net, const uint64_t 
 
 void launch_calib_split(const DevNet &net, const uint64_t *codes, const int *argmax, long long n,
                         const double *rows64, const float *rows32, const int *fm, const int *fids,
-                        const double *fverts, int stride, unsigned long long *out, hipStream_t st) {
+                        const double *fverts, const long long *foff, unsigned long long *out, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_calib_split, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, net, codes, argmax, n, rows64,
-                       rows32, fm, fids, fverts, stride, out);
+                       rows32, fm, fids, fverts, foff, out);
 }
 
 // Positions 0..count-1 of a step: cell lo + p, or list[p] (count read on the
@@ -2058,6 +2221,120 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
                              scratch[wave], out, cand, cand_cap, ctr, 0.0, 0.0, none, off, nullptr);
 }
 
+// ---- persistent march (plain FP64 form).  The cells discovered so far,
+// 0 .. n_cells - 1, are the work queue: a workgroup takes the next (up to)
+// four, waits until their codes are written (ready flags), computes their
+// affine chain into its own rows buffer, and each of its four waves clips one
+// of them and inserts that face's neighbours into the hash set itself
+// (insert_neighbours), which appends new cells to the queue.  The march ends
+// when every discovered cell is finished: a workgroup that finds no cell to
+// take reads done_cells, then n_cells, and leaves when they are equal (a cell
+// is counted done only after its insertions, with release order, so equal
+// counts mean no cell is in flight and none can appear).  Every wait is
+// bounded: spin_limit polls without a cell finishing anywhere (or, for a
+// flag, without the flag) stop the march and count a stall; capacity
+// overflows stop it too.  The host checks both.
+__global__ __launch_bounds__(256) void k_march_persist(DevNet net, uint64_t *codes, int *cell_shape, int *argmax,
+                                                       uint64_t *cell_hash, int *hints, double *rows_ws,
+                                                       long long n_seed_cells, ClipOut out, Counters *ctr,
+                                                       InlineInsert ins) {
+    __shared__ PolyScratch scratch[4];
+    __shared__ uint64_t code_lds[4 * kMaxWords];
+    __shared__ int shape_lds[4];
+    __shared__ long long tile_c0;
+    __shared__ int tile_n;
+    __shared__ int tile_bad;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const long long cs = (long long)net.R * 4;
+    double *zb = rows_ws + (long long)blockIdx.x * 4 * cs;
+    const Candidates none_c{};
+    const Fallback none_f{nullptr, nullptr, 0, 0.0};
+    const PropArgs off{};
+    for (;;) {
+        if (threadIdx.x == 0) {
+            long long c0 = 0;
+            int n = 0;
+            unsigned long long last_done = ~0ull, idle = 0;
+            for (;;) {
+                if (__hip_atomic_load(&ctr->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                const unsigned long long a = __hip_atomic_load(&ctr->next_cell, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                unsigned long long cells = __hip_atomic_load(&ctr->n_cells, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                if (cells > ins.cap_cells) cells = ins.cap_cells;
+                if (a < cells) {
+                    const unsigned long long k = cells - a < 4ull ? cells - a : 4ull;
+                    unsigned long long exp = a;
+                    if (__hip_atomic_compare_exchange_strong(&ctr->next_cell, &exp, a + k, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        c0 = (long long)a;
+                        n = (int)k;
+                        break;
+                    }
+                    continue;
+                }
+                const unsigned long long d = __hip_atomic_load(&ctr->done_cells, __ATOMIC_ACQUIRE,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long c2 = __hip_atomic_load(&ctr->n_cells, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                if (d >= c2) break;   // nothing in flight: the march is over
+                if (d != last_done) {
+                    last_done = d;
+                    idle = 0;
+                } else if (++idle > ins.spin_limit) {
+                    atomicAdd(&ctr->stalled, 1ull);
+                    __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            tile_c0 = c0;
+            tile_n = n;
+            tile_bad = 0;
+        }
+        __syncthreads();
+        const long long c0 = tile_c0;
+        const int n = tile_n;
+        if (n <= 0) break;
+        if (threadIdx.x < n) {
+            // the cell's code and hints are written before its flag (release)
+            bool ok = false;
+            for (unsigned long long k = 0; k < ins.spin_limit; ++k) {
+                if (__hip_atomic_load(&ins.ready[c0 + threadIdx.x], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+                    ins.epoch) {
+                    ok = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (!ok) {
+                atomicAdd(&ctr->stalled, 1ull);
+                __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                tile_bad = 1;
+            }
+        }
+        __syncthreads();   // no thread reads a code before its flag is seen
+        if (tile_bad) break;
+        chain_tile<1, 4>(net, codes, cell_shape, nullptr, c0, n, zb, 4, cs, code_lds, shape_lds);
+        if (wave < n) {
+            clip_cell<double, false>(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zb + wave * cs,
+                                     4, scratch[wave], out, none_c, 0, ctr, 0.0, 0.0, none_f, off, nullptr, &ins);
+            if (lane == 0)
+                __hip_atomic_fetch_add(&ctr->done_cells, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+// Ready flags of the seed cells (0 .. n_cells - 1) for a persistent march.
+__global__ void k_mark_ready(unsigned *ready, const Counters *ctr, unsigned epoch) {
+    const unsigned long long n = ctr->n_cells;
+    for (unsigned long long c = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; c < n;
+         c += (unsigned long long)gridDim.x * blockDim.x)
+        ready[c] = epoch;
+}
+
 // Logits of n feature rows (FP32 [n][kPropD]) by the scorer the proposing
 // clip uses (FP16 operands, FP32 accumulation); one wave per 64 rows.
 __global__ __launch_bounds__(256) void k_prop_score(PropNet P, const float *__restrict__ X, long long n,
@@ -2299,6 +2576,27 @@ void launch_fused(const DevNet &net, const uint64_t *codes, const int *cell_shap
                        cell_shape, argmax, cell_hash, hints, lo, hi, n_seed_cells, out, cand, cand_cap, ctr);
 }
 
+// Workgroups of the persistent march that fit on the device at once.
+hipError_t persist_grid(int *blocks) {
+    int dev = 0, per_cu = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_march_persist, 256, 0);
+    if (e != hipSuccess) return e;
+    *blocks = (per_cu > 0 ? per_cu : 1) * cus;
+    return hipSuccess;
+}
+
+void launch_persist(const DevNet &net, uint64_t *codes, int *cell_shape, int *argmax, uint64_t *cell_hash,
+                    int *hints, double *rows_ws, int blocks, long long n_seed_cells, const ClipOut &out,
+                    Counters *ctr, const InlineInsert &ins, hipStream_t st) {
+    hipLaunchKernelGGL(k_mark_ready, dim3(256), dim3(256), 0, st, ins.ready, ctr, ins.epoch);
+    hipLaunchKernelGGL(k_march_persist, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, cell_shape, argmax,
+                       cell_hash, hints, rows_ws, n_seed_cells, out, ctr, ins);
+}
+
 void launch_rows_unpad(const DevNet &net, long long n, const void *rows, bool f32, double *out, hipStream_t st) {
     if (n <= 0) return;
     const long long total = n * (net.N + net.M);
@@ -2327,7 +2625,7 @@ void launch_prop_score(const PropNet &P, const float *X, long long n, float *z, 
 __global__ void k_step_begin(Counters *c, unsigned long long chunk, unsigned long long cap_cells) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const unsigned long long cells = c->n_cells < cap_cells ? c->n_cells : cap_cells;
-    const bool bad = c->overflow_cells || c->overflow_cand || c->overflow_hash;
+    const bool bad = c->overflowed();
     const unsigned long long lo = c->step_lo;
     unsigned long long n = (!bad && cells > lo) ? cells - lo : 0ull;
     if (n > c->max_frontier) c->max_frontier = n;

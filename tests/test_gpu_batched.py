@@ -96,15 +96,13 @@ def test_shape_ids_are_validated(binding):
 
 
 def test_wide_decoder_batch_equals_single_shape_marches(binding):
-    """The 64-shape decoder's first 12 shapes (the smallest): each shape's part
+    """The 64-shape decoder's first 12 shapes (the smallest boxes): each shape's part
     of one batched march equals that shape's own GPU march (cells, cycles,
     adjacency exact; vertices bit-equal: same rows, same solves)."""
     from gpu_common import compare_meshes_fast
     sb = nets.c4_batch()
     keep = 12
-    o1, d1 = seeds.centre_rays(np.zeros((1, 3)), 16)
-    o = np.tile(o1, (keep, 1)); d = np.tile(d1, (keep, 1))
-    sh = np.repeat(np.arange(keep, dtype=np.int32), len(o1))
+    o, d, sh = nets.c4_seed_rays(keep)
     say("c4 batch of", keep, "shapes")
     ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
     ctx.seed_rays(o, d, shape_id=sh)
@@ -137,9 +135,7 @@ def test_wide_decoder_batch_bf16_with_proposals_equals_plain(binding, propose, g
     from paper_2106_10031_amd.learn import init_params
     sb = nets.c4_batch()
     keep = 12
-    o1, d1 = seeds.centre_rays(np.zeros((1, 3)), 16)
-    o = np.tile(o1, (keep, 1)); d = np.tile(d1, (keep, 1))
-    sh = np.repeat(np.arange(keep, dtype=np.int32), len(o1))
+    o, d, sh = nets.c4_seed_rays(keep)
     say("c4 batch of", keep, "shapes, bf16 + proposals", propose)
     ctx = binding.Context(0).load_net(sb.net, shape_bias=sb.shape_bias)
     ctx.seed_rays(o, d, shape_id=sh)

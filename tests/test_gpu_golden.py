@@ -8,7 +8,8 @@ oracle's bit for bit); sampled vertices within 1e-9 relative on the FP64 path
 and within 1e-5 on the split-BF16 path.  Each launch configuration the
 benchmark times is here: host-driven steps with every chain tile variant,
 device-driven steps replayed from a captured graph with the tuned tile, the
-split-BF16 chain, proposals and the pivoting face routine.
+persistent march, the split-BF16 chain, proposals and the pivoting face
+routine.
 """
 import numpy as np
 import pytest
@@ -64,6 +65,9 @@ CASES = [
     ("c3", dict(chain_groups=7)),
     ("c3", dict(graph_steps=8, chain_groups=8)),
     ("c3", dict(face_routine=1)),
+    ("c1", dict(kernel_path=3)),
+    ("c2", dict(kernel_path=3)),
+    ("c3", dict(kernel_path=3)),
 ]
 
 

@@ -6,8 +6,8 @@ Bars:
   single-shape march array for array (cells, cycles, adjacency exact,
   vertices bit-equal: same rows, same solves), on all 64 shapes;
 * sampled faces of both workloads equal the oracle's faces of the same cells
-  (cycles exact, vertices 1e-9 relative), over the whole radius range for the
-  batch and >= 10,000 faces of the 8x512 fit;
+  (cycles exact, vertices 1e-9 relative), over the whole box-size range for
+  the batch and >= 10,000 faces of the 8x512 fit;
 * closedness (Theorem 1) of the whole 8x512 mesh: across every inner edge on
   unit k the neighbour's edge on unit k points back;
 * the three patterns together (split-BF16 chain, proposals, batching) on all
@@ -93,11 +93,7 @@ def test_c5_sampled_faces_and_closedness(binding):
 
 def c4_rays():
     sb = nets.c4_batch()
-    o1, d1 = seeds.centre_rays(np.zeros((1, 3)), 16)
-    S = sb.n_shapes
-    o = np.tile(o1, (S, 1))
-    d = np.tile(d1, (S, 1))
-    sh = np.repeat(np.arange(S, dtype=np.int32), len(o1))
+    o, d, sh = nets.c4_seed_rays(sb.n_shapes)
     return sb, o, d, sh
 
 
@@ -151,14 +147,14 @@ def test_c4_batched_equals_all_64_single_shape_marches(binding, c4_batched):
     say("c4 faces per shape", int(counts.min()), "..", int(counts.max()))
 
 
-def test_c4_sampled_faces_equal_the_oracle_across_radii(binding, c4_batched):
+def test_c4_sampled_faces_equal_the_oracle_across_box_sizes(binding, c4_batched):
     sb, ctx, st, out = c4_batched
     S = sb.n_shapes
     f_lo, _ = shape_blocks(out, S)
     rng = np.random.default_rng(13)
     off = out["offsets"].cpu().numpy()
     checked = 0
-    for s in (0, 9, 18, 27, 36, 45, 54, 63):           # radii 0.008 ... 0.35, geometric
+    for s in (0, 9, 18, 27, 36, 45, 54, 63):           # box half-sizes 1.2e-3 ... 0.125
         a, b = int(f_lo[s]), int(f_lo[s + 1])
         fs = rng.choice(np.arange(a, b), size=min(150, b - a), replace=False)
         codes = out["codes"][torch.as_tensor(fs, device=out["codes"].device)].cpu().numpy().view(np.uint64)
