@@ -32,8 +32,8 @@ void launch_calib_split(const DevNet &, const uint64_t *, const int *, long long
                         const int *, const int *, const double *, const long long *, unsigned long long *,
                         hipStream_t);
 void launch_prop_score(const PropNet &, const float *, long long, float *, hipStream_t);
-hipError_t persist_grid(int *);
-void launch_persist(const DevNet &, uint64_t *, int *, int *, uint64_t *, int *, double *, int, long long,
+hipError_t persist_setup(const DevNet &, size_t, int *, size_t *, int *);
+void launch_persist(const DevNet &, int, size_t, uint64_t *, int *, int *, uint64_t *, int *, double *, int, long long,
                     const ClipOut &, Counters *, const InlineInsert &, hipStream_t);
 long long prop_param_count();
 int prop_grad_blocks();
@@ -201,7 +201,9 @@ struct am_ctx {
     unsigned epoch = 0;
     double *d_prows = nullptr;
     size_t prows_bytes = 0;
-    int persist_blocks = 0;
+    int persist_blocks = 0;      // 0: not set up for the loaded net
+    int persist_variant = 0;     // chain of the persistent tile (0 dense, 1/2 ping-pong FP64/FP32 fragments)
+    size_t persist_lds = 0;
     Counters *d_ctr = nullptr;
     Counters *h_ctr = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -800,6 +802,7 @@ static am_status load_impl(am_ctx *ctx, const am_net_desc *nd, int n_shapes, con
     dn.bias = ctx->d_bias;
     dn.zobrist = ctx->d_zobrist;
     ctx->calib_ok = false;   // the split-BF16 certificate is measured per net
+    ctx->persist_blocks = 0;  // the persistent tile is chosen per net
     dn.lb_ok = prepare_chain_lb(dn, ctx->lds_limit);
     (void)hipGetLastError();
     ctx->dn = dn;
@@ -1263,7 +1266,8 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
     if (persistent) {
         // one launch: workgroups take cells from the device-side queue until
         // none is left or in flight (k_march_persist)
-        if (ctx->persist_blocks <= 0) HIPCHK(persist_grid(&ctx->persist_blocks));
+        if (ctx->persist_blocks <= 0)
+            HIPCHK(persist_setup(net, ctx->lds_limit, &ctx->persist_variant, &ctx->persist_lds, &ctx->persist_blocks));
         const size_t pb = (size_t)ctx->persist_blocks * 4 * (size_t)net.R * 4 * sizeof(double);
         if (ctx->prows_bytes < pb) {
             dfree(ctx, ctx->d_prows);
@@ -1297,8 +1301,9 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         ins.cap_cells = (unsigned long long)cap;
         ins.spin_limit = 1ull << 23;
         if (o.time_kernels) HIPCHK(hipEventRecord(ctx->evk[0], s));
-        launch_persist(net, ctx->d_codes, ctx->d_shape, ctx->d_am, ctx->d_hash, ctx->d_hints, ctx->d_prows,
-                       ctx->persist_blocks, seed_cells, out, ctx->d_ctr, ins, s);
+        launch_persist(net, ctx->persist_variant, ctx->persist_lds, ctx->d_codes, ctx->d_shape, ctx->d_am,
+                       ctx->d_hash, ctx->d_hints, ctx->d_prows, ctx->persist_blocks, seed_cells, out, ctx->d_ctr, ins,
+                       s);
         HIPCHK(hipGetLastError());
         if (o.time_kernels) HIPCHK(hipEventRecord(ctx->evk[1], s));
         HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->d_ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));

@@ -139,8 +139,11 @@ struct ClipOut {
 };
 
 // Device-side counters of a march (one struct in device memory).
+// The counters that many workgroups update or poll while a march runs
+// (n_cells, slot_n, next_cell, done_cells, stop) each sit on a 128-byte line
+// of their own, so that traffic on one does not queue behind another's.
 struct Counters {
-    unsigned long long n_cells;
+    alignas(128) unsigned long long n_cells;
     unsigned long long n_cand;
     unsigned long long overflow_cells;
     unsigned long long overflow_cand;
@@ -160,14 +163,13 @@ struct Counters {
     unsigned long long max_frontier;     // device-driven steps: largest frontier seen
     unsigned long long n_cand_prev;      // the step's candidate count, copied by commit for resolve
     unsigned long long fb_n;             // device-driven split-BF16 steps: cells handed to FP64
-    unsigned long long slot_n;           // face slots (corners) taken
     unsigned long long overflow_slots;   // faces that found no room for their corners
-    // persistent march: next cell to take, cells finished, stop request, and
-    // bounded waits that ran out (a march with stalled > 0 has failed)
-    unsigned long long next_cell;
-    unsigned long long done_cells;
-    unsigned long long stop;
-    unsigned long long stalled;
+    unsigned long long stalled;          // persistent march: bounded waits that ran out (the march failed)
+    alignas(128) unsigned long long slot_n;   // face slots (corners) taken
+    // persistent march: next cell id to hand out, cells finished, stop request
+    alignas(128) unsigned long long next_cell;
+    alignas(128) unsigned long long done_cells;
+    alignas(128) unsigned long long stop;
 
     __host__ __device__ bool overflowed() const {
         return overflow_cells || overflow_cand || overflow_hash || overflow_slots;
@@ -182,6 +184,42 @@ constexpr uint64_t kPending = 1ull << 63;
 __device__ __forceinline__ uint32_t slot_tag(uint64_t h) {
     return (uint32_t)((h >> 32) & 0x7fffffffu) | 0x40000000u;   // never zero
 }
+
+// Cross-workgroup data of the persistent march (new cells' records, hash
+// slots, ready flags, queue counters) is read and written only with
+// device-scope relaxed atomics: each such access is coherent across the XCDs
+// by itself (it is performed at the device's coherence point), so no
+// acquire or release fence is needed, and none of the cache-wide invalidate
+// or write-back operations those fences imply is issued.  Order between a
+// record and the flag that publishes it comes from publish_wait: the
+// writer's record stores have completed before its flag store is issued, and
+// a reader issues its record loads only after its flag load has returned.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void publish_wait() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);   // the compiler keeps the order
+    __builtin_amdgcn_s_waitcnt(0);             // every earlier memory access has completed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// A cell's record as the persistent march holds it (copied to LDS from the
+// cell arrays with device-scope loads): the clip reads this instead of the
+// arrays, which another workgroup wrote.
+struct CellRec {
+    const uint64_t *code;
+    int am;
+    int shape;
+    int hint[3];
+    uint64_t hash;
+};
 
 // What the persistent march needs to insert a face's neighbours into the
 // hash set as soon as the face is known (no candidate buffer): the cell

@@ -30,6 +30,8 @@
 // Vertices are then recomputed in FP64 from their two edge ids and the plane
 // (Eqn (VertexEquationSystem)), and each edge on a hidden unit or head
 // comparison becomes a neighbour candidate (state flip, Sec. 3.1).
+#include <type_traits>
+
 #include "am_internal.h"
 
 namespace am {
@@ -80,7 +82,8 @@ constexpr int kLdsRows = 128;
 template <int G, int KC>
 __device__ void chain_tile(const DevNet &net, const uint64_t *codes,
                            const int *cell_shape, const int *list, long long c0, int ncell, double *zb,
-                           long long rs, long long cs, uint64_t *code_lds, int *shape_lds, double *zl = nullptr) {
+                           long long rs, long long cs, uint64_t *code_lds, int *shape_lds, double *zl = nullptr,
+                           bool staged = false) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -88,7 +91,7 @@ __device__ void chain_tile(const DevNet &net, const uint64_t *codes,
     const int kq = lane >> 4;        // k within the K-step of 4 (A, B) / row offset (D)
     const int q = col & 3;           // homogeneous component of this column
     const int cl = col >> 2;         // cell of this column within its group
-    stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds, 4 * G);
+    if (!staged) stage_tile(net, codes, cell_shape, list, c0, ncell, code_lds, shape_lds, 4 * G);
     long long bias_base[G];
     const uint64_t *code[G];
     double *zc[G];
@@ -1280,16 +1283,18 @@ __device__ __forceinline__ uint64_t flip_word(const uint64_t *code, int flip, in
     return x;
 }
 
-__device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long long cell, const uint64_t *code,
-                                  int am, int m, int e_out, const ClipOut &out, long long obase, Counters *ctr) {
+__device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long long cell, const CellRec &rec,
+                                  int m, int e_out, const ClipOut &out, long long obase, Counters *ctr) {
+    const uint64_t *code = rec.code;
+    const int am = rec.am;
     const int lane = lane_id();
     const bool want = lane < m && e_out >= 0;
     const int e_prev = shfl(e_out, lane == 0 ? m - 1 : lane - 1);
     const int e_next = shfl(e_out, lane + 1 >= m ? 0 : lane + 1);
     const uint64_t dm = ballot(lane < m && e_out < 0);
     if (lane == 0 && dm) atomicAdd(&ctr->domain_edges, (unsigned long long)__popcll(dm));
-    const uint64_t h = I.cell_hash[cell];
-    const int shp = I.shape[cell];
+    const uint64_t h = rec.hash;
+    const int shp = rec.shape;
     uint64_t hn = 0;
     int nam = am, flip = -1;
     if (want) {
@@ -1312,16 +1317,16 @@ __device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long
     for (unsigned long long probe = 0; state == 0; ++probe) {
         if (probe > I.hmask) {
             atomicAdd(&ctr->overflow_hash, 1ull);
-            __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_dev(&ctr->stop, 1ull);
             state = 3;
             break;
         }
-        // acquire: the code a slot names was written before the slot (a
-        // claim names a cell being processed, whose code came before its
-        // ready flag; a committed id's code comes before the commit)
-        unsigned long long sv = __hip_atomic_load(&I.slots[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        // the record a slot names was complete before the slot was written
+        // (a claim names a cell being processed; a committed id's record was
+        // published before the commit), and is read after the slot
+        unsigned long long sv = ld_dev(&I.slots[pos]);
         if (sv == 0) {
-            if (__hip_atomic_compare_exchange_strong(&I.slots[pos], &sv, mine, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+            if (__hip_atomic_compare_exchange_strong(&I.slots[pos], &sv, mine, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT)) {
                 state = 1;
                 break;
@@ -1335,20 +1340,24 @@ __device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long
                 oc = (int)(sv & 0x7fffffffull);
                 const int oe = (int)((sv >> 31) & 0x3fffull);
                 oflip = oe < net.N ? oe : -1;
-                oam = oe < net.N ? I.argmax[oc] : oe - net.N;
+                oam = oe < net.N ? ld_dev(&I.argmax[oc]) : oe - net.N;
                 cmp = true;
             }
         } else if (((sv >> 32) & 0x7fffffffull) == tag) {
             oc = (int)(sv & 0xffffffffull);
             if ((unsigned long long)oc < I.cap_cells) {
-                oam = I.argmax[oc];
+                oam = ld_dev(&I.argmax[oc]);
                 cmp = true;
             }
         }
-        if (cmp && oam == nam && I.shape[oc] == shp) {
+        if (cmp && oam == nam && ld_dev(&I.shape[oc]) == shp) {
             const uint64_t *ocode = I.codes + (long long)oc * net.W;
             bool eq = true;
-            for (int w = 0; w < net.W && eq; ++w) eq = flip_word(ocode, oflip, w) == flip_word(code, flip, w);
+            for (int w = 0; w < net.W && eq; ++w) {
+                uint64_t x = ld_dev(&ocode[w]);
+                if (oflip >= 0 && (oflip >> 6) == w) x ^= 1ull << (oflip & 63);
+                eq = x == flip_word(code, flip, w);
+            }
             if (eq) {
                 if (sv & kPending) {
                     state = 2;
@@ -1368,35 +1377,37 @@ __device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long
     if (own) {
         if (id >= I.cap_cells) {
             atomicAdd(&ctr->overflow_cells, 1ull);
-            __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&I.slots[pos], (tag << 32) | 0xffffffffull, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            st_dev(&ctr->stop, 1ull);
         } else {
             uint64_t *dst = I.codes + (long long)id * net.W;
-            for (int w = 0; w < net.W; ++w) dst[w] = flip_word(code, flip, w);
-            I.argmax[id] = nam;
-            I.shape[id] = shp;
-            I.cell_hash[id] = hn;
-            I.hints[id * 3 + 0] = e_out < net.N ? e_out : net.N + am;   // the crossed plane, in its ids
-            I.hints[id * 3 + 1] = e_prev;
-            I.hints[id * 3 + 2] = e_next;
-            I.face_m[id] = 0;
-            __hip_atomic_store(&I.slots[pos], (tag << 32) | id, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&I.ready[id], I.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            for (int w = 0; w < net.W; ++w) st_dev(&dst[w], flip_word(code, flip, w));
+            st_dev(&I.argmax[id], nam);
+            st_dev(&I.shape[id], shp);
+            st_dev(&I.cell_hash[id], hn);
+            st_dev(&I.hints[id * 3 + 0], e_out < net.N ? e_out : net.N + am);   // the crossed plane, in its ids
+            st_dev(&I.hints[id * 3 + 1], e_prev);
+            st_dev(&I.hints[id * 3 + 2], e_next);
+            st_dev(&I.face_m[id], 0);
             nid = (long long)id;
         }
+    }
+    // the records are complete before any slot or flag names them
+    publish_wait();
+    if (own) {
+        st_dev(&I.slots[pos], (tag << 32) | (nid >= 0 ? (unsigned long long)nid : 0xffffffffull));
+        if (nid >= 0) st_dev(&I.ready[nid], I.epoch);
     }
     // phase 3
     if (state == 2) {
         unsigned long long sv = kPending;
         for (unsigned long long k = 0; k < I.spin_limit; ++k) {
-            sv = __hip_atomic_load(&I.slots[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            sv = ld_dev(&I.slots[pos]);
             if (!(sv & kPending)) break;
             __builtin_amdgcn_s_sleep(1);
         }
         if (sv & kPending) {
             atomicAdd(&ctr->stalled, 1ull);
-            __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_dev(&ctr->stop, 1ull);
         } else {
             const unsigned long long oc = sv & 0xffffffffull;
             nid = oc < I.cap_cells ? (long long)oc : -1;
@@ -1411,10 +1422,10 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
                           long long n_seed_cells, const RowT *rb, long long rs, PolyScratch &S, const ClipOut &out,
                           const Candidates &cand, unsigned long long cand_cap, Counters *ctr, double margin,
                           double vertex_tol, const Fallback &fb, const PropArgs &pa, PropScratch *ps,
-                          const InlineInsert *ins = nullptr) {
+                          const InlineInsert *ins = nullptr, const CellRec *rec = nullptr) {
     const int lane = lane_id();
-    const uint64_t *code = codes + cell * net.W;
-    const int am_in = argmax ? argmax[cell] : 0;
+    const uint64_t *code = rec ? rec->code : codes + cell * net.W;
+    const int am_in = rec ? rec->am : (argmax ? argmax[cell] : 0);
     const bool am_ok = am_in >= 0 && am_in < net.M;   // a bad argmax gives an empty face
     const int am = am_ok ? am_in : 0;
     const long long oi = cell - out.out_base;
@@ -1484,13 +1495,13 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
         // parent's edges on either side of it (the cells around a cell edge
         // share both planes).  Any order gives the same polygon; these first
         // leave most later lines with nothing to cut.
-        if (hints) {
+        if (hints || rec) {
             // all three rows are loaded before the first cut
             int hid[3];
             double hc[3][4];
 #pragma unroll
             for (int h = 0; h < 3; ++h) {
-                hid[h] = hints[cell * 3 + h];
+                hid[h] = rec ? rec->hint[h] : hints[cell * 3 + h];
                 if (hid[h] < 0 || hid[h] >= net.N + net.M || hid[h] == net.N + am) hid[h] = -1;
             }
 #pragma unroll
@@ -1738,8 +1749,8 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
     }
 
     // ---- neighbour candidates: flip the unit (or the argmax) behind each edge
-    if (ins && m > 0) {
-        insert_neighbours(net, *ins, cell, code, am, m, e_out, out, obase, ctr);
+    if (ins && rec && m > 0) {
+        insert_neighbours(net, *ins, cell, *rec, m, e_out, out, obase, ctr);
     } else if (cand.parent && m > 0) {
         const bool want = lane < m && e_out >= 0;
         const int e_prev = shfl(e_out, lane == 0 ? m - 1 : lane - 1);
@@ -2221,29 +2232,175 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
                              scratch[wave], out, cand, cand_cap, ctr, 0.0, 0.0, none, off, nullptr);
 }
 
-// ---- persistent march (plain FP64 form).  The cells discovered so far,
-// 0 .. n_cells - 1, are the work queue: a workgroup takes the next (up to)
-// four, waits until their codes are written (ready flags), computes their
-// affine chain into its own rows buffer, and each of its four waves clips one
-// of them and inserts that face's neighbours into the hash set itself
-// (insert_neighbours), which appends new cells to the queue.  The march ends
-// when every discovered cell is finished: a workgroup that finds no cell to
-// take reads done_cells, then n_cells, and leaves when they are equal (a cell
-// is counted done only after its insertions, with release order, so equal
-// counts mean no cell is in flight and none can appear).  Every wait is
-// bounded: spin_limit polls without a cell finishing anywhere (or, for a
-// flag, without the flag) stop the march and count a stall; capacity
-// overflows stop it too.  The host checks both.
-__global__ __launch_bounds__(256) void k_march_persist(DevNet net, uint64_t *codes, int *cell_shape, int *argmax,
+// ---- chain of one persistent tile (four cells, four waves) with the
+// staged-B scheme of k_chain_lb, but two LDS buffers used in turn by layer
+// parity (bsh: 2 x lb_kpad x 16 doubles): layer l writes its masked output
+// into buffer l & 1 while every wave still reads layer l - 1 from the other,
+// so a wave can finish its output tiles group by group (MTW tiles at a time)
+// and one barrier per layer suffices at any width.  Rows (plus bias) go to
+// zb[cell * cs + row * 4 + q].  Same products in the same order as the dense
+// tile (equal rows).  Ends with a barrier.
+template <typename AT, int MTW>
+__device__ void chain_tile_pp(const DevNet &net, const uint64_t *code_lds, const int *shape_lds, int ncell,
+                              double *zb, long long cs, double *bsh) {
+    constexpr int KC = 2 * kLbKSteps / MTW;   // K-steps per batch: 2 x 8 MFMAs in flight per prefetch
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int col = lane & 15;
+    const int kq = lane >> 4;
+    const int q = col & 3;
+    const int cl = col >> 2;
+    const bool ok = cl < ncell;
+    const int kpad = net.lb_kpad;
+    const AT *wf = lb_frags<AT>(net);
+    const uint64_t *code = code_lds + cl * net.W;
+    const double *bias_c = net.bias + (long long)shape_lds[cl] * net.bias_stride;
+    double *zc = zb + cl * cs + q;
+    for (int l = 1; l < net.n_layers; ++l) {
+        const int nl = net.width[l];
+        const int mtiles = (nl + 15) >> 4;
+        const bool hidden = l < net.n_layers - 1;
+        double *ob = bsh + (l & 1) * kpad * 16;
+        const double *ib = bsh + ((l - 1) & 1) * kpad * 16;
+        for (int g0 = 0; g0 < mtiles; g0 += nwaves * MTW) {
+            int nmt = 0;
+#pragma unroll
+            for (int s = 0; s < MTW; ++s)
+                if (g0 + wave + s * nwaves < mtiles) nmt = s + 1;
+            if (nmt == 0) break;
+            v4d acc[MTW];
+#pragma unroll
+            for (int s = 0; s < MTW; ++s) acc[s] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < net.n_blocks; ++b) {
+                if (net.blk_dst[b] != l) continue;
+                const int j = net.blk_src[b];
+                const int ks_n = net.blk_ld[b] >> 2;
+                const AT *fr[MTW];
+#pragma unroll
+                for (int s = 0; s < MTW; ++s)
+                    fr[s] = wf + net.blk_frag_off[b] + (long long)min(g0 + wave + s * nwaves, mtiles - 1) * ks_n * 64 +
+                            lane;
+                if (j == 0) {
+                    const double bv = (kq < 3 && kq == q) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int s = 0; s < MTW; ++s) {
+                        if (s >= nmt) break;
+                        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)fr[s][0], bv, acc[s], 0, 0, 0);
+                    }
+                    continue;
+                }
+                if (j == l - 1) {
+                    AT ac[MTW][KC], an[MTW][KC];
+#pragma unroll
+                    for (int s = 0; s < MTW; ++s)
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) ac[s][u] = fr[s][min(u, ks_n - 1) * 64];
+                    const double *bcol = ib + kq * 16 + col;
+                    for (int ks0 = 0; ks0 < ks_n; ks0 += KC) {
+#pragma unroll
+                        for (int s = 0; s < MTW; ++s)
+#pragma unroll
+                            for (int u = 0; u < KC; ++u) an[s][u] = fr[s][min(ks0 + KC + u, ks_n - 1) * 64];
+                        double bv[KC];
+#pragma unroll
+                        for (int u = 0; u < KC; ++u) bv[u] = bcol[(ks0 + u) * 64];
+#pragma unroll
+                        for (int u = 0; u < KC; ++u)
+#pragma unroll
+                            for (int s = 0; s < MTW; ++s) {
+                                if (s >= nmt) break;
+                                acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ac[s][u], bv[u], acc[s], 0, 0, 0);
+                            }
+#pragma unroll
+                        for (int s = 0; s < MTW; ++s)
+#pragma unroll
+                            for (int u = 0; u < KC; ++u) ac[s][u] = an[s][u];
+                    }
+                    continue;
+                }
+                // a shortcut from an earlier hidden layer: its rows, written
+                // by this workgroup, from global memory, masked here
+                const int nj = net.width[j];
+                const int uoff = net.unit_off[j];
+                const long long roff = (long long)net.row_off[j] * 4;
+                for (int ks = 0; ks < ks_n; ++ks) {
+                    const int k = ks * 4 + kq;
+                    const double bv = (k < nj && ok && code_bit(code, uoff + k)) ? zc[roff + (long long)k * 4] : 0.0;
+#pragma unroll
+                    for (int s = 0; s < MTW; ++s) {
+                        if (s >= nmt) break;
+                        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)fr[s][ks * 64], bv, acc[s], 0, 0, 0);
+                    }
+                }
+            }
+            // rows (plus bias) to global memory, masked rows to the B buffer;
+            // v_mfma_f64_16x16x4f64 leaves D[kq + 4 r][col] in register r
+            const double *bias = bias_c + net.bias_off[l];
+            double *z0 = zc + (long long)net.row_off[l] * 4;
+#pragma unroll
+            for (int s = 0; s < MTW; ++s) {
+                if (s >= nmt) break;
+                const int mt = g0 + wave + s * nwaves;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = mt * 16 + kq + 4 * r;
+                    double v = acc[s][r];
+                    if (i < nl) {
+                        if (q == 3) v += bias[i];
+                        if (ok) z0[(long long)i * 4] = v;
+                    }
+                    if (hidden) {
+                        const bool on = ok && i < nl && code_bit(code, net.unit_off[l] + i);
+                        ob[i * 16 + col] = on ? v : 0.0;
+                    }
+                }
+            }
+        }
+        if (hidden) {
+            // rows the next layer's batches may read past this layer's tiles
+            const int r0 = mtiles * 16;
+            const int r1 = min(kpad, (nl + 31) & ~31);
+            for (int t = threadIdx.x; t < (r1 - r0) * 16; t += blockDim.x) ob[r0 * 16 + t] = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- persistent march (plain FP64 form).  Cell ids are tickets: a
+// workgroup takes the next four ids with one fetch-add on next_cell (ids not
+// yet discovered included: cells are numbered in the order they are found),
+// and processes each of them once it is published (its ready flag set by
+// the workgroup that found it).  A round takes the published ones of its
+// held ids (up to four), copies their records to LDS, computes their affine
+// chain into the workgroup's rows buffer, and each wave clips one cell and
+// inserts that face's neighbours into the hash set itself
+// (insert_neighbours), which numbers and publishes the new cells.  All data
+// another workgroup wrote is read with device-scope loads (ld_dev) and all
+// data another workgroup reads is written with device-scope stores, so no
+// cache-wide fence is needed.  The march ends when every discovered cell is
+// finished: done_cells is read before n_cells (a cell is counted done only
+// after its insertions completed), so equal counts mean no cell is in flight
+// and none can appear; the ids a workgroup still holds then name no cell.
+// Every wait is bounded: spin_limit polls without a cell finishing anywhere
+// stop the march and count a stall; capacity overflows stop it too.  The
+// host checks both.  At least three waves per SIMD (the register budget
+// that allows, without spills): three workgroups per CU share the clip's
+// latency.
+template <int CH>
+__global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *codes, int *cell_shape, int *argmax,
                                                        uint64_t *cell_hash, int *hints, double *rows_ws,
                                                        long long n_seed_cells, ClipOut out, Counters *ctr,
                                                        InlineInsert ins) {
+    extern __shared__ double bsh[];   // CH > 0: 2 x lb_kpad x 16 doubles, the chain's B buffers
     __shared__ PolyScratch scratch[4];
     __shared__ uint64_t code_lds[4 * kMaxWords];
     __shared__ int shape_lds[4];
-    __shared__ long long tile_c0;
+    __shared__ int am_lds[4];
+    __shared__ int hint_lds[4][3];
+    __shared__ uint64_t hash_lds[4];
+    __shared__ long long tile_cell_id[4];
     __shared__ int tile_n;
-    __shared__ int tile_bad;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const long long cs = (long long)net.R * 4;
@@ -2251,79 +2408,90 @@ __global__ __launch_bounds__(256) void k_march_persist(DevNet net, uint64_t *cod
     const Candidates none_c{};
     const Fallback none_f{nullptr, nullptr, 0, 0.0};
     const PropArgs off{};
+    // held tickets (thread 0 only): ids not processed yet, -1 = none
+    long long held[4] = {-1, -1, -1, -1};
     for (;;) {
         if (threadIdx.x == 0) {
-            long long c0 = 0;
             int n = 0;
             unsigned long long last_done = ~0ull, idle = 0;
-            for (;;) {
-                if (__hip_atomic_load(&ctr->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                const unsigned long long a = __hip_atomic_load(&ctr->next_cell, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT);
-                unsigned long long cells = __hip_atomic_load(&ctr->n_cells, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-                if (cells > ins.cap_cells) cells = ins.cap_cells;
-                if (a < cells) {
-                    const unsigned long long k = cells - a < 4ull ? cells - a : 4ull;
-                    unsigned long long exp = a;
-                    if (__hip_atomic_compare_exchange_strong(&ctr->next_cell, &exp, a + k, __ATOMIC_RELAXED,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        c0 = (long long)a;
-                        n = (int)k;
+            int nap = 1;
+            for (unsigned poll = 0;; ++poll) {
+                if (ld_dev(&ctr->stop)) break;
+                if (held[0] < 0 && held[1] < 0 && held[2] < 0 && held[3] < 0) {
+                    const unsigned long long a = atomicAdd(&ctr->next_cell, 4ull);
+                    for (int k = 0; k < 4; ++k) held[k] = (long long)a + k;
+                }
+                // the published ones of the held ids form this round's tile
+                for (int k = 0; k < 4; ++k) {
+                    const long long c = held[k];
+                    if (c >= 0 && (unsigned long long)c < ins.cap_cells && ld_dev(&ins.ready[c]) == ins.epoch) {
+                        tile_cell_id[n++] = c;
+                        held[k] = -1;
+                    }
+                }
+                if (n > 0) break;
+                if ((poll & 7) == 7) {
+                    // done_cells first: its count only includes cells whose
+                    // insertions (n_cells increments) had completed
+                    const unsigned long long d = ld_dev(&ctr->done_cells);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    const unsigned long long c2 = ld_dev(&ctr->n_cells);
+                    if (d >= c2) break;   // nothing in flight: the march is over
+                    if (d != last_done) {
+                        last_done = d;
+                        idle = 0;
+                    } else if (++idle > (ins.spin_limit >> 3)) {   // counted every eighth poll
+                        atomicAdd(&ctr->stalled, 1ull);
+                        st_dev(&ctr->stop, 1ull);
                         break;
                     }
-                    continue;
                 }
-                const unsigned long long d = __hip_atomic_load(&ctr->done_cells, __ATOMIC_ACQUIRE,
-                                                               __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long c2 = __hip_atomic_load(&ctr->n_cells, __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                if (d >= c2) break;   // nothing in flight: the march is over
-                if (d != last_done) {
-                    last_done = d;
-                    idle = 0;
-                } else if (++idle > ins.spin_limit) {
-                    atomicAdd(&ctr->stalled, 1ull);
-                    __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+                // back off while nothing held is published (about 64 * nap cycles)
+                for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
+                if (nap < 8) nap <<= 1;
             }
-            tile_c0 = c0;
             tile_n = n;
-            tile_bad = 0;
         }
         __syncthreads();
-        const long long c0 = tile_c0;
         const int n = tile_n;
         if (n <= 0) break;
         if (threadIdx.x < n) {
-            // the cell's code and hints are written before its flag (release)
-            bool ok = false;
-            for (unsigned long long k = 0; k < ins.spin_limit; ++k) {
-                if (__hip_atomic_load(&ins.ready[c0 + threadIdx.x], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
-                    ins.epoch) {
-                    ok = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            if (!ok) {
-                atomicAdd(&ctr->stalled, 1ull);
-                __hip_atomic_store(&ctr->stop, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                tile_bad = 1;
-            }
+            // the flag was seen before these loads are issued
+            const long long c = tile_cell_id[threadIdx.x];
+            const int sh = ld_dev(&cell_shape[c]);
+            shape_lds[threadIdx.x] = (sh >= 0 && sh < net.S) ? sh : 0;
+            am_lds[threadIdx.x] = ld_dev(&argmax[c]);
+            for (int h = 0; h < 3; ++h) hint_lds[threadIdx.x][h] = ld_dev(&hints[c * 3 + h]);
+            hash_lds[threadIdx.x] = ld_dev(&cell_hash[c]);
+        } else if (threadIdx.x < 4) {
+            shape_lds[threadIdx.x] = 0;
         }
-        __syncthreads();   // no thread reads a code before its flag is seen
-        if (tile_bad) break;
-        chain_tile<1, 4>(net, codes, cell_shape, nullptr, c0, n, zb, 4, cs, code_lds, shape_lds);
-        if (wave < n) {
-            clip_cell<double, false>(net, codes, argmax, cell_hash, hints, c0 + wave, n_seed_cells, zb + wave * cs,
-                                     4, scratch[wave], out, none_c, 0, ctr, 0.0, 0.0, none_f, off, nullptr, &ins);
-            if (lane == 0)
-                __hip_atomic_fetch_add(&ctr->done_cells, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (int t = threadIdx.x; t < 4 * net.W; t += blockDim.x) {
+            const int c = t / net.W;
+            code_lds[t] = c < n ? ld_dev(&codes[tile_cell_id[c] * net.W + (t - c * net.W)]) : 0ull;
         }
         __syncthreads();
+        if constexpr (CH == 0)
+            chain_tile<1, 4>(net, codes, cell_shape, nullptr, 0, n, zb, 4, cs, code_lds, shape_lds, nullptr, true);
+        else
+            chain_tile_pp<typename std::conditional<CH == 2, float, double>::type, 2>(net, code_lds, shape_lds, n,
+                                                                                      zb, cs, bsh);
+        if (wave < n) {
+            CellRec rec;
+            rec.code = code_lds + wave * net.W;
+            rec.am = am_lds[wave];
+            rec.shape = shape_lds[wave];
+            rec.hint[0] = hint_lds[wave][0];
+            rec.hint[1] = hint_lds[wave][1];
+            rec.hint[2] = hint_lds[wave][2];
+            rec.hash = hash_lds[wave];
+            clip_cell<double, false>(net, codes, argmax, cell_hash, hints, tile_cell_id[wave], n_seed_cells,
+                                     zb + wave * cs, 4, scratch[wave], out, none_c, 0, ctr, 0.0, 0.0, none_f, off,
+                                     nullptr, &ins, &rec);
+        }
+        __syncthreads();
+        // every wave's insertions have completed (publish_wait) before the barrier
+        if (threadIdx.x == 0) atomicAdd(&ctr->done_cells, (unsigned long long)n);
     }
 }
 
@@ -2576,25 +2744,50 @@ void launch_fused(const DevNet &net, const uint64_t *codes, const int *cell_shap
                        cell_shape, argmax, cell_hash, hints, lo, hi, n_seed_cells, out, cand, cand_cap, ctr);
 }
 
-// Workgroups of the persistent march that fit on the device at once.
-hipError_t persist_grid(int *blocks) {
+// Persistent march: the chain variant for `net` (0 dense tile; 1, 2 the
+// ping-pong staged-B tile with FP64 or FP32 weight fragments, when its two
+// B buffers fit beside the kernel's static LDS), its dynamic LDS, and the
+// workgroups that fit on the device at once.
+template <int CH>
+static hipError_t persist_setup_t(size_t lds, int *blocks) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_march_persist<CH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
     int dev = 0, per_cu = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
+    e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_march_persist, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_march_persist<CH>, 256, lds);
     if (e != hipSuccess) return e;
     *blocks = (per_cu > 0 ? per_cu : 1) * cus;
     return hipSuccess;
 }
 
-void launch_persist(const DevNet &net, uint64_t *codes, int *cell_shape, int *argmax, uint64_t *cell_hash,
-                    int *hints, double *rows_ws, int blocks, long long n_seed_cells, const ClipOut &out,
-                    Counters *ctr, const InlineInsert &ins, hipStream_t st) {
+hipError_t persist_setup(const DevNet &net, size_t lds_limit, int *variant, size_t *lds, int *blocks) {
+    const size_t pp = (size_t)2 * net.lb_kpad * 16 * sizeof(double);
+    const size_t stat = sizeof(PolyScratch) * 4 + sizeof(uint64_t) * 4 * kMaxWords + 256;
+    if (net.lb_kpad > 0 && pp + stat <= lds_limit) {
+        *variant = net.wfrag32 ? 2 : 1;
+        *lds = pp;
+        return *variant == 2 ? persist_setup_t<2>(pp, blocks) : persist_setup_t<1>(pp, blocks);
+    }
+    *variant = 0;
+    *lds = 0;
+    return persist_setup_t<0>(0, blocks);
+}
+
+void launch_persist(const DevNet &net, int variant, size_t lds, uint64_t *codes, int *cell_shape, int *argmax,
+                    uint64_t *cell_hash, int *hints, double *rows_ws, int blocks, long long n_seed_cells,
+                    const ClipOut &out, Counters *ctr, const InlineInsert &ins, hipStream_t st) {
     hipLaunchKernelGGL(k_mark_ready, dim3(256), dim3(256), 0, st, ins.ready, ctr, ins.epoch);
-    hipLaunchKernelGGL(k_march_persist, dim3((unsigned)blocks), dim3(256), 0, st, net, codes, cell_shape, argmax,
-                       cell_hash, hints, rows_ws, n_seed_cells, out, ctr, ins);
+#define AM_PERSIST_GO(CH_)                                                                                    \
+    hipLaunchKernelGGL(k_march_persist<CH_>, dim3((unsigned)blocks), dim3(256), lds, st, net, codes, cell_shape, \
+                       argmax, cell_hash, hints, rows_ws, n_seed_cells, out, ctr, ins)
+    if (variant == 2) AM_PERSIST_GO(2);
+    else if (variant == 1) AM_PERSIST_GO(1);
+    else AM_PERSIST_GO(0);
+#undef AM_PERSIST_GO
 }
 
 void launch_rows_unpad(const DevNet &net, long long n, const void *rows, bool f32, double *out, hipStream_t st) {
