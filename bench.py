@@ -343,8 +343,21 @@ def chain_kernel_name(net, groups, graph_steps):
             4: "k_chain_f64<4, 4>", 5: "k_chain_f64<1, 8>"}[v]
 
 
+def persist_kernel_name(net) -> str:
+    """The persistent march kernel the library launches for `net`: the
+    ping-pong staged-B tile (2 with FP32 weight fragments when every weight
+    is an FP32 number, else 1) when its two B buffers (widest hidden layer,
+    rounded up to 32, x 16 doubles each) fit beside the kernel's static LDS
+    in the 160 KiB a workgroup may use, else the dense tile (0)."""
+    kpad = -(-max(net.widths[1:-1]) // 32) * 32
+    if 2 * kpad * 16 * 8 + 15.5 * 1024 > 160 * 1024:
+        return "k_march_persist<0>"
+    f32 = all(np.array_equal(W.astype(np.float32).astype(np.float64), W) for _, _, W in net.blocks)
+    return "k_march_persist<2>" if f32 else "k_march_persist<1>"
+
+
 def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tune=False, graph_steps=0,
-              face_routine=0, time_kernels=None):
+              face_routine=0, time_kernels=None, kernel_path=0):
     """Times `steps` full passes (seed + march + fetch) after `warmup` passes
     (and, with tune, the chain-tile autotuner run on the warm-up's cells).
     Kernel-class durations come from HIP events recorded on the library's
@@ -355,7 +368,7 @@ def time_form(ctx, o_d, d_d, precision, steps, warmup, max_cells, propose=0, tun
         ctx.seed_rays(o_d, d_d)
         tk = graph_steps == 0 if time_kernels is None else time_kernels
         st = ctx.march(max_cells=max_cells, time_kernels=tk, precision=precision, propose=propose,
-                       graph_steps=graph_steps, face_routine=face_routine)
+                       graph_steps=graph_steps, face_routine=face_routine, kernel_path=kernel_path)
         out = ctx.fetch()
         return st, out
 
@@ -493,6 +506,8 @@ def c4_forms(B, dev, steps, max_cells, scorer=None, graph_steps=8):
 
     march(time_kernels=True)
     groups, _ = ctx.tune_chain(reps=3)
+    st_p, t_p = timed(steps, kernel_path=3)
+    pers_digest = cell_set_digest(ctx.fetch())
     st, t_b = timed(steps, graph_steps=graph_steps)
     plain_out = ctx.fetch()
     counts = np.bincount(plain_out["shape"].cpu().numpy(), minlength=S)
@@ -546,7 +561,12 @@ def c4_forms(B, dev, steps, max_cells, scorer=None, graph_steps=8):
                            "faces_per_shape_min_max": [int(counts.min()), int(counts.max())],
                            "chain_groups_tuned": groups, "workload": desc, "chain_roofline": fr_plain},
             "c4_per_shape": {"faces_per_s": round(faces_single / t_s, 1), "ms_per_step": round(t_s * 1e3, 3),
-                             "faces": faces_single, "note": "one march per shape, same context, one pass"}}
+                             "faces": faces_single, "note": "one march per shape, same context, one pass"},
+            "c4_batched_persistent": {"faces_per_s": round(st_p["faces"] / t_p, 1),
+                                      "ms_per_step": round(t_p * 1e3, 3), "faces": st_p["faces"],
+                                      "cell_set_digest": pers_digest,
+                                      "exact_cell_set_match": pers_digest == plain_digest,
+                                      "launch": "one persistent launch for all 64 shapes"}}
     if combined is not None:
         out["c4_learned_bf16"] = combined
     return out
@@ -603,9 +623,11 @@ def main(argv=None):
                          "graph replays); 0: host-driven steps")
     ap.add_argument("--chain-groups", default="",
                     help="fixed chain tile variants per launch-size bucket, e.g. 1,3,3,3 (default: autotune)")
-    ap.add_argument("--legs", default="timed,graph,host",
-                    help="legs of the plain form: timed (device-driven, HIP events; gives the roofline), graph "
-                         "(the same steps as graph replays; gives value), host (host-driven steps)")
+    ap.add_argument("--legs", default="persistent,timed,graph,host",
+                    help="legs of the plain form: persistent (the whole march as one persistent launch, HIP events "
+                         "around it), timed (device-driven steps, HIP events around every kernel class), graph "
+                         "(the same steps as graph replays), host (host-driven steps); value is the faster of "
+                         "persistent and graph (else timed)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the bench, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--chain-sweep", default="",
@@ -644,52 +666,77 @@ def main(argv=None):
     net, o, d, desc, ctx, o_d, d_d = prepare(a.workload)
     if scorer is not None:
         ctx.prop_set(scorer, k=16, rho=6.0)
-    # value: device-driven steps (each step reads its frontier on the device;
-    # the host reads the counters once per graph_steps steps) replayed from a
-    # captured HIP graph.  Kernel durations cannot be read inside graph
-    # replays, so the same steps are also launched one by one with HIP events
-    # around every kernel class: that run gives the roofline.  Host-driven
-    # steps are timed as a form.
+    # value: the faster launch of the plain form, the persistent march or
+    # device-driven steps replayed from a captured HIP graph
     gs = a.graph_steps
     legs = set(x for x in a.legs.split(",") if x)
     fixed_groups = [int(x) for x in a.chain_groups.split(",")] if a.chain_groups else None
     if fixed_groups:
         ctx.set_chain_groups(fixed_groups)
-    timed = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=fixed_groups is None,
-                      graph_steps=gs, time_kernels=True)
-    chain_tiles = {a.workload: ctx.chain_groups()}
-    if gs > 0:
-        timed_launch = (f"device-driven steps launched one by one, {gs} per counter read, HIP events around "
-                        "every kernel class")
-    else:
-        timed_launch = "host-driven steps, HIP events around every kernel class"
-    if gs > 0 and "graph" in legs:
-        main_run = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, graph_steps=gs)
-        assert main_run["faces"] == timed["faces"], "graph-launched form changed the face count"
-        main_launch = f"device-driven steps, {gs} per HIP graph replay"
-    else:
-        main_run = timed
-        main_launch = timed_launch
-    print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step",
-          file=sys.stderr, flush=True)
-    plain_digest = cell_set_digest(main_run["out"])
-    golden = {a.workload: golden_check(ctx, a.workload)}   # the last march is the timed configuration
-    print(f"[bench] golden {a.workload}: {golden[a.workload]}", file=sys.stderr, flush=True)
-    forms = {f"{a.workload}_plain": {"faces_per_s": round(main_run["faces_per_s"], 1),
-                                     "ms_per_step": round(main_run["ms_per_step"], 3),
-                                     "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
-                                     "launch": main_launch, "cell_set_digest": plain_digest}}
-    if gs > 0 and "graph" in legs:
+    fp64_desc = "FP64 chain (MFMA), FP64 clip and vertex solves"
+    forms = {}
+    golden = {}
+    runs = []   # (run, launch description, golden record check) of the legs that can give value
+    # the whole march as one persistent launch (HIP events around it)
+    pers = None
+    pers_launch = ("one persistent launch: workgroups take discovered cells from a device-side queue, chain, "
+                   "clip and insert their neighbours until none is left or in flight")
+    if "persistent" in legs:
+        pers = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, kernel_path=3, time_kernels=True)
+        gp = golden_check(ctx, a.workload)   # the last march is this configuration
+        print(f"[bench] {a.workload} persistent: {pers['faces']} faces, {pers['ms_per_step']:.2f} ms/step, "
+              f"golden {gp}", file=sys.stderr, flush=True)
+        forms[f"{a.workload}_plain_persistent"] = {
+            "faces_per_s": round(pers["faces_per_s"], 1), "ms_per_step": round(pers["ms_per_step"], 3),
+            "precision": fp64_desc, "launch": pers_launch, "cell_set_digest": cell_set_digest(pers["out"])}
+        runs.append((pers, pers_launch, gp))
+    # device-driven steps (each step reads its frontier on the device; the
+    # host reads the counters once per graph_steps steps), launched one by
+    # one with HIP events around every kernel class (gives the stepped
+    # kernels' rooflines), and the same steps replayed from a captured HIP
+    # graph; host-driven steps are timed as a form
+    timed = None
+    if legs & {"timed", "graph", "host"}:
+        timed = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, tune=fixed_groups is None,
+                          graph_steps=gs, time_kernels=True)
+        if gs > 0:
+            timed_launch = (f"device-driven steps launched one by one, {gs} per counter read, HIP events around "
+                            "every kernel class")
+        else:
+            timed_launch = "host-driven steps, HIP events around every kernel class"
+        gt = golden_check(ctx, a.workload)
         forms[f"{a.workload}_plain_timed"] = {
             "faces_per_s": round(timed["faces_per_s"], 1), "ms_per_step": round(timed["ms_per_step"], 3),
-            "precision": "FP64 chain (MFMA), FP64 clip and vertex solves", "launch": timed_launch}
+            "precision": fp64_desc, "launch": timed_launch}
         print(f"[bench] {a.workload}_plain_timed: {timed['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
-    if gs > 0 and "host" in legs:
+        if gs > 0 and "graph" in legs:
+            g = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells, graph_steps=gs)
+            assert g["faces"] == timed["faces"], "graph-launched form changed the face count"
+            g_launch = f"device-driven steps, {gs} per HIP graph replay"
+            gg = golden_check(ctx, a.workload)
+            forms[f"{a.workload}_plain_graph"] = {
+                "faces_per_s": round(g["faces_per_s"], 1), "ms_per_step": round(g["ms_per_step"], 3),
+                "precision": fp64_desc, "launch": g_launch, "cell_set_digest": cell_set_digest(g["out"])}
+            print(f"[bench] {a.workload}_plain_graph: {g['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+            runs.append((g, g_launch, gg))
+        else:
+            runs.append((timed, timed_launch, gt))
+    chain_tiles = {a.workload: ctx.chain_groups()}
+    assert runs, "no leg of the plain form ran"
+    assert all(r[0]["faces"] == runs[0][0]["faces"] for r in runs), "the legs disagree on the face count"
+    main_run, main_launch, golden[a.workload] = min(runs, key=lambda r: r[0]["ms_per_step"])
+    print(f"[bench] {a.workload} plain: {main_run['faces']} faces, {main_run['ms_per_step']:.2f} ms/step "
+          f"({main_launch})", file=sys.stderr, flush=True)
+    plain_digest = cell_set_digest(main_run["out"])
+    forms[f"{a.workload}_plain"] = {"faces_per_s": round(main_run["faces_per_s"], 1),
+                                    "ms_per_step": round(main_run["ms_per_step"], 3),
+                                    "precision": fp64_desc, "launch": main_launch, "cell_set_digest": plain_digest}
+    if timed is not None and gs > 0 and "host" in legs:
         r = time_form(ctx, o_d, d_d, 0, a.steps, a.warmup, a.max_cells)
         assert r["faces"] == main_run["faces"], "host-driven form changed the face count"
         forms[f"{a.workload}_plain_host"] = {
             "faces_per_s": round(r["faces_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
-            "precision": "FP64 chain (MFMA), FP64 clip and vertex solves",
+            "precision": fp64_desc,
             "launch": "host-driven steps (one counter read per step), HIP events around every kernel class"}
         print(f"[bench] {a.workload}_plain_host: {r['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     bf16_desc = ("split-BF16 chain (3 terms, 6 MFMA products, FP32 accumulate); FP64 clip and vertex solves on "
@@ -746,51 +793,78 @@ def main(argv=None):
         assert r["faces"] == main_run["faces"], f"{v} form changed the face count"
         record(f"{a.workload}_{v}", r, precision, propose, routine, ref_digest=plain_digest, net_=net)
 
-    # roofline of the dominant kernel of the timed plain steps: the chain
-    # (FP64 MFMA) or the clip (HBM: it reads every row the chain wrote)
-    kst = timed["kernels"]
-    codes = sample_codes(timed["out"]["codes"])
-    flops_cell = chain_flops_per_cell(net, codes)
-    st_t = timed["stats"]
-    cells = st_t["cells"]
-    chain_avg_ms = kst["chain_ms"] / max(1, kst["chain_launches"])
-    cells_per_launch = cells * a.steps / max(1, kst["chain_launches"])
-    chain_tflops = flops_cell * cells_per_launch / (chain_avg_ms * 1e-3) / 1e12 if chain_avg_ms > 0 else 0.0
-    kname = chain_kernel_name(net, chain_tiles[a.workload], gs)
-    traffic = measured_traffic(kname)
-    split = {k: round(kst[k] / a.steps, 3) for k in ("chain_ms", "clip_ms", "hash_ms", "march_ms")}
-    chain_entry = {"kernel": kname, "bound": "mfma",
-                   "achieved": round(chain_tflops, 4),
-                   "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                   "frac": round(chain_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
-                   "traffic": traffic["bytes_per_launch"] if traffic else None,
-                   "algorithmic_flops_per_cell": round(flops_cell, 1), "cells_per_launch": round(cells_per_launch, 1),
-                   "avg_launch_ms": round(chain_avg_ms, 5), "timed_on": timed_launch,
-                   "time_split_ms_per_step": split}
-    if traffic:
-        chain_entry["traffic_note"] = traffic.get("note", "")
-    # clip: per cell it reads the cell's rows, code, argmax, hints and
-    # fingerprint and writes its face (ids, vertices, neighbour slots, size,
-    # flags) and one candidate per edge (parent, slot, unit, fingerprint,
-    # hints, key)
-    N, M = net.n_hidden, net.n_heads
-    W = max(1, -(-N // 64))
-    mbar = st_t["face_verts"] / max(1, st_t["faces"])
-    clip_bytes_cell = (N + M) * 32 + W * 8 + 4 + 12 + 8 + mbar * (4 + 24 + 4) + 8 + mbar * 32
-    clip_avg_ms = kst["clip_ms"] / max(1, kst["clip_launches"])
-    clip_gbs = clip_bytes_cell * cells_per_launch / (clip_avg_ms * 1e-3) / 1e9 if clip_avg_ms > 0 else 0.0
-    ctraffic = measured_traffic("k_clip<double>")
-    clip_entry = {"kernel": "k_clip<double>", "bound": "hbm", "achieved": round(clip_gbs, 2), "peak": PEAK_HBM_GBS,
-                  "unit": "GB/s", "frac": round(clip_gbs / PEAK_HBM_GBS, 6),
-                  "traffic": ctraffic["bytes_per_launch"] if ctraffic else None,
-                  "algorithmic_bytes_per_cell": round(clip_bytes_cell, 1), "cells_per_launch": round(cells_per_launch, 1),
-                  "avg_launch_ms": round(clip_avg_ms, 5), "timed_on": timed_launch, "time_split_ms_per_step": split}
-    if ctraffic:
-        clip_entry["traffic_note"] = ctraffic.get("note", "")
-    if kst["clip_ms"] > kst["chain_ms"]:
-        roofline, roofline_other = clip_entry, chain_entry
+    # roofline of the dominant kernel of the value's launch.  Persistent: the
+    # one fused kernel (chain, clip, insertion); its dense contraction is the
+    # FP64 chain on MFMA, so its algorithmic flops are the chain's.  Stepped:
+    # the chain (FP64 MFMA) or the clip (HBM: it reads every row the chain
+    # wrote), whichever took longer.
+    flops_cell = chain_flops_per_cell(net, sample_codes(main_run["out"]["codes"]))
+    pers_entry = chain_entry = clip_entry = None
+    if pers is not None:
+        kp = pers["kernels"]
+        p_ms = kp["chain_ms"] / max(1, kp["chain_launches"])   # the march's one launch
+        p_cells = pers["stats"]["cells"]
+        p_tflops = flops_cell * p_cells / (p_ms * 1e-3) / 1e12 if p_ms > 0 else 0.0
+        pname = persist_kernel_name(net)
+        ptraffic = measured_traffic(pname)
+        pers_entry = {"kernel": pname, "bound": "mfma", "achieved": round(p_tflops, 4),
+                      "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                      "frac": round(p_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
+                      "traffic": ptraffic["bytes_per_launch"] if ptraffic else None,
+                      "algorithmic_flops_per_cell": round(flops_cell, 1), "cells_per_launch": p_cells,
+                      "avg_launch_ms": round(p_ms, 4), "timed_on": pers_launch + "; HIP events around the launch",
+                      "note": "fused chain + clip + neighbour insertion in one launch; the FP64 chain is its only "
+                              "dense contraction"}
+        if ptraffic:
+            pers_entry["traffic_note"] = ptraffic.get("note", "")
+    if timed is not None:
+        kst = timed["kernels"]
+        st_t = timed["stats"]
+        cells = st_t["cells"]
+        chain_avg_ms = kst["chain_ms"] / max(1, kst["chain_launches"])
+        cells_per_launch = cells * a.steps / max(1, kst["chain_launches"])
+        chain_tflops = flops_cell * cells_per_launch / (chain_avg_ms * 1e-3) / 1e12 if chain_avg_ms > 0 else 0.0
+        kname = chain_kernel_name(net, chain_tiles[a.workload], gs)
+        traffic = measured_traffic(kname)
+        split = {k: round(kst[k] / a.steps, 3) for k in ("chain_ms", "clip_ms", "hash_ms", "march_ms")}
+        chain_entry = {"kernel": kname, "bound": "mfma",
+                       "achieved": round(chain_tflops, 4),
+                       "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(chain_tflops / PEAK_FP64_MFMA_TFLOPS, 6),
+                       "traffic": traffic["bytes_per_launch"] if traffic else None,
+                       "algorithmic_flops_per_cell": round(flops_cell, 1),
+                       "cells_per_launch": round(cells_per_launch, 1),
+                       "avg_launch_ms": round(chain_avg_ms, 5), "timed_on": timed_launch,
+                       "time_split_ms_per_step": split}
+        if traffic:
+            chain_entry["traffic_note"] = traffic.get("note", "")
+        # clip: per cell it reads the cell's rows, code, argmax, hints and
+        # fingerprint and writes its face (ids, vertices, neighbour slots,
+        # size, flags) and one candidate per edge (parent, slot, unit,
+        # fingerprint, hints, key)
+        N, M = net.n_hidden, net.n_heads
+        W = max(1, -(-N // 64))
+        mbar = st_t["face_verts"] / max(1, st_t["faces"])
+        clip_bytes_cell = (N + M) * 32 + W * 8 + 4 + 12 + 8 + mbar * (4 + 24 + 4) + 8 + mbar * 32
+        clip_avg_ms = kst["clip_ms"] / max(1, kst["clip_launches"])
+        clip_gbs = clip_bytes_cell * cells_per_launch / (clip_avg_ms * 1e-3) / 1e9 if clip_avg_ms > 0 else 0.0
+        ctraffic = measured_traffic("k_clip<double>")
+        clip_entry = {"kernel": "k_clip<double>", "bound": "hbm", "achieved": round(clip_gbs, 2),
+                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(clip_gbs / PEAK_HBM_GBS, 6),
+                      "traffic": ctraffic["bytes_per_launch"] if ctraffic else None,
+                      "algorithmic_bytes_per_cell": round(clip_bytes_cell, 1),
+                      "cells_per_launch": round(cells_per_launch, 1),
+                      "avg_launch_ms": round(clip_avg_ms, 5), "timed_on": timed_launch,
+                      "time_split_ms_per_step": split}
+        if ctraffic:
+            clip_entry["traffic_note"] = ctraffic.get("note", "")
+    stepped = None
+    if chain_entry is not None:
+        stepped = clip_entry if kst["clip_ms"] > kst["chain_ms"] else chain_entry
+    if main_run is pers:
+        roofline, roofline_other = pers_entry, stepped
     else:
-        roofline, roofline_other = chain_entry, clip_entry
+        roofline, roofline_other = stepped, pers_entry
     ctx.close()
 
     for name in ("c3", "c5"):
