@@ -1536,16 +1536,34 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
             }
         }
         }
-        // hidden units, 64 lines per pass
+        // hidden units, 64 lines per pass; each pass loads the next pass's
+        // rows (and code word: the 64 units of a pass share one) before it
+        // tests and cuts its own, so the loads' latency overlaps that work
+        RowT nz0 = 0, nz1 = 0, nz2 = 0, nz3 = 0;
+        uint64_t nword = 0;
+        auto load_pass = [&](int b) {
+            const int g = b + lane;
+            if (g < net.N) {
+                const RowT *z = rb + (long long)g * rs;
+                nz0 = z[0];
+                nz1 = z[1];
+                nz2 = z[2];
+                nz3 = z[3];
+            }
+            nword = code[b >> 6];
+        };
+        if (net.N > 0 && P.m > 0) load_pass(0);
         for (int base = 0; base < net.N && P.m > 0; base += kWave) {
             const int g = base + lane;
             const bool valid = g < net.N;
+            const RowT z0 = nz0, z1 = nz1, z2 = nz2, z3 = nz3;
+            const uint64_t word = nword;
+            if (base + kWave < net.N) load_pass(base + kWave);
             double cu = 0.0, cv = 0.0, cw = 0.0, nrm = 0.0, cn = 0.0;
             bool cuts = false, close = false;
             if (valid) {
-                const RowT *z = rb + (long long)(g) * rs;
-                const double sg = code_bit(code, g) ? -1.0 : 1.0;
-                const double c0 = sg * z[0], c1 = sg * z[1], c2 = sg * z[2], c3 = sg * z[3];
+                const double sg = ((word >> lane) & 1ull) ? -1.0 : 1.0;
+                const double c0 = sg * z0, c1 = sg * z1, c2 = sg * z2, c3 = sg * z3;
                 cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
                 cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
                 cw = c0 * p0[0] + c1 * p0[1] + c2 * p0[2] + c3;
@@ -2243,7 +2261,9 @@ __global__ __launch_bounds__(256) void k_march_fused(DevNet net, const uint64_t 
 template <typename AT, int MTW>
 __device__ void chain_tile_pp(const DevNet &net, const uint64_t *code_lds, const int *shape_lds, int ncell,
                               double *zb, long long cs, double *bsh) {
-    constexpr int KC = 2 * kLbKSteps / MTW;   // K-steps per batch: 2 x 8 MFMAs in flight per prefetch
+    // K-steps per batch: 2 x 8 MFMAs in flight per prefetch with FP32
+    // fragments, 8 with FP64 ones (the register budget of three waves per SIMD)
+    constexpr int KC = (sizeof(AT) == 4 ? 2 : 1) * kLbKSteps / MTW;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
