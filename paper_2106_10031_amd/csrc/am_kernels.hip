@@ -976,6 +976,9 @@ struct alignas(16) PropScratch {
 // top-k list held by lanes 0..k-1 (tk_s, tk_id), best first.
 __device__ void topk_merge(float s, int id, float &tk_s, int &tk_id, int k) {
     const int lane = lane_id();
+    // the list changes only if a candidate beats the current k-th best
+    const float kth = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tk_s), k - 1));
+    if (!ballot(s > kth)) return;
     float s2 = lane < k ? tk_s : -INFINITY;
     const int id2 = tk_id;
     float ns = -INFINITY;
@@ -1016,23 +1019,49 @@ __device__ int propose_lines(const DevNet &net, const PropArgs &pa, PropScratch 
     float tk_s = -INFINITY;
     int tk_id = -1;
     int nbuf = 0;
+    // the next pass's rows and code word are loaded before this pass's work
+    RowT nz0 = 0, nz1 = 0, nz2 = 0, nz3 = 0;
+    uint64_t nword = 0;
+    auto load_pass = [&](int b) {
+        const int g = b + lane;
+        if (g < net.N) {
+            const RowT *z = rb + (long long)g * rs;
+            nz0 = z[0];
+            nz1 = z[1];
+            nz2 = z[2];
+            nz3 = z[3];
+        }
+        nword = code[b >> 6];
+    };
+    if (net.N > 0) load_pass(0);
     for (int base = 0; base < net.N; base += kWave) {
         const int g = base + lane;
         bool cand = false;
         float f[kPropF];
         double sd = 0.0;
+        const RowT z0 = nz0, z1 = nz1, z2 = nz2, z3 = nz3;
+        const uint64_t word = nword;
+        if (base + kWave < net.N) load_pass(base + kWave);
         if (g < net.N && g != E.id[0] && g != E.id[1] && g != E.id[2]) {
-            const RowT *z = rb + (long long)(g) * rs;
-            const int bit = code_bit(code, g);
+            const int bit = (int)((word >> lane) & 1ull);
             const double sg = bit ? -1.0 : 1.0;
-            const double c0 = sg * z[0], c1 = sg * z[1], c2 = sg * z[2], c3 = sg * z[3];
+            const double c0 = sg * z0, c1 = sg * z1, c2 = sg * z2, c3 = sg * z3;
             const double cu = c0 * u[0] + c1 * u[1] + c2 * u[2];
             const double cv = c0 * v[0] + c1 * v[1] + c2 * v[2];
             const double cw = c0 * p0[0] + c1 * p0[1] + c2 * p0[2] + c3;
-            const double n = sqrt(cu * cu + cv * cv);
-            if (n > 0.0) {
-                sd = line_features(net, E, g, bit, cu / n, cv / n, cw / n, f);
-                cand = fabs(sd) <= (double)pa.rho;
+            if (pa.mode == 2) {
+                // distance order: only the midpoint's distance, in entry
+                // lengths, as an FP32 rank (no features, one FP32 divide)
+                const float nf = sqrtf((float)(cu * cu + cv * cv)) * (float)E.h;
+                const float num = fabsf((float)(cu * E.qa + cv * E.qb + cw));
+                cand = nf > 0.f && num <= pa.rho * nf;
+                sd = cand ? (double)(num / nf) : 0.0;
+            } else {
+                const double n = sqrt(cu * cu + cv * cv);
+                if (n > 0.0) {
+                    sd = line_features(net, E, g, bit, cu / n, cv / n, cw / n, f);
+                    cand = fabs(sd) <= (double)pa.rho;
+                }
             }
         }
         if (pa.mode == 2) {
@@ -1524,15 +1553,21 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
             have_entry = entry_edge(net, hints, cell, code, am, rb, rs, u, v, p0, E);
         if (have_entry && ((pa.mode == 1 && ps) || pa.mode == 2)) {
             const int pid = propose_lines(net, pa, ps, E, code, am, rb, rs, u, v, p0);
+            // lane t holds proposal t: its line is loaded and projected by
+            // all lanes at once, then the lines are clipped in rank order
+            double hu = 0.0, hv = 0.0, hw = 0.0, hn = 0.0;
+            if (lane < pa.k && pid >= 0) {
+                double c[4];
+                constraint_row(net, pid, code, am, rb, rs, c);
+                hu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+                hv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
+                hw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
+                hn = sqrt(hu * hu + hv * hv);
+            }
             for (int t = 0; t < pa.k && P.m > 0; ++t) {
                 const int id = bcast(pid, t);
                 if (id < 0) break;
-                double c[4];
-                constraint_row(net, id, code, am, rb, rs, c);
-                const double hu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
-                const double hv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
-                const double hw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
-                sh_clip(P, hu, hv, hw, sqrt(hu * hu + hv * hv), id, S, flags);
+                sh_clip(P, bcast(hu, t), bcast(hv, t), bcast(hw, t), bcast(hn, t), id, S, flags);
             }
         }
         }
@@ -2207,7 +2242,7 @@ __global__ __launch_bounds__(256) void k_clip_pivot(DevNet net, const uint64_t *
 }
 
 template <typename RowT>
-__global__ __launch_bounds__(256) void k_clip_prop(DevNet net, const uint64_t *__restrict__ codes,
+__global__ __launch_bounds__(256, 3) void k_clip_prop(DevNet net, const uint64_t *__restrict__ codes,
                                                    const int *__restrict__ argmax,
                                                    const uint64_t *__restrict__ cell_hash,
                                                    const int *__restrict__ hints, CellRange rg, long long n_seed_cells,
