@@ -1524,6 +1524,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
         // parent's edges on either side of it (the cells around a cell edge
         // share both planes).  Any order gives the same polygon; these first
         // leave most later lines with nothing to cut.
+        int entry_id = -1;
         if (hints || rec) {
             // all three rows are loaded before the first cut
             int hid[3];
@@ -1533,6 +1534,7 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
                 hid[h] = rec ? rec->hint[h] : hints[cell * 3 + h];
                 if (hid[h] < 0 || hid[h] >= net.N + net.M || hid[h] == net.N + am) hid[h] = -1;
             }
+            entry_id = hid[0];
 #pragma unroll
             for (int h = 0; h < 3; ++h)
                 if (hid[h] >= 0) constraint_row(net, hid[h], code, am, rb, rs, hc[h]);
@@ -1573,7 +1575,27 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
         }
         // hidden units, 64 lines per pass; each pass loads the next pass's
         // rows (and code word: the 64 units of a pass share one) before it
-        // tests and cuts its own, so the loads' latency overlaps that work
+        // tests and cuts its own, so the loads' latency overlaps that work.
+        // A pass's cutting lines are applied nearest first to a point of the
+        // face's boundary (the entry edge's midpoint after the hint cuts,
+        // else the mean of the polygon's vertices), the rest re-tested after
+        // each cut: the lines near the face, which bound it, go first, and
+        // fewer of the others still cut.  Every line is tested, and a line
+        // that does not cut when tested never cuts later (the polygon only
+        // shrinks), so the face is the same in any order.
+        float qa = 0.f, qb = 0.f;
+        if (P.m > 0) {
+            const uint64_t em = ballot(lane < P.m && entry_id >= 0 && P.e == entry_id);
+            if (em) {
+                const int i = __builtin_ctzll(em);
+                const int j = i + 1 >= P.m ? 0 : i + 1;
+                qa = (float)(0.5 * (bcast(P.a, i) + bcast(P.a, j)));
+                qb = (float)(0.5 * (bcast(P.b, i) + bcast(P.b, j)));
+            } else {
+                qa = (float)(wave_sum(lane < P.m ? P.a : 0.0) / P.m);
+                qb = (float)(wave_sum(lane < P.m ? P.b : 0.0) / P.m);
+            }
+        }
         RowT nz0 = 0, nz1 = 0, nz2 = 0, nz3 = 0;
         uint64_t nword = 0;
         auto load_pass = [&](int b) {
@@ -1620,11 +1642,33 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
                 n_near += __popcll(nm);
             }
             uint64_t mask = ballot(valid && cuts);
-            ncuts += __popcll(mask);
-            while (mask) {
-                const int t = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                if (!sh_clip(P, bcast(cu, t), bcast(cv, t), bcast(cw, t), bcast(nrm, t), base + t, S, flags)) break;
+            if (mask) {
+                const float key =
+                    nrm > 0.0 ? fabsf((float)cu * qa + (float)cv * qb + (float)cw) / (float)nrm : INFINITY;
+                while (mask) {
+                    float k = ((mask >> lane) & 1ull) ? key : INFINITY;
+                    int kid = lane;
+                    for (int o = 32; o > 0; o >>= 1) {
+                        const float k2 = __shfl_xor(k, o, kWave);
+                        const int i2 = __shfl_xor(kid, o, kWave);
+                        if (k2 < k || (k2 == k && i2 < kid)) {
+                            k = k2;
+                            kid = i2;
+                        }
+                    }
+                    const int t = __builtin_amdgcn_readfirstlane(kid);
+                    mask &= ~(1ull << t);
+                    ++ncuts;
+                    if (!sh_clip(P, bcast(cu, t), bcast(cv, t), bcast(cw, t), bcast(nrm, t), base + t, S, flags)) break;
+                    if (!mask) break;
+                    bool c = false;
+                    for (int i = 0; i < P.m; ++i) {
+                        const double ai = bcast(P.a, i), bi = bcast(P.b, i), ri = bcast(P.r, i);
+                        const double d = cu * ai + cv * bi + cw;
+                        c |= d > kTau * (nrm * ri + fabs(cw));
+                    }
+                    mask = ballot(((mask >> lane) & 1ull) && c);
+                }
             }
         }
         // max-pool comparisons with every other head
