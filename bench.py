@@ -344,13 +344,12 @@ def chain_kernel_name(net, groups, graph_steps):
 
 
 def persist_kernel_name(net) -> str:
-    """The persistent march kernel the library launches for `net`: the
-    ping-pong staged-B tile (2 with FP32 weight fragments when every weight
-    is an FP32 number, else 1) when its two B buffers (widest hidden layer,
-    rounded up to 32, x 16 doubles each) fit beside the kernel's static LDS
-    in the 160 KiB a workgroup may use, else the dense tile (0)."""
+    """The persistent march kernel the library launches for `net`: for
+    hidden layers of at most 256 units the ping-pong staged-B tile (2 with
+    FP32 weight fragments when every weight is an FP32 number, else 1), else
+    the dense tile (0)."""
     kpad = -(-max(net.widths[1:-1]) // 32) * 32
-    if 2 * kpad * 16 * 8 + 15.5 * 1024 > 160 * 1024:
+    if kpad > 256:
         return "k_march_persist<0>"
     f32 = all(np.array_equal(W.astype(np.float32).astype(np.float64), W) for _, _, W in net.blocks)
     return "k_march_persist<2>" if f32 else "k_march_persist<1>"

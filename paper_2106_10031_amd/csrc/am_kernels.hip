@@ -2844,9 +2844,11 @@ void launch_fused(const DevNet &net, const uint64_t *codes, const int *cell_shap
 }
 
 // Persistent march: the chain variant for `net` (0 dense tile; 1, 2 the
-// ping-pong staged-B tile with FP64 or FP32 weight fragments, when its two
-// B buffers fit beside the kernel's static LDS), its dynamic LDS, and the
-// workgroups that fit on the device at once.
+// ping-pong staged-B tile with FP64 or FP32 weight fragments, for hidden
+// layers of at most 256 units, whose two B buffers (64 KB) still leave two
+// or three workgroups per CU; wider, the buffers would leave one, and the
+// dense tile is faster), its dynamic LDS, and the workgroups that fit on the
+// device at once.
 template <int CH>
 static hipError_t persist_setup_t(size_t lds, int *blocks) {
     hipError_t e = hipFuncSetAttribute((const void *)k_march_persist<CH>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2866,7 +2868,7 @@ static hipError_t persist_setup_t(size_t lds, int *blocks) {
 hipError_t persist_setup(const DevNet &net, size_t lds_limit, int *variant, size_t *lds, int *blocks) {
     const size_t pp = (size_t)2 * net.lb_kpad * 16 * sizeof(double);
     const size_t stat = sizeof(PolyScratch) * 4 + sizeof(uint64_t) * 4 * kMaxWords + 256;
-    if (net.lb_kpad > 0 && pp + stat <= lds_limit) {
+    if (net.lb_kpad > 0 && net.lb_kpad <= 256 && pp + stat <= lds_limit) {
         *variant = net.wfrag32 ? 2 : 1;
         *lds = pp;
         return *variant == 2 ? persist_setup_t<2>(pp, blocks) : persist_setup_t<1>(pp, blocks);
