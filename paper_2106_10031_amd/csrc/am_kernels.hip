@@ -1695,11 +1695,14 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
         // the six box planes, ids -1..-6.  The box section lies strictly inside
         // the starting square, so the result does not depend on when they are
         // applied; last, they rarely cut.
-        for (int t = 0; t < 6 && P.m > 0; ++t) {
+        // (unrolled: the axis is a constant, so u, v and p0 stay in registers)
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
             const int axb = t >> 1;
             const double sg = (t & 1) ? -1.0 : 1.0;
-            sh_clip(P, sg * u[axb], sg * v[axb], sg * p0[axb] - 1.0, sqrt(u[axb] * u[axb] + v[axb] * v[axb]), -1 - t,
-                    S, flags);
+            if (P.m > 0)
+                sh_clip(P, sg * u[axb], sg * v[axb], sg * p0[axb] - 1.0, sqrt(u[axb] * u[axb] + v[axb] * v[axb]),
+                        -1 - t, S, flags);
         }
         }   // !walked
     }
