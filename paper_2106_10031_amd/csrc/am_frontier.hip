@@ -64,10 +64,22 @@ __device__ __forceinline__ uint64_t code_word(const CodeRef &r, int w) {
     return x;
 }
 
+// Eight words of each code are loaded before any is compared (the loads of
+// a batch overlap, and the argmax and shape compare with the first batch).
 __device__ __forceinline__ bool code_eq(int W, const CodeRef &a, const CodeRef &b) {
-    if (a.am != b.am || a.shape != b.shape) return false;
-    for (int w = 0; w < W; ++w)
-        if (code_word(a, w) != code_word(b, w)) return false;
+    bool eq = a.am == b.am && a.shape == b.shape;
+    for (int w0 = 0; w0 < W; w0 += 8) {
+        uint64_t x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int w = min(w0 + u, W - 1);   // a repeated last word compares as it did
+            x[u] = code_word(a, w);
+            y[u] = code_word(b, w);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) eq = eq && x[u] == y[u];
+        if (!eq) return false;
+    }
     return true;
 }
 

@@ -1352,40 +1352,50 @@ __device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long
         }
         // the record a slot names was complete before the slot was written
         // (a claim names a cell being processed; a committed id's record was
-        // published before the commit), and is read after the slot
-        unsigned long long sv = ld_dev(&I.slots[pos]);
-        if (sv == 0) {
-            if (__hip_atomic_compare_exchange_strong(&I.slots[pos], &sv, mine, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)) {
-                state = 1;
-                break;
-            }
+        // published before the commit), and is read after the slot.  The claim
+        // is tried at once: a failed compare-exchange returns the slot's
+        // value, as a load would, so an empty slot costs one round trip
+        unsigned long long sv = 0;
+        if (__hip_atomic_compare_exchange_strong(&I.slots[pos], &sv, mine, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+            state = 1;
+            break;
         }
-        int oc = -1, oflip = -1, oam = 0;
+        int oc = -1, oflip = -1, oam_claim = -1;
         bool cmp = false;
         if (sv & kPending) {
             if (((sv >> 45) & 0x3ffffull) == ptag) {
-                // a claim: the code of cell (low 31 bits) with constraint e flipped
+                // a claim: the code of cell (low 31 bits) with constraint e
+                // flipped; its argmax is the cell's, or the head e - N
                 oc = (int)(sv & 0x7fffffffull);
                 const int oe = (int)((sv >> 31) & 0x3fffull);
                 oflip = oe < net.N ? oe : -1;
-                oam = oe < net.N ? ld_dev(&I.argmax[oc]) : oe - net.N;
+                oam_claim = oe < net.N ? -1 : oe - net.N;
                 cmp = true;
             }
         } else if (((sv >> 32) & 0x7fffffffull) == tag) {
             oc = (int)(sv & 0xffffffffull);
-            if ((unsigned long long)oc < I.cap_cells) {
-                oam = ld_dev(&I.argmax[oc]);
-                cmp = true;
-            }
+            cmp = (unsigned long long)oc < I.cap_cells;
         }
-        if (cmp && oam == nam && ld_dev(&I.shape[oc]) == shp) {
+        if (cmp) {
+            // argmax, shape and the code words are loaded before any is
+            // compared (eight words at a time), not one round trip each
             const uint64_t *ocode = I.codes + (long long)oc * net.W;
+            const int oam_l = ld_dev(&I.argmax[oc]);
+            const int osh = ld_dev(&I.shape[oc]);
             bool eq = true;
-            for (int w = 0; w < net.W && eq; ++w) {
-                uint64_t x = ld_dev(&ocode[w]);
-                if (oflip >= 0 && (oflip >> 6) == w) x ^= 1ull << (oflip & 63);
-                eq = x == flip_word(code, flip, w);
+            for (int w0 = 0; w0 < net.W; w0 += 8) {
+                uint64_t x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = ld_dev(&ocode[min(w0 + u, net.W - 1)]);
+                if (w0 == 0) eq = (oam_claim >= 0 ? oam_claim : oam_l) == nam && osh == shp;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int w = min(w0 + u, net.W - 1);   // a repeated last word compares as it did
+                    if (oflip >= 0 && (oflip >> 6) == w) x[u] ^= 1ull << (oflip & 63);
+                    eq = eq && x[u] == flip_word(code, flip, w);
+                }
+                if (!eq) break;
             }
             if (eq) {
                 if (sv & kPending) {
