@@ -1479,6 +1479,40 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
     int ncuts = 0;   // lines that cut in the every-line pass
     (void)ps;
 
+    // rows the first cuts need, loaded with the face plane's so that their
+    // latencies overlap: the three lines the parent's face says bound this
+    // one (below) and the first pass's 64 hidden lines
+    int hid[3] = {-1, -1, -1};
+    RowT hr[3][4] = {};
+    if (hints || rec) {
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            hid[h] = rec ? rec->hint[h] : hints[cell * 3 + h];
+            if (hid[h] < 0 || hid[h] >= net.N + net.M || hid[h] == net.N + am) hid[h] = -1;
+            if (hid[h] >= 0) {
+                const RowT *z = rb + (long long)hid[h] * rs;
+                hr[h][0] = z[0];
+                hr[h][1] = z[1];
+                hr[h][2] = z[2];
+                hr[h][3] = z[3];
+            }
+        }
+    }
+    RowT nz0 = 0, nz1 = 0, nz2 = 0, nz3 = 0;
+    uint64_t nword = 0;
+    auto load_pass = [&](int b) {
+        const int g = b + lane;
+        if (g < net.N) {
+            const RowT *z = rb + (long long)g * rs;
+            nz0 = z[0];
+            nz1 = z[1];
+            nz2 = z[2];
+            nz3 = z[3];
+        }
+        nword = code[b >> 6];
+    };
+    if (net.N > 0) load_pass(0);
+
     // ---- plane frame: n = a_F[0:3], foot point p0, orthonormal u, v with u x v = n/|n|
     const RowT *aF = rb + (long long)(net.N + am) * rs;
     const double fx = aF[0], fy = aF[1], fz = aF[2], fw = aF[3];
@@ -1536,22 +1570,20 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
         // leave most later lines with nothing to cut.
         int entry_id = -1;
         if (hints || rec) {
-            // all three rows are loaded before the first cut
-            int hid[3];
-            double hc[3][4];
-#pragma unroll
-            for (int h = 0; h < 3; ++h) {
-                hid[h] = rec ? rec->hint[h] : hints[cell * 3 + h];
-                if (hid[h] < 0 || hid[h] >= net.N + net.M || hid[h] == net.N + am) hid[h] = -1;
-            }
             entry_id = hid[0];
-#pragma unroll
-            for (int h = 0; h < 3; ++h)
-                if (hid[h] >= 0) constraint_row(net, hid[h], code, am, rb, rs, hc[h]);
 #pragma unroll
             for (int h = 0; h < 3; ++h) {
                 if (hid[h] < 0 || P.m <= 0) continue;
-                const double *c = hc[h];
+                // the oriented constraint row, as constraint_row forms it
+                double c[4];
+                if (hid[h] < net.N) {
+                    const double sg = code_bit(code, hid[h]) ? -1.0 : 1.0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) c[k] = sg * hr[h][k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) c[k] = hr[h][k] - aF[k];
+                }
                 const double hu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
                 const double hv = c[0] * v[0] + c[1] * v[1] + c[2] * v[2];
                 const double hw = c[0] * p0[0] + c[1] * p0[1] + c[2] * p0[2] + c[3];
@@ -1606,20 +1638,6 @@ __device__ void clip_cell(const DevNet &net, const uint64_t *codes, const int *a
                 qb = (float)(wave_sum(lane < P.m ? P.b : 0.0) / P.m);
             }
         }
-        RowT nz0 = 0, nz1 = 0, nz2 = 0, nz3 = 0;
-        uint64_t nword = 0;
-        auto load_pass = [&](int b) {
-            const int g = b + lane;
-            if (g < net.N) {
-                const RowT *z = rb + (long long)g * rs;
-                nz0 = z[0];
-                nz1 = z[1];
-                nz2 = z[2];
-                nz3 = z[3];
-            }
-            nword = code[b >> 6];
-        };
-        if (net.N > 0 && P.m > 0) load_pass(0);
         for (int base = 0; base < net.N && P.m > 0; base += kWave) {
             const int g = base + lane;
             const bool valid = g < net.N;
