@@ -249,7 +249,32 @@ __device__ double wg_forward(const DevNet &net, int shape, const double x[3], do
                 const double *Wr = net.weights + net.blk_off[b] + (long long)k * net.blk_ld[b];
                 const double *aj = act + (j == 0 ? 0 : 3 + net.unit_off[j]);
                 const int nj = net.width[j];
-                for (int q = 0; q < nj; ++q) acc += Wr[q] * aj[q];
+                // sixteen weights of the row (wide loads, then L1 hits) and
+                // activations are loaded at once; the last, partial chunk
+                // clamps its indices; the products are summed in order q = 0, 1, ...
+                int q0 = 0;
+                for (; q0 + 16 <= nj; q0 += 16) {
+                    double wv[16], av[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        wv[u] = Wr[q0 + u];
+                        av[u] = aj[q0 + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) acc += wv[u] * av[u];
+                }
+                if (q0 < nj) {
+                    double wv[16], av[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int q = min(q0 + u, nj - 1);
+                        wv[u] = Wr[q];
+                        av[u] = aj[q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (q0 + u < nj) acc += wv[u] * av[u];
+                }
             }
             if (l < L2 - 1) {
                 act[aoff + k] = acc > 0.0 ? acc : 0.0;
@@ -398,6 +423,7 @@ __device__ void wg_grad(const DevNet &net, const uint64_t *code, int am, double 
             const int ld = net.blk_ld[b];
             for (int q = tid; q < nj; q += nt) {
                 double acc = 0.0;
+#pragma unroll 8
                 for (int k = 0; k < nl; ++k) {
                     const double a = al[k];
                     if (a == 0.0 || (hidden && !code_bit(code, net.unit_off[l] + k))) continue;
