@@ -556,32 +556,58 @@ __global__ void k_face_flags(const int *face_m, long long n, int *has, long long
     }
 }
 
-__global__ void k_fetch(const DevNet net, long long n, const int *face_m, const int *fidx, const long long *voff,
-                        const int *ids, const double *verts, const int *nbr, const uint64_t *codes,
-                        const int *argmax, const int *shape, const long long *foff, long long *o_off, int *o_ids,
-                        double *o_verts, long long *o_nbr, uint64_t *o_codes, int *o_am, int *o_shape) {
+// The outputs never alias the march's arrays, and each face's corners are
+// taken four at a time with every load of the four issued before any store,
+// so a face costs a few dependent round trips (neighbour id, then its face
+// index) instead of three per corner.
+__global__ void k_fetch(const DevNet net, long long n, const int *__restrict__ face_m, const int *__restrict__ fidx,
+                        const long long *__restrict__ voff, const int *__restrict__ ids,
+                        const double *__restrict__ verts, const int *__restrict__ nbr,
+                        const uint64_t *__restrict__ codes, const int *__restrict__ argmax,
+                        const int *__restrict__ shape, const long long *__restrict__ foff,
+                        long long *__restrict__ o_off, int *__restrict__ o_ids, double *__restrict__ o_verts,
+                        long long *__restrict__ o_nbr, uint64_t *__restrict__ o_codes, int *__restrict__ o_am,
+                        int *__restrict__ o_shape) {
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
         const int m = face_m[c];
         if (m <= 0) continue;
         const long long f = fidx[c];
         const long long o = voff[c];
+        const long long s0 = foff[c];
         if (o_off) o_off[f] = o;
         if (o_codes)
             for (int w = 0; w < net.W; ++w) o_codes[f * net.W + w] = codes[c * net.W + w];
         if (o_am) o_am[f] = argmax[c];
         if (o_shape) o_shape[f] = shape[c];
-        for (int i = 0; i < m; ++i) {
-            const long long s = foff[c] + i;
-            if (o_ids) o_ids[o + i] = ids[s];
-            if (o_verts) {
-                o_verts[(o + i) * 3 + 0] = verts[s * 3 + 0];
-                o_verts[(o + i) * 3 + 1] = verts[s * 3 + 1];
-                o_verts[(o + i) * 3 + 2] = verts[s * 3 + 2];
+        for (int i0 = 0; i0 < m; i0 += 4) {
+            int id[4], g[4], gm[4], gf[4];
+            double x[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long long s = s0 + min(i0 + u, m - 1);
+                id[u] = ids[s];
+                x[u][0] = verts[s * 3 + 0];
+                x[u][1] = verts[s * 3 + 1];
+                x[u][2] = verts[s * 3 + 2];
+                g[u] = o_nbr ? nbr[s] : -1;
             }
-            if (o_nbr) {
-                const int g = nbr[s];
-                o_nbr[o + i] = g < 0 ? -1 : (face_m[g] > 0 ? (long long)fidx[g] : -2);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                gm[u] = g[u] >= 0 ? face_m[g[u]] : 0;
+                gf[u] = g[u] >= 0 ? fidx[g[u]] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i0 + u >= m) break;
+                const long long t = o + i0 + u;
+                if (o_ids) o_ids[t] = id[u];
+                if (o_verts) {
+                    o_verts[t * 3 + 0] = x[u][0];
+                    o_verts[t * 3 + 1] = x[u][1];
+                    o_verts[t * 3 + 2] = x[u][2];
+                }
+                if (o_nbr) o_nbr[t] = g[u] < 0 ? -1 : (gm[u] > 0 ? (long long)gf[u] : -2);
             }
         }
     }
