@@ -2546,7 +2546,6 @@ __global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *
             unsigned long long last_done = ~0ull, idle = 0;
             int nap = 1;
             for (unsigned poll = 0;; ++poll) {
-                if (ld_dev(&ctr->stop)) break;
                 if (held[0] < 0 && held[1] < 0 && held[2] < 0 && held[3] < 0) {
                     const unsigned long long a = atomicAdd(&ctr->next_cell, 4ull);
                     for (int k = 0; k < 4; ++k) held[k] = (long long)a + k;
@@ -2561,6 +2560,7 @@ __global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *
                 }
                 if (n > 0) break;
                 if ((poll & 7) == 7) {
+                    if (ld_dev(&ctr->stop)) break;
                     // done_cells first: its count only includes cells whose
                     // insertions (n_cells increments) had completed
                     const unsigned long long d = ld_dev(&ctr->done_cells);
@@ -2576,9 +2576,11 @@ __global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *
                         break;
                     }
                 }
-                // back off while nothing held is published (about 64 * nap cycles)
+                // back off while nothing held is published (about 64 * nap
+                // cycles, at most about 2k): idle workgroups' polls are
+                // device-scope loads that compete with the working ones
                 for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
-                if (nap < 8) nap <<= 1;
+                if (nap < 32) nap <<= 1;
             }
             tile_n = n;
         }
