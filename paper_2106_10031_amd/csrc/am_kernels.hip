@@ -2577,10 +2577,10 @@ __global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *
                     }
                 }
                 // back off while nothing held is published (about 64 * nap
-                // cycles, at most about 2k): idle workgroups' polls are
+                // cycles, at most about 8k): idle workgroups' polls are
                 // device-scope loads that compete with the working ones
                 for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
-                if (nap < 32) nap <<= 1;
+                if (nap < 128) nap <<= 1;
             }
             tile_n = n;
         }
