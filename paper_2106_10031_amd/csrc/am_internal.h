@@ -237,7 +237,7 @@ struct InlineInsert {
     unsigned *ready;
     unsigned epoch;
     unsigned long long cap_cells;
-    unsigned long long spin_limit;   // polls of one wait before the march gives up
+    unsigned long long spin_limit;   // bound of one wait: naps (~64 cycles) of a queue poll, 16x polls of a slot
 };
 
 // ---------------------------------------------------------------- helpers

@@ -1439,7 +1439,7 @@ __device__ void insert_neighbours(const DevNet &net, const InlineInsert &I, long
     // phase 3
     if (state == 2) {
         unsigned long long sv = kPending;
-        for (unsigned long long k = 0; k < I.spin_limit; ++k) {
+        for (unsigned long long k = 0; k < (I.spin_limit >> 4); ++k) {   // polls of ~1-2 us: under a second
             sv = ld_dev(&I.slots[pos]);
             if (!(sv & kPending)) break;
             __builtin_amdgcn_s_sleep(1);
@@ -2512,8 +2512,12 @@ __device__ void chain_tile_pp(const DevNet &net, const uint64_t *code_lds, const
 // finished: done_cells is read before n_cells (a cell is counted done only
 // after its insertions completed), so equal counts mean no cell is in flight
 // and none can appear; the ids a workgroup still holds then name no cell.
-// Every wait is bounded: spin_limit polls without a cell finishing anywhere
-// stop the march and count a stall; capacity overflows stop it too.  The
+// Every wait is bounded: a workgroup that has slept spin_limit naps (about
+// 64 cycles each) in its queue polls without a cell finishing anywhere stops
+// the march and counts a stall, and so does a wait for another wave's claim
+// that outlasts spin_limit / 16 polls; capacity overflows stop it too.  Idle
+// workgroups back off to about 8k cycles between polls: their device-scope
+// loads would otherwise compete with the working ones.  The
 // host checks both.  At least three waves per SIMD (the register budget
 // that allows, without spills): three workgroups per CU share the clip's
 // latency.
@@ -2543,7 +2547,7 @@ __global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *
     for (;;) {
         if (threadIdx.x == 0) {
             int n = 0;
-            unsigned long long last_done = ~0ull, idle = 0;
+            unsigned long long last_done = ~0ull, slept = 0;   // naps since done_cells last moved
             int nap = 1;
             for (unsigned poll = 0;; ++poll) {
                 if (held[0] < 0 && held[1] < 0 && held[2] < 0 && held[3] < 0) {
@@ -2569,8 +2573,8 @@ __global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *
                     if (d >= c2) break;   // nothing in flight: the march is over
                     if (d != last_done) {
                         last_done = d;
-                        idle = 0;
-                    } else if (++idle > (ins.spin_limit >> 3)) {   // counted every eighth poll
+                        slept = 0;
+                    } else if (slept > ins.spin_limit) {   // spin_limit naps of ~64 cycles: ~0.2 s
                         atomicAdd(&ctr->stalled, 1ull);
                         st_dev(&ctr->stop, 1ull);
                         break;
@@ -2580,6 +2584,7 @@ __global__ __launch_bounds__(256, 3) void k_march_persist(DevNet net, uint64_t *
                 // cycles, at most about 8k): idle workgroups' polls are
                 // device-scope loads that compete with the working ones
                 for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
+                slept += nap;
                 if (nap < 128) nap <<= 1;
             }
             tile_n = n;
