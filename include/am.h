@@ -175,6 +175,13 @@ typedef struct {
     double vertex_tol;    /* precision 1: a cell is also redone in FP64 when a vertex's
                              estimated relative error (stats.split_row_eps x its first-order
                              sensitivity to the rows) exceeds this (0: 1e-5) */
+    int32_t wait_limit;   /* kernel_path 3: bound of each wait of the march, in naps of about
+                             64 cycles that a workgroup polling the queue may sleep while no
+                             cell finishes anywhere (a wait for another wave's claim gets a
+                             sixteenth of it in polls); a wait that runs out stops the march
+                             with AM_E_STALL and the context can march again.  0: 1 << 23
+                             (about 0.2 s); a tiny value forces the stall (tests of that
+                             path).  Negative: AM_E_INVALID; ignored by the other paths */
 } am_march_opts;
 
 typedef struct {

@@ -55,7 +55,7 @@ class MarchOpts(C.Structure):
                 ("propose", C.c_int32), ("chain_groups", C.c_int32), ("graph_steps", C.c_int32),
                 ("face_routine", C.c_int32), ("async_", C.c_int32),
                 ("margin", C.c_double),
-                ("vertex_tol", C.c_double)]
+                ("vertex_tol", C.c_double), ("wait_limit", C.c_int32)]
 
 
 class MarchStats(C.Structure):
@@ -338,7 +338,7 @@ class Context:
 
     def march(self, max_cells=0, max_steps=0, strict=False, time_kernels=False, kernel_path=0, precision=0,
               margin=0.0, vertex_tol=0.0, propose=0, chain_groups=0, graph_steps=0, face_routine=0,
-              wait=True):
+              wait=True, wait_limit=0):
         """am_march; with wait=False it returns None at once (asynchronous
         march) and wait() gives its stats."""
         opts = MarchOpts(int(max_cells), int(max_steps), int(bool(strict)), int(bool(time_kernels)),
@@ -346,6 +346,7 @@ class Context:
                          int(face_routine), 0 if wait else 1)
         opts.margin = float(margin)
         opts.vertex_tol = float(vertex_tol)
+        opts.wait_limit = int(wait_limit)
         stats = MarchStats()
         st = self.L.am_march(self.h, C.byref(opts), C.byref(stats))
         if st != AM_OK:

@@ -1133,6 +1133,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         TRY(ensure_march(ctx, cap));
     }
     if (o.kernel_path < 0 || o.kernel_path > 3) return fail(ctx, AM_E_INVALID, "kernel_path must be 0..3");
+    if (o.wait_limit < 0) return fail(ctx, AM_E_INVALID, "wait_limit must be >= 0");
     const bool persistent = o.kernel_path == 3;
     if (persistent && (o.precision != 0 || o.propose != 0 || ctx->prop.samples || o.face_routine != 0 ||
                        o.graph_steps != 0 || o.max_steps != 0))
@@ -1299,7 +1300,7 @@ static am_status march_impl(am_ctx *ctx, const am_march_opts *opts, am_march_sta
         ins.ready = ctx->d_ready;
         ins.epoch = ctx->epoch;
         ins.cap_cells = (unsigned long long)cap;
-        ins.spin_limit = 1ull << 23;
+        ins.spin_limit = o.wait_limit > 0 ? (unsigned long long)o.wait_limit : 1ull << 23;
         if (o.time_kernels) HIPCHK(hipEventRecord(ctx->evk[0], s));
         launch_persist(net, ctx->persist_variant, ctx->persist_lds, ctx->d_codes, ctx->d_shape, ctx->d_am,
                        ctx->d_hash, ctx->d_hints, ctx->d_prows, ctx->persist_blocks, seed_cells, out, ctx->d_ctr, ins,

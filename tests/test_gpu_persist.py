@@ -12,6 +12,8 @@ test_gpu_golden.py):
   differ from run to run, the mesh does not);
 * a cell capacity that is too small ends the march with AM_E_CAPACITY (the
   queue drains, every workgroup leaves), and the context marches again;
+* a wait bound set from the host too small for the first round ends the march
+  with AM_E_STALL, and the context marches again;
 * options the persistent march does not take are refused.
 """
 import numpy as np
@@ -69,6 +71,34 @@ def test_persistent_repeats(binding):
         assert f == outs[0][0]
         for k in KEYS:
             assert torch.equal(out[k], outs[0][1][k]), k
+    ctx.close()
+
+
+def test_persistent_stall_is_reported_and_recovers(binding):
+    """A wait bound of four naps, set from the host (wait_limit), makes the
+    workgroups that start without a published cell give up before the first
+    round has finished anywhere: the march stops with AM_E_STALL, every
+    workgroup leaves (each wait stays bounded), and the same context then
+    marches with the default bound and gives the whole mesh again.  A
+    negative bound is refused before anything runs."""
+    net = nets.load_fitted("c2")
+    prim = np.load(nets.DATA_DIR + "/c2_primitives.npz")
+    o, d = seeds.centre_rays(prim["p0"], 128)
+    say("persistent: forced stall on c2")
+    ctx = binding.Context(0).load_net(net)
+    ctx.seed_rays(o, d)
+    ref = ctx.march(max_cells=1 << 21, kernel_path=3)
+    ctx.seed_rays(o, d)
+    with pytest.raises(binding.AmError) as e:
+        ctx.march(max_cells=1 << 21, kernel_path=3, wait_limit=4)
+    assert e.value.status == binding.AM_E_STALL
+    ctx.seed_rays(o, d)
+    st = ctx.march(max_cells=1 << 21, kernel_path=3)
+    assert st["faces"] == ref["faces"] and st["cells"] == ref["cells"]
+    with pytest.raises(binding.AmError) as e:
+        ctx.march(max_cells=1 << 21, kernel_path=3, wait_limit=-1)
+    assert e.value.status == binding.AM_E_INVALID
+    say("persistent: stall reported, then", st["faces"], "faces")
     ctx.close()
 
 
